@@ -1,0 +1,109 @@
+"""Independent textbook routines the oracle is pinned against.
+
+None of these reuse the oracle's code; each is a different algorithm (or the
+brute-force definition) for a quantity the oracle also produces.
+"""
+
+import numpy as np
+
+
+def tiny_problem(Q=3, KM=8, N=12, seed=0, scale=1.0):
+    """Random complex operators/measurements small enough for brute force."""
+    rng = np.random.default_rng(seed)
+    A = [(rng.standard_normal((KM, N)) + 1j * rng.standard_normal((KM, N))) / np.sqrt(2)
+         for _ in range(Q)]
+    xt = np.zeros((Q, N))
+    sup = rng.choice(N, size=max(1, N // 4), replace=False)
+    for q in range(Q):
+        xt[q, sup] = rng.uniform(0.5, 1.0, size=sup.size)
+    y = np.stack([A[q] @ xt[q] for q in range(Q)])
+    y = y + 0.05 * (rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape))
+    return A, scale * y
+
+
+def prox_bruteforce(v, lam, beta, half_width=None, n=801):
+    """argmin_z lam|z| + beta/2 |z - v|^2 by exhaustive search on a 2-D grid,
+    refined twice around the best point."""
+    if half_width is None:
+        half_width = abs(v) + 1.0
+    cx, cy, hw = 0.0, 0.0, half_width
+    best = 0j
+    for _ in range(3):
+        xs = np.linspace(cx - hw, cx + hw, n)
+        ys = np.linspace(cy - hw, cy + hw, n)
+        Z = xs[None, :] + 1j * ys[:, None]
+        F = lam * np.abs(Z) + 0.5 * beta * np.abs(Z - v) ** 2
+        i = np.unravel_index(np.argmin(F), F.shape)
+        best = Z[i]
+        cx, cy, hw = best.real, best.imag, 4 * hw / (n - 1)
+    return best
+
+
+def cd_quadratic_l1(H, b, lam, tol=1e-15, maxit=200000):
+    """Complex coordinate descent for  min 1/2 s^H H s - Re(b^H s) + lam ||s||_1
+    (H Hermitian positive definite).  Each coordinate step is exact:
+    s_j = S_lam(b_j - sum_{i != j} H_ji s_i) / H_jj."""
+    n = b.size
+    s = np.zeros(n, dtype=np.complex128)
+    Hs = np.zeros(n, dtype=np.complex128)
+    for _ in range(maxit):
+        delta = 0.0
+        for j in range(n):
+            hjj = H[j, j].real
+            rho = b[j] - (Hs[j] - hjj * s[j])
+            m = abs(rho)
+            new = 0j if m <= lam else rho * (1 - lam / m) / hjj
+            d = new - s[j]
+            if d != 0:
+                Hs += H[:, j] * d
+                s[j] = new
+                delta = max(delta, abs(d))
+        if delta <= tol * max(1.0, np.abs(s).max()):
+            break
+    return s
+
+
+def sharing_reduction(A, y, mu, gamma):
+    """H, btilde of the single-variable problem in s = sum_q x_q that the
+    Q-sensor problem reduces to (inf-convolution of the per-sensor quadratics):
+    H = (sum_q G_q^-1)^-1, btilde = H sum_q G_q^-1 mu A_q^H y_q,
+    G_q = mu A_q^H A_q + gamma I."""
+    N = A[0].shape[1]
+    Sinv = np.zeros((N, N), dtype=np.complex128)
+    rhs = np.zeros(N, dtype=np.complex128)
+    for a, yy in zip(A, y):
+        G = mu * a.conj().T @ a + gamma * np.eye(N)
+        Gi = np.linalg.inv(G)
+        Sinv += Gi
+        rhs += Gi @ (mu * a.conj().T @ yy)
+    H = np.linalg.inv(Sinv)
+    H = 0.5 * (H + H.conj().T)
+    return H, H @ rhs
+
+
+def lasso_admm_boyd(A, y, mu, beta, gamma, lam, iters, eps_abs, eps_rel):
+    """Boyd et al. 2011 Sec. 6.4 LASSO ADMM (one block x, one block z) for
+    min mu/2||y-Ax||^2 + gamma/2||x||^2 + lam||z||_1, x = z, scaled form,
+    with the Sec. 3.3.1 residuals and tolerances.  Returns per-iteration
+    (z, r, s, eps_pri, eps_dual)."""
+    N = A.shape[1]
+    M = mu * A.conj().T @ A + (gamma + beta) * np.eye(N)
+    Minv = np.linalg.inv(M)
+    Aty = mu * A.conj().T @ y
+    x = np.zeros(N, complex)
+    z = np.zeros(N, complex)
+    u = np.zeros(N, complex)
+    out = []
+    for _ in range(iters):
+        x = Minv @ (Aty + beta * (z - u))
+        v = x + u
+        m = np.abs(v)
+        zn = np.where(m > lam / beta, v * (1 - (lam / beta) / np.maximum(m, 1e-300)), 0)
+        u = u + x - zn
+        r = np.linalg.norm(x - zn)
+        s = beta * np.linalg.norm(zn - z)
+        z = zn
+        ep = np.sqrt(N) * eps_abs + eps_rel * max(np.linalg.norm(x), np.linalg.norm(z))
+        ed = np.sqrt(N) * eps_abs + eps_rel * np.linalg.norm(beta * u)
+        out.append((z.copy(), r, s, ep, ed))
+    return out
