@@ -1,0 +1,183 @@
+/*
+ * sadmm.h -- C ABI of the MI355X sharing-ADMM radar imaging engine.
+ *
+ * Problem (Sec. II, eq. (1); Sec. III, eq. (2)).  Q radar sensors observe one
+ * scene of N pixels.  Sensor q measures y_q = A_q x_q + w_q in C^{KM}, with
+ * A_q in C^{KM x N} (K fast-time samples times M receive antennas) and x_q the
+ * scene's reflectivity as seen by sensor q.  The engine solves
+ *
+ *   min  sum_q [ mu/2 ||y_q - A_q x_q||^2 + gamma/2 ||x_q||^2 ]
+ *        + lambda ||sum_q x_q||_1
+ *
+ * by sharing ADMM (eq. (3)): per-sensor ridge x-updates through a cached
+ * factor of (c/mu) I + Ahat_q Ahat_q^H (Woodbury form, c = beta + gamma), a
+ * global soft-threshold update of the image z, and a dual update.  With
+ * `prune` set, the selector update of eq. (3) (subroutine SSC, Alg. 1)
+ * removes pixels whose mean change over the last Kp iterations falls below
+ * eps_p, once the primal residual meets its tolerance; removed pixels are
+ * frozen at their last value.  The returned image is z, the global image at
+ * the scale of the average sub-image (1/Q) sum_q x_q.
+ *
+ * Conventions
+ *   - Every call returns an sadmm_status (0 = success).  No exception or
+ *     abort crosses the ABI; sadmm_last_error() gives a message for the last
+ *     failing call on a handle.
+ *   - Complex buffers are interleaved (re, im) in the sadmm_dtype given.
+ *     Operators are column-major: column n (pixel n) holds KM contiguous
+ *     entries, row index m*K + k; consecutive columns are `ld` entries apart.
+ *   - Pointers flagged `on_device` are HIP device pointers on the handle's
+ *     device; others are host pointers.  The caller owns every buffer it
+ *     passes; the engine copies inputs (converting to its storage precision)
+ *     before the call returns, and writes outputs into caller buffers.
+ *   - A handle is used by one host thread at a time and issues all work on
+ *     params.stream (a hipStream_t, 0 = the null stream).  Calls return after
+ *     their work on that stream has completed.
+ */
+#ifndef SADMM_H
+#define SADMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sadmm_s* sadmm_t;
+
+typedef enum {
+  SADMM_OK = 0,
+  SADMM_E_ARG = -1,      /* null pointer, out-of-range value */
+  SADMM_E_SHAPE = -2,    /* sizes inconsistent with the handle */
+  SADMM_E_STATE = -3,    /* call order (e.g. solve before every operator is set) */
+  SADMM_E_HIP = -4,      /* a HIP runtime call failed */
+  SADMM_E_NOMEM = -5,    /* device allocation failed */
+  SADMM_E_NUMERIC = -6   /* non-finite value, or a factor lost positive definiteness */
+} sadmm_status;
+
+typedef enum { SADMM_C128 = 0, SADMM_C64 = 1 } sadmm_dtype;
+
+/* Storage and arithmetic of the operator.  FP64: complex128 storage and FP64
+ * arithmetic throughout.  FP32: complex64 storage, FP32 arithmetic, FP64 factor
+ * build.  FP16P / BF16P: operator stored as separate real and imaginary half /
+ * bfloat16 planes per column, FP32 arithmetic, FP64 factor build. */
+typedef enum {
+  SADMM_ST_FP64 = 0,
+  SADMM_ST_FP32 = 1,
+  SADMM_ST_FP16P = 2,
+  SADMM_ST_BF16P = 3
+} sadmm_storage;
+
+typedef struct {
+  int32_t Q, K, M, N;         /* sensors, fast-time samples, Rx antennas, pixels */
+  double mu, beta, gamma;     /* data weight, ADMM penalty, per-sensor ridge (> 0) */
+  double lambda;              /* absolute l1 weight on sum_q x_q */
+  double eps_abs, eps_rel;    /* residual tolerances (Boyd Sec. 3.3.1 form) */
+  int32_t max_iter;           /* iteration cap (>= 1) */
+  int32_t stop;               /* 1: stop at convergence; 0: run exactly max_iter */
+  int32_t check_every;        /* iterations queued between host status reads (>= 1) */
+  int32_t prune;              /* 0: plain SADMM; 1: accelerated (SSC, Alg. 1) */
+  int32_t Kp;                 /* SSC window (iterations), 1..64 */
+  double eps_p;               /* SSC tolerance on the mean |change| */
+  int32_t prune_mode;         /* 0: freeze eliminated pixels; 1: zero them */
+  int32_t kkt;                /* 1: after convergence, re-check eliminated pixels
+                                 against the optimality condition and reinstate */
+  double kkt_tol;             /* reinstate when |g| > kkt_tol * lambda */
+  int32_t storage;            /* sadmm_storage */
+  int32_t reuse_factor;       /* 1: a later solve reuses a factor built for the same
+                                 starting selector; 0: every solve rebuilds it */
+  void* stream;               /* hipStream_t */
+} sadmm_params;
+
+typedef struct {
+  int32_t iters;              /* iterations run */
+  int32_t status;             /* 0 converged, 1 max_iter reached, 2 NMSE target reached */
+  int32_t prune_events;       /* iterations at which SSC removed pixels */
+  int32_t reinstated;         /* pixels put back by the optimality re-check */
+  int32_t refactors;          /* full factor rebuilds (excluding the initial one) */
+  int32_t updates;            /* low-rank factor up/down-dates */
+  double r, s, eps_pri, eps_dual;   /* residuals of the last iteration */
+  double max_active_frac;     /* max_q N_q / N at the end */
+  double nmse;                /* NMSE of z vs the reference image, if one is set */
+} sadmm_info;
+
+/* Fills *p with defaults: mu = beta = gamma = 1, eps_rel = 1e-4, Kp = 5,
+ * eps_p = 1e-5, storage FP32, stop = 1, check_every = 8, kkt_tol = 1e-2,
+ * reuse_factor = 1. */
+void sadmm_default_params(sadmm_params* p);
+
+/* Creates a handle on the current HIP device.  Allocates all per-problem
+ * device memory sized for Q, K*M and N.  Errors: E_ARG on invalid params. */
+int sadmm_create(const sadmm_params* p, sadmm_t* out);
+
+/* Operator of sensor q (eq. (1)): A, KM x N column-major with leading
+ * dimension ld >= KM, complex128 or complex64.  Copied and converted to the
+ * storage precision.  Invalidates the factor of sensor q. */
+int sadmm_set_operator(sadmm_t h, int32_t q, const void* A, int32_t dtype,
+                       int64_t ld, int32_t on_device);
+
+/* Operator of sensor q generated on the device from the LFM geometry of
+ * eq. (1): A[m*K+k, n] = exp(-j 2 pi f_k tau_{m,n}), f_k = f0 + bw*k/K,
+ * tau_{m,n} = (|tx - p_n| + |rx_m - p_n|)/c.  tx_xy: 2 doubles; rx_xy: 2*M
+ * doubles; pix_xy: 2*N doubles (host pointers).  The phase f_k*tau is reduced
+ * modulo one cycle in FP64 before the complex exponential. */
+int sadmm_set_operator_geometry(sadmm_t h, int32_t q, const double* tx_xy,
+                                const double* rx_xy, const double* pix_xy,
+                                double f0, double bw);
+
+/* Initial selector of sensor q (eq. (3), P_q at the first iteration):
+ * mask[n] = 1 keeps pixel n active, 0 eliminates it from the start (frozen at
+ * x = 0).  Host pointer, N bytes.  Persists for later solves until reset by
+ * passing mask = NULL (all active). */
+int sadmm_set_active_mask(sadmm_t h, int32_t q, const uint8_t* mask);
+
+/* Optional reference image x_ref (N complex): the NMSE ||z - x_ref||^2 /
+ * ||x_ref||^2 is recorded each iteration, and when nmse_target > 0 the solve
+ * stops at the first iteration with NMSE <= nmse_target (info.status = 2).
+ * Pass x_ref = NULL to clear. */
+int sadmm_set_reference(sadmm_t h, const void* x_ref, int32_t dtype,
+                        int32_t on_device, double nmse_target);
+
+/* Solves for measurements y (Q x KM complex, sensor-major).  Runs from X = 0,
+ * z = 0, u = 0 with the selectors set by sadmm_set_active_mask.  Builds or
+ * reuses the per-sensor factors.  info may be NULL.  Errors: E_STATE when an
+ * operator is missing, E_NUMERIC on a non-finite residual. */
+int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
+                sadmm_info* info);
+
+/* Global image z (N complex) of the last solve. */
+int sadmm_get_image(sadmm_t h, void* xG, int32_t dtype, int32_t on_device);
+
+/* Sub-image x_q (N complex) of sensor q, eliminated pixels included. */
+int sadmm_get_sensor_image(sadmm_t h, int32_t q, void* xq, int32_t dtype,
+                           int32_t on_device);
+
+/* Final selector of sensor q: mask[n] = 1 if pixel n is active (host, N bytes). */
+int sadmm_get_active_mask(sadmm_t h, int32_t q, uint8_t* mask);
+
+/* Active pixel indices of sensor q in ascending order (host, capacity N
+ * int32); *count receives N_q. */
+int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count);
+
+/* Per-iteration history of the last solve (host buffers of capacity cap):
+ * which = 0 r, 1 s, 2 eps_pri, 3 eps_dual, 4 nmse, 5 max_q N_q / N.
+ * *count receives the number of iterations recorded. */
+int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap,
+                      int32_t* count);
+
+/* Matched-filter images |A_q^H y_q| (Q x N doubles, host) of the given
+ * measurements, over all pixels (the CNN input and the back-projection image). */
+int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
+                         double* out);
+
+/* Wall time of the last solve on its stream (HIP events), milliseconds:
+ * which = 0 whole solve, 1 factor builds/updates, 2 iterations. */
+int sadmm_get_timing(sadmm_t h, int32_t which, double* ms);
+
+void sadmm_destroy(sadmm_t h);
+const char* sadmm_last_error(sadmm_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SADMM_H */

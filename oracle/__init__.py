@@ -12,8 +12,9 @@ Modules
   cnn         FP64 reference of the pixel-pruning CNN (forward, backward, BCE)
 """
 
-from .sadmm import Params, Result, solve, soft_threshold, kkt_gradient, residual_norms
+from .sadmm import (Params, Result, solve, soft_threshold, kkt_gradient, residual_norms,
+                    matched_filter)
 from .lambda_max import lambda_max
 
 __all__ = ["Params", "Result", "solve", "soft_threshold", "kkt_gradient",
-           "residual_norms", "lambda_max"]
+           "residual_norms", "lambda_max", "matched_filter"]

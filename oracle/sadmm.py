@@ -311,3 +311,9 @@ def _reinstate(A, y, X, u, p, active, yp, D) -> int:
         D[:, q, bad] = np.inf
         back += bad.size
     return back
+
+
+def matched_filter(A: List[np.ndarray], y: np.ndarray) -> np.ndarray:
+    """|A_q^H y_q| per sensor and pixel, shape (Q, N): the back-projection image
+    of each sensor (the data term's gradient at x = 0, up to mu)."""
+    return np.stack([np.abs(_adjoint(np.asarray(a), np.asarray(yy))) for a, yy in zip(A, y)])

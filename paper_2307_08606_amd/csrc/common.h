@@ -1,0 +1,154 @@
+// Shared device helpers: complex arithmetic, operator storage formats,
+// wavefront reductions.  gfx950 (CDNA4): 64-lane wavefronts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#define SADMM_WAVE 64
+
+template <class T> struct C2 { T re, im; };
+using cf = C2<float>;
+using cd = C2<double>;
+
+template <class T> __host__ __device__ inline C2<T> cmk(T r, T i) { return C2<T>{r, i}; }
+template <class T> __device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __device__ inline C2<T> cscale(C2<T> a, T s) { return {a.re * s, a.im * s}; }
+// a*b
+template <class T> __device__ inline C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc += a*b
+template <class T> __device__ inline void cfma(C2<T>& acc, C2<T> a, C2<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += conj(a)*b
+template <class T> __device__ inline void cfmac(C2<T>& acc, C2<T> a, C2<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
+template <class T> __device__ inline T cabs2(C2<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------- storage formats
+// Storage ids match sadmm_storage.
+enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP16P = 2, ST_BF16P = 3 };
+
+// Column layout per storage (ld counts storage "slots" per column):
+//   ST_FP64 : KM complex128 entries               (ld >= KM, slot = 16 B)
+//   ST_FP32 : KM complex64 entries                (ld >= KM, slot = 8 B)
+//   ST_FP16P/ST_BF16P : KM real halves then KM imaginary halves
+//                       (ld >= 2*KM slots of 2 B; real plane at +0, imag at +KM)
+// RPT = rows covered by one 16-byte vector load (per plane for planar).
+template <int ST> struct Store;
+template <> struct Store<ST_FP64> {
+  using T = double;
+  static constexpr int RPT = 1;
+  static constexpr int BYTES = 16;   // per complex entry
+  __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
+    (void)KM;
+    const double2 v = reinterpret_cast<const double2*>(col)[i];
+    re[0] = v.x; im[0] = v.y;
+  }
+  __device__ static inline cd get(const void* col, int i, int KM) {
+    (void)KM;
+    const double2 v = reinterpret_cast<const double2*>(col)[i];
+    return {v.x, v.y};
+  }
+};
+template <> struct Store<ST_FP32> {
+  using T = float;
+  static constexpr int RPT = 2;
+  static constexpr int BYTES = 8;
+  __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
+    (void)KM;
+    const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(col) + i);
+    re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w;
+  }
+  __device__ static inline cd get(const void* col, int i, int KM) {
+    (void)KM;
+    const float2 v = reinterpret_cast<const float2*>(col)[i];
+    return {(double)v.x, (double)v.y};
+  }
+};
+__device__ inline float h2f(uint16_t b) { return __half2float(__ushort_as_half(b)); }
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+template <int ST> __device__ inline float p16_to_f(uint16_t b) {
+  if constexpr (ST == ST_FP16P) return h2f(b); else return bf2f(b);
+}
+template <int STP> struct StoreP16 {
+  using T = float;
+  static constexpr int RPT = 8;
+  static constexpr int BYTES = 4;
+  __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
+    const uint16_t* c = reinterpret_cast<const uint16_t*>(col);
+    const uint4 vr = *reinterpret_cast<const uint4*>(c + i);
+    const uint4 vi = *reinterpret_cast<const uint4*>(c + KM + i);
+    const uint32_t r4[4] = {vr.x, vr.y, vr.z, vr.w};
+    const uint32_t i4[4] = {vi.x, vi.y, vi.z, vi.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      re[2 * t] = p16_to_f<STP>((uint16_t)(r4[t] & 0xffffu));
+      re[2 * t + 1] = p16_to_f<STP>((uint16_t)(r4[t] >> 16));
+      im[2 * t] = p16_to_f<STP>((uint16_t)(i4[t] & 0xffffu));
+      im[2 * t + 1] = p16_to_f<STP>((uint16_t)(i4[t] >> 16));
+    }
+  }
+  __device__ static inline cd get(const void* col, int i, int KM) {
+    const uint16_t* c = reinterpret_cast<const uint16_t*>(col);
+    return {(double)p16_to_f<STP>(c[i]), (double)p16_to_f<STP>(c[KM + i])};
+  }
+};
+template <> struct Store<ST_FP16P> : StoreP16<ST_FP16P> {};
+template <> struct Store<ST_BF16P> : StoreP16<ST_BF16P> {};
+
+// Address of column `n` for a storage with leading dimension ld (in slots).
+template <int ST> __device__ inline const void* col_ptr(const void* base, int64_t ld, int64_t n) {
+  if constexpr (ST == ST_FP64) return reinterpret_cast<const double2*>(base) + ld * n;
+  else if constexpr (ST == ST_FP32) return reinterpret_cast<const float2*>(base) + ld * n;
+  else return reinterpret_cast<const uint16_t*>(base) + ld * n;
+}
+
+// ---------------------------------------------------------------- reductions
+template <class T> __device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, SADMM_WAVE);
+  return v;
+}
+
+// Deterministic block sum of NV values per thread (blockDim.x = 256).
+// Result valid in thread 0.  `sm` must hold 4*NV values.
+template <class T, int NV> __device__ inline void block_sum256(T (&v)[NV], T* sm) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) sm[w * NV + j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = ((sm[j] + sm[NV + j]) + sm[2 * NV + j]) + sm[3 * NV + j];
+  }
+  __syncthreads();
+}
+
+// Device control block shared by all per-iteration kernels.
+struct Ctl {
+  int k;            // completed iterations
+  int halt;         // bit mask of HALT_* : set => per-iteration kernels do nothing
+  int gate;         // r <= eps_pri at the last iteration
+  int nan;          // non-finite value seen
+  int gone_total;   // pixels SSC decided to eliminate at the last iteration
+  int max_iter;
+  int pad[2];
+  double r, s, eps_pri, eps_dual, nmse;
+};
+enum : int { HALT_CONV = 1, HALT_PRUNE = 2, HALT_MAXIT = 4, HALT_NAN = 8, HALT_NMSE = 16 };

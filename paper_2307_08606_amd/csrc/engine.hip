@@ -1,0 +1,857 @@
+// Host engine and C ABI of the sharing-ADMM radar imager (see include/sadmm.h).
+//
+// Layout in HBM (per handle; KMp = K*M rounded up to 32, rows beyond K*M zero):
+//   Afull[q]  operator A_q, column-major, one column per pixel, storage format
+//             per sadmm_storage (ldA slots per column)
+//   Ahat[q]   active columns of A_q in ascending pixel order (the compacted
+//             A_q P_q^T of eq. (3)); aliases Afull[q] while every pixel is active
+//   W64[q]    ((c/mu) I + Ahat Ahat^H)^{-1}, complex128 KMp x KMp (master copy)
+//   W[q]      the same in compute precision, applied every iteration
+//   X, dX     Q x N compute-precision complex, sensor-major
+//   xbar,z,u  N complex;  D  Kp x Q x N ring of |x^(i) - x^(i-1)|
+//   y, yp     Q x KMp complex128 measurements and y' (frozen pixels removed)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sadmm.h"
+#include "iter.h"
+#include "linalg.h"
+#include "util.h"
+
+namespace {
+
+constexpr int KKT_ROUNDS = 8;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sadmm_s {
+  sadmm_params p{};
+  int Q = 0, K = 0, M = 0, KM = 0, KMp = 0, N = 0;
+  int st = ST_FP32;
+  bool dbl = false;
+  size_t csz = 8;        // bytes per compute-precision complex
+  int64_t ldA = 0;       // slots per operator column
+  size_t slot = 8;       // bytes per slot
+  hipStream_t s = nullptr;
+  std::string err;
+  std::vector<void*> allocs;
+
+  std::vector<void*> Afull, Ahat_buf, W, Wc;   // Wc: compute-precision W
+  std::vector<cd*> W64;
+  std::vector<int*> J, Jnew;
+  std::vector<void*> b0;
+  std::vector<int> nq;
+  std::vector<bool> op_set, fac_valid;
+  std::vector<std::vector<int>> facJ;          // active set the factor was built for
+  std::vector<std::vector<uint8_t>> mask0;     // caller's initial selectors
+
+  void *X = nullptr, *dX = nullptr, *xbar = nullptr, *z = nullptr, *u = nullptr, *D = nullptr;
+  void *tpart = nullptr, *t = nullptr, *w = nullptr, *gtmp = nullptr, *xref = nullptr;
+  double *y = nullptr, *yp = nullptr, *e = nullptr, *red = nullptr, *hist = nullptr;
+  double* mf = nullptr;
+  uint8_t *mask = nullptr, *keep = nullptr, *flag = nullptr, *ones = nullptr;
+  int *gone = nullptr, *fail = nullptr, *counts = nullptr, *lst = nullptr, *lst2 = nullptr;
+  Ctl* ctl = nullptr;
+  Ctl* ctl_h = nullptr;      // pinned mirror
+  int* counts_h = nullptr;   // pinned
+  int* halt_h = nullptr;     // pinned
+  SensorDesc* sens_d = nullptr;
+  std::vector<SensorDesc> sens_h;
+  GemmDesc* gemm_d = nullptr;
+  HpdDesc* hpd_d = nullptr;
+  cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Rg = nullptr,
+     *Cg = nullptr;
+  std::vector<cd*> hpdD, hpdR, hpdC;          // per-sensor GJ scratch
+  int rmax = 0, rpad_max = 0;
+  int chunk = 256, nchunk = 0, nblk = 0;
+  double xref_norm2 = 0.0, nmse_target = 0.0;
+  bool have_ref = false;
+
+  // results of the last solve
+  sadmm_info info{};
+  std::vector<double> hist_h;   // 6 x max_iter
+  int hist_count = 0;
+  double t_total = 0, t_factor = 0, t_iter = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
+  bool solved = false;
+};
+
+namespace {
+
+int fail_msg(sadmm_t h, int code, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(h, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail_msg(h, SADMM_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+  } while (0)
+
+#define TRY(x)              \
+  do {                      \
+    int rc_ = (x);          \
+    if (rc_ != SADMM_OK) return rc_; \
+  } while (0)
+
+int dalloc(sadmm_t h, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  h->allocs.push_back(*p);
+  return SADMM_OK;
+}
+template <class P> int dalloc_t(sadmm_t h, P** p, size_t bytes) {
+  void* v = nullptr;
+  int rc = dalloc(h, &v, bytes);
+  *p = static_cast<P*>(v);
+  return rc;
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+IterArgs make_args(sadmm_t h) {
+  IterArgs a{};
+  a.Q = h->Q; a.KMp = h->KMp; a.N = h->N; a.Kp = h->p.Kp;
+  a.chunk = h->chunk; a.nchunk = h->nchunk;
+  a.prune = h->p.prune; a.stop = h->p.stop;
+  a.beta = h->p.beta;
+  a.c = h->p.beta + h->p.gamma;
+  a.tau = h->p.lambda / h->p.beta;
+  a.eps_abs = h->p.eps_abs; a.eps_rel = h->p.eps_rel; a.eps_p = h->p.eps_p;
+  a.inv_Q = 1.0 / h->Q;
+  a.nmse_target = h->nmse_target;
+  a.xref_norm2 = h->xref_norm2;
+  a.sens = h->sens_d;
+  a.X = h->X; a.dX = h->dX; a.xbar = h->xbar; a.z = h->z; a.u = h->u; a.D = h->D;
+  a.tpart = h->tpart; a.t = h->t; a.w = h->w;
+  a.xref = h->have_ref ? h->xref : nullptr;
+  a.yp = h->yp;
+  a.red = h->red; a.nblk = h->nblk;
+  a.max_iter = h->p.max_iter;
+  a.ctl = h->ctl; a.hist = h->hist;
+  a.keep = h->keep; a.gone = h->gone;
+  return a;
+}
+
+const void* ahat_ptr(sadmm_t h, int q) {
+  return (h->nq[q] == h->N) ? h->Afull[q] : h->Ahat_buf[q];
+}
+
+int push_descs(sadmm_t h) {
+  for (int q = 0; q < h->Q; ++q) {
+    SensorDesc& d = h->sens_h[q];
+    d.A = ahat_ptr(h, q);
+    d.Afull = h->Afull[q];
+    d.J = h->J[q];
+    d.b0 = h->b0[q];
+    d.W = h->Wc[q];
+    d.lda = h->ldA;
+    d.nq = h->nq[q];
+  }
+  HIPCHK(h, hipMemcpyAsync(h->sens_d, h->sens_h.data(), sizeof(SensorDesc) * h->Q,
+                           hipMemcpyHostToDevice, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return SADMM_OK;
+}
+
+// Ahat[q] <- Afull[q][:, J[q]] (only when some pixel is inactive)
+int compact_operator(sadmm_t h, int q) {
+  if (h->nq[q] == h->N) return SADMM_OK;
+  if (!h->Ahat_buf[q]) TRY(dalloc(h, &h->Ahat_buf[q], (size_t)h->ldA * h->slot * h->N));
+  gather_columns(h->Afull[q], h->Ahat_buf[q], h->ldA, (int64_t)h->slot, h->J[q], h->nq[q], h->s);
+  return SADMM_OK;
+}
+
+int check_fail(sadmm_t h) {
+  int f = 0;
+  HIPCHK(h, hipMemcpyAsync(&f, h->fail, sizeof(int), hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  if (f) {
+    HIPCHK(h, hipMemsetAsync(h->fail, 0, sizeof(int), h->s));
+    return fail_msg(h, SADMM_E_NUMERIC, "factor lost positive definiteness");
+  }
+  return SADMM_OK;
+}
+
+// Full factor build for the listed sensors: W64 = ((c/mu) I + Ahat Ahat^H)^{-1}
+int build_factors(sadmm_t h, const std::vector<int>& qs) {
+  if (qs.empty()) return SADMM_OK;
+  const double rho = (h->p.beta + h->p.gamma) / h->p.mu;
+  std::vector<GemmDesc> gd(qs.size());
+  std::vector<HpdDesc> hd(qs.size());
+  for (size_t i = 0; i < qs.size(); ++i) {
+    const int q = qs[i];
+    GemmDesc& g = gd[i];
+    g.A = ahat_ptr(h, q); g.B = ahat_ptr(h, q); g.C = h->W64[q];
+    g.m = h->KMp; g.n = h->KMp; g.k = h->nq[q];
+    g.kmpA = h->KMp; g.kmpB = h->KMp;
+    g.lda = h->ldA; g.ldb = h->ldA; g.ldc = h->KMp;
+    g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta = 0.0; g.diag = rho;
+    hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdR[q], h->hpdC[q]};
+  }
+  HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
+  zgemm_batched(h->gemm_d, (int)qs.size(), h->KMp, h->KMp, h->st, h->st, OP_N, OP_C, true, h->s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->hpd_d, hd.data(), sizeof(HpdDesc) * hd.size(), hipMemcpyHostToDevice, h->s));
+  hpd_inverse_batched(h->hpd_d, (int)qs.size(), h->KMp, h->fail, h->s);
+  HIPCHK(h, hipGetLastError());
+  for (int q : qs) {
+    cast_hermitian(h->W64[q], h->KMp, h->Wc[q], h->KMp, h->KMp, !h->dbl, h->s);
+    h->fac_valid[q] = true;
+  }
+  HIPCHK(h, hipGetLastError());
+  return check_fail(h);
+}
+
+// Low-rank correction of W64[q] for r columns (pixel list lst) leaving
+// (sign = -1: removal) or joining (sign = +1: reinstatement) Ahat:
+//   G' = G + sign * Ar Ar^H,
+//   W' = W - sign * W Ar (I + sign * Ar^H W Ar)^{-1} Ar^H W.
+int lowrank_update(sadmm_t h, int q, const int* d_list, int r, int sign) {
+  const int KMp = h->KMp;
+  const int rp = round_up(r, HPD_NB);
+  gather_columns_fp64(h->Afull[q], h->ldA, h->st, KMp, d_list, r, h->Ar, h->s);
+  std::array<GemmDesc, 4> g;
+  // V = W Ar
+  g[0] = GemmDesc{h->W64[q], h->Ar, h->V, KMp, r, KMp, KMp, KMp, KMp, KMp, KMp, 1.0, 0.0, 0.0, 0.0};
+  // Cm = I + sign * Ar^H V   (identity-padded to rp)
+  g[1] = GemmDesc{h->Ar, h->V, h->Cm, r, r, KMp, KMp, KMp, KMp, KMp, rp, (double)sign, 0.0, 1.0, 0.0};
+  // Tm = V Cm^{-1}
+  g[2] = GemmDesc{h->V, h->Cm, h->Tm, KMp, r, r, KMp, KMp, KMp, rp, KMp, 1.0, 0.0, 0.0, 0.0};
+  // W += -sign * Tm V^H
+  g[3] = GemmDesc{h->Tm, h->V, h->W64[q], KMp, KMp, r, KMp, KMp, KMp, KMp, KMp, -(double)sign, 0.0, 1.0, 0.0};
+  HpdDesc hd{h->Cm, rp, h->Dg, h->Rg, h->Cg};
+  HIPCHK(h, hipMemcpyAsync(h->gemm_d, g.data(), sizeof(GemmDesc) * 4, hipMemcpyHostToDevice, h->s));
+  HIPCHK(h, hipMemcpyAsync(h->hpd_d, &hd, sizeof hd, hipMemcpyHostToDevice, h->s));
+  zgemm_batched(h->gemm_d, 1, KMp, r, ST_FP64, ST_FP64, OP_N, OP_N, false, h->s);
+  HIPCHK(h, hipMemsetAsync(h->Cm, 0, sizeof(cd) * (size_t)rp * rp, h->s));
+  set_identity_pad(h->Cm, 0, rp, 0.0, h->s);
+  zgemm_batched(h->gemm_d + 1, 1, r, r, ST_FP64, ST_FP64, OP_C, OP_N, false, h->s);
+  hpd_inverse_batched(h->hpd_d, 1, rp, h->fail, h->s);
+  zgemm_batched(h->gemm_d + 2, 1, KMp, r, ST_FP64, ST_FP64, OP_N, OP_N, false, h->s);
+  zgemm_batched(h->gemm_d + 3, 1, KMp, KMp, ST_FP64, ST_FP64, OP_N, OP_C, false, h->s);
+  cast_hermitian(h->W64[q], KMp, h->Wc[q], KMp, KMp, !h->dbl, h->s);
+  HIPCHK(h, hipGetLastError());
+  h->info.updates += 1;
+  return check_fail(h);
+}
+
+// Is a rank-r correction cheaper than rebuilding the factor for nq_new columns?
+bool prefer_lowrank(sadmm_t h, int r, int nq_new) {
+  if (r > h->rmax) return false;
+  const double K2 = (double)h->KMp * h->KMp;
+  const double upd = 2.0 * K2 * r + (double)r * r * r;
+  const double full = 0.5 * K2 * nq_new + (double)h->KMp * K2;
+  return upd < full;
+}
+
+int refresh_factor(sadmm_t h, int q, const int* d_list, int r, int sign) {
+  if (r <= 0) return SADMM_OK;
+  if (prefer_lowrank(h, r, h->nq[q])) return lowrank_update(h, q, d_list, r, sign);
+  h->info.refactors += 1;
+  return build_factors(h, std::vector<int>{q});
+}
+
+int read_counts(sadmm_t h) {
+  HIPCHK(h, hipMemcpyAsync(h->counts_h, h->counts, 2 * sizeof(int), hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return SADMM_OK;
+}
+
+// Apply the eliminations the SSC check decided at the last iteration.
+int apply_prune(sadmm_t h) {
+  std::vector<int> gone(h->Q);
+  HIPCHK(h, hipMemcpyAsync(gone.data(), h->gone, sizeof(int) * h->Q, hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  const IterArgs a0 = make_args(h);
+  for (int q = 0; q < h->Q; ++q) {
+    if (gone[q] <= 0) continue;
+    const int nq_old = h->nq[q];
+    partition_flags(h->keep + (size_t)q * h->N, h->J[q], nq_old, h->Jnew[q], h->lst, h->counts, h->s);
+    TRY(read_counts(h));
+    const int kept = h->counts_h[0], r = h->counts_h[1];
+    if (r != gone[q] || kept != nq_old - r)
+      return fail_msg(h, SADMM_E_STATE, "selector compaction mismatch (sensor %d)", q);
+    if (h->p.prune_mode == 0) {
+      launch_gather_fwd(a0, h->st, h->dbl, q, h->lst, r, -1.0, h->yp + 2 * (size_t)q * h->KMp,
+                        h->gtmp, h->s);
+    } else {
+      zero_complex_at(static_cast<char*>(h->X) + h->csz * (size_t)q * h->N, h->dbl, h->lst, r, h->s);
+    }
+    set_bytes_at(h->mask + (size_t)q * h->N, h->lst, r, 0, h->s);
+    zero_complex_at(static_cast<char*>(h->dX) + h->csz * (size_t)q * h->N, h->dbl, h->lst, r, h->s);
+    std::swap(h->J[q], h->Jnew[q]);
+    h->nq[q] = kept;
+    TRY(compact_operator(h, q));
+    TRY(push_descs(h));
+    TRY(refresh_factor(h, q, h->lst, r, -1));
+    h->fac_valid[q] = false;
+    launch_b0(make_args(h), h->st, h->dbl, h->p.mu, q, q + 1, h->s);
+    HIPCHK(h, hipGetLastError());
+  }
+  HIPCHK(h, hipMemsetAsync(h->gone, 0, sizeof(int) * h->Q, h->s));
+  return SADMM_OK;
+}
+
+// Optimality re-check of eliminated pixels after convergence; returns the
+// number of pixels reinstated (negative on error).
+int kkt_reinstate(sadmm_t h, int* n_back) {
+  *n_back = 0;
+  const double thr = h->p.kkt_tol * (h->p.lambda > 0 ? h->p.lambda : 1.0);
+  for (int q = 0; q < h->Q; ++q) {
+    if (h->nq[q] == h->N) continue;
+    IterArgs a = make_args(h);
+    // e = A_q x_q - y_q over all pixels (original measurement)
+    scale_c128(h->y + 2 * (size_t)q * h->KMp, h->e, h->KMp, -1.0, h->s);
+    launch_gather_fwd(a, h->st, h->dbl, q, nullptr, h->N, 1.0, h->e, h->gtmp, h->s);
+    // eliminated list
+    partition_flags(h->mask + (size_t)q * h->N, nullptr, h->N, nullptr, h->lst, h->counts, h->s);
+    TRY(read_counts(h));
+    const int ne = h->counts_h[1];
+    if (ne == 0) continue;
+    launch_kkt_check(a, h->st, h->dbl, q, h->lst, ne, h->e, h->p.mu, h->p.gamma, thr, h->flag, h->s);
+    partition_flags(h->flag, h->lst, ne, h->lst2, nullptr, h->counts, h->s);
+    TRY(read_counts(h));
+    const int r = h->counts_h[0];
+    if (r == 0) continue;
+    if (h->p.prune_mode == 0)
+      launch_gather_fwd(a, h->st, h->dbl, q, h->lst2, r, 1.0, h->yp + 2 * (size_t)q * h->KMp, h->gtmp, h->s);
+    set_bytes_at(h->mask + (size_t)q * h->N, h->lst2, r, 1, h->s);
+    set_ring_inf(h->D, h->dbl, h->p.Kp, h->Q, h->N, q, h->lst2, r, h->s);
+    partition_flags(h->mask + (size_t)q * h->N, nullptr, h->N, h->J[q], nullptr, h->counts, h->s);
+    TRY(read_counts(h));
+    h->nq[q] = h->counts_h[0];
+    TRY(compact_operator(h, q));
+    TRY(push_descs(h));
+    TRY(refresh_factor(h, q, h->lst2, r, +1));
+    h->fac_valid[q] = false;
+    launch_b0(make_args(h), h->st, h->dbl, h->p.mu, q, q + 1, h->s);
+    HIPCHK(h, hipGetLastError());
+    *n_back += r;
+  }
+  return SADMM_OK;
+}
+
+double max_active_frac(sadmm_t h) {
+  int m = 0;
+  for (int q = 0; q < h->Q; ++q) m = std::max(m, h->nq[q]);
+  return (double)m / h->N;
+}
+
+int validate(const sadmm_params* p) {
+  if (!p) return SADMM_E_ARG;
+  if (p->Q < 1 || p->K < 1 || p->M < 1 || p->N < 1) return SADMM_E_ARG;
+  if (!(p->mu > 0) || !(p->beta > 0) || !(p->gamma >= 0) || !(p->lambda >= 0)) return SADMM_E_ARG;
+  if (p->max_iter < 1 || p->check_every < 1) return SADMM_E_ARG;
+  if (p->Kp < 1 || p->Kp > 64 || !(p->eps_p >= 0)) return SADMM_E_ARG;
+  if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_BF16P) return SADMM_E_ARG;
+  if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
+  if ((int64_t)p->K * p->M > 4096) return SADMM_E_SHAPE;   // W_q and LDS staging limits
+  return SADMM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void sadmm_default_params(sadmm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->mu = 1.0; p->beta = 1.0; p->gamma = 1.0; p->lambda = 0.0;
+  p->eps_abs = 0.0; p->eps_rel = 1e-4;
+  p->max_iter = 200; p->stop = 1; p->check_every = 8;
+  p->prune = 0; p->Kp = 5; p->eps_p = 1e-5; p->prune_mode = 0;
+  p->kkt = 0; p->kkt_tol = 1e-2;
+  p->storage = SADMM_ST_FP32;
+  p->reuse_factor = 1;
+  p->stream = nullptr;
+}
+
+int sadmm_create(const sadmm_params* p, sadmm_t* out) {
+  if (!out) return SADMM_E_ARG;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc != SADMM_OK) return rc;
+  sadmm_t h = new sadmm_s();
+  h->p = *p;
+  h->Q = p->Q; h->K = p->K; h->M = p->M; h->N = p->N;
+  h->KM = p->K * p->M;
+  h->KMp = round_up(h->KM, 32);
+  h->st = p->storage;
+  h->dbl = (h->st == ST_FP64);
+  h->csz = h->dbl ? 16 : 8;
+  h->s = static_cast<hipStream_t>(p->stream);
+  if (h->st == ST_FP64) { h->ldA = h->KMp; h->slot = 16; }
+  else if (h->st == ST_FP32) { h->ldA = h->KMp; h->slot = 8; }
+  else { h->ldA = 2 * (int64_t)h->KMp; h->slot = 2; }
+  h->chunk = 256;
+  h->nchunk = (h->N + h->chunk - 1) / h->chunk;
+  h->nblk = (h->N + 255) / 256;
+  const int Q = h->Q, N = h->N, KMp = h->KMp;
+  const size_t cN = h->csz * N;
+  h->Afull.assign(Q, nullptr); h->Ahat_buf.assign(Q, nullptr);
+  h->W64.assign(Q, nullptr); h->Wc.assign(Q, nullptr); h->W.assign(Q, nullptr);
+  h->J.assign(Q, nullptr); h->Jnew.assign(Q, nullptr); h->b0.assign(Q, nullptr);
+  h->nq.assign(Q, N); h->op_set.assign(Q, false); h->fac_valid.assign(Q, false);
+  h->facJ.assign(Q, {}); h->mask0.assign(Q, {});
+  h->hpdD.assign(Q, nullptr); h->hpdR.assign(Q, nullptr); h->hpdC.assign(Q, nullptr);
+  h->sens_h.assign(Q, SensorDesc{});
+  h->rmax = std::min(KMp, 1024);
+  h->rpad_max = round_up(h->rmax, HPD_NB);
+#define A_(expr) do { int r_ = (expr); if (r_ != SADMM_OK) { sadmm_destroy(h); return r_; } } while (0)
+  for (int q = 0; q < Q; ++q) {
+    A_(dalloc(h, &h->Afull[q], (size_t)h->ldA * h->slot * N));
+    A_(dalloc_t(h, &h->W64[q], sizeof(cd) * (size_t)KMp * KMp));
+    A_(dalloc(h, &h->Wc[q], h->csz * (size_t)KMp * KMp));
+    A_(dalloc_t(h, &h->J[q], sizeof(int) * N));
+    A_(dalloc_t(h, &h->Jnew[q], sizeof(int) * N));
+    A_(dalloc(h, &h->b0[q], cN));
+    A_(dalloc_t(h, &h->hpdD[q], sizeof(cd) * HPD_NB * HPD_NB));
+    A_(dalloc_t(h, &h->hpdR[q], sizeof(cd) * (size_t)HPD_NB * KMp));
+    A_(dalloc_t(h, &h->hpdC[q], sizeof(cd) * (size_t)HPD_NB * KMp));
+  }
+  A_(dalloc(h, &h->X, cN * Q));
+  A_(dalloc(h, &h->dX, cN * Q));
+  A_(dalloc(h, &h->xbar, cN));
+  A_(dalloc(h, &h->z, cN));
+  A_(dalloc(h, &h->u, cN));
+  A_(dalloc(h, &h->xref, cN));
+  A_(dalloc(h, &h->D, (h->dbl ? 8 : 4) * (size_t)p->Kp * Q * N));
+  A_(dalloc(h, &h->tpart, h->csz * (size_t)Q * h->nchunk * KMp));
+  A_(dalloc(h, &h->gtmp, h->csz * (size_t)h->nchunk * KMp));
+  A_(dalloc(h, &h->t, h->csz * (size_t)Q * KMp));
+  A_(dalloc(h, &h->w, h->csz * (size_t)Q * KMp));
+  A_(dalloc_t(h, &h->y, 16 * (size_t)Q * KMp));
+  A_(dalloc_t(h, &h->yp, 16 * (size_t)Q * KMp));
+  A_(dalloc_t(h, &h->e, 16 * (size_t)KMp));
+  A_(dalloc_t(h, &h->red, sizeof(double) * 8 * h->nblk));
+  A_(dalloc_t(h, &h->hist, sizeof(double) * 6 * (size_t)p->max_iter));
+  A_(dalloc_t(h, &h->mf, sizeof(double) * (size_t)Q * N));
+  A_(dalloc_t(h, &h->mask, (size_t)Q * N));
+  A_(dalloc_t(h, &h->keep, (size_t)Q * N));
+  A_(dalloc_t(h, &h->flag, (size_t)N));
+  A_(dalloc_t(h, &h->gone, sizeof(int) * Q));
+  A_(dalloc_t(h, &h->fail, sizeof(int)));
+  A_(dalloc_t(h, &h->counts, sizeof(int) * 2));
+  A_(dalloc_t(h, &h->lst, sizeof(int) * N));
+  A_(dalloc_t(h, &h->lst2, sizeof(int) * N));
+  A_(dalloc_t(h, &h->ctl, sizeof(Ctl)));
+  A_(dalloc_t(h, &h->sens_d, sizeof(SensorDesc) * Q));
+  A_(dalloc_t(h, &h->gemm_d, sizeof(GemmDesc) * std::max(Q, 4)));
+  A_(dalloc_t(h, &h->hpd_d, sizeof(HpdDesc) * Q));
+  A_(dalloc_t(h, &h->Ar, sizeof(cd) * (size_t)KMp * h->rmax));
+  A_(dalloc_t(h, &h->V, sizeof(cd) * (size_t)KMp * h->rmax));
+  A_(dalloc_t(h, &h->Tm, sizeof(cd) * (size_t)KMp * h->rmax));
+  A_(dalloc_t(h, &h->Cm, sizeof(cd) * (size_t)h->rpad_max * h->rpad_max));
+  A_(dalloc_t(h, &h->Dg, sizeof(cd) * HPD_NB * HPD_NB));
+  A_(dalloc_t(h, &h->Rg, sizeof(cd) * (size_t)HPD_NB * h->rpad_max));
+  A_(dalloc_t(h, &h->Cg, sizeof(cd) * (size_t)HPD_NB * h->rpad_max));
+  if (hipHostMalloc((void**)&h->ctl_h, sizeof(Ctl)) != hipSuccess ||
+      hipHostMalloc((void**)&h->counts_h, 2 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&h->halt_h, sizeof(int)) != hipSuccess) {
+    sadmm_destroy(h);
+    return SADMM_E_NOMEM;
+  }
+  if (hipMemsetAsync(h->fail, 0, sizeof(int), h->s) != hipSuccess ||
+      hipMemsetAsync(h->gone, 0, sizeof(int) * Q, h->s) != hipSuccess ||
+      hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipEventCreate(&h->evf0) != hipSuccess || hipEventCreate(&h->evf1) != hipSuccess ||
+      hipStreamSynchronize(h->s) != hipSuccess) {
+    sadmm_destroy(h);
+    return SADMM_E_HIP;
+  }
+#undef A_
+  *out = h;
+  return SADMM_OK;
+}
+
+int sadmm_set_operator(sadmm_t h, int32_t q, const void* A, int32_t dtype, int64_t ld,
+                       int32_t on_device) {
+  if (!h) return SADMM_E_ARG;
+  if (!A || q < 0 || q >= h->Q || (dtype != SADMM_C128 && dtype != SADMM_C64))
+    return fail_msg(h, SADMM_E_ARG, "set_operator: bad argument");
+  if (ld < h->KM) return fail_msg(h, SADMM_E_SHAPE, "set_operator: ld %lld < KM %d", (long long)ld, h->KM);
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  const void* src = A;
+  void* stage = nullptr;
+  if (!on_device) {
+    // stage through device memory in the caller's dtype, packed ld = KM
+    if (hipMalloc(&stage, esz * (size_t)h->KM * h->N) != hipSuccess)
+      return fail_msg(h, SADMM_E_NOMEM, "set_operator: staging allocation failed");
+    hipError_t e = hipMemcpy2DAsync(stage, esz * h->KM, A, esz * ld, esz * h->KM, h->N,
+                                    hipMemcpyHostToDevice, h->s);
+    if (e != hipSuccess) {
+      hipFree(stage);
+      return fail_msg(h, SADMM_E_HIP, "set_operator: copy failed: %s", hipGetErrorString(e));
+    }
+    src = stage;
+    ld = h->KM;
+  }
+  convert_operator(src, dtype == SADMM_C128, ld, h->KM, h->N, h->st, h->Afull[q], h->ldA, h->KMp, h->s);
+  hipError_t e = hipStreamSynchronize(h->s);
+  if (stage) hipFree(stage);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator: %s", hipGetErrorString(e));
+  h->op_set[q] = true;
+  h->fac_valid[q] = false;
+  return SADMM_OK;
+}
+
+int sadmm_set_operator_geometry(sadmm_t h, int32_t q, const double* tx_xy, const double* rx_xy,
+                                const double* pix_xy, double f0, double bw) {
+  if (!h) return SADMM_E_ARG;
+  if (q < 0 || q >= h->Q || !tx_xy || !rx_xy || !pix_xy)
+    return fail_msg(h, SADMM_E_ARG, "set_operator_geometry: bad argument");
+  double* g = nullptr;
+  const size_t nb = sizeof(double) * (2 + 2 * (size_t)h->M + 2 * (size_t)h->N);
+  if (hipMalloc((void**)&g, nb) != hipSuccess)
+    return fail_msg(h, SADMM_E_NOMEM, "set_operator_geometry: allocation failed");
+  hipMemcpyAsync(g, tx_xy, 2 * sizeof(double), hipMemcpyHostToDevice, h->s);
+  hipMemcpyAsync(g + 2, rx_xy, 2 * sizeof(double) * h->M, hipMemcpyHostToDevice, h->s);
+  hipMemcpyAsync(g + 2 + 2 * h->M, pix_xy, 2 * sizeof(double) * h->N, hipMemcpyHostToDevice, h->s);
+  geometry_operator(g, g + 2, g + 2 + 2 * h->M, h->M, h->K, h->N, f0, bw, h->st, h->Afull[q], h->ldA,
+                    h->KMp, h->s);
+  hipError_t e = hipStreamSynchronize(h->s);
+  hipFree(g);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator_geometry: %s", hipGetErrorString(e));
+  h->op_set[q] = true;
+  h->fac_valid[q] = false;
+  return SADMM_OK;
+}
+
+int sadmm_set_active_mask(sadmm_t h, int32_t q, const uint8_t* mask) {
+  if (!h) return SADMM_E_ARG;
+  if (q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "set_active_mask: bad sensor");
+  if (!mask) { h->mask0[q].clear(); return SADMM_OK; }
+  h->mask0[q].assign(mask, mask + h->N);
+  for (auto& v : h->mask0[q]) v = v ? 1 : 0;
+  return SADMM_OK;
+}
+
+int sadmm_set_reference(sadmm_t h, const void* x_ref, int32_t dtype, int32_t on_device,
+                        double nmse_target) {
+  if (!h) return SADMM_E_ARG;
+  if (!x_ref) { h->have_ref = false; h->nmse_target = 0; return SADMM_OK; }
+  if (dtype != SADMM_C128 && dtype != SADMM_C64) return fail_msg(h, SADMM_E_ARG, "set_reference: dtype");
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  std::vector<double> hostc(2 * (size_t)h->N);
+  if (on_device) {
+    if (hipMemcpy(hostc.data(), x_ref, esz * h->N, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail_msg(h, SADMM_E_HIP, "set_reference: copy failed");
+    if (dtype == SADMM_C64) {
+      std::vector<float> f(2 * (size_t)h->N);
+      std::memcpy(f.data(), hostc.data(), esz * h->N);
+      for (size_t i = 0; i < f.size(); ++i) hostc[i] = f[i];
+    }
+  } else if (dtype == SADMM_C128) {
+    std::memcpy(hostc.data(), x_ref, esz * h->N);
+  } else {
+    const float* f = static_cast<const float*>(x_ref);
+    for (size_t i = 0; i < 2 * (size_t)h->N; ++i) hostc[i] = f[i];
+  }
+  double n2 = 0.0;
+  for (double v : hostc) n2 += v * v;
+  if (!(n2 > 0)) return fail_msg(h, SADMM_E_ARG, "set_reference: zero reference");
+  double* d = nullptr;
+  if (hipMalloc((void**)&d, 16 * (size_t)h->N) != hipSuccess) return fail_msg(h, SADMM_E_NOMEM, "set_reference");
+  hipMemcpyAsync(d, hostc.data(), 16 * (size_t)h->N, hipMemcpyHostToDevice, h->s);
+  c128_to_compute(d, h->xref, h->dbl, h->N, h->s);
+  hipError_t e = hipStreamSynchronize(h->s);
+  hipFree(d);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_reference: %s", hipGetErrorString(e));
+  h->xref_norm2 = n2;
+  h->nmse_target = nmse_target;
+  h->have_ref = true;
+  return SADMM_OK;
+}
+
+int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadmm_info* info) {
+  if (!h) return SADMM_E_ARG;
+  if (!y || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "solve: bad y");
+  for (int q = 0; q < h->Q; ++q)
+    if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "solve: operator of sensor %d not set", q);
+  const int Q = h->Q, N = h->N, KMp = h->KMp;
+  hipStream_t s = h->s;
+  h->info = sadmm_info{};
+  h->solved = false;
+  HIPCHK(h, hipEventRecord(h->ev0, s));
+  // ---- measurements
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  const void* ysrc = y;
+  void* ystage = nullptr;
+  if (!on_device) {
+    if (hipMalloc(&ystage, esz * (size_t)Q * h->KM) != hipSuccess) return fail_msg(h, SADMM_E_NOMEM, "solve: y staging");
+    HIPCHK(h, hipMemcpyAsync(ystage, y, esz * (size_t)Q * h->KM, hipMemcpyHostToDevice, s));
+    ysrc = ystage;
+  }
+  load_measurements(ysrc, dtype == SADMM_C128, Q, h->KM, KMp, h->y, s);
+  HIPCHK(h, hipMemcpyAsync(h->yp, h->y, 16 * (size_t)Q * KMp, hipMemcpyDeviceToDevice, s));
+  // ---- state
+  const size_t cN = h->csz * N;
+  HIPCHK(h, hipMemsetAsync(h->X, 0, cN * Q, s));
+  HIPCHK(h, hipMemsetAsync(h->dX, 0, cN * Q, s));
+  HIPCHK(h, hipMemsetAsync(h->xbar, 0, cN, s));
+  HIPCHK(h, hipMemsetAsync(h->z, 0, cN, s));
+  HIPCHK(h, hipMemsetAsync(h->u, 0, cN, s));
+  HIPCHK(h, hipMemsetAsync(h->D, 0, (h->dbl ? 8 : 4) * (size_t)h->p.Kp * Q * N, s));
+  HIPCHK(h, hipMemsetAsync(h->gone, 0, sizeof(int) * Q, s));
+  HIPCHK(h, hipMemsetAsync(h->hist, 0, sizeof(double) * 6 * (size_t)h->p.max_iter, s));
+  Ctl c0{};
+  c0.max_iter = h->p.max_iter;
+  *h->ctl_h = c0;
+  HIPCHK(h, hipMemcpyAsync(h->ctl, h->ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  // ---- selectors and compaction
+  std::vector<int> rebuild;
+  std::vector<int> Jh;
+  for (int q = 0; q < Q; ++q) {
+    Jh.clear();
+    std::vector<uint8_t> m(N, 1);
+    if (!h->mask0[q].empty()) m = h->mask0[q];
+    for (int n = 0; n < N; ++n)
+      if (m[n]) Jh.push_back(n);
+    h->nq[q] = (int)Jh.size();
+    HIPCHK(h, hipMemcpyAsync(h->mask + (size_t)q * N, m.data(), N, hipMemcpyHostToDevice, s));
+    if (!Jh.empty())
+      HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    TRY(compact_operator(h, q));
+    if (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh) rebuild.push_back(q);
+    h->facJ[q] = Jh;
+  }
+  if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
+  TRY(push_descs(h));
+  HIPCHK(h, hipEventRecord(h->evf0, s));
+  TRY(build_factors(h, rebuild));
+  launch_b0(make_args(h), h->st, h->dbl, h->p.mu, 0, Q, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->evf1, s));
+  HIPCHK(h, hipEventSynchronize(h->evf1));
+  float fms = 0.f;
+  hipEventElapsedTime(&fms, h->evf0, h->evf1);
+  h->t_factor = fms;
+  // ---- iterations
+  std::vector<std::pair<int, double>> frac_pts;     // (iteration, max active fraction from it on)
+  frac_pts.push_back({1, max_active_frac(h)});
+  int kkt_rounds = 0;
+  int status = 1;
+  for (;;) {
+    const IterArgs a = make_args(h);
+    for (int i = 0; i < h->p.check_every; ++i) launch_iteration(a, h->st, h->dbl, s);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    const Ctl c = *h->ctl_h;
+    if (c.halt & HALT_NAN) return fail_msg(h, SADMM_E_NUMERIC, "non-finite residual at iteration %d", c.k);
+    if (!c.halt) continue;
+    if (c.halt & HALT_PRUNE) {
+      HIPCHK(h, hipEventRecord(h->evf0, s));
+      TRY(apply_prune(h));
+      HIPCHK(h, hipEventRecord(h->evf1, s));
+      HIPCHK(h, hipEventSynchronize(h->evf1));
+      hipEventElapsedTime(&fms, h->evf0, h->evf1);
+      h->t_factor += fms;
+      h->info.prune_events += 1;
+      // the new selector counts from the iteration that decided it
+      frac_pts.push_back({c.k, max_active_frac(h)});
+      const int nh = c.halt & ~HALT_PRUNE;
+      *h->halt_h = nh;
+      HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      if (nh == 0) continue;
+    }
+    const int hb = c.halt & ~HALT_PRUNE;
+    if (hb & HALT_NMSE) { status = 2; break; }
+    if (hb & HALT_CONV) {
+      if (h->p.kkt && h->p.prune && kkt_rounds < KKT_ROUNDS) {
+        bool any_frozen = false;
+        for (int q = 0; q < Q; ++q) any_frozen = any_frozen || h->nq[q] < N;
+        if (any_frozen) {
+          ++kkt_rounds;
+          int back = 0;
+          HIPCHK(h, hipEventRecord(h->evf0, s));
+          TRY(kkt_reinstate(h, &back));
+          HIPCHK(h, hipEventRecord(h->evf1, s));
+          HIPCHK(h, hipEventSynchronize(h->evf1));
+          hipEventElapsedTime(&fms, h->evf0, h->evf1);
+          h->t_factor += fms;
+          if (back > 0) {
+            h->info.reinstated += back;
+            frac_pts.push_back({c.k + 1, max_active_frac(h)});
+            if (c.k >= h->p.max_iter) { status = 1; break; }
+            *h->halt_h = 0;
+            HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            continue;
+          }
+        }
+      }
+      status = 0;
+      break;
+    }
+    if (hb & HALT_MAXIT) { status = 1; break; }
+  }
+  HIPCHK(h, hipEventRecord(h->ev1, s));
+  HIPCHK(h, hipEventSynchronize(h->ev1));
+  hipEventElapsedTime(&fms, h->ev0, h->ev1);
+  h->t_total = fms;
+  h->t_iter = h->t_total - h->t_factor;
+  const Ctl c = *h->ctl_h;
+  // ---- history
+  h->hist_count = c.k;
+  h->hist_h.assign(6 * (size_t)h->p.max_iter, 0.0);
+  HIPCHK(h, hipMemcpy(h->hist_h.data(), h->hist, sizeof(double) * 5 * h->p.max_iter, hipMemcpyDeviceToHost));
+  for (int k = 1; k <= c.k; ++k) {
+    double f = frac_pts[0].second;
+    for (auto& pt : frac_pts)
+      if (pt.first <= k) f = pt.second;
+    h->hist_h[5 * (size_t)h->p.max_iter + k - 1] = f;
+  }
+  h->info.iters = c.k;
+  h->info.status = status;
+  h->info.r = c.r; h->info.s = c.s; h->info.eps_pri = c.eps_pri; h->info.eps_dual = c.eps_dual;
+  h->info.nmse = c.nmse;
+  h->info.max_active_frac = max_active_frac(h);
+  h->solved = true;
+  if (info) *info = h->info;
+  return SADMM_OK;
+}
+
+int sadmm_get_image(sadmm_t h, void* xG, int32_t dtype, int32_t on_device) {
+  if (!h) return SADMM_E_ARG;
+  if (!xG || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "get_image: bad argument");
+  if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_image: no solve yet");
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  void* d = xG;
+  if (!on_device) HIPCHK(h, hipMalloc(&d, esz * h->N));
+  if (dtype == SADMM_C128) compute_to_c128(h->z, h->dbl, static_cast<double*>(d), h->N, h->s);
+  else compute_to_c64(h->z, h->dbl, static_cast<float*>(d), h->N, h->s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(xG, d, esz * h->N, hipMemcpyDeviceToHost, h->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+  if (!on_device) hipFree(d);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "get_image: %s", hipGetErrorString(e));
+  return SADMM_OK;
+}
+
+int sadmm_get_sensor_image(sadmm_t h, int32_t q, void* xq, int32_t dtype, int32_t on_device) {
+  if (!h) return SADMM_E_ARG;
+  if (!xq || q < 0 || q >= h->Q || (dtype != SADMM_C128 && dtype != SADMM_C64))
+    return fail_msg(h, SADMM_E_ARG, "get_sensor_image: bad argument");
+  if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_sensor_image: no solve yet");
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  void* d = xq;
+  if (!on_device) HIPCHK(h, hipMalloc(&d, esz * h->N));
+  const void* src = static_cast<const char*>(h->X) + h->csz * (size_t)q * h->N;
+  if (dtype == SADMM_C128) compute_to_c128(src, h->dbl, static_cast<double*>(d), h->N, h->s);
+  else compute_to_c64(src, h->dbl, static_cast<float*>(d), h->N, h->s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(xq, d, esz * h->N, hipMemcpyDeviceToHost, h->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+  if (!on_device) hipFree(d);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "get_sensor_image: %s", hipGetErrorString(e));
+  return SADMM_OK;
+}
+
+int sadmm_get_active_mask(sadmm_t h, int32_t q, uint8_t* mask) {
+  if (!h) return SADMM_E_ARG;
+  if (!mask || q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "get_active_mask: bad argument");
+  HIPCHK(h, hipMemcpyAsync(mask, h->mask + (size_t)q * h->N, h->N, hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return SADMM_OK;
+}
+
+int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count) {
+  if (!h) return SADMM_E_ARG;
+  if (!idx || !count || q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "get_active_indices: bad argument");
+  *count = h->nq[q];
+  if (h->nq[q] > 0)
+    HIPCHK(h, hipMemcpyAsync(idx, h->J[q], sizeof(int) * h->nq[q], hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return SADMM_OK;
+}
+
+int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap, int32_t* count) {
+  if (!h) return SADMM_E_ARG;
+  if (!out || !count || which < 0 || which > 5 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
+  if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_history: no solve yet");
+  const int n = std::min(cap, h->hist_count);
+  std::memcpy(out, h->hist_h.data() + (size_t)which * h->p.max_iter, sizeof(double) * n);
+  *count = h->hist_count;
+  return SADMM_OK;
+}
+
+int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, double* out) {
+  if (!h) return SADMM_E_ARG;
+  if (!y || !out || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "matched_filter: bad argument");
+  for (int q = 0; q < h->Q; ++q)
+    if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "matched_filter: operator %d not set", q);
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  const void* ysrc = y;
+  void* ystage = nullptr;
+  if (!on_device) {
+    HIPCHK(h, hipMalloc(&ystage, esz * (size_t)h->Q * h->KM));
+    HIPCHK(h, hipMemcpyAsync(ystage, y, esz * (size_t)h->Q * h->KM, hipMemcpyHostToDevice, h->s));
+    ysrc = ystage;
+  }
+  load_measurements(ysrc, dtype == SADMM_C128, h->Q, h->KM, h->KMp, h->yp, h->s);
+  // full-operator descriptors for the matched filter
+  for (int q = 0; q < h->Q; ++q) h->nq[q] = h->N;
+  TRY(push_descs(h));
+  launch_matched_filter(make_args(h), h->st, h->dbl, h->yp, h->mf, h->s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(out, h->mf, sizeof(double) * (size_t)h->Q * h->N, hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  if (ystage) hipFree(ystage);
+  h->solved = false;
+  return SADMM_OK;
+}
+
+int sadmm_get_timing(sadmm_t h, int32_t which, double* ms) {
+  if (!h) return SADMM_E_ARG;
+  if (!ms || which < 0 || which > 2) return fail_msg(h, SADMM_E_ARG, "get_timing: bad argument");
+  *ms = which == 0 ? h->t_total : (which == 1 ? h->t_factor : h->t_iter);
+  return SADMM_OK;
+}
+
+void sadmm_destroy(sadmm_t h) {
+  if (!h) return;
+  if (h->s) hipStreamSynchronize(h->s);
+  else hipDeviceSynchronize();
+  for (void* p : h->allocs) hipFree(p);
+  if (h->ctl_h) hipHostFree(h->ctl_h);
+  if (h->counts_h) hipHostFree(h->counts_h);
+  if (h->halt_h) hipHostFree(h->halt_h);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->evf0) hipEventDestroy(h->evf0);
+  if (h->evf1) hipEventDestroy(h->evf1);
+  delete h;
+}
+
+const char* sadmm_last_error(sadmm_t h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Per-iteration kernels of sharing ADMM (eq. (3)) and the SSC check (Alg. 1).
+#pragma once
+#include "common.h"
+
+// Per-sensor view used by the iteration kernels (device array, one per sensor).
+struct SensorDesc {
+  const void* A;       // active columns Ahat_q (compacted, ascending pixel order)
+  const void* Afull;   // full operator A_q
+  const int* J;        // active pixel indices, nq entries (ascending)
+  const void* b0;      // mu * Ahat^H y'_q, nq complex (compute precision)
+  const void* W;       // KMp x KMp factor, compute precision, ld = KMp
+  int64_t lda;         // column stride of A and Afull (storage slots)
+  int nq;
+  int pad;
+};
+
+// Everything the per-iteration kernels need; passed by value.
+struct IterArgs {
+  int Q, KMp, N, Kp;
+  int chunk, nchunk;   // forward kernel: columns per work-group, chunks per sensor
+  int prune, stop;
+  double beta, c, tau, eps_abs, eps_rel, eps_p, inv_Q;
+  double nmse_target, xref_norm2;
+  const SensorDesc* sens;
+  void* X;             // Q x N complex
+  void* dX;            // Q x N complex, x^(k) - x^(k-1) (0 on eliminated pixels)
+  void* xbar;          // N complex
+  void* z;             // N complex
+  void* u;             // N complex
+  void* D;             // Kp x Q x N real: |x^(i) - x^(i-1)| ring
+  void* tpart;         // Q x nchunk x KMp complex partial forward products
+  void* t;             // Q x KMp complex
+  void* w;             // Q x KMp complex
+  const void* xref;    // N complex or null
+  const double* yp;    // Q x KMp complex128: y'_q (measurement minus frozen pixels)
+  double* red;         // pixel-kernel block partials (nblk x 8)
+  int nblk;
+  int max_iter;
+  Ctl* ctl;
+  double* hist;        // 6 x max_iter
+  uint8_t* keep;       // Q x N: SSC keep flag per active position
+  int* gone;           // Q: pixels to eliminate per sensor
+};
+
+constexpr int FWD_THREADS = 256;
+constexpr int DOT_COLS_PER_WAVE = 4;
+
+// Launchers.  `st` is the operator storage (sadmm_storage), `dbl` selects FP64
+// compute (only with ST_FP64).
+void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s);
+int fwd_row_tile(int st);   // rows covered by one forward work-group
+
+// b0_q = mu * Ahat_q^H y'_q for the sensors in [q0, q1).
+void launch_b0(const IterArgs& a, int st, bool dbl, double mu, int q0, int q1, hipStream_t s);
+
+// Generic gathered forward product for one sensor q:
+//   out += sign * sum_j coef_j * Afull[:, idx_j],   coef_j = X[q, idx_j]
+// with idx = null meaning all N columns; out is complex128 KMp (e.g. y'_q).
+// `tmp` holds nchunk x KMp compute-precision partials.
+void launch_gather_fwd(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
+                       double sign, double* out, void* tmp, hipStream_t s);
+
+// Optimality re-check of eliminated pixels of sensor q (idx, count):
+// g = mu A[:,n]^H e + gamma X[q,n] + beta u[n] with e = A_q x_q - y_q
+// (complex128, KMp); flag[j] = |g| > thr.
+void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
+                      const double* e, double mu, double gamma, double thr, uint8_t* flag,
+                      hipStream_t s);
+
+// |A_q^H y_q| over all pixels for every sensor, into out (Q x N doubles).
+void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,
+                           hipStream_t s);

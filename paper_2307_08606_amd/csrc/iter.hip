@@ -1,0 +1,513 @@
+// Per-iteration kernels of sharing ADMM (eq. (3)) with the SSC check of Alg. 1.
+//
+// One iteration = seven launches, each covering all Q sensors:
+//   fwd      t_q = Ahat_q b_q, b_q = b0_q + beta (x_q - xbar + z - u)[J_q]
+//            (column chunks per work-group -> partial sums, no atomics)
+//   reduce   t_q = sum of the chunk partials, fixed order
+//   wdot     w_q = W_q t_q  (W_q Hermitian: one wavefront dot per column)
+//   xupd     x_q[J_q] = (b_q - Ahat_q^H w_q) / c, fused epilogue writes
+//            x_q, dx_q and |dx_q| into the SSC history ring
+//   pixel    xbar, z = S_{lambda/beta}(xbar + u), u += xbar - z, and block
+//            partial sums of the residual norms
+//   finalize residuals r, s, eps_pri, eps_dual, stop / gate flags, history
+//   ssc      zeta = mean |dx| over the ring; pixels with zeta < eps_p flagged
+// Every kernel reads the device control block first and does nothing once
+// the solve has halted (converged, max_iter, NMSE target, numeric error, or a
+// pending pixel elimination the host must apply), so the host can queue many
+// iterations ahead and synchronise rarely.
+#include "iter.h"
+
+namespace {
+
+constexpr int MAX_CHUNK = 1024;
+
+template <class T> __device__ inline C2<T> ldc(const void* p, int64_t i) {
+  return reinterpret_cast<const C2<T>*>(p)[i];
+}
+template <class T> __device__ inline void stc(void* p, int64_t i, C2<T> v) {
+  reinterpret_cast<C2<T>*>(p)[i] = v;
+}
+template <class T> __device__ inline T habs(C2<T> v) { return hypot(v.re, v.im); }
+
+// b_q[p] of the x-update right-hand side (eq. (3), row 1, sharing form)
+template <class T>
+__device__ inline C2<T> rhs_b(const IterArgs& a, const SensorDesc& sd, int q, int p, int n) {
+  const C2<T> x = ldc<T>(a.X, (int64_t)q * a.N + n);
+  const C2<T> xb = ldc<T>(a.xbar, n);
+  const C2<T> zz = ldc<T>(a.z, n);
+  const C2<T> uu = ldc<T>(a.u, n);
+  C2<T> v = csub(cadd(csub(x, xb), zz), uu);
+  const C2<T> b0 = ldc<T>(sd.b0, p);
+  const T beta = (T)a.beta;
+  return {b0.re + beta * v.re, b0.im + beta * v.im};
+}
+
+// ------------------------------------------------------------------ forward
+template <int ST>
+__device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* colidx, int p0, int np,
+                                      const C2<typename Store<ST>::T>* coef, int row, int KMp,
+                                      C2<typename Store<ST>::T>* acc) {
+  using T = typename Store<ST>::T;
+  constexpr int R = Store<ST>::RPT;
+#pragma unroll 8
+  for (int e = 0; e < np; ++e) {
+    const int col = colidx ? colidx[p0 + e] : p0 + e;
+    T re[R], im[R];
+    Store<ST>::load(col_ptr<ST>(A, lda, col), row, KMp, re, im);
+    const C2<T> cf = coef[e];
+#pragma unroll
+    for (int r = 0; r < R; ++r) cfma(acc[r], C2<T>{re[r], im[r]}, cf);
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(IterArgs a) {
+  using T = typename Store<ST>::T;
+  constexpr int R = Store<ST>::RPT;
+  if (a.ctl->halt) return;
+  const int q = blockIdx.z, ch = blockIdx.y;
+  const SensorDesc sd = a.sens[q];
+  const int p0 = ch * a.chunk;
+  if (p0 >= sd.nq) return;
+  const int np = min(a.chunk, sd.nq - p0);
+  __shared__ C2<T> coef[MAX_CHUNK];
+  for (int e = threadIdx.x; e < np; e += FWD_THREADS) {
+    const int p = p0 + e;
+    coef[e] = rhs_b<T>(a, sd, q, p, sd.J[p]);
+  }
+  __syncthreads();
+  const int row = (blockIdx.x * FWD_THREADS + threadIdx.x) * R;
+  if (row >= a.KMp) return;
+  C2<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = {(T)0, (T)0};
+  fwd_accumulate<ST>(sd.A, sd.lda, nullptr, p0, np, coef, row, a.KMp, acc);
+  C2<T>* out = reinterpret_cast<C2<T>*>(a.tpart) + ((int64_t)q * a.nchunk + ch) * a.KMp + row;
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[r] = acc[r];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(IterArgs a) {
+  if (a.ctl->halt) return;
+  const int q = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.KMp) return;
+  const int nq = a.sens[q].nq;
+  const int nch = (nq + a.chunk - 1) / a.chunk;
+  const C2<T>* tp = reinterpret_cast<const C2<T>*>(a.tpart) + (int64_t)q * a.nchunk * a.KMp + i;
+  C2<T> s = {(T)0, (T)0};
+  for (int c = 0; c < nch; ++c) s = cadd(s, tp[(int64_t)c * a.KMp]);
+  stc<T>(a.t, (int64_t)q * a.KMp + i, s);
+}
+
+// Gathered forward product (host-orchestrated, no halt check):
+// partials of sum_j X[q, idx_j] * A[:, idx_j]
+template <int ST>
+__global__ __launch_bounds__(FWD_THREADS) void fwd_gather_kernel(IterArgs a, int q, const int* idx,
+                                                                 int count, void* tmp) {
+  using T = typename Store<ST>::T;
+  constexpr int R = Store<ST>::RPT;
+  const SensorDesc sd = a.sens[q];
+  const int ch = blockIdx.y;
+  const int p0 = ch * a.chunk;
+  if (p0 >= count) return;
+  const int np = min(a.chunk, count - p0);
+  __shared__ C2<T> coef[MAX_CHUNK];
+  for (int e = threadIdx.x; e < np; e += FWD_THREADS) {
+    const int n = idx ? idx[p0 + e] : p0 + e;
+    coef[e] = ldc<T>(a.X, (int64_t)q * a.N + n);
+  }
+  __syncthreads();
+  const int row = (blockIdx.x * FWD_THREADS + threadIdx.x) * R;
+  if (row >= a.KMp) return;
+  C2<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = {(T)0, (T)0};
+  fwd_accumulate<ST>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
+  C2<T>* out = reinterpret_cast<C2<T>*>(tmp) + (int64_t)ch * a.KMp + row;
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[r] = acc[r];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gather_reduce_kernel(int KMp, int nch, const void* tmp,
+                                                            double sign, double* out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= KMp) return;
+  const C2<T>* tp = reinterpret_cast<const C2<T>*>(tmp) + i;
+  C2<T> s = {(T)0, (T)0};
+  for (int c = 0; c < nch; ++c) s = cadd(s, tp[(int64_t)c * KMp]);
+  out[2 * i] += sign * (double)s.re;
+  out[2 * i + 1] += sign * (double)s.im;
+}
+
+// ------------------------------------------------------------------ column dots
+enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_B0 = 2, EPI_KKT = 3, EPI_MF = 4 };
+
+struct DotExtra {
+  const int* idx;       // KKT: eliminated pixel list
+  int count;
+  int q;                // KKT: sensor
+  const double* vec;    // B0 / KKT / MF: complex128 source vector(s)
+  int64_t vec_stride;   // per-sensor stride (complex entries)
+  double mu, gamma, thr;
+  uint8_t* flag;        // KKT
+  double* out;          // MF
+  int q0;               // B0: first sensor of the launch
+};
+
+template <int ST>
+__device__ inline C2<typename Store<ST>::T> coldot_core(const void* col,
+                                                       const C2<typename Store<ST>::T>* sv,
+                                                       int KMp, int lane) {
+  using T = typename Store<ST>::T;
+  constexpr int R = Store<ST>::RPT;
+  C2<T> acc = {(T)0, (T)0};
+#pragma unroll 4
+  for (int i0 = lane * R; i0 < KMp; i0 += SADMM_WAVE * R) {
+    T re[R], im[R];
+    Store<ST>::load(col, i0, KMp, re, im);
+#pragma unroll
+    for (int r = 0; r < R; ++r) cfmac(acc, C2<T>{re[r], im[r]}, sv[i0 + r]);
+  }
+  acc.re = wave_sum(acc.re);
+  acc.im = wave_sum(acc.im);
+  return acc;
+}
+
+template <int ST, int EPI>
+__global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
+  using T = typename Store<ST>::T;
+  if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
+  const int q = (EPI == EPI_KKT) ? x.q : (EPI == EPI_B0 ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
+  const SensorDesc sd = a.sens[q];
+  int ncols;
+  if constexpr (EPI == EPI_W) ncols = a.KMp;
+  else if constexpr (EPI == EPI_XUPD || EPI == EPI_B0) ncols = sd.nq;
+  else if constexpr (EPI == EPI_KKT) ncols = x.count;
+  else ncols = a.N;
+  const int cols_per_block = 4 * DOT_COLS_PER_WAVE;
+  const int col0 = blockIdx.x * cols_per_block;
+  if (col0 >= ncols) return;
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* sv = reinterpret_cast<C2<T>*>(smem_raw);
+  // stage the vector operand
+  for (int i = threadIdx.x; i < a.KMp; i += 256) {
+    C2<T> v;
+    if constexpr (EPI == EPI_W) v = ldc<T>(a.t, (int64_t)q * a.KMp + i);
+    else if constexpr (EPI == EPI_XUPD) v = ldc<T>(a.w, (int64_t)q * a.KMp + i);
+    else {
+      const double* src = x.vec + 2 * ((EPI == EPI_KKT ? 0 : (int64_t)q * x.vec_stride) + i);
+      v = {(T)src[0], (T)src[1]};
+    }
+    sv[i] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
+    const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
+    if (p >= ncols) break;
+    const void* col;
+    if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W, a.KMp, p);
+    else if constexpr (EPI == EPI_XUPD || EPI == EPI_B0) col = col_ptr<ST>(sd.A, sd.lda, p);
+    else if constexpr (EPI == EPI_KKT) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
+    else col = col_ptr<ST>(sd.Afull, sd.lda, p);
+    const C2<T> d = coldot_core<ST>(col, sv, a.KMp, lane);
+    if (lane != 0) continue;
+    if constexpr (EPI == EPI_W) {
+      stc<T>(a.w, (int64_t)q * a.KMp + p, d);
+    } else if constexpr (EPI == EPI_XUPD) {
+      const int n = sd.J[p];
+      const C2<T> b = rhs_b<T>(a, sd, q, p, n);
+      const T cc = (T)a.c;
+      const C2<T> xn = {(b.re - d.re) / cc, (b.im - d.im) / cc};
+      const int64_t o = (int64_t)q * a.N + n;
+      const C2<T> xo = ldc<T>(a.X, o);
+      const C2<T> dx = csub(xn, xo);
+      stc<T>(a.X, o, xn);
+      stc<T>(a.dX, o, dx);
+      const int slot = a.ctl->k % a.Kp;
+      reinterpret_cast<T*>(a.D)[((int64_t)slot * a.Q + q) * a.N + n] = habs(dx);
+    } else if constexpr (EPI == EPI_B0) {
+      const T mu = (T)x.mu;
+      stc<T>(const_cast<void*>(sd.b0), p, C2<T>{mu * d.re, mu * d.im});
+    } else if constexpr (EPI == EPI_KKT) {
+      const int n = x.idx[p];
+      const C2<T> xv = ldc<T>(a.X, (int64_t)q * a.N + n);
+      const C2<T> uv = ldc<T>(a.u, n);
+      const double gre = x.mu * (double)d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
+      const double gim = x.mu * (double)d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
+      x.flag[p] = hypot(gre, gim) > x.thr ? 1 : 0;
+    } else {
+      x.out[(int64_t)q * a.N + p] = hypot((double)d.re, (double)d.im);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ pixel update
+template <class T>
+__global__ __launch_bounds__(256) void pixel_kernel(IterArgs a) {
+  if (a.ctl->halt) return;
+  __shared__ double sm[4 * 8];
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n < a.N) {
+    C2<T> sum = {(T)0, (T)0};
+    for (int q = 0; q < a.Q; ++q) sum = cadd(sum, ldc<T>(a.X, (int64_t)q * a.N + n));
+    const T Qt = (T)a.Q;
+    const C2<T> xb = {sum.re / Qt, sum.im / Qt};
+    const C2<T> zo = ldc<T>(a.z, n), xbo = ldc<T>(a.xbar, n), uo = ldc<T>(a.u, n);
+    const C2<T> v = cadd(xb, uo);
+    const T mag = habs(v);
+    const T tau = (T)a.tau;
+    C2<T> zn = {(T)0, (T)0};
+    if (mag > tau) {
+      const T sc = (T)1 - tau / mag;
+      zn = {v.re * sc, v.im * sc};
+    }
+    const C2<T> un = csub(cadd(uo, xb), zn);
+    const C2<T> dz = csub(csub(zn, xb), csub(zo, xbo));
+    double s2 = 0.0, nx2 = 0.0;
+    for (int q = 0; q < a.Q; ++q) {
+      const int64_t o = (int64_t)q * a.N + n;
+      const C2<T> d = cadd(ldc<T>(a.dX, o), dz);
+      s2 += (double)cabs2(d);
+      nx2 += (double)cabs2(ldc<T>(a.X, o));
+    }
+    part[0] = (double)cabs2(csub(xb, zn));
+    part[1] = s2;
+    part[2] = nx2;
+    part[3] = (double)cabs2(zn);
+    part[4] = (double)cabs2(un);
+    if (a.xref) {
+      const C2<T> r = ldc<T>(a.xref, n);
+      part[5] = (double)cabs2(csub(zn, r));
+    }
+    stc<T>(a.xbar, n, xb);
+    stc<T>(a.z, n, zn);
+    stc<T>(a.u, n, un);
+  }
+  block_sum256<double, 8>(part, sm);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a.red[(int64_t)blockIdx.x * 8 + j] = part[j];
+  }
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(IterArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->halt) return;
+  __shared__ double sm[4 * 8];
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < a.nblk; b += 256) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part[j] += a.red[(int64_t)b * 8 + j];
+  }
+  block_sum256<double, 8>(part, sm);
+  if (threadIdx.x != 0) return;
+  const double Q = a.Q;
+  const int k = ctl->k + 1;
+  const double r = sqrt(Q) * sqrt(part[0]);
+  const double s = a.beta * sqrt(part[1]);
+  const double sqQN = sqrt(Q * (double)a.N);
+  const double eps_pri = sqQN * a.eps_abs + a.eps_rel * fmax(sqrt(part[2]), sqrt(Q) * sqrt(part[3]));
+  const double eps_dual = sqQN * a.eps_abs + a.eps_rel * a.beta * sqrt(Q) * sqrt(part[4]);
+  const double nmse = a.xref ? part[5] / a.xref_norm2 : 0.0;
+  int halt = 0;
+  bool finite = true;
+  for (int j = 0; j < 6; ++j) finite = finite && isfinite(part[j]);
+  if (!finite) halt |= HALT_NAN;
+  if (a.stop && r <= eps_pri && s <= eps_dual) halt |= HALT_CONV;
+  if (a.xref && a.nmse_target > 0.0 && nmse <= a.nmse_target) halt |= HALT_NMSE;
+  if (k >= a.max_iter) halt |= HALT_MAXIT;
+  double* h = a.hist;
+  const int mi = a.max_iter;
+  h[0 * mi + k - 1] = r;
+  h[1 * mi + k - 1] = s;
+  h[2 * mi + k - 1] = eps_pri;
+  h[3 * mi + k - 1] = eps_dual;
+  h[4 * mi + k - 1] = nmse;
+  ctl->r = r; ctl->s = s; ctl->eps_pri = eps_pri; ctl->eps_dual = eps_dual; ctl->nmse = nmse;
+  ctl->gate = (r <= eps_pri) ? 1 : 0;
+  ctl->nan = finite ? 0 : 1;
+  ctl->k = k;
+  ctl->halt = halt;
+}
+
+// SSC check (Alg. 1, steps 1-2): runs when the gate is open and K_p
+// differences exist.  Runs at the last permitted iteration too (max_iter),
+// but not once converged.
+template <class T>
+__global__ __launch_bounds__(256) void ssc_kernel(IterArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_PRUNE)) return;
+  const int k = ctl->k;
+  if (k < a.Kp || !ctl->gate) return;
+  const int q = blockIdx.y;
+  const SensorDesc sd = a.sens[q];
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= sd.nq) return;
+  const int n = sd.J[p];
+  const T* D = reinterpret_cast<const T*>(a.D);
+  T zs = (T)0;
+  for (int sl = 0; sl < a.Kp; ++sl) zs += D[((int64_t)sl * a.Q + q) * a.N + n];
+  const T zeta = zs / (T)a.Kp;
+  const bool keep = zeta >= (T)a.eps_p;
+  a.keep[(int64_t)q * a.N + p] = keep ? 1 : 0;
+  if (!keep) atomicAdd(&a.gone[q], 1);
+}
+
+// Raises the prune halt bit when the SSC check removed anything.
+__global__ void ssc_flag_kernel(IterArgs a) {
+  Ctl* ctl = a.ctl;
+  if (threadIdx.x != 0) return;
+  if (ctl->halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_PRUNE)) return;
+  int tot = 0;
+  for (int q = 0; q < a.Q; ++q) tot += a.gone[q];
+  if (tot > 0) {
+    ctl->gone_total = tot;
+    ctl->halt |= HALT_PRUNE;
+  }
+}
+
+template <int ST>
+void run_iteration(const IterArgs& a, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  constexpr int WST = std::is_same<T, double>::value ? ST_FP64 : ST_FP32;
+  const int rows = FWD_THREADS * Store<ST>::RPT;
+  dim3 gf((a.KMp + rows - 1) / rows, a.nchunk, a.Q);
+  fwd_iter_kernel<ST><<<gf, FWD_THREADS, 0, s>>>(a);
+  fwd_reduce_kernel<T><<<dim3((a.KMp + 255) / 256, a.Q), 256, 0, s>>>(a);
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
+  DotExtra x{};
+  coldot_kernel<WST, EPI_W><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+  coldot_kernel<ST, EPI_XUPD><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+  pixel_kernel<T><<<a.nblk, 256, 0, s>>>(a);
+  finalize_kernel<<<1, 256, 0, s>>>(a);
+  if (a.prune) {
+    ssc_kernel<T><<<dim3((a.N + 255) / 256, a.Q), 256, 0, s>>>(a);
+    ssc_flag_kernel<<<1, 64, 0, s>>>(a);
+  }
+}
+
+}  // namespace
+
+int fwd_row_tile(int st) {
+  switch (st) {
+    case ST_FP64: return FWD_THREADS * Store<ST_FP64>::RPT;
+    case ST_FP32: return FWD_THREADS * Store<ST_FP32>::RPT;
+    default: return FWD_THREADS * Store<ST_FP16P>::RPT;
+  }
+}
+
+void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s) {
+  (void)dbl;
+  switch (st) {
+    case ST_FP64: run_iteration<ST_FP64>(a, s); break;
+    case ST_FP32: run_iteration<ST_FP32>(a, s); break;
+    case ST_FP16P: run_iteration<ST_FP16P>(a, s); break;
+    case ST_BF16P: run_iteration<ST_BF16P>(a, s); break;
+  }
+}
+
+template <int ST>
+static void b0_impl(const IterArgs& a, double mu, int q0, int q1, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  DotExtra x{};
+  x.vec = a.yp;
+  x.vec_stride = a.KMp;
+  x.mu = mu;
+  x.q0 = q0;
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
+  coldot_kernel<ST, EPI_B0><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
+}
+
+void launch_b0(const IterArgs& a, int st, bool dbl, double mu, int q0, int q1, hipStream_t s) {
+  (void)dbl;
+  if (q1 <= q0) return;
+  switch (st) {
+    case ST_FP64: b0_impl<ST_FP64>(a, mu, q0, q1, s); break;
+    case ST_FP32: b0_impl<ST_FP32>(a, mu, q0, q1, s); break;
+    case ST_FP16P: b0_impl<ST_FP16P>(a, mu, q0, q1, s); break;
+    case ST_BF16P: b0_impl<ST_BF16P>(a, mu, q0, q1, s); break;
+  }
+}
+
+template <int ST>
+static void gather_impl(const IterArgs& a, int q, const int* idx, int count, double sign,
+                        double* out, void* tmp, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  if (count <= 0) return;
+  const int rows = FWD_THREADS * Store<ST>::RPT;
+  const int nch = (count + a.chunk - 1) / a.chunk;
+  fwd_gather_kernel<ST><<<dim3((a.KMp + rows - 1) / rows, nch, 1), FWD_THREADS, 0, s>>>(a, q, idx, count, tmp);
+  gather_reduce_kernel<T><<<(a.KMp + 255) / 256, 256, 0, s>>>(a.KMp, nch, tmp, sign, out);
+}
+
+void launch_gather_fwd(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
+                       double sign, double* out, void* tmp, hipStream_t s) {
+  (void)dbl;
+  switch (st) {
+    case ST_FP64: gather_impl<ST_FP64>(a, q, idx, count, sign, out, tmp, s); break;
+    case ST_FP32: gather_impl<ST_FP32>(a, q, idx, count, sign, out, tmp, s); break;
+    case ST_FP16P: gather_impl<ST_FP16P>(a, q, idx, count, sign, out, tmp, s); break;
+    case ST_BF16P: gather_impl<ST_BF16P>(a, q, idx, count, sign, out, tmp, s); break;
+  }
+}
+
+template <int ST>
+static void kkt_impl(const IterArgs& a, int q, const int* idx, int count, const double* e,
+                     double mu, double gamma, double thr, uint8_t* flag, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  if (count <= 0) return;
+  DotExtra x{};
+  x.idx = idx;
+  x.count = count;
+  x.q = q;
+  x.vec = e;
+  x.mu = mu;
+  x.gamma = gamma;
+  x.thr = thr;
+  x.flag = flag;
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
+  coldot_kernel<ST, EPI_KKT><<<dim3((count + cpb - 1) / cpb, 1), 256, smem, s>>>(a, x);
+}
+
+void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
+                      const double* e, double mu, double gamma, double thr, uint8_t* flag,
+                      hipStream_t s) {
+  (void)dbl;
+  switch (st) {
+    case ST_FP64: kkt_impl<ST_FP64>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
+    case ST_FP32: kkt_impl<ST_FP32>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
+    case ST_FP16P: kkt_impl<ST_FP16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
+    case ST_BF16P: kkt_impl<ST_BF16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
+  }
+}
+
+template <int ST>
+static void mf_impl(const IterArgs& a, const double* y, double* out, hipStream_t s) {
+  using T = typename Store<ST>::T;
+  DotExtra x{};
+  x.vec = y;
+  x.vec_stride = a.KMp;
+  x.out = out;
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
+  coldot_kernel<ST, EPI_MF><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+}
+
+void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,
+                           hipStream_t s) {
+  (void)dbl;
+  switch (st) {
+    case ST_FP64: mf_impl<ST_FP64>(a, y, out, s); break;
+    case ST_FP32: mf_impl<ST_FP32>(a, y, out, s); break;
+    case ST_FP16P: mf_impl<ST_FP16P>(a, y, out, s); break;
+    case ST_BF16P: mf_impl<ST_BF16P>(a, y, out, s); break;
+  }
+}

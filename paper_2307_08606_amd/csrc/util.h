@@ -1,0 +1,47 @@
+// Data movement kernels: operator ingest (conversion, LFM generation), stream
+// compaction of the SSC selectors, column gathers, small fills.
+#pragma once
+#include "common.h"
+
+// Convert a caller operator (complex128 if src_c128 else complex64, column
+// stride src_ld complex entries, KM x N) into storage `st` with column stride
+// ldA slots and KMp rows (rows KM..KMp-1 zero).
+void convert_operator(const void* src, bool src_c128, int64_t src_ld, int KM, int N, int st,
+                      void* dst, int64_t ldA, int KMp, hipStream_t s);
+
+// Generate A[m*K+k, n] = exp(-j 2 pi f_k tau_{m,n}) on the device (eq. (1)).
+// tx: 2 doubles, rx: 2*M doubles, pix: 2*N doubles (device).
+void geometry_operator(const double* tx, const double* rx, const double* pix, int M, int K, int N,
+                       double f0, double bw, int st, void* dst, int64_t ldA, int KMp,
+                       hipStream_t s);
+
+// Stable partition of n flags: kept[] receives in[i] (or i when in is null)
+// for flag[i] != 0 in order, dropped[] the others in order (either output may
+// be null); counts[0] = #kept, counts[1] = #dropped.  One work-group.
+void partition_flags(const uint8_t* flag, const int* in, int n, int* kept, int* dropped,
+                     int* counts, hipStream_t s);
+
+// dst[:, p] = src[:, idx[p]] for p < count (whole columns of `slots` slots).
+void gather_columns(const void* src, void* dst, int64_t ld, int64_t slot_bytes, const int* idx,
+                    int count, hipStream_t s);
+
+// dst (complex128, ld KMp) [:, p] = src[:, idx[p]] converted from storage st.
+void gather_columns_fp64(const void* src, int64_t ldA, int st, int KMp, const int* idx, int count,
+                         cd* dst, hipStream_t s);
+
+// Small element-wise helpers on (q, index list) sets.
+void set_bytes_at(uint8_t* base, const int* idx, int count, uint8_t v, hipStream_t s);
+void zero_complex_at(void* base, bool dbl, const int* idx, int count, hipStream_t s);
+void set_ring_inf(void* D, bool dbl, int Kp, int Q, int N, int q, const int* idx, int count,
+                  hipStream_t s);
+void iota_int(int* dst, int n, hipStream_t s);
+// dst = src * scale (complex128 vectors of n entries)
+void scale_c128(const double* src, double* dst, int n, double scale, hipStream_t s);
+// complex copy with precision change: dst (T) = src (complex128) for n entries
+void c128_to_compute(const double* src, void* dst, bool dbl, int n, hipStream_t s);
+void compute_to_c128(const void* src, bool dbl, double* dst, int n, hipStream_t s);
+void compute_to_c64(const void* src, bool dbl, float* dst, int n, hipStream_t s);
+void c64_to_compute(const float* src, void* dst, bool dbl, int n, hipStream_t s);
+// y (c128 or c64, Q x KM) -> dst complex128 Q x KMp zero padded
+void load_measurements(const void* src, bool src_c128, int Q, int KM, int KMp, double* dst,
+                       hipStream_t s);

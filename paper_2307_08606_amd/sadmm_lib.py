@@ -1,0 +1,257 @@
+"""ctypes binding of libsadmm.so (the C ABI in include/sadmm.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions keep the C names; `Solver` wraps a handle for torch tensors
+(device memory and the current HIP stream come from PyTorch).  Importing this
+module raises if the shared library has not been built -- there is no other
+implementation to fall back to.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsadmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_08606_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+SADMM_OK, SADMM_E_ARG, SADMM_E_SHAPE, SADMM_E_STATE = 0, -1, -2, -3
+SADMM_E_HIP, SADMM_E_NOMEM, SADMM_E_NUMERIC = -4, -5, -6
+SADMM_C128, SADMM_C64 = 0, 1
+ST_FP64, ST_FP32, ST_FP16P, ST_BF16P = 0, 1, 2, 3
+STORAGE = {"fp64": ST_FP64, "fp32": ST_FP32, "fp16": ST_FP16P, "bf16": ST_BF16P}
+HIST = {"r": 0, "s": 1, "eps_pri": 2, "eps_dual": 3, "nmse": 4, "max_active_frac": 5}
+
+
+class sadmm_params(C.Structure):
+    _fields_ = [
+        ("Q", C.c_int32), ("K", C.c_int32), ("M", C.c_int32), ("N", C.c_int32),
+        ("mu", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
+        ("lambda_", C.c_double),
+        ("eps_abs", C.c_double), ("eps_rel", C.c_double),
+        ("max_iter", C.c_int32), ("stop", C.c_int32), ("check_every", C.c_int32),
+        ("prune", C.c_int32), ("Kp", C.c_int32), ("eps_p", C.c_double),
+        ("prune_mode", C.c_int32), ("kkt", C.c_int32), ("kkt_tol", C.c_double),
+        ("storage", C.c_int32), ("reuse_factor", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class sadmm_info(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32), ("status", C.c_int32), ("prune_events", C.c_int32),
+        ("reinstated", C.c_int32), ("refactors", C.c_int32), ("updates", C.c_int32),
+        ("r", C.c_double), ("s", C.c_double), ("eps_pri", C.c_double),
+        ("eps_dual", C.c_double), ("max_active_frac", C.c_double), ("nmse", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_H = C.c_void_p
+_P = C.c_void_p
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+sadmm_default_params = _sig("sadmm_default_params", None, C.POINTER(sadmm_params))
+sadmm_create = _sig("sadmm_create", C.c_int, C.POINTER(sadmm_params), C.POINTER(_H))
+sadmm_set_operator = _sig("sadmm_set_operator", C.c_int, _H, C.c_int32, _P, C.c_int32,
+                          C.c_int64, C.c_int32)
+sadmm_set_operator_geometry = _sig("sadmm_set_operator_geometry", C.c_int, _H, C.c_int32,
+                                   _P, _P, _P, C.c_double, C.c_double)
+sadmm_set_active_mask = _sig("sadmm_set_active_mask", C.c_int, _H, C.c_int32, _P)
+sadmm_set_reference = _sig("sadmm_set_reference", C.c_int, _H, _P, C.c_int32, C.c_int32,
+                           C.c_double)
+sadmm_solve = _sig("sadmm_solve", C.c_int, _H, _P, C.c_int32, C.c_int32, C.POINTER(sadmm_info))
+sadmm_get_image = _sig("sadmm_get_image", C.c_int, _H, _P, C.c_int32, C.c_int32)
+sadmm_get_sensor_image = _sig("sadmm_get_sensor_image", C.c_int, _H, C.c_int32, _P, C.c_int32,
+                              C.c_int32)
+sadmm_get_active_mask = _sig("sadmm_get_active_mask", C.c_int, _H, C.c_int32, _P)
+sadmm_get_active_indices = _sig("sadmm_get_active_indices", C.c_int, _H, C.c_int32, _P, _P)
+sadmm_get_history = _sig("sadmm_get_history", C.c_int, _H, C.c_int32, _P, C.c_int32, _P)
+sadmm_matched_filter = _sig("sadmm_matched_filter", C.c_int, _H, _P, C.c_int32, C.c_int32, _P)
+sadmm_get_timing = _sig("sadmm_get_timing", C.c_int, _H, C.c_int32, C.POINTER(C.c_double))
+sadmm_destroy = _sig("sadmm_destroy", None, _H)
+sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
+
+EXPORTED = [n for n in dir() if n.startswith("sadmm_") and callable(globals()[n])
+            and n not in ("sadmm_params", "sadmm_info")]
+
+
+class SadmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sadmm error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a) -> int:
+    """Address of a numpy array or torch tensor (contiguous)."""
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"] or a.flags["F_CONTIGUOUS"]
+        return a.ctypes.data
+    return int(a.data_ptr())
+
+
+def _dtype_code(a) -> int:
+    name = str(a.dtype)
+    if name in ("complex128", "torch.complex128"):
+        return SADMM_C128
+    if name in ("complex64", "torch.complex64"):
+        return SADMM_C64
+    raise TypeError(f"complex128 or complex64 expected, got {a.dtype}")
+
+
+def _on_device(a) -> int:
+    return 0 if isinstance(a, np.ndarray) else int(a.is_cuda)
+
+
+class Solver:
+    """One sadmm handle.  `params` keys follow sadmm_params (lambda as `lam`)."""
+
+    def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
+                 eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
+                 eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=1e-2, storage="fp32",
+                 reuse_factor=True, stream=None):
+        p = sadmm_params()
+        sadmm_default_params(C.byref(p))
+        p.Q, p.K, p.M, p.N = Q, K, M, N
+        p.mu, p.beta, p.gamma, p.lambda_ = mu, beta, gamma, lam
+        p.eps_abs, p.eps_rel = eps_abs, eps_rel
+        p.max_iter, p.stop, p.check_every = max_iter, int(bool(stop)), check_every
+        p.prune, p.Kp, p.eps_p = int(bool(prune)), Kp, eps_p
+        p.prune_mode = {"freeze": 0, "zero": 1}[prune_mode]
+        p.kkt, p.kkt_tol = int(bool(kkt)), kkt_tol
+        p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p.reuse_factor = int(bool(reuse_factor))
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        p.stream = C.c_void_p(int(stream))
+        self.params = p
+        self.Q, self.K, self.M, self.N = Q, K, M, N
+        self._h = _H()
+        self._check(sadmm_create(C.byref(p), C.byref(self._h)), create=True)
+
+    def _check(self, rc, create=False):
+        if rc != SADMM_OK:
+            msg = "" if create else sadmm_last_error(self._h).decode()
+            raise SadmmError(rc, msg)
+
+    def close(self):
+        if self._h:
+            sadmm_destroy(self._h)
+            self._h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- inputs
+    def set_operator(self, q, A):
+        """A: (KM, N) complex array/tensor; Fortran-ordered numpy (column-major)
+        or a torch tensor holding A^T contiguously (shape (N, KM))."""
+        if isinstance(A, np.ndarray):
+            if A.shape == (self.K * self.M, self.N):
+                A = np.asfortranarray(A)
+            ld = A.shape[0] if A.shape == (self.K * self.M, self.N) else A.shape[1]
+        else:
+            assert A.is_contiguous() and A.shape == (self.N, self.K * self.M)
+            ld = A.shape[1]
+        self._keep = A
+        self._check(sadmm_set_operator(self._h, q, _ptr(A), _dtype_code(A), ld, _on_device(A)))
+
+    def set_operator_geometry(self, q, tx, rx, pix, f0, bw):
+        tx = np.ascontiguousarray(tx, dtype=np.float64)
+        rx = np.ascontiguousarray(rx, dtype=np.float64)
+        pix = np.ascontiguousarray(pix, dtype=np.float64)
+        self._check(sadmm_set_operator_geometry(self._h, q, _ptr(tx), _ptr(rx), _ptr(pix),
+                                                f0, bw))
+
+    def set_active_mask(self, q, mask):
+        if mask is None:
+            self._check(sadmm_set_active_mask(self._h, q, None))
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        self._check(sadmm_set_active_mask(self._h, q, _ptr(m)))
+
+    def set_reference(self, x_ref, nmse_target=0.0):
+        if x_ref is None:
+            self._check(sadmm_set_reference(self._h, None, 0, 0, 0.0))
+            return
+        if isinstance(x_ref, np.ndarray):
+            x_ref = np.ascontiguousarray(x_ref)
+        self._check(sadmm_set_reference(self._h, _ptr(x_ref), _dtype_code(x_ref),
+                                        _on_device(x_ref), nmse_target))
+
+    # -- solve
+    def solve(self, y) -> dict:
+        if isinstance(y, np.ndarray):
+            y = np.ascontiguousarray(y)
+        info = sadmm_info()
+        self._check(sadmm_solve(self._h, _ptr(y), _dtype_code(y), _on_device(y), C.byref(info)))
+        return info.as_dict()
+
+    # -- outputs
+    def image(self, dtype=np.complex128) -> np.ndarray:
+        out = np.empty(self.N, dtype=dtype)
+        self._check(sadmm_get_image(self._h, _ptr(out), _dtype_code(out), 0))
+        return out
+
+    def image_into(self, t):
+        self._check(sadmm_get_image(self._h, _ptr(t), _dtype_code(t), _on_device(t)))
+
+    def sensor_image(self, q, dtype=np.complex128) -> np.ndarray:
+        out = np.empty(self.N, dtype=dtype)
+        self._check(sadmm_get_sensor_image(self._h, q, _ptr(out), _dtype_code(out), 0))
+        return out
+
+    def active_mask(self, q) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.uint8)
+        self._check(sadmm_get_active_mask(self._h, q, _ptr(out)))
+        return out
+
+    def active_indices(self, q) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.int32)
+        cnt = C.c_int32(0)
+        self._check(sadmm_get_active_indices(self._h, q, _ptr(out), C.addressof(cnt)))
+        return out[:cnt.value].copy()
+
+    def history(self, which) -> np.ndarray:
+        w = HIST[which] if isinstance(which, str) else int(which)
+        cap = self.params.max_iter
+        out = np.zeros(cap, dtype=np.float64)
+        cnt = C.c_int32(0)
+        self._check(sadmm_get_history(self._h, w, _ptr(out), cap, C.addressof(cnt)))
+        return out[:min(cnt.value, cap)].copy()
+
+    def matched_filter(self, y) -> np.ndarray:
+        if isinstance(y, np.ndarray):
+            y = np.ascontiguousarray(y)
+        out = np.empty((self.Q, self.N), dtype=np.float64)
+        self._check(sadmm_matched_filter(self._h, _ptr(y), _dtype_code(y), _on_device(y),
+                                         _ptr(out)))
+        return out
+
+    def timing(self) -> dict:
+        v = C.c_double(0)
+        out = {}
+        for i, k in enumerate(("total_ms", "factor_ms", "iter_ms")):
+            self._check(sadmm_get_timing(self._h, i, C.byref(v)))
+            out[k] = v.value
+        return out

@@ -1,0 +1,245 @@
+"""GPU engine vs the FP64 oracle on the same seeded inputs, through the C ABI.
+
+Tolerances: FP64 storage/arithmetic -- relative L2 error <= 1e-9 on images and
+bit-exact selectors / index lists; FP32 -- image NMSE <= 1e-6 against the
+oracle; 16-bit operator storage -- NMSE <= 1e-3.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from scenegen import config_scene, make_geometry, make_scene, steering
+
+pytestmark = pytest.mark.gpu
+
+
+def nmse(a, b):
+    return float(np.linalg.norm(a - b) ** 2 / max(np.linalg.norm(b) ** 2, 1e-300))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def problem(Q=4, M=4, K=64, n_side=32, seed=1, n_targets=10, snr=20.0, lam_frac=0.2,
+            mu=1.0, beta=1.0, gamma=1.0):
+    g = make_geometry(Q, M, K, n_side)
+    sc = make_scene(g, seed, n_targets, snr)
+    A = [steering(g, q) for q in range(Q)]
+    lam = lam_frac * oracle.lambda_max(A, sc.y, mu, gamma)
+    return g, sc, A, dict(mu=mu, beta=beta, gamma=gamma, lam=lam)
+
+
+def gpu_run(lib, g, A, y, hp, storage, mask0=None, ref=None, nmse_target=0.0, **kw):
+    s = lib.Solver(g.Q, g.K, g.M, g.N, storage=storage, **hp, **kw)
+    for q in range(g.Q):
+        s.set_operator(q, A[q])
+        if mask0 is not None:
+            s.set_active_mask(q, mask0[q])
+    if ref is not None:
+        s.set_reference(ref, nmse_target)
+    info = s.solve(y)
+    return s, info
+
+
+def oracle_params(hp, **kw):
+    return oracle.Params(mu=hp["mu"], beta=hp["beta"], gamma=hp["gamma"], lam=hp["lam"], **kw)
+
+
+# ---------------------------------------------------------------- single iteration
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_first_iteration_matches(gpu_lib, storage, tol):
+    """One iteration exercises every per-iteration kernel once."""
+    g, sc, A, hp = problem(Q=3, M=4, K=32, n_side=20, seed=2)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, storage, max_iter=1, stop=False)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=1, stop=False))
+    assert info["iters"] == 1
+    for q in range(g.Q):
+        assert rel(s.sensor_image(q), ref.X[q]) < tol
+    assert rel(s.image(), ref.z) < tol if np.linalg.norm(ref.z) > 0 else np.abs(s.image()).max() < tol
+    r = s.history("r")[0]
+    assert r == pytest.approx(ref.history["r"][0], rel=tol * 10)
+
+
+# ---------------------------------------------------------------- plain SADMM
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_plain_fp64_trajectory_c1(gpu_lib, seed):
+    """Config c1 (Q=4, M=4, K=64, 32x32), 200 fixed iterations, FP64."""
+    g, sc, A, hp = problem(seed=seed)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", max_iter=200, stop=False)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=200, stop=False))
+    assert info["iters"] == 200
+    assert rel(s.image(), ref.z) < 1e-9
+    for q in range(g.Q):
+        assert rel(s.sensor_image(q), ref.X[q]) < 1e-9
+
+
+@pytest.mark.parametrize("lam_frac", [0.05, 0.2])
+def test_plain_fp32_converged_c1(gpu_lib, lam_frac):
+    g, sc, A, hp = problem(seed=3, lam_frac=lam_frac)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp32", max_iter=500, eps_rel=1e-6)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=500, eps_rel=1e-6))
+    assert info["status"] == 0
+    assert abs(info["iters"] - ref.iters) <= 2
+    assert nmse(s.image(), ref.z) <= 1e-6
+
+
+def test_stop_iteration_and_residuals_fp64(gpu_lib):
+    g, sc, A, hp = problem(seed=4)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", max_iter=500, eps_rel=1e-5)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=500, eps_rel=1e-5))
+    assert info["status"] == 0 and info["iters"] == ref.iters
+    np.testing.assert_allclose(s.history("r"), ref.history["r"], rtol=1e-7)
+    np.testing.assert_allclose(s.history("s"), ref.history["s"], rtol=1e-7, atol=1e-12)
+    np.testing.assert_allclose(s.history("eps_pri"), ref.history["eps_pri"], rtol=1e-9)
+
+
+# ---------------------------------------------------------------- pruned (ASADMM)
+
+@pytest.mark.parametrize("seed,lam_frac", [(1, 0.2), (2, 0.05)])
+def test_pruned_fp64_masks_bit_exact(gpu_lib, seed, lam_frac):
+    """Alg. 1 selectors and compaction indices equal the oracle's exactly."""
+    g, sc, A, hp = problem(seed=seed, lam_frac=lam_frac)
+    kw = dict(max_iter=300, eps_rel=1e-6, prune=True, Kp=5, eps_p=1e-5)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, **kw))
+    assert ref.prune_events > 0
+    assert info["iters"] == ref.iters
+    assert info["prune_events"] == ref.prune_events
+    for q in range(g.Q):
+        m = s.active_mask(q).astype(bool)
+        assert np.array_equal(m, ref.active[q])
+        assert np.array_equal(s.active_indices(q), np.flatnonzero(ref.active[q]))
+    assert rel(s.image(), ref.z) < 1e-8
+    np.testing.assert_allclose(s.history("max_active_frac"), ref.history["max_active_frac"])
+
+
+def test_pruned_fp32_image_c1(gpu_lib):
+    g, sc, A, hp = problem(seed=5)
+    kw = dict(max_iter=300, eps_rel=1e-5, prune=True, Kp=5, eps_p=1e-5)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp32", **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, **kw))
+    assert info["prune_events"] > 0
+    assert nmse(s.image(), ref.z) <= 1e-6
+
+
+def test_zero_mode_fp64(gpu_lib):
+    g, sc, A, hp = problem(seed=6)
+    kw = dict(max_iter=60, stop=False, prune=True, Kp=4, eps_p=1e-4, eps_rel=1e-3)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", prune_mode="zero", **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, mode="zero", **kw))
+    assert ref.prune_events > 0
+    for q in range(g.Q):
+        assert np.array_equal(s.active_mask(q).astype(bool), ref.active[q])
+    assert rel(s.image(), ref.z) < 1e-8
+
+
+def test_kkt_reinstates_forced_false_prune_fp64(gpu_lib):
+    g, sc, A, hp = problem(seed=7)
+    plain = oracle.solve(A, sc.y, oracle_params(hp, max_iter=2000, eps_rel=1e-6))
+    supp = np.flatnonzero(np.abs(plain.z) > 0)[:3]
+    mask0 = np.ones((g.Q, g.N), bool)
+    mask0[:, supp] = False
+    kw = dict(max_iter=2000, eps_rel=1e-6, prune=True, kkt=True)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", mask0=mask0.astype(np.uint8), **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, **kw), mask0=mask0)
+    assert ref.reinstated >= 3
+    assert info["reinstated"] == ref.reinstated
+    assert info["iters"] == ref.iters
+    assert rel(s.image(), ref.z) < 1e-8
+    assert nmse(s.image(), plain.z) < 1e-6
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_ragged_shapes_fp64(gpu_lib):
+    """KM not a multiple of 32 (padding), N not a multiple of the column chunk,
+    several row tiles in the forward product (KM > 256 in FP64)."""
+    g, sc, A, hp = problem(Q=3, M=5, K=60, n_side=23, seed=8, n_targets=6)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", max_iter=40, stop=False)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=40, stop=False))
+    assert rel(s.image(), ref.z) < 1e-9
+
+
+def test_larger_km_and_ragged_chunks_fp32(gpu_lib):
+    """KM = 1024 (two FP32 row tiles), N = 50^2 (ragged last chunk)."""
+    g, sc, A, hp = problem(Q=4, M=8, K=128, n_side=50, seed=9, n_targets=25)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp32", max_iter=30, stop=False)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=30, stop=False))
+    assert nmse(s.image(), ref.z) <= 1e-6
+
+
+def test_single_sensor_and_empty_sensor(gpu_lib):
+    g, sc, A, hp = problem(Q=1, M=4, K=32, n_side=16, seed=10, n_targets=4)
+    s, _ = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", max_iter=50, stop=False)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=50, stop=False))
+    assert rel(s.image(), ref.z) < 1e-9
+    # one sensor with every pixel eliminated from the start
+    g, sc, A, hp = problem(Q=3, M=4, K=32, n_side=16, seed=11, n_targets=4)
+    mask0 = np.ones((3, g.N), bool)
+    mask0[1] = False
+    s, _ = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", mask0=mask0.astype(np.uint8),
+                   max_iter=50, stop=False, prune=True)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=50, stop=False, prune=True),
+                       mask0=mask0)
+    assert rel(s.image(), ref.z) < 1e-9
+    assert s.active_indices(1).size == 0
+
+
+def test_lambda_above_max_gives_zero_image(gpu_lib):
+    g, sc, A, hp = problem(Q=3, M=4, K=32, n_side=16, seed=12, lam_frac=1.01)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp32", max_iter=300, eps_rel=1e-6)
+    assert np.abs(s.image()).max() == 0.0
+
+
+def test_repeated_solves_reuse_factor(gpu_lib):
+    """A second frame on the same handle (factor reused) equals a fresh handle."""
+    g, sc, A, hp = problem(seed=13)
+    sc2 = make_scene(g, 14, 10, 20.0)
+    s, _ = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", max_iter=30, stop=False)
+    s.solve(sc2.y)
+    z2 = s.image()
+    ref = oracle.solve(A, sc2.y, oracle_params(hp, max_iter=30, stop=False))
+    assert rel(z2, ref.z) < 1e-9
+
+
+def test_geometry_operator_equals_host_operator(gpu_lib):
+    g, sc, A, hp = problem(Q=2, M=4, K=32, n_side=12, seed=15, n_targets=3)
+    s1, _ = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", max_iter=20, stop=False)
+    s2 = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp64", max_iter=20, stop=False, **hp)
+    for q in range(g.Q):
+        s2.set_operator_geometry(q, g.tx[q], g.rx[q], g.pix, g.f0, g.bw)
+    s2.solve(sc.y)
+    assert rel(s2.image(), s1.image()) < 1e-9
+
+
+def test_matched_filter(gpu_lib):
+    g, sc, A, hp = problem(Q=3, M=4, K=32, n_side=16, seed=16)
+    s = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp64", **hp)
+    for q in range(g.Q):
+        s.set_operator(q, A[q])
+    mf = s.matched_filter(sc.y)
+    np.testing.assert_allclose(mf, oracle.matched_filter(A, sc.y), rtol=1e-12, atol=1e-12)
+
+
+def test_reference_nmse_stop(gpu_lib):
+    g, sc, A, hp = problem(seed=17)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp32", ref=ref.z, nmse_target=1e-3,
+                      max_iter=500, eps_rel=1e-8)
+    assert info["status"] == 2
+    h = s.history("nmse")
+    assert h[-1] <= 1e-3 and (len(h) == 1 or h[-2] > 1e-3)
+    assert nmse(s.image(), ref.z) == pytest.approx(h[-1], rel=1e-3)
+
+
+def test_bad_arguments_raise(gpu_lib):
+    g, sc, A, hp = problem(Q=2, M=4, K=32, n_side=8, seed=18, n_targets=2)
+    s = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", **hp)
+    with pytest.raises(gpu_lib.SadmmError):
+        s.solve(sc.y)                      # operators not set
+    with pytest.raises(gpu_lib.SadmmError):
+        s.set_operator(5, A[0])            # sensor out of range
