@@ -151,6 +151,16 @@ int sadmm_get_image(sadmm_t h, void* xG, int32_t dtype, int32_t on_device);
 int sadmm_get_sensor_image(sadmm_t h, int32_t q, void* xq, int32_t dtype,
                            int32_t on_device);
 
+/* Scaled dual u (N complex) of the last solve; beta*u is the multiplier of the
+ * sharing constraint (eq. (3), row 3) and satisfies |beta*u_j| <= lambda at
+ * the optimum. */
+int sadmm_get_dual(sadmm_t h, void* u, int32_t dtype, int32_t on_device);
+
+/* Factor W_q = ((c/mu) I + Ahat_q Ahat_q^H)^{-1} of sensor q as last built or
+ * updated (complex128, KM x KM column-major, host buffer of KM*KM entries);
+ * *n receives KM.  Diagnostic: lets callers check the factor directly. */
+int sadmm_get_factor(sadmm_t h, int32_t q, void* W, int32_t* n);
+
 /* Final selector of sensor q: mask[n] = 1 if pixel n is active (host, N bytes). */
 int sadmm_get_active_mask(sadmm_t h, int32_t q, uint8_t* mask);
 
@@ -173,7 +183,33 @@ int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_dev
  * which = 0 whole solve, 1 factor builds/updates, 2 iterations. */
 int sadmm_get_timing(sadmm_t h, int32_t which, double* ms);
 
+/* Kernel classes timed when profiling is on. */
+enum {
+  SADMM_KC_GRAM = 0,     /* FP64 Gram Ahat Ahat^H of a factor build */
+  SADMM_KC_INVERSE = 1,  /* Cholesky, triangular inverse and W = X^H X */
+  SADMM_KC_FWD = 2,      /* forward product Ahat v (+ partial-sum reduction) */
+  SADMM_KC_WPROD = 3,    /* W t */
+  SADMM_KC_XUPD = 4,     /* adjoint product Ahat^H w with the fused x-update */
+  SADMM_KC_PIXEL = 5,    /* image/dual update, residuals, SSC check */
+  SADMM_KC_COUNT = 6
+};
+
+/* on != 0: record HIP events on the handle's stream around every launch of the
+ * classes above during later solves (adds a little launch overhead); resets
+ * the accumulated times. */
+int sadmm_set_profiling(sadmm_t h, int32_t on);
+
+/* Launch count, summed event time (ms) and algorithmic work of a kernel class
+ * since the last sadmm_set_profiling call.  Work is in flops for GRAM and
+ * INVERSE (complex multiply-add = 8 flops; Hermitian product counts one
+ * triangle) and in bytes for the others (operator, factor and state bytes each
+ * launch must move at least once). */
+int sadmm_get_kernel_stats(sadmm_t h, int32_t kclass, int32_t* launches, double* total_ms,
+                           double* work);
+
 void sadmm_destroy(sadmm_t h);
+/* Message of the last failing call on h; with h = NULL, of the last failed
+ * sadmm_create on this thread. */
 const char* sadmm_last_error(sadmm_t h);
 
 #ifdef __cplusplus

@@ -29,6 +29,7 @@
 namespace {
 
 constexpr int KKT_ROUNDS = 8;
+thread_local std::string g_create_err;   // message of the last failed sadmm_create
 
 struct DevBuf {
   void* p = nullptr;
@@ -52,7 +53,7 @@ struct sadmm_s {
   std::vector<void*> Afull, Ahat_buf, W, Wc;   // Wc: compute-precision W
   std::vector<cd*> W64;
   std::vector<int*> J, Jnew;
-  std::vector<void*> b0;
+  std::vector<void*> xy;                      // Ahat^H W y' per sensor (compute precision)
   std::vector<int> nq;
   std::vector<bool> op_set, fac_valid;
   std::vector<std::vector<int>> facJ;          // active set the factor was built for
@@ -60,7 +61,7 @@ struct sadmm_s {
 
   void *X = nullptr, *dX = nullptr, *xbar = nullptr, *z = nullptr, *u = nullptr, *D = nullptr;
   void *tpart = nullptr, *t = nullptr, *w = nullptr, *gtmp = nullptr, *xref = nullptr;
-  double *y = nullptr, *yp = nullptr, *e = nullptr, *red = nullptr, *hist = nullptr;
+  double *y = nullptr, *yp = nullptr, *e = nullptr, *red = nullptr, *hist = nullptr, *wy = nullptr;
   double* mf = nullptr;
   uint8_t *mask = nullptr, *keep = nullptr, *flag = nullptr, *ones = nullptr;
   int *gone = nullptr, *fail = nullptr, *counts = nullptr, *lst = nullptr, *lst2 = nullptr;
@@ -72,9 +73,8 @@ struct sadmm_s {
   std::vector<SensorDesc> sens_h;
   GemmDesc* gemm_d = nullptr;
   HpdDesc* hpd_d = nullptr;
-  cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Rg = nullptr,
-     *Cg = nullptr;
-  std::vector<cd*> hpdD, hpdR, hpdC;          // per-sensor GJ scratch
+  cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Xg = nullptr;
+  std::vector<cd*> hpdD, hpdX;                // per-sensor inverse scratch
   int rmax = 0, rpad_max = 0;
   int chunk = 256, nchunk = 0, nblk = 0;
   double xref_norm2 = 0.0, nmse_target = 0.0;
@@ -87,6 +87,15 @@ struct sadmm_s {
   double t_total = 0, t_factor = 0, t_iter = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
   bool solved = false;
+
+  // optional per-kernel-class event timing (sadmm_set_profiling)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  std::vector<std::array<int, 3>> marks;       // (class, start event, end event)
+  double kt_ms[SADMM_KC_COUNT] = {0};
+  int kt_n[SADMM_KC_COUNT] = {0};
+  double kt_work[SADMM_KC_COUNT] = {0};       // algorithmic flops or bytes
 };
 
 namespace {
@@ -120,7 +129,11 @@ int dalloc(sadmm_t h, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) return fail_msg(h, SADMM_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  if (e != hipSuccess) {
+    fail_msg(h, SADMM_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    g_create_err = h->err;
+    return SADMM_E_NOMEM;
+  }
   h->allocs.push_back(*p);
   return SADMM_OK;
 }
@@ -133,6 +146,41 @@ template <class P> int dalloc_t(sadmm_t h, P** p, size_t bytes) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// ---- per-kernel-class timing: events recorded around launches on the
+// handle's stream when profiling is on; resolved after the stream syncs.
+int prof_begin(sadmm_t h) {
+  if (!h->prof) return -1;
+  if (h->evnext + 2 > h->evpool.size()) return -1;
+  const int e = (int)h->evnext;
+  h->evnext += 2;
+  hipEventRecord(h->evpool[e], h->s);
+  return e;
+}
+void prof_end(sadmm_t h, int cls, int e) {
+  if (e < 0) return;
+  hipEventRecord(h->evpool[e + 1], h->s);
+  h->marks.push_back({cls, e, e + 1});
+}
+void prof_work(sadmm_t h, int cls, double w) {
+  if (h->prof) h->kt_work[cls] += w;
+}
+// bytes per stored complex operator entry
+double op_bytes(sadmm_t h) { return h->st == ST_FP64 ? 16.0 : (h->st == ST_FP32 ? 8.0 : 4.0); }
+
+void prof_resolve(sadmm_t h) {
+  if (h->marks.empty()) { h->evnext = 0; return; }
+  hipEventSynchronize(h->evpool[h->marks.back()[2]]);
+  for (auto& m : h->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->evpool[m[1]], h->evpool[m[2]]) == hipSuccess) {
+      h->kt_ms[m[0]] += ms;
+      h->kt_n[m[0]] += 1;
+    }
+  }
+  h->marks.clear();
+  h->evnext = 0;
+}
+
 IterArgs make_args(sadmm_t h) {
   IterArgs a{};
   a.Q = h->Q; a.KMp = h->KMp; a.N = h->N; a.Kp = h->p.Kp;
@@ -140,6 +188,7 @@ IterArgs make_args(sadmm_t h) {
   a.prune = h->p.prune; a.stop = h->p.stop;
   a.beta = h->p.beta;
   a.c = h->p.beta + h->p.gamma;
+  a.bc = a.beta / a.c;
   a.tau = h->p.lambda / h->p.beta;
   a.eps_abs = h->p.eps_abs; a.eps_rel = h->p.eps_rel; a.eps_p = h->p.eps_p;
   a.inv_Q = 1.0 / h->Q;
@@ -150,6 +199,7 @@ IterArgs make_args(sadmm_t h) {
   a.tpart = h->tpart; a.t = h->t; a.w = h->w;
   a.xref = h->have_ref ? h->xref : nullptr;
   a.yp = h->yp;
+  a.wy = h->wy;
   a.red = h->red; a.nblk = h->nblk;
   a.max_iter = h->p.max_iter;
   a.ctl = h->ctl; a.hist = h->hist;
@@ -167,8 +217,9 @@ int push_descs(sadmm_t h) {
     d.A = ahat_ptr(h, q);
     d.Afull = h->Afull[q];
     d.J = h->J[q];
-    d.b0 = h->b0[q];
+    d.xy = h->xy[q];
     d.W = h->Wc[q];
+    d.W64 = h->W64[q];
     d.lda = h->ldA;
     d.nq = h->nq[q];
   }
@@ -211,13 +262,23 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
     g.kmpA = h->KMp; g.kmpB = h->KMp;
     g.lda = h->ldA; g.ldb = h->ldA; g.ldc = h->KMp;
     g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta = 0.0; g.diag = rho;
-    hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdR[q], h->hpdC[q]};
+    hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q]};
   }
   HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
-  zgemm_batched(h->gemm_d, (int)qs.size(), h->KMp, h->KMp, h->st, h->st, OP_N, OP_C, true, h->s);
-  HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->hpd_d, hd.data(), sizeof(HpdDesc) * hd.size(), hipMemcpyHostToDevice, h->s));
+  int pe = prof_begin(h);
+  zgemm_batched(h->gemm_d, (int)qs.size(), h->KMp, h->KMp, h->st, h->st, OP_N, OP_C, true, h->s);
+  prof_end(h, SADMM_KC_GRAM, pe);
+  for (int q : qs) {
+    // Hermitian product: KM(KM+1)/2 entries, N_q complex MACs each (8 flops)
+    prof_work(h, SADMM_KC_GRAM, 8.0 * 0.5 * h->KM * (h->KM + 1.0) * h->nq[q]);
+    // Cholesky n^3/3, triangular inverse n^3/6, X^H X n^3/3 complex MACs
+    prof_work(h, SADMM_KC_INVERSE, 8.0 * (5.0 / 6.0) * (double)h->KM * h->KM * h->KM);
+  }
+  HIPCHK(h, hipGetLastError());
+  pe = prof_begin(h);
   hpd_inverse_batched(h->hpd_d, (int)qs.size(), h->KMp, h->fail, h->s);
+  prof_end(h, SADMM_KC_INVERSE, pe);
   HIPCHK(h, hipGetLastError());
   for (int q : qs) {
     cast_hermitian(h->W64[q], h->KMp, h->Wc[q], h->KMp, h->KMp, !h->dbl, h->s);
@@ -244,7 +305,7 @@ int lowrank_update(sadmm_t h, int q, const int* d_list, int r, int sign) {
   g[2] = GemmDesc{h->V, h->Cm, h->Tm, KMp, r, r, KMp, KMp, KMp, rp, KMp, 1.0, 0.0, 0.0, 0.0};
   // W += -sign * Tm V^H
   g[3] = GemmDesc{h->Tm, h->V, h->W64[q], KMp, KMp, r, KMp, KMp, KMp, KMp, KMp, -(double)sign, 0.0, 1.0, 0.0};
-  HpdDesc hd{h->Cm, rp, h->Dg, h->Rg, h->Cg};
+  HpdDesc hd{h->Cm, rp, h->Dg, h->Xg};
   HIPCHK(h, hipMemcpyAsync(h->gemm_d, g.data(), sizeof(GemmDesc) * 4, hipMemcpyHostToDevice, h->s));
   HIPCHK(h, hipMemcpyAsync(h->hpd_d, &hd, sizeof hd, hipMemcpyHostToDevice, h->s));
   zgemm_batched(h->gemm_d, 1, KMp, r, ST_FP64, ST_FP64, OP_N, OP_N, false, h->s);
@@ -310,7 +371,7 @@ int apply_prune(sadmm_t h) {
     TRY(push_descs(h));
     TRY(refresh_factor(h, q, h->lst, r, -1));
     h->fac_valid[q] = false;
-    launch_b0(make_args(h), h->st, h->dbl, h->p.mu, q, q + 1, h->s);
+    launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
     HIPCHK(h, hipGetLastError());
   }
   HIPCHK(h, hipMemsetAsync(h->gone, 0, sizeof(int) * h->Q, h->s));
@@ -349,7 +410,7 @@ int kkt_reinstate(sadmm_t h, int* n_back) {
     TRY(push_descs(h));
     TRY(refresh_factor(h, q, h->lst2, r, +1));
     h->fac_valid[q] = false;
-    launch_b0(make_args(h), h->st, h->dbl, h->p.mu, q, q + 1, h->s);
+    launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
     HIPCHK(h, hipGetLastError());
     *n_back += r;
   }
@@ -416,10 +477,10 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   const size_t cN = h->csz * N;
   h->Afull.assign(Q, nullptr); h->Ahat_buf.assign(Q, nullptr);
   h->W64.assign(Q, nullptr); h->Wc.assign(Q, nullptr); h->W.assign(Q, nullptr);
-  h->J.assign(Q, nullptr); h->Jnew.assign(Q, nullptr); h->b0.assign(Q, nullptr);
+  h->J.assign(Q, nullptr); h->Jnew.assign(Q, nullptr); h->xy.assign(Q, nullptr);
   h->nq.assign(Q, N); h->op_set.assign(Q, false); h->fac_valid.assign(Q, false);
   h->facJ.assign(Q, {}); h->mask0.assign(Q, {});
-  h->hpdD.assign(Q, nullptr); h->hpdR.assign(Q, nullptr); h->hpdC.assign(Q, nullptr);
+  h->hpdD.assign(Q, nullptr); h->hpdX.assign(Q, nullptr);
   h->sens_h.assign(Q, SensorDesc{});
   h->rmax = std::min(KMp, 1024);
   h->rpad_max = round_up(h->rmax, HPD_NB);
@@ -430,10 +491,9 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
     A_(dalloc(h, &h->Wc[q], h->csz * (size_t)KMp * KMp));
     A_(dalloc_t(h, &h->J[q], sizeof(int) * N));
     A_(dalloc_t(h, &h->Jnew[q], sizeof(int) * N));
-    A_(dalloc(h, &h->b0[q], cN));
-    A_(dalloc_t(h, &h->hpdD[q], sizeof(cd) * HPD_NB * HPD_NB));
-    A_(dalloc_t(h, &h->hpdR[q], sizeof(cd) * (size_t)HPD_NB * KMp));
-    A_(dalloc_t(h, &h->hpdC[q], sizeof(cd) * (size_t)HPD_NB * KMp));
+    A_(dalloc(h, &h->xy[q], cN));
+    A_(dalloc_t(h, &h->hpdD[q], sizeof(cd) * (size_t)HPD_NB * KMp));
+    A_(dalloc_t(h, &h->hpdX[q], sizeof(cd) * (size_t)KMp * KMp));
   }
   A_(dalloc(h, &h->X, cN * Q));
   A_(dalloc(h, &h->dX, cN * Q));
@@ -449,6 +509,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   A_(dalloc_t(h, &h->y, 16 * (size_t)Q * KMp));
   A_(dalloc_t(h, &h->yp, 16 * (size_t)Q * KMp));
   A_(dalloc_t(h, &h->e, 16 * (size_t)KMp));
+  A_(dalloc_t(h, &h->wy, 16 * (size_t)Q * KMp));
   A_(dalloc_t(h, &h->red, sizeof(double) * 8 * h->nblk));
   A_(dalloc_t(h, &h->hist, sizeof(double) * 6 * (size_t)p->max_iter));
   A_(dalloc_t(h, &h->mf, sizeof(double) * (size_t)Q * N));
@@ -468,12 +529,13 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   A_(dalloc_t(h, &h->V, sizeof(cd) * (size_t)KMp * h->rmax));
   A_(dalloc_t(h, &h->Tm, sizeof(cd) * (size_t)KMp * h->rmax));
   A_(dalloc_t(h, &h->Cm, sizeof(cd) * (size_t)h->rpad_max * h->rpad_max));
-  A_(dalloc_t(h, &h->Dg, sizeof(cd) * HPD_NB * HPD_NB));
-  A_(dalloc_t(h, &h->Rg, sizeof(cd) * (size_t)HPD_NB * h->rpad_max));
-  A_(dalloc_t(h, &h->Cg, sizeof(cd) * (size_t)HPD_NB * h->rpad_max));
+  A_(dalloc_t(h, &h->Dg, sizeof(cd) * (size_t)HPD_NB * h->rpad_max));
+  A_(dalloc_t(h, &h->Xg, sizeof(cd) * (size_t)h->rpad_max * h->rpad_max));
+  g_create_err.clear();
   if (hipHostMalloc((void**)&h->ctl_h, sizeof(Ctl)) != hipSuccess ||
       hipHostMalloc((void**)&h->counts_h, 2 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void**)&h->halt_h, sizeof(int)) != hipSuccess) {
+    g_create_err = "pinned host allocation failed";
     sadmm_destroy(h);
     return SADMM_E_NOMEM;
   }
@@ -646,10 +708,11 @@ int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadm
   TRY(push_descs(h));
   HIPCHK(h, hipEventRecord(h->evf0, s));
   TRY(build_factors(h, rebuild));
-  launch_b0(make_args(h), h->st, h->dbl, h->p.mu, 0, Q, s);
+  launch_xy(make_args(h), h->st, h->dbl, 0, Q, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->evf1, s));
   HIPCHK(h, hipEventSynchronize(h->evf1));
+  prof_resolve(h);
   float fms = 0.f;
   hipEventElapsedTime(&fms, h->evf0, h->evf1);
   h->t_factor = fms;
@@ -660,10 +723,38 @@ int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadm
   int status = 1;
   for (;;) {
     const IterArgs a = make_args(h);
-    for (int i = 0; i < h->p.check_every; ++i) launch_iteration(a, h->st, h->dbl, s);
+    for (int i = 0; i < h->p.check_every; ++i) {
+      if (h->prof) {
+        int ev[IT_NSTAGE + 1];
+        for (int k = 0; k <= IT_NSTAGE; ++k) ev[k] = -1;
+        if (h->evnext + 2 * IT_NSTAGE <= h->evpool.size()) {
+          for (int k = 0; k < IT_NSTAGE; ++k) ev[k] = (int)(h->evnext + 2 * k);
+          h->evnext += 2 * IT_NSTAGE;
+        }
+        {
+          // algorithmic bytes of one iteration, per stage
+          const double ob = op_bytes(h), cz = (double)h->csz;
+          double nqs = 0;
+          for (int q = 0; q < Q; ++q) nqs += h->nq[q];
+          const double KM = h->KM;
+          prof_work(h, SADMM_KC_FWD, nqs * KM * ob + nqs * 4 * cz + Q * KM * cz);
+          prof_work(h, SADMM_KC_WPROD, Q * (KM * KM * cz + 2 * KM * cz));
+          prof_work(h, SADMM_KC_XUPD, nqs * KM * ob + Q * KM * cz + nqs * (7 * cz + cz / 2));
+          prof_work(h, SADMM_KC_PIXEL, (double)Q * N * 2 * cz + (double)N * 6 * cz);
+        }
+        launch_iteration_staged(a, h->st, h->dbl, s, [&](int stage, bool begin) {
+          if (ev[0] < 0) return;
+          hipEventRecord(h->evpool[ev[stage] + (begin ? 0 : 1)], s);
+          if (!begin) h->marks.push_back({SADMM_KC_FWD + stage, ev[stage], ev[stage] + 1});
+        });
+      } else {
+        launch_iteration(a, h->st, h->dbl, s);
+      }
+    }
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
+    prof_resolve(h);
     const Ctl c = *h->ctl_h;
     if (c.halt & HALT_NAN) return fail_msg(h, SADMM_E_NUMERIC, "non-finite residual at iteration %d", c.k);
     if (!c.halt) continue;
@@ -776,6 +867,34 @@ int sadmm_get_sensor_image(sadmm_t h, int32_t q, void* xq, int32_t dtype, int32_
   return SADMM_OK;
 }
 
+int sadmm_get_dual(sadmm_t h, void* u, int32_t dtype, int32_t on_device) {
+  if (!h) return SADMM_E_ARG;
+  if (!u || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "get_dual: bad argument");
+  if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_dual: no solve yet");
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  void* d = u;
+  if (!on_device) HIPCHK(h, hipMalloc(&d, esz * h->N));
+  if (dtype == SADMM_C128) compute_to_c128(h->u, h->dbl, static_cast<double*>(d), h->N, h->s);
+  else compute_to_c64(h->u, h->dbl, static_cast<float*>(d), h->N, h->s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(u, d, esz * h->N, hipMemcpyDeviceToHost, h->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+  if (!on_device) hipFree(d);
+  if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "get_dual: %s", hipGetErrorString(e));
+  return SADMM_OK;
+}
+
+int sadmm_get_factor(sadmm_t h, int32_t q, void* W, int32_t* n) {
+  if (!h) return SADMM_E_ARG;
+  if (!W || !n || q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "get_factor: bad argument");
+  if (!h->fac_valid[q] && !h->solved) return fail_msg(h, SADMM_E_STATE, "get_factor: no factor");
+  *n = h->KM;
+  HIPCHK(h, hipMemcpy2DAsync(W, 16 * (size_t)h->KM, h->W64[q], 16 * (size_t)h->KMp, 16 * (size_t)h->KM,
+                             h->KM, hipMemcpyDeviceToHost, h->s));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return SADMM_OK;
+}
+
 int sadmm_get_active_mask(sadmm_t h, int32_t q, uint8_t* mask) {
   if (!h) return SADMM_E_ARG;
   if (!mask || q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "get_active_mask: bad argument");
@@ -830,6 +949,31 @@ int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_dev
   return SADMM_OK;
 }
 
+int sadmm_set_profiling(sadmm_t h, int32_t on) {
+  if (!h) return SADMM_E_ARG;
+  h->prof = on != 0;
+  if (h->prof && h->evpool.empty()) {
+    h->evpool.resize(8192);
+    for (auto& e : h->evpool)
+      if (hipEventCreate(&e) != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_profiling: event creation");
+  }
+  for (int i = 0; i < SADMM_KC_COUNT; ++i) { h->kt_ms[i] = 0.0; h->kt_n[i] = 0; h->kt_work[i] = 0.0; }
+  h->marks.clear();
+  h->evnext = 0;
+  return SADMM_OK;
+}
+
+int sadmm_get_kernel_stats(sadmm_t h, int32_t kclass, int32_t* launches, double* total_ms,
+                           double* work) {
+  if (!h) return SADMM_E_ARG;
+  if (kclass < 0 || kclass >= SADMM_KC_COUNT || !launches || !total_ms || !work)
+    return fail_msg(h, SADMM_E_ARG, "get_kernel_stats: bad argument");
+  *launches = h->kt_n[kclass];
+  *total_ms = h->kt_ms[kclass];
+  *work = h->kt_work[kclass];
+  return SADMM_OK;
+}
+
 int sadmm_get_timing(sadmm_t h, int32_t which, double* ms) {
   if (!h) return SADMM_E_ARG;
   if (!ms || which < 0 || which > 2) return fail_msg(h, SADMM_E_ARG, "get_timing: bad argument");
@@ -849,9 +993,10 @@ void sadmm_destroy(sadmm_t h) {
   if (h->ev1) hipEventDestroy(h->ev1);
   if (h->evf0) hipEventDestroy(h->evf0);
   if (h->evf1) hipEventDestroy(h->evf1);
+  for (auto& e : h->evpool) hipEventDestroy(e);
   delete h;
 }
 
-const char* sadmm_last_error(sadmm_t h) { return h ? h->err.c_str() : "null handle"; }
+const char* sadmm_last_error(sadmm_t h) { return h ? h->err.c_str() : g_create_err.c_str(); }
 
 }  // extern "C"

@@ -1,5 +1,7 @@
 // Per-iteration kernels of sharing ADMM (eq. (3)) and the SSC check (Alg. 1).
 #pragma once
+#include <functional>
+
 #include "common.h"
 
 // Per-sensor view used by the iteration kernels (device array, one per sensor).
@@ -7,8 +9,10 @@ struct SensorDesc {
   const void* A;       // active columns Ahat_q (compacted, ascending pixel order)
   const void* Afull;   // full operator A_q
   const int* J;        // active pixel indices, nq entries (ascending)
-  const void* b0;      // mu * Ahat^H y'_q, nq complex (compute precision)
+  const void* xy;      // Ahat^H W y'_q, nq complex (compute precision): the
+                       // data part of the x-update, (mu Ahat^H Ahat + cI)^{-1} mu Ahat^H y'
   const void* W;       // KMp x KMp factor, compute precision, ld = KMp
+  const cd* W64;       // the same factor in complex128
   int64_t lda;         // column stride of A and Afull (storage slots)
   int nq;
   int pad;
@@ -20,6 +24,7 @@ struct IterArgs {
   int chunk, nchunk;   // forward kernel: columns per work-group, chunks per sensor
   int prune, stop;
   double beta, c, tau, eps_abs, eps_rel, eps_p, inv_Q;
+  double bc;           // beta / c
   double nmse_target, xref_norm2;
   const SensorDesc* sens;
   void* X;             // Q x N complex
@@ -33,6 +38,7 @@ struct IterArgs {
   void* w;             // Q x KMp complex
   const void* xref;    // N complex or null
   const double* yp;    // Q x KMp complex128: y'_q (measurement minus frozen pixels)
+  double* wy;          // Q x KMp complex128 scratch: W_q y'_q
   double* red;         // pixel-kernel block partials (nblk x 8)
   int nblk;
   int max_iter;
@@ -48,10 +54,18 @@ constexpr int DOT_COLS_PER_WAVE = 4;
 // Launchers.  `st` is the operator storage (sadmm_storage), `dbl` selects FP64
 // compute (only with ST_FP64).
 void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s);
+
+// The same launches with a hook called before (begin = true) and after each
+// stage: 0 forward + partial reduce, 1 W product, 2 adjoint + x-update,
+// 3 pixel update + finalize + SSC check.
+constexpr int IT_NSTAGE = 4;
+void launch_iteration_staged(const IterArgs& a, int st, bool dbl, hipStream_t s,
+                             const std::function<void(int, bool)>& hook);
 int fwd_row_tile(int st);   // rows covered by one forward work-group
 
-// b0_q = mu * Ahat_q^H y'_q for the sensors in [q0, q1).
-void launch_b0(const IterArgs& a, int st, bool dbl, double mu, int q0, int q1, hipStream_t s);
+// xy_q = Ahat_q^H (W_q y'_q) for the sensors in [q0, q1), FP64 arithmetic
+// (rounded to the compute precision on store).
+void launch_xy(const IterArgs& a, int st, bool dbl, int q0, int q1, hipStream_t s);
 
 // Generic gathered forward product for one sensor q:
 //   out += sign * sum_j coef_j * Afull[:, idx_j],   coef_j = X[q, idx_j]

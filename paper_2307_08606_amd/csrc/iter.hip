@@ -1,11 +1,20 @@
 // Per-iteration kernels of sharing ADMM (eq. (3)) with the SSC check of Alg. 1.
 //
+// The x-update of eq. (3), x = (mu Ahat^H Ahat + cI)^{-1} (mu Ahat^H y' + beta v),
+// is applied as
+//     x = Ahat^H W y'  +  (beta/c) (v - Ahat^H W Ahat v),   W = ((c/mu) I + Ahat Ahat^H)^{-1},
+// (push-through and Woodbury identities; exact in exact arithmetic).  The
+// data part Ahat^H W y' is fixed between selector changes and is computed once
+// in FP64; only the v-part goes through W every iteration.  Applying W to the
+// whole right-hand side instead would cancel catastrophically in FP32, since
+// mu Ahat^H y' lies in the row space of Ahat where W is tiny.
+//
 // One iteration = seven launches, each covering all Q sensors:
-//   fwd      t_q = Ahat_q b_q, b_q = b0_q + beta (x_q - xbar + z - u)[J_q]
+//   fwd      t_q = Ahat_q v_q, v_q = (x_q - xbar + z - u)[J_q]
 //            (column chunks per work-group -> partial sums, no atomics)
 //   reduce   t_q = sum of the chunk partials, fixed order
 //   wdot     w_q = W_q t_q  (W_q Hermitian: one wavefront dot per column)
-//   xupd     x_q[J_q] = (b_q - Ahat_q^H w_q) / c, fused epilogue writes
+//   xupd     x_q[J_q] = xy_q + (beta/c)(v_q - Ahat_q^H w_q), fused epilogue writes
 //            x_q, dx_q and |dx_q| into the SSC history ring
 //   pixel    xbar, z = S_{lambda/beta}(xbar + u), u += xbar - z, and block
 //            partial sums of the residual norms
@@ -29,17 +38,14 @@ template <class T> __device__ inline void stc(void* p, int64_t i, C2<T> v) {
 }
 template <class T> __device__ inline T habs(C2<T> v) { return hypot(v.re, v.im); }
 
-// b_q[p] of the x-update right-hand side (eq. (3), row 1, sharing form)
+// v_q[n] = x_q - xbar + z - u at pixel n (eq. (3), row 1, sharing form)
 template <class T>
-__device__ inline C2<T> rhs_b(const IterArgs& a, const SensorDesc& sd, int q, int p, int n) {
+__device__ inline C2<T> shared_v(const IterArgs& a, int q, int n) {
   const C2<T> x = ldc<T>(a.X, (int64_t)q * a.N + n);
   const C2<T> xb = ldc<T>(a.xbar, n);
   const C2<T> zz = ldc<T>(a.z, n);
   const C2<T> uu = ldc<T>(a.u, n);
-  C2<T> v = csub(cadd(csub(x, xb), zz), uu);
-  const C2<T> b0 = ldc<T>(sd.b0, p);
-  const T beta = (T)a.beta;
-  return {b0.re + beta * v.re, b0.im + beta * v.im};
+  return csub(cadd(csub(x, xb), zz), uu);
 }
 
 // ------------------------------------------------------------------ forward
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(IterArgs a) {
   __shared__ C2<T> coef[MAX_CHUNK];
   for (int e = threadIdx.x; e < np; e += FWD_THREADS) {
     const int p = p0 + e;
-    coef[e] = rhs_b<T>(a, sd, q, p, sd.J[p]);
+    coef[e] = shared_v<T>(a, q, sd.J[p]);
   }
   __syncthreads();
   const int row = (blockIdx.x * FWD_THREADS + threadIdx.x) * R;
@@ -143,63 +149,73 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(int KMp, int nch, co
 }
 
 // ------------------------------------------------------------------ column dots
-enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_B0 = 2, EPI_KKT = 3, EPI_MF = 4 };
+enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5 };
 
 struct DotExtra {
   const int* idx;       // KKT: eliminated pixel list
   int count;
   int q;                // KKT: sensor
-  const double* vec;    // B0 / KKT / MF: complex128 source vector(s)
+  const double* vec;    // WY / XY / KKT / MF: complex128 source vector(s)
   int64_t vec_stride;   // per-sensor stride (complex entries)
   double mu, gamma, thr;
   uint8_t* flag;        // KKT
-  double* out;          // MF
-  int q0;               // B0: first sensor of the launch
+  double* out;          // MF (|.|), WY (complex)
+  int q0;               // WY / XY: first sensor of the launch
 };
 
-template <int ST>
-__device__ inline C2<typename Store<ST>::T> coldot_core(const void* col,
-                                                       const C2<typename Store<ST>::T>* sv,
-                                                       int KMp, int lane) {
+// Dot of one operator column with the LDS vector sv, accumulated in TA.
+template <int ST, class TA>
+__device__ inline C2<TA> coldot_core(const void* col, const C2<TA>* sv, int KMp, int lane) {
   using T = typename Store<ST>::T;
   constexpr int R = Store<ST>::RPT;
-  C2<T> acc = {(T)0, (T)0};
+  C2<TA> acc = {(TA)0, (TA)0};
 #pragma unroll 4
   for (int i0 = lane * R; i0 < KMp; i0 += SADMM_WAVE * R) {
     T re[R], im[R];
     Store<ST>::load(col, i0, KMp, re, im);
 #pragma unroll
-    for (int r = 0; r < R; ++r) cfmac(acc, C2<T>{re[r], im[r]}, sv[i0 + r]);
+    for (int r = 0; r < R; ++r) cfmac(acc, C2<TA>{(TA)re[r], (TA)im[r]}, sv[i0 + r]);
   }
   acc.re = wave_sum(acc.re);
   acc.im = wave_sum(acc.im);
   return acc;
 }
 
+// Accumulation precision: the per-iteration products run in the compute
+// precision; the once-per-factor data term (WY, XY) and the certificate
+// products (KKT, MF) accumulate in FP64.
+template <int ST, int EPI> struct DotAcc {
+  using type = typename std::conditional<(EPI == EPI_W || EPI == EPI_XUPD),
+                                         typename Store<ST>::T, double>::type;
+};
+
 template <int ST, int EPI>
 __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
-  using T = typename Store<ST>::T;
+  using T = typename Store<ST>::T;            // compute precision of the state
+  using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
-  const int q = (EPI == EPI_KKT) ? x.q : (EPI == EPI_B0 ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
+  const int q = (EPI == EPI_KKT) ? x.q
+              : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
   const SensorDesc sd = a.sens[q];
   int ncols;
-  if constexpr (EPI == EPI_W) ncols = a.KMp;
-  else if constexpr (EPI == EPI_XUPD || EPI == EPI_B0) ncols = sd.nq;
+  if constexpr (EPI == EPI_W || EPI == EPI_WY) ncols = a.KMp;
+  else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) ncols = sd.nq;
   else if constexpr (EPI == EPI_KKT) ncols = x.count;
   else ncols = a.N;
   const int cols_per_block = 4 * DOT_COLS_PER_WAVE;
   const int col0 = blockIdx.x * cols_per_block;
   if (col0 >= ncols) return;
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* sv = reinterpret_cast<C2<T>*>(smem_raw);
+  C2<TA>* sv = reinterpret_cast<C2<TA>*>(smem_raw);
   // stage the vector operand
   for (int i = threadIdx.x; i < a.KMp; i += 256) {
-    C2<T> v;
-    if constexpr (EPI == EPI_W) v = ldc<T>(a.t, (int64_t)q * a.KMp + i);
-    else if constexpr (EPI == EPI_XUPD) v = ldc<T>(a.w, (int64_t)q * a.KMp + i);
+    C2<TA> v;
+    if constexpr (EPI == EPI_W) v = ldc<TA>(a.t, (int64_t)q * a.KMp + i);
+    else if constexpr (EPI == EPI_XUPD) v = ldc<TA>(a.w, (int64_t)q * a.KMp + i);
+    else if constexpr (EPI == EPI_XY) v = {a.wy[2 * ((int64_t)q * a.KMp + i)], a.wy[2 * ((int64_t)q * a.KMp + i) + 1]};
     else {
       const double* src = x.vec + 2 * ((EPI == EPI_KKT ? 0 : (int64_t)q * x.vec_stride) + i);
-      v = {(T)src[0], (T)src[1]};
+      v = {(TA)src[0], (TA)src[1]};
     }
     sv[i] = v;
   }
@@ -210,18 +226,20 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
     if (p >= ncols) break;
     const void* col;
     if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W, a.KMp, p);
-    else if constexpr (EPI == EPI_XUPD || EPI == EPI_B0) col = col_ptr<ST>(sd.A, sd.lda, p);
+    else if constexpr (EPI == EPI_WY) col = col_ptr<ST>(sd.W64, a.KMp, p);
+    else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) col = col_ptr<ST>(sd.A, sd.lda, p);
     else if constexpr (EPI == EPI_KKT) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
     else col = col_ptr<ST>(sd.Afull, sd.lda, p);
-    const C2<T> d = coldot_core<ST>(col, sv, a.KMp, lane);
+    const C2<TA> d = coldot_core<ST, TA>(col, sv, a.KMp, lane);
     if (lane != 0) continue;
     if constexpr (EPI == EPI_W) {
       stc<T>(a.w, (int64_t)q * a.KMp + p, d);
     } else if constexpr (EPI == EPI_XUPD) {
       const int n = sd.J[p];
-      const C2<T> b = rhs_b<T>(a, sd, q, p, n);
-      const T cc = (T)a.c;
-      const C2<T> xn = {(b.re - d.re) / cc, (b.im - d.im) / cc};
+      const C2<T> v = shared_v<T>(a, q, n);
+      const C2<T> xy = ldc<T>(sd.xy, p);
+      const T bc = (T)a.bc;
+      const C2<T> xn = {xy.re + bc * (v.re - d.re), xy.im + bc * (v.im - d.im)};
       const int64_t o = (int64_t)q * a.N + n;
       const C2<T> xo = ldc<T>(a.X, o);
       const C2<T> dx = csub(xn, xo);
@@ -229,18 +247,20 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
       stc<T>(a.dX, o, dx);
       const int slot = a.ctl->k % a.Kp;
       reinterpret_cast<T*>(a.D)[((int64_t)slot * a.Q + q) * a.N + n] = habs(dx);
-    } else if constexpr (EPI == EPI_B0) {
-      const T mu = (T)x.mu;
-      stc<T>(const_cast<void*>(sd.b0), p, C2<T>{mu * d.re, mu * d.im});
+    } else if constexpr (EPI == EPI_WY) {
+      a.wy[2 * ((int64_t)q * a.KMp + p)] = d.re;
+      a.wy[2 * ((int64_t)q * a.KMp + p) + 1] = d.im;
+    } else if constexpr (EPI == EPI_XY) {
+      stc<T>(const_cast<void*>(sd.xy), p, C2<T>{(T)d.re, (T)d.im});
     } else if constexpr (EPI == EPI_KKT) {
       const int n = x.idx[p];
       const C2<T> xv = ldc<T>(a.X, (int64_t)q * a.N + n);
       const C2<T> uv = ldc<T>(a.u, n);
-      const double gre = x.mu * (double)d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
-      const double gim = x.mu * (double)d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
+      const double gre = x.mu * d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
+      const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
       x.flag[p] = hypot(gre, gim) > x.thr ? 1 : 0;
     } else {
-      x.out[(int64_t)q * a.N + p] = hypot((double)d.re, (double)d.im);
+      x.out[(int64_t)q * a.N + p] = hypot(d.re, d.im);
     }
   }
 }
@@ -372,24 +392,33 @@ __global__ void ssc_flag_kernel(IterArgs a) {
 }
 
 template <int ST>
-void run_iteration(const IterArgs& a, hipStream_t s) {
+void run_iteration(const IterArgs& a, hipStream_t s, const std::function<void(int, bool)>* hook) {
   using T = typename Store<ST>::T;
   constexpr int WST = std::is_same<T, double>::value ? ST_FP64 : ST_FP32;
+  auto mark = [&](int stage, bool begin) { if (hook) (*hook)(stage, begin); };
   const int rows = FWD_THREADS * Store<ST>::RPT;
   dim3 gf((a.KMp + rows - 1) / rows, a.nchunk, a.Q);
+  mark(0, true);
   fwd_iter_kernel<ST><<<gf, FWD_THREADS, 0, s>>>(a);
   fwd_reduce_kernel<T><<<dim3((a.KMp + 255) / 256, a.Q), 256, 0, s>>>(a);
+  mark(0, false);
   const int cpb = 4 * DOT_COLS_PER_WAVE;
   const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
   DotExtra x{};
+  mark(1, true);
   coldot_kernel<WST, EPI_W><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+  mark(1, false);
+  mark(2, true);
   coldot_kernel<ST, EPI_XUPD><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+  mark(2, false);
+  mark(3, true);
   pixel_kernel<T><<<a.nblk, 256, 0, s>>>(a);
   finalize_kernel<<<1, 256, 0, s>>>(a);
   if (a.prune) {
     ssc_kernel<T><<<dim3((a.N + 255) / 256, a.Q), 256, 0, s>>>(a);
     ssc_flag_kernel<<<1, 64, 0, s>>>(a);
   }
+  mark(3, false);
 }
 
 }  // namespace
@@ -405,34 +434,45 @@ int fwd_row_tile(int st) {
 void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s) {
   (void)dbl;
   switch (st) {
-    case ST_FP64: run_iteration<ST_FP64>(a, s); break;
-    case ST_FP32: run_iteration<ST_FP32>(a, s); break;
-    case ST_FP16P: run_iteration<ST_FP16P>(a, s); break;
-    case ST_BF16P: run_iteration<ST_BF16P>(a, s); break;
+    case ST_FP64: run_iteration<ST_FP64>(a, s, nullptr); break;
+    case ST_FP32: run_iteration<ST_FP32>(a, s, nullptr); break;
+    case ST_FP16P: run_iteration<ST_FP16P>(a, s, nullptr); break;
+    case ST_BF16P: run_iteration<ST_BF16P>(a, s, nullptr); break;
+  }
+}
+
+void launch_iteration_staged(const IterArgs& a, int st, bool dbl, hipStream_t s,
+                             const std::function<void(int, bool)>& hook) {
+  (void)dbl;
+  switch (st) {
+    case ST_FP64: run_iteration<ST_FP64>(a, s, &hook); break;
+    case ST_FP32: run_iteration<ST_FP32>(a, s, &hook); break;
+    case ST_FP16P: run_iteration<ST_FP16P>(a, s, &hook); break;
+    case ST_BF16P: run_iteration<ST_BF16P>(a, s, &hook); break;
   }
 }
 
 template <int ST>
-static void b0_impl(const IterArgs& a, double mu, int q0, int q1, hipStream_t s) {
-  using T = typename Store<ST>::T;
+static void xy_impl(const IterArgs& a, int q0, int q1, hipStream_t s) {
   DotExtra x{};
-  x.vec = a.yp;
-  x.vec_stride = a.KMp;
-  x.mu = mu;
   x.q0 = q0;
   const int cpb = 4 * DOT_COLS_PER_WAVE;
-  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
-  coldot_kernel<ST, EPI_B0><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
+  const size_t smem = (size_t)a.KMp * sizeof(cd);
+  // W_q y'_q in FP64, then Ahat_q^H (W_q y'_q) accumulated in FP64
+  x.vec = a.yp;
+  x.vec_stride = a.KMp;
+  coldot_kernel<ST_FP64, EPI_WY><<<dim3((a.KMp + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
+  coldot_kernel<ST, EPI_XY><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
 }
 
-void launch_b0(const IterArgs& a, int st, bool dbl, double mu, int q0, int q1, hipStream_t s) {
+void launch_xy(const IterArgs& a, int st, bool dbl, int q0, int q1, hipStream_t s) {
   (void)dbl;
   if (q1 <= q0) return;
   switch (st) {
-    case ST_FP64: b0_impl<ST_FP64>(a, mu, q0, q1, s); break;
-    case ST_FP32: b0_impl<ST_FP32>(a, mu, q0, q1, s); break;
-    case ST_FP16P: b0_impl<ST_FP16P>(a, mu, q0, q1, s); break;
-    case ST_BF16P: b0_impl<ST_BF16P>(a, mu, q0, q1, s); break;
+    case ST_FP64: xy_impl<ST_FP64>(a, q0, q1, s); break;
+    case ST_FP32: xy_impl<ST_FP32>(a, q0, q1, s); break;
+    case ST_FP16P: xy_impl<ST_FP16P>(a, q0, q1, s); break;
+    case ST_BF16P: xy_impl<ST_BF16P>(a, q0, q1, s); break;
   }
 }
 
@@ -473,7 +513,7 @@ static void kkt_impl(const IterArgs& a, int q, const int* idx, int count, const 
   x.thr = thr;
   x.flag = flag;
   const int cpb = 4 * DOT_COLS_PER_WAVE;
-  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
+  const size_t smem = (size_t)a.KMp * sizeof(cd);
   coldot_kernel<ST, EPI_KKT><<<dim3((count + cpb - 1) / cpb, 1), 256, smem, s>>>(a, x);
 }
 
@@ -497,7 +537,7 @@ static void mf_impl(const IterArgs& a, const double* y, double* out, hipStream_t
   x.vec_stride = a.KMp;
   x.out = out;
   const int cpb = 4 * DOT_COLS_PER_WAVE;
-  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
+  const size_t smem = (size_t)a.KMp * sizeof(cd);
   coldot_kernel<ST, EPI_MF><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
 }
 

@@ -24,18 +24,17 @@ struct GemmDesc {
 void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int sta, int stb,
                    int opa, int opb, bool herm, hipStream_t s);
 
-// One matrix of a batched in-place Hermitian-positive-definite inverse.
+// One matrix of a batched Hermitian-positive-definite inverse.
 struct HpdDesc {
-  cd* G;        // n_pad x n_pad column-major, ld = n_pad; rows/cols >= n hold identity
-  int n_pad;
-  cd* D;        // scratch nb x nb
-  cd* R;        // scratch nb x n_pad
-  cd* Cp;       // scratch n_pad x nb
+  cd* G;        // n_pad x n_pad column-major, ld = n_pad; rows/cols >= n hold identity.
+                // In: the matrix.  Out: its inverse (both triangles).
+  int n_pad;    // multiple of HPD_NB
+  cd* D;        // scratch NB x n_pad: inverses of the diagonal Cholesky blocks
+  cd* X;        // scratch n_pad x n_pad: X = L^{-1}
 };
 constexpr int HPD_NB = 32;
-// In-place inverse by blocked Gauss-Jordan elimination without pivoting
-// (valid for Hermitian positive definite input).  *d_fail is set non-zero if
-// a pivot is not positive (loss of definiteness).
+// G <- G^{-1} through the Cholesky factor G = L L^H: X = L^{-1}, G^{-1} = X^H X.
+// *d_fail is set non-zero if a pivot is not positive (loss of definiteness).
 void hpd_inverse_batched(const HpdDesc* d_desc, int batch, int max_npad, int* d_fail,
                          hipStream_t s);
 

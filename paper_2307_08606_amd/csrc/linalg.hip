@@ -7,6 +7,8 @@
 // the optimality re-check puts them back.  MI355X runs FP64 FMA on the vector
 // units at the same peak as FP64 matrix instructions, so these are plain
 // register-blocked FMA kernels.
+#include <algorithm>
+
 #include "linalg.h"
 
 namespace {
@@ -104,131 +106,276 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
   }
 }
 
-// ------------------------------------------------------------------ Gauss-Jordan
-// Pivot block inverse: P = G[k0:k0+NB, k0:k0+NB] -> D = P^{-1}, in LDS.
-__global__ __launch_bounds__(256) void gj_diag_kernel(const HpdDesc* __restrict__ descs, int k0,
-                                                      int* fail) {
+// ------------------------------------------------------------------ HPD inverse
+// W = G^{-1} for Hermitian positive definite G through its Cholesky factor:
+//   1. blocked right-looking Cholesky G = L L^H (NB x NB diagonal blocks
+//      factored in LDS, panel solve, rank-NB trailing update of the lower part)
+//   2. X = L^{-1} by blocked forward substitution, block row by block row
+//   3. W = X^H X
+// All steps in FP64.  (Gauss-Jordan elimination without pivoting is
+// unstable on the strongly correlated Gram matrices of radar operators.)
+
+// Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS; write
+// Lkk into G (upper part zeroed) and Lkk^{-1} into Dinv[:, k0:k0+NB].
+__global__ __launch_bounds__(256) void chol_diag_kernel(const HpdDesc* __restrict__ descs, int k0,
+                                                        int* fail) {
   const HpdDesc h = descs[blockIdx.x];
   if (k0 >= h.n_pad) return;
   constexpr int NB = HPD_NB;
-  __shared__ cd P[NB][NB + 1];   // P[col][row]
-  __shared__ cd prow[NB], pcol[NB];
+  __shared__ cd P[NB][NB + 1];    // P[c][r] = element (r, c)
+  __shared__ cd Li[NB][NB + 1];   // Li[c][r] = element (r, c) of Lkk^{-1}
+  __shared__ double sdiag;
   const int t = threadIdx.x;
   for (int e = t; e < NB * NB; e += 256) {
     const int r = e % NB, c = e / NB;
     P[c][r] = h.G[(int64_t)(k0 + c) * h.n_pad + k0 + r];
   }
   __syncthreads();
-  for (int piv = 0; piv < NB; ++piv) {
-    const double p = P[piv][piv].re;
-    if (t == 0 && !(p > 0.0)) atomicOr(fail, 1);
-    const double ip = 1.0 / p;
-    if (t < NB) { prow[t] = P[t][piv]; pcol[t] = P[piv][t]; }
+  for (int c = 0; c < NB; ++c) {
+    if (t == 0) {
+      const double d = P[c][c].re;
+      if (!(d > 0.0)) atomicOr(fail, 1);
+      sdiag = sqrt(fmax(d, 1e-300));
+    }
+    __syncthreads();
+    const double sd = sdiag;
+    if (t > c && t < NB) P[c][t] = cscale(P[c][t], 1.0 / sd);   // column c below the diagonal
+    if (t == c) P[c][c] = {sd, 0.0};
     __syncthreads();
     for (int e = t; e < NB * NB; e += 256) {
-      const int r = e % NB, c = e / NB;
-      cd v = P[c][r];
-      if (r == piv && c == piv) {
-        v = {ip, 0.0};
-      } else if (r == piv) {
-        v = cscale(v, ip);                       // pivot row: P^{-1} G_kj
-      } else if (c == piv) {
-        v = cscale(v, -ip);                      // pivot column: -G_ik P^{-1}
-      } else {
-        cd prod = cmul(pcol[r], prow[c]);        // G_ik * G_kj / p
-        v = csub(v, cscale(prod, ip));
+      const int r = e % NB, s2 = e / NB;
+      if (s2 > c && r >= s2) {
+        // (r, s2) -= L(r, c) conj(L(s2, c))
+        const cd a = P[c][r], b = P[c][s2];
+        cd v = P[s2][r];
+        v.re -= a.re * b.re + a.im * b.im;
+        v.im -= a.im * b.re - a.re * b.im;
+        P[s2][r] = v;
       }
-      P[c][r] = v;
     }
     __syncthreads();
   }
+  // column j of Lkk^{-1} by forward substitution (one thread per column)
+  if (t < NB) {
+    const int j = t;
+    for (int r = 0; r < j; ++r) Li[j][r] = {0.0, 0.0};
+    const double djj = P[j][j].re;
+    Li[j][j] = {1.0 / djj, 0.0};
+    for (int r = j + 1; r < NB; ++r) {
+      cd acc = {0.0, 0.0};
+      for (int k = j; k < r; ++k) cfma(acc, P[k][r], Li[j][k]);
+      Li[j][r] = cscale(acc, -1.0 / P[r][r].re);
+    }
+  }
+  __syncthreads();
   for (int e = t; e < NB * NB; e += 256) {
     const int r = e % NB, c = e / NB;
-    h.D[c * NB + r] = P[c][r];
+    h.G[(int64_t)(k0 + c) * h.n_pad + k0 + r] = (r >= c) ? P[c][r] : cd{0.0, 0.0};
+    h.D[(int64_t)(k0 + c) * NB + r] = Li[c][r];
   }
 }
 
-// R = D * G[k0:k0+NB, :] with R[:, k0:k0+NB] = D; Cp = G[:, k0:k0+NB].
-__global__ __launch_bounds__(256) void gj_panel_kernel(const HpdDesc* __restrict__ descs, int k0) {
+// Panel: L[i, kb] = G[i, kb] Lkk^{-H} for rows i >= k0 + NB (in place).
+__global__ __launch_bounds__(256) void chol_panel_kernel(const HpdDesc* __restrict__ descs, int k0) {
   const HpdDesc h = descs[blockIdx.y];
   constexpr int NB = HPD_NB;
   if (k0 >= h.n_pad) return;
-  __shared__ cd Ds[NB][NB + 1];
+  __shared__ cd Ls[NB][NB + 1];   // Ls[c][r] = element (r, c) of Lkk^{-1}
   const int t = threadIdx.x;
-  for (int e = t; e < NB * NB; e += 256) Ds[e / NB][e % NB] = h.D[e];
+  for (int e = t; e < NB * NB; e += 256) Ls[e / NB][e % NB] = h.D[(int64_t)k0 * NB + e];
   __syncthreads();
-  const int j = blockIdx.x * 256 + t;
-  if (j >= h.n_pad) return;
-  if (j >= k0 && j < k0 + NB) {
-    for (int r = 0; r < NB; ++r) h.R[(int64_t)j * NB + r] = Ds[j - k0][r];
-  } else {
-    cd g[NB];
-    for (int c = 0; c < NB; ++c) g[c] = h.G[(int64_t)j * h.n_pad + k0 + c];
-    for (int r = 0; r < NB; ++r) {
-      cd acc = {0.0, 0.0};
-      for (int c = 0; c < NB; ++c) cfma(acc, Ds[c][r], g[c]);
-      h.R[(int64_t)j * NB + r] = acc;
-    }
+  const int i = k0 + NB + blockIdx.x * 256 + t;
+  if (i >= h.n_pad) return;
+  cd g[NB];
+  for (int s2 = 0; s2 < NB; ++s2) g[s2] = h.G[(int64_t)(k0 + s2) * h.n_pad + i];
+  for (int c = 0; c < NB; ++c) {
+    cd acc = {0.0, 0.0};
+    for (int s2 = 0; s2 <= c; ++s2) cfmac(acc, Ls[s2][c], g[s2]);   // g[s2] * conj(Linv(c, s2))
+    h.G[(int64_t)(k0 + c) * h.n_pad + i] = acc;
   }
-  // column panel copy (row j of G[:, k0:k0+NB])
-  for (int c = 0; c < NB; ++c) h.Cp[(int64_t)c * h.n_pad + j] = h.G[(int64_t)(k0 + c) * h.n_pad + j];
 }
 
-// G[i,j] <- rows in block: R[i-k0, j];  others: (j in block ? 0 : G[i,j]) - Cp[i,:] R[:,j]
-__global__ __launch_bounds__(256) void gj_update_kernel(const HpdDesc* __restrict__ descs, int k0) {
+// Trailing update of the lower part: G[i, j] -= L[i, kb] L[j, kb]^H,
+// i >= j >= k0 + NB.  K = NB in two halves (33 KB of LDS).
+__global__ __launch_bounds__(256) void chol_update_kernel(const HpdDesc* __restrict__ descs, int k0) {
   const HpdDesc h = descs[blockIdx.z];
   constexpr int NB = HPD_NB;
-  const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TN;
-  if (k0 >= h.n_pad || i0 >= h.n_pad || j0 >= h.n_pad) return;
-  __shared__ cd sC[NB][TM + 1];
-  __shared__ cd sR[NB][TN + 1];
+  constexpr int HB = NB / 2;
+  const int ti = blockIdx.x, tj = blockIdx.y;
+  if (tj > ti) return;
+  const int base = k0 + NB;
+  const int i0 = base + ti * TM, j0 = base + tj * TN;
+  if (i0 >= h.n_pad || j0 >= h.n_pad) return;
+  __shared__ cd sC[HB][TM + 1];
+  __shared__ cd sR[HB][TN + 1];
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
-  for (int e = t; e < NB * TM; e += 256) {
-    const int ii = e % TM, c = e / TM;
-    const int gi = i0 + ii;
-    sC[c][ii] = gi < h.n_pad ? h.Cp[(int64_t)c * h.n_pad + gi] : cd{0.0, 0.0};
-  }
-  for (int e = t; e < NB * TN; e += 256) {
-    const int r = e % NB, jj = e / NB;
-    const int gj = j0 + jj;
-    sR[r][jj] = gj < h.n_pad ? h.R[(int64_t)gj * NB + r] : cd{0.0, 0.0};
-  }
-  __syncthreads();
   cd acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = {0.0, 0.0};
+  for (int h0 = 0; h0 < NB; h0 += HB) {
+    for (int e = t; e < HB * TM; e += 256) {
+      const int ii = e % TM, c = e / TM;
+      const int gi = i0 + ii;
+      sC[c][ii] = gi < h.n_pad ? h.G[(int64_t)(k0 + h0 + c) * h.n_pad + gi] : cd{0.0, 0.0};
+    }
+    for (int e = t; e < HB * TN; e += 256) {
+      const int jj = e % TN, c = e / TN;
+      const int gj = j0 + jj;
+      cd v = gj < h.n_pad ? h.G[(int64_t)(k0 + h0 + c) * h.n_pad + gj] : cd{0.0, 0.0};
+      v.im = -v.im;
+      sR[c][jj] = v;
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int c = 0; c < NB; ++c) {
-    cd av[4], bv[4];
+    for (int c = 0; c < HB; ++c) {
+      cd av[4], bv[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = sC[c][tx + 16 * a];
+      for (int a = 0; a < 4; ++a) av[a] = sC[c][tx + 16 * a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = sR[c][ty + 16 * b];
+      for (int b = 0; b < 4; ++b) bv[b] = sR[c][ty + 16 * b];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+        for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int i = i0 + tx + 16 * a;
     if (i >= h.n_pad) continue;
-    const bool irow = (i >= k0 && i < k0 + NB);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j = j0 + ty + 16 * b;
-      if (j >= h.n_pad) continue;
+      if (j >= h.n_pad || j > i) continue;
       cd* g = h.G + (int64_t)j * h.n_pad + i;
-      if (irow) {
-        *g = sR[i - k0][j - j0];
-      } else {
-        const bool jcol = (j >= k0 && j < k0 + NB);
-        cd base = jcol ? cd{0.0, 0.0} : *g;
-        *g = csub(base, acc[a][b]);
-      }
+      *g = csub(*g, acc[a][b]);
+    }
+  }
+}
+
+// Block row ib of X = L^{-1} (X zero-initialised, lower triangular):
+//   X[ib, jb] = -Lib,ib^{-1} sum_{k = jb..ib-1} L[ib, k] X[k, jb]   (jb < ib)
+//   X[ib, ib] = Lib,ib^{-1}
+// One work-group per NB x NB output tile.
+__global__ __launch_bounds__(256) void trtri_row_kernel(const HpdDesc* __restrict__ descs, int i0) {
+  const HpdDesc h = descs[blockIdx.y];
+  constexpr int NB = HPD_NB;
+  if (i0 >= h.n_pad) return;
+  const int j0 = blockIdx.x * NB;
+  if (j0 > i0) return;
+  __shared__ cd sL[NB][NB + 1];   // sL[k][r] = L(i0 + r, k0 + k)
+  __shared__ cd sX[NB][NB + 1];   // sX[c][k] = X(k0 + k, j0 + c)
+  __shared__ cd sT[NB][NB + 1];   // sT[c][r] = T(r, c)
+  const int t = threadIdx.x;
+  cd* X = h.X;
+  if (j0 == i0) {
+    for (int e = t; e < NB * NB; e += 256) {
+      const int r = e % NB, c = e / NB;
+      X[(int64_t)(i0 + c) * h.n_pad + i0 + r] = h.D[(int64_t)(i0 + c) * NB + r];
+    }
+    return;
+  }
+  // each thread owns 4 outputs: rows r = t % NB, columns c = t / NB + 8 * q4
+  const int r = t % NB, cb = t / NB;
+  cd acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  for (int k0 = j0; k0 < i0; k0 += NB) {
+    for (int e = t; e < NB * NB; e += 256) {
+      const int rr = e % NB, cc = e / NB;
+      sL[cc][rr] = h.G[(int64_t)(k0 + cc) * h.n_pad + i0 + rr];
+      sX[cc][rr] = X[(int64_t)(j0 + cc) * h.n_pad + k0 + rr];
+    }
+    __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+      const cd lv = sL[k][r];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) cfma(acc[q4], lv, sX[cb + 8 * q4][k]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) sT[cb + 8 * q4][r] = acc[q4];
+  for (int e = t; e < NB * NB; e += 256) {
+    const int rr = e % NB, cc = e / NB;
+    sL[cc][rr] = h.D[(int64_t)(i0 + cc) * NB + rr];     // Lii^{-1}
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) {
+    const int c = cb + 8 * q4;
+    cd v = {0.0, 0.0};
+    for (int s2 = 0; s2 <= r; ++s2) cfma(v, sL[s2][r], sT[c][s2]);
+    X[(int64_t)(j0 + c) * h.n_pad + i0 + r] = {-v.re, -v.im};
+  }
+}
+
+__global__ void zero_x_kernel(const HpdDesc* __restrict__ descs) {
+  const HpdDesc h = descs[blockIdx.y];
+  const int64_t n2 = (int64_t)h.n_pad * h.n_pad;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (int64_t)gridDim.x * 256)
+    h.X[e] = {0.0, 0.0};
+}
+
+// W = X^H X into G (lower tiles computed, mirrored to the upper part).
+__global__ __launch_bounds__(256) void xhx_kernel(const HpdDesc* __restrict__ descs) {
+  const HpdDesc h = descs[blockIdx.z];
+  const int ti = blockIdx.x, tj = blockIdx.y;
+  if (tj > ti) return;
+  const int i0 = ti * TM, j0 = tj * TN;
+  if (i0 >= h.n_pad || j0 >= h.n_pad) return;
+  __shared__ cd sA[TK][TM + 1];
+  __shared__ cd sB[TK][TN + 1];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  cd acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = {0.0, 0.0};
+  // W[i, j] = sum_k conj(X[k, i]) X[k, j]; X lower triangular: k >= max(i, j) >= j0
+  for (int p0 = (j0 / TK) * TK; p0 < h.n_pad; p0 += TK) {
+    for (int e = t; e < TK * TM; e += 256) {
+      const int pp = e % TK, ii = e / TK;
+      const int gi = i0 + ii, gp = p0 + pp;
+      cd v = (gi < h.n_pad && gp < h.n_pad) ? h.X[(int64_t)gi * h.n_pad + gp] : cd{0.0, 0.0};
+      v.im = -v.im;
+      sA[pp][ii] = v;
+    }
+    for (int e = t; e < TK * TN; e += 256) {
+      const int pp = e % TK, jj = e / TK;
+      const int gj = j0 + jj, gp = p0 + pp;
+      sB[pp][jj] = (gj < h.n_pad && gp < h.n_pad) ? h.X[(int64_t)gj * h.n_pad + gp] : cd{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      cd av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sA[kk][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = sB[kk][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + tx + 16 * a;
+    if (i >= h.n_pad) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + ty + 16 * b;
+      if (j >= h.n_pad || j > i) continue;
+      cd v = acc[a][b];
+      if (i == j) v.im = 0.0;
+      h.G[(int64_t)j * h.n_pad + i] = v;
+      if (i != j) h.G[(int64_t)i * h.n_pad + j] = {v.re, -v.im};
     }
   }
 }
@@ -292,12 +439,20 @@ void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int 
 void hpd_inverse_batched(const HpdDesc* d_desc, int batch, int max_npad, int* d_fail,
                          hipStream_t s) {
   if (batch <= 0 || max_npad <= 0) return;
-  const int tiles = (max_npad + TM - 1) / TM;
+  zero_x_kernel<<<dim3(std::min<int64_t>(((int64_t)max_npad * max_npad + 255) / 256, 4096), batch), 256, 0, s>>>(d_desc);
   for (int k0 = 0; k0 < max_npad; k0 += HPD_NB) {
-    gj_diag_kernel<<<batch, 256, 0, s>>>(d_desc, k0, d_fail);
-    gj_panel_kernel<<<dim3((max_npad + 255) / 256, batch), 256, 0, s>>>(d_desc, k0);
-    gj_update_kernel<<<dim3(tiles, tiles, batch), 256, 0, s>>>(d_desc, k0);
+    chol_diag_kernel<<<batch, 256, 0, s>>>(d_desc, k0, d_fail);
+    const int rest = max_npad - k0 - HPD_NB;
+    if (rest > 0) {
+      chol_panel_kernel<<<dim3((rest + 255) / 256, batch), 256, 0, s>>>(d_desc, k0);
+      const int tiles = (rest + TM - 1) / TM;
+      chol_update_kernel<<<dim3(tiles, tiles, batch), 256, 0, s>>>(d_desc, k0);
+    }
   }
+  for (int i0 = 0; i0 < max_npad; i0 += HPD_NB)
+    trtri_row_kernel<<<dim3(i0 / HPD_NB + 1, batch), 256, 0, s>>>(d_desc, i0);
+  const int tiles = (max_npad + TM - 1) / TM;
+  xhx_kernel<<<dim3(tiles, tiles, batch), 256, 0, s>>>(d_desc);
 }
 
 void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, int n, bool to_float,
@@ -310,3 +465,4 @@ void set_identity_pad(cd* G, int n, int n_pad, double diag_add, hipStream_t s) {
   if (n_pad <= 0) return;
   identity_pad_kernel<<<dim3((n_pad + 255) / 256, n_pad), 256, 0, s>>>(G, n, n_pad, diag_add);
 }
+

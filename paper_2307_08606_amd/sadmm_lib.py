@@ -80,12 +80,17 @@ sadmm_solve = _sig("sadmm_solve", C.c_int, _H, _P, C.c_int32, C.c_int32, C.POINT
 sadmm_get_image = _sig("sadmm_get_image", C.c_int, _H, _P, C.c_int32, C.c_int32)
 sadmm_get_sensor_image = _sig("sadmm_get_sensor_image", C.c_int, _H, C.c_int32, _P, C.c_int32,
                               C.c_int32)
+sadmm_get_dual = _sig("sadmm_get_dual", C.c_int, _H, _P, C.c_int32, C.c_int32)
+sadmm_get_factor = _sig("sadmm_get_factor", C.c_int, _H, C.c_int32, _P, _P)
 sadmm_get_active_mask = _sig("sadmm_get_active_mask", C.c_int, _H, C.c_int32, _P)
 sadmm_get_active_indices = _sig("sadmm_get_active_indices", C.c_int, _H, C.c_int32, _P, _P)
 sadmm_get_history = _sig("sadmm_get_history", C.c_int, _H, C.c_int32, _P, C.c_int32, _P)
 sadmm_matched_filter = _sig("sadmm_matched_filter", C.c_int, _H, _P, C.c_int32, C.c_int32, _P)
 sadmm_get_timing = _sig("sadmm_get_timing", C.c_int, _H, C.c_int32, C.POINTER(C.c_double))
+sadmm_set_profiling = _sig("sadmm_set_profiling", C.c_int, _H, C.c_int32)
+sadmm_get_kernel_stats = _sig("sadmm_get_kernel_stats", C.c_int, _H, C.c_int32, _P, _P, _P)
 sadmm_destroy = _sig("sadmm_destroy", None, _H)
+KERNEL_CLASSES = {"gram": 0, "inverse": 1, "fwd": 2, "wprod": 3, "xupd": 4, "pixel": 5}
 sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
 
 EXPORTED = [n for n in dir() if n.startswith("sadmm_") and callable(globals()[n])
@@ -148,7 +153,7 @@ class Solver:
 
     def _check(self, rc, create=False):
         if rc != SADMM_OK:
-            msg = "" if create else sadmm_last_error(self._h).decode()
+            msg = sadmm_last_error(None if create else self._h).decode()
             raise SadmmError(rc, msg)
 
     def close(self):
@@ -221,6 +226,18 @@ class Solver:
         self._check(sadmm_get_sensor_image(self._h, q, _ptr(out), _dtype_code(out), 0))
         return out
 
+    def dual(self, dtype=np.complex128) -> np.ndarray:
+        out = np.empty(self.N, dtype=dtype)
+        self._check(sadmm_get_dual(self._h, _ptr(out), _dtype_code(out), 0))
+        return out
+
+    def factor(self, q) -> np.ndarray:
+        km = self.K * self.M
+        out = np.empty((km, km), dtype=np.complex128, order="F")
+        n = C.c_int32(0)
+        self._check(sadmm_get_factor(self._h, q, _ptr(out), C.addressof(n)))
+        return out
+
     def active_mask(self, q) -> np.ndarray:
         out = np.empty(self.N, dtype=np.uint8)
         self._check(sadmm_get_active_mask(self._h, q, _ptr(out)))
@@ -246,6 +263,21 @@ class Solver:
         out = np.empty((self.Q, self.N), dtype=np.float64)
         self._check(sadmm_matched_filter(self._h, _ptr(y), _dtype_code(y), _on_device(y),
                                          _ptr(out)))
+        return out
+
+    def set_profiling(self, on=True):
+        self._check(sadmm_set_profiling(self._h, int(bool(on))))
+
+    def kernel_stats(self) -> dict:
+        """{class: (launches, total_ms, work)}; work in flops (gram, inverse) or bytes."""
+        out = {}
+        for name, k in KERNEL_CLASSES.items():
+            n = C.c_int32(0)
+            ms = C.c_double(0)
+            w = C.c_double(0)
+            self._check(sadmm_get_kernel_stats(self._h, k, C.addressof(n), C.addressof(ms),
+                                               C.addressof(w)))
+            out[name] = (n.value, ms.value, w.value)
         return out
 
     def timing(self) -> dict:

@@ -9,7 +9,8 @@ Recipe (all draws from one `numpy.random.default_rng(seed)`, in this order):
    L ~ U{2..6} pixels from the centre along one of the four grid directions
    (horizontal, vertical, two diagonals), clipped to the grid.
 2. Visibility (aspect-dependent scattering, Sec. IV).  Each target is seen by
-   a uniform number of sensors in {2..Q}, chosen without replacement, each
+   a uniform number of sensors in {2..Q} ({1} when Q = 1), chosen without
+   replacement, each
    with its own gain U(0.3, 1).  x_q[j] = amplitude * gain_q; a pixel covered
    by two targets keeps the larger value, so every entry stays in [0, 1].
 3. Noise.  Per sensor, sigma_w^2 = mean |A_q x_q|^2 / 10^(SNR/10); w_q is
@@ -72,7 +73,7 @@ def make_scene(g: Geometry, seed: int, n_targets: int, snr_db: float,
     shapes = [_target_pixels(rng, g.n_side, int(c), extended) for c in centres]
     x_true = np.zeros((Q, N))
     for t in range(n_targets):
-        count = int(rng.integers(2, Q + 1))
+        count = int(rng.integers(min(2, Q), Q + 1))
         seen = rng.choice(Q, size=count, replace=False)
         gains = rng.uniform(0.3, 1.0, size=count)
         for q, gq in zip(seen, gains):

@@ -1,0 +1,66 @@
+"""Writes the stored reference values of the benchmark workload using only the
+FP64 oracle (never the GPU path).
+
+    python tests/golden/make_refs.py
+
+Workload c2 (Q=8 sensors, M=8 Rx, K=256 samples, 128x128 pixels, 60
+point/extended targets, 15 dB), scene seed 100:
+  c2_seed100.json        lambda_max, lambda (= 0.2 lambda_max), oracle run info
+  c2_seed100_xref.npy    the optimum image x_ref (complex128, N): plain SADMM
+                         iterated until the primal residual reaches the FP64
+                         round-off floor (eps_rel = 1e-10 is below that floor,
+                         so the run ends at max_iter)
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from scenegen import CONFIGS, config_scene, steering  # noqa: E402
+
+
+def main(seed: int = 100, max_iter: int = 300):
+    cfg = CONFIGS["c2"]
+    sc = config_scene("c2", seed)
+    g = sc.geom
+    A = [steering(g, q) for q in range(g.Q)]
+    t0 = time.time()
+    lmax = oracle.lambda_max(A, sc.y, cfg["mu"], cfg["gamma"])
+    lam = cfg["lambda_frac"] * lmax
+    p = oracle.Params(mu=cfg["mu"], beta=cfg["beta"], gamma=cfg["gamma"], lam=lam,
+                      eps_abs=0.0, eps_rel=1e-10, max_iter=max_iter, stop=True)
+    R = oracle.solve(A, sc.y, p)
+    x_ref = R.z
+    # iterations the oracle needs to bring NMSE vs x_ref to 1e-3 (plain and pruned)
+    ks = {}
+    for name, prune in (("plain", False), ("pruned", True)):
+        q = oracle.Params(mu=cfg["mu"], beta=cfg["beta"], gamma=cfg["gamma"], lam=lam,
+                          eps_abs=0.0, eps_rel=cfg["eps_rel"], max_iter=200, stop=True,
+                          prune=prune, Kp=cfg["Kp"], eps_p=cfg["eps_p"])
+        Rq = oracle.solve(A, sc.y, q, x_ref=x_ref)
+        nm = Rq.history["nmse"]
+        ks[name] = dict(iters_to_eps_rel=Rq.iters,
+                        iters_to_nmse_1e3=next((i + 1 for i, v in enumerate(nm) if v <= 1e-3), None),
+                        final_nmse=nm[-1],
+                        final_max_active_frac=Rq.history["max_active_frac"][-1])
+    info = dict(workload="c2", seed=seed, lambda_max=lmax, lambda_frac=cfg["lambda_frac"],
+                lam=lam, mu=cfg["mu"], beta=cfg["beta"], gamma=cfg["gamma"],
+                x_ref_iters=R.iters, x_ref_final_r=R.history["r"][-1],
+                x_ref_final_eps_pri=R.history["eps_pri"][-1],
+                x_ref_nnz=int(np.count_nonzero(np.abs(x_ref) > 0)),
+                runs=ks, seconds=time.time() - t0)
+    np.save(os.path.join(HERE, f"c2_seed{seed}_xref.npy"), x_ref)
+    with open(os.path.join(HERE, f"c2_seed{seed}.json"), "w") as f:
+        json.dump(info, f, indent=1)
+    print(json.dumps(info, indent=1))
+
+
+if __name__ == "__main__":
+    main()
