@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct sadmm_s* sadmm_t;
+typedef struct sadmm_cnn_s* sadmm_cnn_t;
 
 typedef enum {
   SADMM_OK = 0,
@@ -183,6 +184,51 @@ int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_dev
  * which = 0 whole solve, 1 factor builds/updates, 2 iterations. */
 int sadmm_get_timing(sadmm_t h, int32_t which, double* ms);
 
+/* ---------------------------------------------------------------------------
+ * Learned pixel elimination.  A small CNN maps the Q matched-filter images
+ * |A_q^H y_q| (each H x W, pixel n = i*W + j, scaled by their common maximum)
+ * to a per-pixel probability that the pixel can be eliminated from every
+ * sensor's sub-problem before the solve (an initial selector P_q of eq. (3)).
+ * Layers: four 3x3 zero-padded convolutions Q -> C -> C -> C -> 1 with ReLU
+ * after the first three and a sigmoid output; FP32.  Parameters are one flat
+ * FP32 vector: W1 (C x Q x 3 x 3), b1 (C), W2 (C x C x 3 x 3), b2, W3, b3,
+ * W4 (1 x C x 3 x 3), b4 (1).  Training minimises the pixel-averaged weighted
+ * binary cross-entropy (positive pixels weighted by pos_weight) with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  The CNN only proposes eliminations: the
+ * solver's optimality re-check (params.kkt) reinstates false ones.
+ * ------------------------------------------------------------------------- */
+
+/* Creates a CNN for Q input channels, C hidden channels (C, Q <= 32) and H x W
+ * images on the given hipStream_t.  Parameters start at zero. */
+int sadmm_cnn_create(int32_t Q, int32_t C, int32_t H, int32_t W, void* stream,
+                     sadmm_cnn_t* out);
+/* Number of FP32 parameters. */
+int64_t sadmm_cnn_param_count(sadmm_cnn_t c);
+/* Copy parameters in / out (host buffers of param_count floats); setting them
+ * resets the Adam state. */
+int sadmm_cnn_set_params(sadmm_cnn_t c, const float* params, int64_t count);
+int sadmm_cnn_get_params(sadmm_cnn_t c, float* params, int64_t count);
+/* Probability map (H*W floats) of the input x (Q x H x W floats). */
+int sadmm_cnn_forward(sadmm_cnn_t c, const float* x, int32_t x_on_device, float* prob,
+                      int32_t prob_on_device);
+/* Loss and gradient (host buffer of param_count floats) for input x and
+ * target map (H*W floats, 1 = eliminate). */
+int sadmm_cnn_gradients(sadmm_cnn_t c, const float* x, const float* target, int32_t on_device,
+                        float pos_weight, float* grads, double* loss);
+/* One Adam step on (x, target); *loss receives the loss before the step. */
+int sadmm_cnn_train_step(sadmm_cnn_t c, const float* x, const float* target, int32_t on_device,
+                         float pos_weight, float lr, double* loss);
+void sadmm_cnn_destroy(sadmm_cnn_t c);
+const char* sadmm_cnn_last_error(sadmm_cnn_t c);
+
+/* Attach a CNN to a solver (NULL detaches).  Each later solve computes the
+ * matched-filter images of its y, runs the CNN, and eliminates from every
+ * sensor, before the factor build, the pixels whose probability is >=
+ * threshold (combined with any mask set by sadmm_set_active_mask).  The CNN's
+ * image size must be N pixels and its input channels Q; it must use the
+ * solver's stream.  Eliminated pixels are frozen at x = 0. */
+int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold);
+
 /* Kernel classes timed when profiling is on. */
 enum {
   SADMM_KC_GRAM = 0,     /* FP64 Gram Ahat Ahat^H of a factor build */
@@ -191,7 +237,8 @@ enum {
   SADMM_KC_WPROD = 3,    /* W t */
   SADMM_KC_XUPD = 4,     /* adjoint product Ahat^H w with the fused x-update */
   SADMM_KC_PIXEL = 5,    /* image/dual update, residuals, SSC check */
-  SADMM_KC_COUNT = 6
+  SADMM_KC_CNN = 6,      /* matched filter + CNN inference before a solve */
+  SADMM_KC_COUNT = 7
 };
 
 /* on != 0: record HIP events on the handle's stream around every launch of the

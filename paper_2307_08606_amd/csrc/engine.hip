@@ -26,6 +26,11 @@
 #include "linalg.h"
 #include "util.h"
 
+// provided by cnn.hip
+int sadmm_cnn_prob_from_mf(sadmm_cnn_t c, const double* mf_dev, const float** prob_dev);
+hipStream_t sadmm_cnn_stream(sadmm_cnn_t c);
+int sadmm_cnn_shape(sadmm_cnn_t c, int* Q, int* H, int* W);
+
 namespace {
 
 constexpr int KKT_ROUNDS = 8;
@@ -79,6 +84,9 @@ struct sadmm_s {
   int chunk = 256, nchunk = 0, nblk = 0;
   double xref_norm2 = 0.0, nmse_target = 0.0;
   bool have_ref = false;
+  sadmm_cnn_t cnn = nullptr;
+  double cnn_thr = 0.5;
+  int cnn_pruned = 0;            // pixels the CNN eliminated at the last solve
 
   // results of the last solve
   sadmm_info info{};
@@ -686,6 +694,26 @@ int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadm
   c0.max_iter = h->p.max_iter;
   *h->ctl_h = c0;
   HIPCHK(h, hipMemcpyAsync(h->ctl, h->ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  // ---- learned elimination (optional): matched filter -> CNN -> shared mask
+  std::vector<uint8_t> cnn_keep;
+  h->cnn_pruned = 0;
+  if (h->cnn) {
+    TRY(push_descs(h));
+    int pe = prof_begin(h);
+    launch_matched_filter(make_args(h), h->st, h->dbl, h->y, h->mf, s);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    const float* prob = nullptr;
+    if (sadmm_cnn_prob_from_mf(h->cnn, h->mf, &prob) != SADMM_OK)
+      return fail_msg(h, SADMM_E_HIP, "solve: CNN inference failed");
+    std::vector<float> ph(N);
+    HIPCHK(h, hipMemcpyAsync(ph.data(), prob, sizeof(float) * N, hipMemcpyDeviceToHost, sadmm_cnn_stream(h->cnn)));
+    HIPCHK(h, hipStreamSynchronize(sadmm_cnn_stream(h->cnn)));
+    prof_end(h, SADMM_KC_CNN, pe);
+    cnn_keep.assign(N, 1);
+    for (int n = 0; n < N; ++n)
+      if (ph[n] >= h->cnn_thr) { cnn_keep[n] = 0; h->cnn_pruned += 1; }
+  }
   // ---- selectors and compaction
   std::vector<int> rebuild;
   std::vector<int> Jh;
@@ -693,6 +721,8 @@ int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadm
     Jh.clear();
     std::vector<uint8_t> m(N, 1);
     if (!h->mask0[q].empty()) m = h->mask0[q];
+    if (!cnn_keep.empty())
+      for (int n = 0; n < N; ++n) m[n] = m[n] && cnn_keep[n];
     for (int n = 0; n < N; ++n)
       if (m[n]) Jh.push_back(n);
     h->nq[q] = (int)Jh.size();
@@ -946,6 +976,19 @@ int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_dev
   HIPCHK(h, hipStreamSynchronize(h->s));
   if (ystage) hipFree(ystage);
   h->solved = false;
+  return SADMM_OK;
+}
+
+int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold) {
+  if (!h) return SADMM_E_ARG;
+  if (!cnn) { h->cnn = nullptr; return SADMM_OK; }
+  int cq = 0, ch = 0, cw = 0;
+  sadmm_cnn_shape(cnn, &cq, &ch, &cw);
+  if (cq != h->Q || (int64_t)ch * cw != h->N)
+    return fail_msg(h, SADMM_E_SHAPE, "set_pruning_cnn: CNN shape does not match Q x N");
+  if (!(threshold > 0.0 && threshold <= 1.0)) return fail_msg(h, SADMM_E_ARG, "set_pruning_cnn: threshold");
+  h->cnn = cnn;
+  h->cnn_thr = threshold;
   return SADMM_OK;
 }
 

@@ -20,6 +20,11 @@ LIB_PATH = os.path.join(_HERE, "libsadmm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_08606_amd.build`")
 
+# PyTorch ships its own HIP runtime.  Import it before the library so that the
+# process holds one HIP runtime (the library then binds to the one already
+# loaded); loading the library first would bring in a second runtime.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 SADMM_OK, SADMM_E_ARG, SADMM_E_SHAPE, SADMM_E_STATE = 0, -1, -2, -3
@@ -90,7 +95,21 @@ sadmm_get_timing = _sig("sadmm_get_timing", C.c_int, _H, C.c_int32, C.POINTER(C.
 sadmm_set_profiling = _sig("sadmm_set_profiling", C.c_int, _H, C.c_int32)
 sadmm_get_kernel_stats = _sig("sadmm_get_kernel_stats", C.c_int, _H, C.c_int32, _P, _P, _P)
 sadmm_destroy = _sig("sadmm_destroy", None, _H)
-KERNEL_CLASSES = {"gram": 0, "inverse": 1, "fwd": 2, "wprod": 3, "xupd": 4, "pixel": 5}
+KERNEL_CLASSES = {"gram": 0, "inverse": 1, "fwd": 2, "wprod": 3, "xupd": 4, "pixel": 5, "cnn": 6}
+
+sadmm_cnn_create = _sig("sadmm_cnn_create", C.c_int, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                        C.c_void_p, C.POINTER(_H))
+sadmm_cnn_param_count = _sig("sadmm_cnn_param_count", C.c_int64, _H)
+sadmm_cnn_set_params = _sig("sadmm_cnn_set_params", C.c_int, _H, _P, C.c_int64)
+sadmm_cnn_get_params = _sig("sadmm_cnn_get_params", C.c_int, _H, _P, C.c_int64)
+sadmm_cnn_forward = _sig("sadmm_cnn_forward", C.c_int, _H, _P, C.c_int32, _P, C.c_int32)
+sadmm_cnn_gradients = _sig("sadmm_cnn_gradients", C.c_int, _H, _P, _P, C.c_int32, C.c_float, _P,
+                           C.POINTER(C.c_double))
+sadmm_cnn_train_step = _sig("sadmm_cnn_train_step", C.c_int, _H, _P, _P, C.c_int32, C.c_float,
+                            C.c_float, C.POINTER(C.c_double))
+sadmm_cnn_destroy = _sig("sadmm_cnn_destroy", None, _H)
+sadmm_cnn_last_error = _sig("sadmm_cnn_last_error", C.c_char_p, _H)
+sadmm_set_pruning_cnn = _sig("sadmm_set_pruning_cnn", C.c_int, _H, _H, C.c_double)
 sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
 
 EXPORTED = [n for n in dir() if n.startswith("sadmm_") and callable(globals()[n])
@@ -265,6 +284,10 @@ class Solver:
                                          _ptr(out)))
         return out
 
+    def set_pruning_cnn(self, cnn, threshold=0.5):
+        self._cnn = cnn
+        self._check(sadmm_set_pruning_cnn(self._h, cnn._h if cnn is not None else None, threshold))
+
     def set_profiling(self, on=True):
         self._check(sadmm_set_profiling(self._h, int(bool(on))))
 
@@ -287,3 +310,92 @@ class Solver:
             self._check(sadmm_get_timing(self._h, i, C.byref(v)))
             out[k] = v.value
         return out
+
+
+# ---------------------------------------------------------------- CNN
+CNN_LAYERS = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+
+
+class Cnn:
+    """Pixel-pruning CNN handle (sadmm_cnn_*).  Parameters are exchanged as a
+    dict {W1, b1, ..., W4, b4} of arrays with the shapes of the C header."""
+
+    def __init__(self, Q, channels, H, W, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.Q, self.C, self.H, self.W = Q, channels, H, W
+        self._h = _H()
+        rc = sadmm_cnn_create(Q, channels, H, W, C_void(stream), C.byref(self._h))
+        if rc != SADMM_OK:
+            raise SadmmError(rc, "sadmm_cnn_create failed")
+        self.n = int(sadmm_cnn_param_count(self._h))
+
+    def shapes(self):
+        Q, Cc = self.Q, self.C
+        return {"W1": (Cc, Q, 3, 3), "b1": (Cc,), "W2": (Cc, Cc, 3, 3), "b2": (Cc,),
+                "W3": (Cc, Cc, 3, 3), "b3": (Cc,), "W4": (1, Cc, 3, 3), "b4": (1,)}
+
+    def flatten(self, params) -> np.ndarray:
+        return np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k in CNN_LAYERS])
+
+    def unflatten(self, flat) -> dict:
+        out, o = {}, 0
+        for k in CNN_LAYERS:
+            shp = self.shapes()[k]
+            sz = int(np.prod(shp))
+            out[k] = np.asarray(flat[o:o + sz]).reshape(shp)
+            o += sz
+        return out
+
+    def _check(self, rc):
+        if rc != SADMM_OK:
+            raise SadmmError(rc, sadmm_cnn_last_error(self._h).decode())
+
+    def set_params(self, params):
+        f = np.ascontiguousarray(self.flatten(params) if isinstance(params, dict) else params,
+                                 dtype=np.float32)
+        assert f.size == self.n
+        self._check(sadmm_cnn_set_params(self._h, _ptr(f), self.n))
+
+    def get_params(self) -> dict:
+        f = np.empty(self.n, np.float32)
+        self._check(sadmm_cnn_get_params(self._h, _ptr(f), self.n))
+        return self.unflatten(f)
+
+    def forward(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        out = np.empty((self.H, self.W), np.float32)
+        self._check(sadmm_cnn_forward(self._h, _ptr(x), 0, _ptr(out), 0))
+        return out
+
+    def gradients(self, x, target, pos_weight):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        g = np.empty(self.n, np.float32)
+        loss = C.c_double(0)
+        self._check(sadmm_cnn_gradients(self._h, _ptr(x), _ptr(t), 0, pos_weight, _ptr(g),
+                                        C.byref(loss)))
+        return self.unflatten(g), loss.value
+
+    def train_step(self, x, target, pos_weight, lr) -> float:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        loss = C.c_double(0)
+        self._check(sadmm_cnn_train_step(self._h, _ptr(x), _ptr(t), 0, pos_weight, lr,
+                                         C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self._h:
+            sadmm_cnn_destroy(self._h)
+            self._h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def C_void(v):
+    return C.c_void_p(int(v) if v else None)

@@ -1,0 +1,99 @@
+"""GPU CNN kernels vs the FP64 CNN oracle, and the CNN-driven initial selector
+of the solver.  FP32 kernels: probabilities within 1e-5 absolute, gradients
+within 1e-4 relative (norm) of the FP64 reference."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn as ocnn
+from scenegen import make_geometry, make_scene, steering
+
+pytestmark = pytest.mark.gpu
+
+
+def rnd_problem(Q=3, C=8, H=20, W=23, seed=0):
+    rng = np.random.default_rng(seed)
+    p = ocnn.init_params(Q, C, seed=seed)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+    x = np.abs(rng.standard_normal((Q, H, W)))
+    t = (rng.random((H, W)) > 0.7).astype(np.float64)
+    return p, x, t
+
+
+def test_cnn_forward_matches_oracle(gpu_lib):
+    """Ragged tiles: 20 x 23 is not a multiple of the 16 x 16 tile."""
+    p, x, _ = rnd_problem()
+    c = gpu_lib.Cnn(3, 8, 20, 23)
+    c.set_params(p)
+    got = c.forward(x)
+    ref, _ = ocnn.forward(p, x)
+    assert np.abs(got - ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("Q,C,H,W", [(3, 8, 20, 23), (8, 32, 32, 32)])
+def test_cnn_gradients_match_oracle(gpu_lib, Q, C, H, W):
+    p, x, t = rnd_problem(Q, C, H, W, seed=Q + C)
+    c = gpu_lib.Cnn(Q, C, H, W)
+    c.set_params(p)
+    g, loss = c.gradients(x, t, 3.0)
+    prob, cache = ocnn.forward(p, x)
+    gr = ocnn.backward(p, cache, t, 3.0)
+    assert loss == pytest.approx(ocnn.bce_loss(prob, t, 3.0), rel=1e-5)
+    for k in gr:
+        err = np.linalg.norm(g[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
+        assert err < 1e-4, (k, err)
+
+
+def test_cnn_adam_step_matches_oracle(gpu_lib):
+    p, x, t = rnd_problem(seed=5)
+    c = gpu_lib.Cnn(3, 8, 20, 23)
+    c.set_params(p)
+    g, _ = c.gradients(x, t, 2.0)
+    c.train_step(x, t, 2.0, 1e-3)
+    got = c.get_params()
+    ref = {k: v.copy() for k, v in p.items()}
+    ocnn.Adam(ref, lr=1e-3).step(ref, {k: v.astype(np.float64) for k, v in g.items()})
+    for k in ref:
+        assert np.abs(got[k] - ref[k]).max() < 1e-6, k
+
+
+def test_cnn_training_reduces_loss(gpu_lib):
+    p, x, t = rnd_problem(seed=6)
+    c = gpu_lib.Cnn(3, 8, 20, 23)
+    c.set_params(p)
+    losses = [c.train_step(x, t, 2.0, 1e-2) for _ in range(60)]
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_solver_uses_cnn_selector(gpu_lib):
+    """The solver eliminates exactly the pixels whose CNN probability is >= the
+    threshold, from every sensor (decisions within 1e-6 of the threshold are
+    not asserted), and then matches the oracle run with that initial selector
+    (FP64, no SSC, so the final selector is the initial one)."""
+    g = make_geometry(3, 4, 32, 16)
+    sc = make_scene(g, 3, 5, 20.0)
+    A = [steering(g, q) for q in range(3)]
+    lam = 0.2 * oracle.lambda_max(A, sc.y, 1.0, 1.0)
+    p = ocnn.init_params(3, 8, seed=9)
+    c = gpu_lib.Cnn(3, 8, 16, 16)
+    c.set_params(p)
+    mf = oracle.matched_filter(A, sc.y).reshape(3, 16, 16)
+    prob = c.forward(ocnn.normalize_input(mf)).reshape(-1)
+    thr = float(np.quantile(prob, 0.4))
+    s = gpu_lib.Solver(3, 32, 4, g.N, storage="fp64", lam=lam, max_iter=40, stop=False)
+    for q in range(3):
+        s.set_operator(q, A[q])
+    s.set_pruning_cnn(c, thr)
+    s.solve(sc.y)
+    keep = prob < thr
+    sure = np.abs(prob - thr) > 1e-6
+    masks = np.stack([s.active_mask(q).astype(bool) for q in range(3)])
+    assert (~masks).sum() > 0
+    for q in range(3):
+        assert np.array_equal(masks[q][sure], keep[sure])
+    ref = oracle.solve(A, sc.y, oracle.Params(lam=lam, max_iter=40, stop=False), mask0=masks)
+    z = s.image()
+    assert np.linalg.norm(z - ref.z) <= 1e-8 * np.linalg.norm(ref.z)
