@@ -5,8 +5,8 @@
 //             per sadmm_storage (ldA slots per column)
 //   Ahat[q]   active columns of A_q in ascending pixel order (the compacted
 //             A_q P_q^T of eq. (3)); aliases Afull[q] while every pixel is active
-//   W64[q]    ((c/mu) I + Ahat Ahat^H)^{-1}, complex128 KMp x KMp (master copy)
-//   W[q]      the same in compute precision, applied every iteration
+//   W64[q]    ((c/mu) I + Ahat Ahat^H)^{-1}, complex128 KMp x KMp, applied every
+//             iteration in FP64 (see the W product in iter.hip)
 //   X, dX     Q x N compute-precision complex, sensor-major
 //   xbar,z,u  N complex;  D  Kp x Q x N ring of |x^(i) - x^(i-1)|
 //   y, yp     Q x KMp complex128 measurements and y' (frozen pixels removed)
@@ -226,7 +226,7 @@ int push_descs(sadmm_t h) {
     d.Afull = h->Afull[q];
     d.J = h->J[q];
     d.xy = h->xy[q];
-    d.W = h->Wc[q];
+    d.W = h->W64[q];
     d.W64 = h->W64[q];
     d.lda = h->ldA;
     d.nq = h->nq[q];
@@ -288,10 +288,7 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
   hpd_inverse_batched(h->hpd_d, (int)qs.size(), h->KMp, h->fail, h->s);
   prof_end(h, SADMM_KC_INVERSE, pe);
   HIPCHK(h, hipGetLastError());
-  for (int q : qs) {
-    cast_hermitian(h->W64[q], h->KMp, h->Wc[q], h->KMp, h->KMp, !h->dbl, h->s);
-    h->fac_valid[q] = true;
-  }
+  for (int q : qs) h->fac_valid[q] = true;
   HIPCHK(h, hipGetLastError());
   return check_fail(h);
 }
@@ -323,7 +320,7 @@ int lowrank_update(sadmm_t h, int q, const int* d_list, int r, int sign) {
   hpd_inverse_batched(h->hpd_d, 1, rp, h->fail, h->s);
   zgemm_batched(h->gemm_d + 2, 1, KMp, r, ST_FP64, ST_FP64, OP_N, OP_N, false, h->s);
   zgemm_batched(h->gemm_d + 3, 1, KMp, KMp, ST_FP64, ST_FP64, OP_N, OP_C, false, h->s);
-  cast_hermitian(h->W64[q], KMp, h->Wc[q], KMp, KMp, !h->dbl, h->s);
+  hermitian_inplace(h->W64[q], KMp, KMp, h->s);
   HIPCHK(h, hipGetLastError());
   h->info.updates += 1;
   return check_fail(h);
@@ -496,7 +493,6 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   for (int q = 0; q < Q; ++q) {
     A_(dalloc(h, &h->Afull[q], (size_t)h->ldA * h->slot * N));
     A_(dalloc_t(h, &h->W64[q], sizeof(cd) * (size_t)KMp * KMp));
-    A_(dalloc(h, &h->Wc[q], h->csz * (size_t)KMp * KMp));
     A_(dalloc_t(h, &h->J[q], sizeof(int) * N));
     A_(dalloc_t(h, &h->Jnew[q], sizeof(int) * N));
     A_(dalloc(h, &h->xy[q], cN));
@@ -768,7 +764,7 @@ int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadm
           for (int q = 0; q < Q; ++q) nqs += h->nq[q];
           const double KM = h->KM;
           prof_work(h, SADMM_KC_FWD, nqs * KM * ob + nqs * 4 * cz + Q * KM * cz);
-          prof_work(h, SADMM_KC_WPROD, Q * (KM * KM * cz + 2 * KM * cz));
+          prof_work(h, SADMM_KC_WPROD, Q * (KM * KM * 16.0 + 2 * KM * cz));
           prof_work(h, SADMM_KC_XUPD, nqs * KM * ob + Q * KM * cz + nqs * (7 * cz + cz / 2));
           prof_work(h, SADMM_KC_PIXEL, (double)Q * N * 2 * cz + (double)N * 6 * cz);
         }

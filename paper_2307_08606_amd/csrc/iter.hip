@@ -185,13 +185,15 @@ __device__ inline C2<TA> coldot_core(const void* col, const C2<TA>* sv, int KMp,
 // precision; the once-per-factor data term (WY, XY) and the certificate
 // products (KKT, MF) accumulate in FP64.
 template <int ST, int EPI> struct DotAcc {
-  using type = typename std::conditional<(EPI == EPI_W || EPI == EPI_XUPD),
-                                         typename Store<ST>::T, double>::type;
+  using type = typename std::conditional<(EPI == EPI_XUPD), typename Store<ST>::T, double>::type;
 };
 
-template <int ST, int EPI>
+// The W product always reads the FP64 factor and accumulates in FP64: W_q has
+// condition number (c/mu + s_max^2)/(c/mu) and rounding it to FP32 would put a
+// relative error of about 6e-8 * s_max^2 / (c/mu) on every x-update.
+template <int ST, int EPI, class TS = typename Store<ST>::T>
 __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
-  using T = typename Store<ST>::T;            // compute precision of the state
+  using T = TS;                               // compute precision of the state
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
   const int q = (EPI == EPI_KKT) ? x.q
@@ -210,7 +212,10 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
   // stage the vector operand
   for (int i = threadIdx.x; i < a.KMp; i += 256) {
     C2<TA> v;
-    if constexpr (EPI == EPI_W) v = ldc<TA>(a.t, (int64_t)q * a.KMp + i);
+    if constexpr (EPI == EPI_W) {
+      const C2<T> tv = ldc<T>(a.t, (int64_t)q * a.KMp + i);
+      v = {(TA)tv.re, (TA)tv.im};
+    }
     else if constexpr (EPI == EPI_XUPD) v = ldc<TA>(a.w, (int64_t)q * a.KMp + i);
     else if constexpr (EPI == EPI_XY) v = {a.wy[2 * ((int64_t)q * a.KMp + i)], a.wy[2 * ((int64_t)q * a.KMp + i) + 1]};
     else {
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
     const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
     if (p >= ncols) break;
     const void* col;
-    if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W, a.KMp, p);
+    if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_WY) col = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) col = col_ptr<ST>(sd.A, sd.lda, p);
     else if constexpr (EPI == EPI_KKT) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
     const C2<TA> d = coldot_core<ST, TA>(col, sv, a.KMp, lane);
     if (lane != 0) continue;
     if constexpr (EPI == EPI_W) {
-      stc<T>(a.w, (int64_t)q * a.KMp + p, d);
+      stc<T>(a.w, (int64_t)q * a.KMp + p, C2<T>{(T)d.re, (T)d.im});
     } else if constexpr (EPI == EPI_XUPD) {
       const int n = sd.J[p];
       const C2<T> v = shared_v<T>(a, q, n);
@@ -394,7 +399,6 @@ __global__ void ssc_flag_kernel(IterArgs a) {
 template <int ST>
 void run_iteration(const IterArgs& a, hipStream_t s, const std::function<void(int, bool)>* hook) {
   using T = typename Store<ST>::T;
-  constexpr int WST = std::is_same<T, double>::value ? ST_FP64 : ST_FP32;
   auto mark = [&](int stage, bool begin) { if (hook) (*hook)(stage, begin); };
   const int rows = FWD_THREADS * Store<ST>::RPT;
   dim3 gf((a.KMp + rows - 1) / rows, a.nchunk, a.Q);
@@ -406,7 +410,7 @@ void run_iteration(const IterArgs& a, hipStream_t s, const std::function<void(in
   const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
   DotExtra x{};
   mark(1, true);
-  coldot_kernel<WST, EPI_W><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+  coldot_kernel<ST_FP64, EPI_W, T><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256, a.KMp * sizeof(cd), s>>>(a, x);
   mark(1, false);
   mark(2, true);
   coldot_kernel<ST, EPI_XUPD><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);

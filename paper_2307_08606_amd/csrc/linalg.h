@@ -42,5 +42,8 @@ void hpd_inverse_batched(const HpdDesc* d_desc, int batch, int max_npad, int* d_
 void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, int n,
                     bool to_float, hipStream_t s);
 
+// G <- (G + G^H) / 2 in place (n x n, column-major, ld).
+void hermitian_inplace(cd* G, int64_t ld, int n, hipStream_t s);
+
 // G[i,i] += v for i < n; G[i,j] = (i==j) for n <= i or j < n_pad (identity padding).
 void set_identity_pad(cd* G, int n, int n_pad, double diag_add, hipStream_t s);

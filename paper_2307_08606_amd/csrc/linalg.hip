@@ -393,6 +393,18 @@ __global__ void cast_herm_kernel(const cd* __restrict__ src, int64_t lds, void* 
   else reinterpret_cast<double2*>(dst)[(int64_t)j * ldd + i] = make_double2(v.re, v.im);
 }
 
+__global__ void herm_inplace_kernel(cd* G, int64_t ld, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n || i < j) return;
+  cd* a = G + (int64_t)j * ld + i;
+  if (i == j) { a->im = 0.0; return; }
+  cd* b = G + (int64_t)i * ld + j;
+  const cd v = {0.5 * (a->re + b->re), 0.5 * (a->im - b->im)};
+  *a = v;
+  *b = {v.re, -v.im};
+}
+
 __global__ void identity_pad_kernel(cd* G, int n, int n_pad, double diag_add) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int j = blockIdx.y;
@@ -459,6 +471,11 @@ void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, in
                     hipStream_t s) {
   if (n <= 0) return;
   cast_herm_kernel<<<dim3((n + 255) / 256, n), 256, 0, s>>>(src, ld_src, dst, ld_dst, n, to_float ? 1 : 0);
+}
+
+void hermitian_inplace(cd* G, int64_t ld, int n, hipStream_t s) {
+  if (n <= 0) return;
+  herm_inplace_kernel<<<dim3((n + 255) / 256, n), 256, 0, s>>>(G, ld, n);
 }
 
 void set_identity_pad(cd* G, int n, int n_pad, double diag_add, hipStream_t s) {
