@@ -190,6 +190,27 @@ def main():
     roof["avg_launch_ms"] = round(ms / max(n, 1), 4)
     roof["work_per_launch"] = work / max(n, 1)
 
+    # matrix-free operator at 512 x 512 pixels (c5 geometry): steady-state rate
+    if not args.only:
+        from scenegen import config_geometry, make_scene
+        g5 = config_geometry("c5")
+        sc5 = make_scene(g5, 100, 600, 15.0, extended=True)
+        s5 = lib.Solver(g5.Q, g5.K, g5.M, g5.N, storage="mf", prune=False, reuse_factor=True,
+                        max_iter=10, stop=False, check_every=10, stream=stream, **hp)
+        for q in range(g5.Q):
+            s5.set_operator_geometry(q, g5.tx[q], g5.rx[q], g5.pix, g5.f0, g5.bw)
+        y5 = torch.from_numpy(np.ascontiguousarray(sc5.y)).to("cuda")
+        s5.solve(y5)                                 # factor build (one-time)
+        t5 = s5.timing()
+        s5.set_profiling(True)
+        s5.solve(y5)
+        t5b = s5.timing()
+        st5 = s5.kernel_stats()
+        s5.close()
+        el = 2.0 * g5.Q * g5.KM * g5.N               # generated entries per iteration
+        results["c5_mf"] = dict(factor_ms=t5["factor_ms"], iter_ms=t5b["iter_ms"] / 10,
+                                stats=st5, elems_per_iter=el)
+
     steady = results.get("steady")
     extra = {}
     if steady:
@@ -201,6 +222,11 @@ def main():
                 extra[f"{k}_GBps"] = round(ww / (mm * 1e-3) / 1e9, 1)
                 extra[f"{k}_hbm_frac"] = round(ww / (mm * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)
                 extra[f"{k}_avg_us"] = round(mm / nn * 1e3, 1)
+    if "c5_mf" in results:
+        r5 = results["c5_mf"]
+        extra["c5_matrix_free_factor_ms"] = round(r5["factor_ms"], 1)
+        extra["c5_matrix_free_iter_ms"] = round(r5["iter_ms"], 3)
+        extra["c5_matrix_free_Gelem_per_s"] = round(r5["elems_per_iter"] / (r5["iter_ms"] * 1e-3) / 1e9, 1)
     for name in ("pruned", "plain"):
         if name in results:
             r = results[name]

@@ -60,12 +60,17 @@ typedef enum { SADMM_C128 = 0, SADMM_C64 = 1 } sadmm_dtype;
 /* Storage and arithmetic of the operator.  FP64: complex128 storage and FP64
  * arithmetic throughout.  FP32: complex64 storage, FP32 arithmetic, FP64 factor
  * build.  FP16P / BF16P: operator stored as separate real and imaginary half /
- * bfloat16 planes per column, FP32 arithmetic, FP64 factor build. */
+ * bfloat16 planes per column, FP32 arithmetic, FP64 factor build.
+ * MATRIX_FREE: no operator entries are stored; every product regenerates the
+ * LFM steering entries of eq. (1) from per-pixel phase records (FP64 phase
+ * fraction, FP32 complex exponential); operators must be given by
+ * sadmm_set_operator_geometry. */
 typedef enum {
   SADMM_ST_FP64 = 0,
   SADMM_ST_FP32 = 1,
   SADMM_ST_FP16P = 2,
-  SADMM_ST_BF16P = 3
+  SADMM_ST_BF16P = 3,
+  SADMM_ST_MATRIX_FREE = 4
 } sadmm_storage;
 
 typedef struct {

@@ -38,7 +38,7 @@ template <class T> __device__ inline T cabs2(C2<T> a) { return a.re * a.re + a.i
 
 // ---------------------------------------------------------------- storage formats
 // Storage ids match sadmm_storage.
-enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP16P = 2, ST_BF16P = 3 };
+enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP16P = 2, ST_BF16P = 3, ST_MF = 4 };
 
 // Column layout per storage (ld counts storage "slots" per column):
 //   ST_FP64 : KM complex128 entries               (ld >= KM, slot = 16 B)
@@ -108,10 +108,56 @@ template <int STP> struct StoreP16 {
 template <> struct Store<ST_FP16P> : StoreP16<ST_FP16P> {};
 template <> struct Store<ST_BF16P> : StoreP16<ST_BF16P> {};
 
+// Matrix-free LFM operator (eq. (1)): instead of stored entries, each pixel has
+// a record of 2 + 2M doubles [K, M, c0_0, d_0, ..., c0_{M-1}, d_{M-1}] with
+// c0_m = frac(f0 tau_m) and d_m = frac(bw tau_m / K) (cycles, FP64), so that
+// entry (m*K + k) = exp(-j 2 pi frac(c0_m + k d_m)).  The fraction is taken in
+// FP64 (f0 tau is several thousand cycles) and the exponential in FP32.
+__device__ inline void mf_entry(double c0, double d, int k, float* re, float* im) {
+  const double cyc = fma((double)k, d, c0);
+  const float fr = (float)(cyc - floor(cyc));
+  float sn, cs;
+  sincospif(2.0f * fr, &sn, &cs);
+  *re = cs;
+  *im = -sn;
+}
+template <> struct Store<ST_MF> {
+  using T = float;
+  static constexpr int RPT = 8;
+  static constexpr int BYTES = 0;   // nothing stored per entry
+  __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
+    (void)KM;
+    const double* rec = reinterpret_cast<const double*>(col);
+    const int K = (int)rec[0], M = (int)rec[1];
+    int m = i / K, k = i - m * K;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (m < M) {
+        mf_entry(rec[2 + 2 * m], rec[3 + 2 * m], k, &re[r], &im[r]);
+      } else {
+        re[r] = 0.f;
+        im[r] = 0.f;
+      }
+      if (++k == K) { k = 0; ++m; }
+    }
+  }
+  __device__ static inline cd get(const void* col, int i, int KM) {
+    (void)KM;
+    const double* rec = reinterpret_cast<const double*>(col);
+    const int K = (int)rec[0], M = (int)rec[1];
+    const int m = i / K, k = i - m * K;
+    if (m >= M) return {0.0, 0.0};
+    float re, im;
+    mf_entry(rec[2 + 2 * m], rec[3 + 2 * m], k, &re, &im);
+    return {(double)re, (double)im};
+  }
+};
+
 // Address of column `n` for a storage with leading dimension ld (in slots).
 template <int ST> __device__ inline const void* col_ptr(const void* base, int64_t ld, int64_t n) {
   if constexpr (ST == ST_FP64) return reinterpret_cast<const double2*>(base) + ld * n;
   else if constexpr (ST == ST_FP32) return reinterpret_cast<const float2*>(base) + ld * n;
+  else if constexpr (ST == ST_MF) return reinterpret_cast<const double*>(base) + ld * n;
   else return reinterpret_cast<const uint16_t*>(base) + ld * n;
 }
 

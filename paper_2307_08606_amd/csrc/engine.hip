@@ -173,7 +173,10 @@ void prof_work(sadmm_t h, int cls, double w) {
   if (h->prof) h->kt_work[cls] += w;
 }
 // bytes per stored complex operator entry
-double op_bytes(sadmm_t h) { return h->st == ST_FP64 ? 16.0 : (h->st == ST_FP32 ? 8.0 : 4.0); }
+double op_bytes(sadmm_t h) {
+  if (h->st == ST_MF) return 8.0 * (2.0 + 2.0 * h->M) / h->KM;   // record bytes per entry
+  return h->st == ST_FP64 ? 16.0 : (h->st == ST_FP32 ? 8.0 : 4.0);
+}
 
 void prof_resolve(sadmm_t h) {
   if (h->marks.empty()) { h->evnext = 0; return; }
@@ -434,7 +437,7 @@ int validate(const sadmm_params* p) {
   if (!(p->mu > 0) || !(p->beta > 0) || !(p->gamma >= 0) || !(p->lambda >= 0)) return SADMM_E_ARG;
   if (p->max_iter < 1 || p->check_every < 1) return SADMM_E_ARG;
   if (p->Kp < 1 || p->Kp > 64 || !(p->eps_p >= 0)) return SADMM_E_ARG;
-  if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_BF16P) return SADMM_E_ARG;
+  if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_MATRIX_FREE) return SADMM_E_ARG;
   if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
   if ((int64_t)p->K * p->M > 4096) return SADMM_E_SHAPE;   // W_q and LDS staging limits
   return SADMM_OK;
@@ -474,6 +477,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   h->s = static_cast<hipStream_t>(p->stream);
   if (h->st == ST_FP64) { h->ldA = h->KMp; h->slot = 16; }
   else if (h->st == ST_FP32) { h->ldA = h->KMp; h->slot = 8; }
+  else if (h->st == ST_MF) { h->ldA = 2 + 2 * (int64_t)h->M; h->slot = 8; }
   else { h->ldA = 2 * (int64_t)h->KMp; h->slot = 2; }
   h->chunk = 256;
   h->nchunk = (h->N + h->chunk - 1) / h->chunk;
@@ -562,6 +566,8 @@ int sadmm_set_operator(sadmm_t h, int32_t q, const void* A, int32_t dtype, int64
   if (!A || q < 0 || q >= h->Q || (dtype != SADMM_C128 && dtype != SADMM_C64))
     return fail_msg(h, SADMM_E_ARG, "set_operator: bad argument");
   if (ld < h->KM) return fail_msg(h, SADMM_E_SHAPE, "set_operator: ld %lld < KM %d", (long long)ld, h->KM);
+  if (h->st == ST_MF)
+    return fail_msg(h, SADMM_E_STATE, "set_operator: a matrix-free handle takes sadmm_set_operator_geometry");
   const size_t esz = dtype == SADMM_C128 ? 16 : 8;
   const void* src = A;
   void* stage = nullptr;
@@ -599,8 +605,12 @@ int sadmm_set_operator_geometry(sadmm_t h, int32_t q, const double* tx_xy, const
   hipMemcpyAsync(g, tx_xy, 2 * sizeof(double), hipMemcpyHostToDevice, h->s);
   hipMemcpyAsync(g + 2, rx_xy, 2 * sizeof(double) * h->M, hipMemcpyHostToDevice, h->s);
   hipMemcpyAsync(g + 2 + 2 * h->M, pix_xy, 2 * sizeof(double) * h->N, hipMemcpyHostToDevice, h->s);
-  geometry_operator(g, g + 2, g + 2 + 2 * h->M, h->M, h->K, h->N, f0, bw, h->st, h->Afull[q], h->ldA,
-                    h->KMp, h->s);
+  if (h->st == ST_MF)
+    mf_records(g, g + 2, g + 2 + 2 * h->M, h->M, h->K, h->N, f0, bw, static_cast<double*>(h->Afull[q]),
+               h->ldA, h->s);
+  else
+    geometry_operator(g, g + 2, g + 2 + 2 * h->M, h->M, h->K, h->N, f0, bw, h->st, h->Afull[q], h->ldA,
+                      h->KMp, h->s);
   hipError_t e = hipStreamSynchronize(h->s);
   hipFree(g);
   if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator_geometry: %s", hipGetErrorString(e));

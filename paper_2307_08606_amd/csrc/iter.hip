@@ -431,6 +431,7 @@ int fwd_row_tile(int st) {
   switch (st) {
     case ST_FP64: return FWD_THREADS * Store<ST_FP64>::RPT;
     case ST_FP32: return FWD_THREADS * Store<ST_FP32>::RPT;
+    case ST_MF: return FWD_THREADS * Store<ST_MF>::RPT;
     default: return FWD_THREADS * Store<ST_FP16P>::RPT;
   }
 }
@@ -442,6 +443,7 @@ void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s) {
     case ST_FP32: run_iteration<ST_FP32>(a, s, nullptr); break;
     case ST_FP16P: run_iteration<ST_FP16P>(a, s, nullptr); break;
     case ST_BF16P: run_iteration<ST_BF16P>(a, s, nullptr); break;
+    case ST_MF: run_iteration<ST_MF>(a, s, nullptr); break;
   }
 }
 
@@ -453,6 +455,7 @@ void launch_iteration_staged(const IterArgs& a, int st, bool dbl, hipStream_t s,
     case ST_FP32: run_iteration<ST_FP32>(a, s, &hook); break;
     case ST_FP16P: run_iteration<ST_FP16P>(a, s, &hook); break;
     case ST_BF16P: run_iteration<ST_BF16P>(a, s, &hook); break;
+    case ST_MF: run_iteration<ST_MF>(a, s, &hook); break;
   }
 }
 
@@ -477,6 +480,7 @@ void launch_xy(const IterArgs& a, int st, bool dbl, int q0, int q1, hipStream_t 
     case ST_FP32: xy_impl<ST_FP32>(a, q0, q1, s); break;
     case ST_FP16P: xy_impl<ST_FP16P>(a, q0, q1, s); break;
     case ST_BF16P: xy_impl<ST_BF16P>(a, q0, q1, s); break;
+    case ST_MF: xy_impl<ST_MF>(a, q0, q1, s); break;
   }
 }
 
@@ -499,6 +503,7 @@ void launch_gather_fwd(const IterArgs& a, int st, bool dbl, int q, const int* id
     case ST_FP32: gather_impl<ST_FP32>(a, q, idx, count, sign, out, tmp, s); break;
     case ST_FP16P: gather_impl<ST_FP16P>(a, q, idx, count, sign, out, tmp, s); break;
     case ST_BF16P: gather_impl<ST_BF16P>(a, q, idx, count, sign, out, tmp, s); break;
+    case ST_MF: gather_impl<ST_MF>(a, q, idx, count, sign, out, tmp, s); break;
   }
 }
 
@@ -530,6 +535,7 @@ void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx
     case ST_FP32: kkt_impl<ST_FP32>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
     case ST_FP16P: kkt_impl<ST_FP16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
     case ST_BF16P: kkt_impl<ST_BF16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
+    case ST_MF: kkt_impl<ST_MF>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
   }
 }
 
@@ -553,5 +559,6 @@ void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y,
     case ST_FP32: mf_impl<ST_FP32>(a, y, out, s); break;
     case ST_FP16P: mf_impl<ST_FP16P>(a, y, out, s); break;
     case ST_BF16P: mf_impl<ST_BF16P>(a, y, out, s); break;
+    case ST_MF: mf_impl<ST_MF>(a, y, out, s); break;
   }
 }

@@ -436,6 +436,7 @@ void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int 
       case ST_FP32: launch_gemm<ST_FP32, ST_FP32, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
       case ST_FP16P: launch_gemm<ST_FP16P, ST_FP16P, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
       case ST_BF16P: launch_gemm<ST_BF16P, ST_BF16P, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
+      case ST_MF: launch_gemm<ST_MF, ST_MF, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
     }
   }
   if (sta == ST_FP64 && stb == ST_FP64 && !herm) {

@@ -15,6 +15,11 @@ void geometry_operator(const double* tx, const double* rx, const double* pix, in
                        double f0, double bw, int st, void* dst, int64_t ldA, int KMp,
                        hipStream_t s);
 
+// Matrix-free operator records (per pixel: K, M, frac(f0 tau_m), frac(bw tau_m / K)),
+// column stride ld doubles (>= 2 + 2M).
+void mf_records(const double* tx, const double* rx, const double* pix, int M, int K, int N, double f0,
+                double bw, double* rec, int64_t ld, hipStream_t s);
+
 // Stable partition of n flags: kept[] receives in[i] (or i when in is null)
 // for flag[i] != 0 in order, dropped[] the others in order (either output may
 // be null); counts[0] = #kept, counts[1] = #dropped.  One work-group.

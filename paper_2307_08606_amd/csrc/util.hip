@@ -66,6 +66,24 @@ __global__ void geometry_kernel(const double* tx, const double* rx, const double
   store_entry<ST>(col_wptr<ST>(dst, ldA, n), i, KMp, re, im);
 }
 
+// Matrix-free records (see Store<ST_MF>): one thread per pixel.
+__global__ void mf_records_kernel(const double* tx, const double* rx, const double* pix, int M, int K,
+                                  int N, double f0, double bw, double* rec, int64_t ld) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const double px = pix[2 * n], py = pix[2 * n + 1];
+  const double dt = hypot(px - tx[0], py - tx[1]);
+  double* r = rec + (int64_t)n * ld;
+  r[0] = (double)K;
+  r[1] = (double)M;
+  for (int m = 0; m < M; ++m) {
+    const double tau = (dt + hypot(px - rx[2 * m], py - rx[2 * m + 1])) / 299792458.0;
+    const double a = f0 * tau, b = bw * tau / (double)K;
+    r[2 + 2 * m] = a - floor(a);
+    r[3 + 2 * m] = b - floor(b);
+  }
+}
+
 // One work-group of 1024 threads walks the flags in tiles of 1024 with a
 // running offset; wave ballots give the in-wave ranks.
 __global__ __launch_bounds__(1024) void partition_kernel(const uint8_t* flag, const int* in, int n,
@@ -235,6 +253,11 @@ void geometry_operator(const double* tx, const double* rx, const double* pix, in
   }
 }
 
+void mf_records(const double* tx, const double* rx, const double* pix, int M, int K, int N, double f0,
+                double bw, double* rec, int64_t ld, hipStream_t s) {
+  mf_records_kernel<<<(N + 255) / 256, 256, 0, s>>>(tx, rx, pix, M, K, N, f0, bw, rec, ld);
+}
+
 void partition_flags(const uint8_t* flag, const int* in, int n, int* kept, int* dropped,
                      int* counts, hipStream_t s) {
   partition_kernel<<<1, 1024, 0, s>>>(flag, in, n, kept, dropped, counts);
@@ -258,6 +281,7 @@ void gather_columns_fp64(const void* src, int64_t ldA, int st, int KMp, const in
     case ST_FP32: gather_fp64_kernel<ST_FP32><<<g, 256, 0, s>>>(src, ldA, KMp, idx, count, dst); break;
     case ST_FP16P: gather_fp64_kernel<ST_FP16P><<<g, 256, 0, s>>>(src, ldA, KMp, idx, count, dst); break;
     case ST_BF16P: gather_fp64_kernel<ST_BF16P><<<g, 256, 0, s>>>(src, ldA, KMp, idx, count, dst); break;
+    case ST_MF: gather_fp64_kernel<ST_MF><<<g, 256, 0, s>>>(src, ldA, KMp, idx, count, dst); break;
   }
 }
 

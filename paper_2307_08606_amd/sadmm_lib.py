@@ -30,8 +30,9 @@ _lib = C.CDLL(LIB_PATH)
 SADMM_OK, SADMM_E_ARG, SADMM_E_SHAPE, SADMM_E_STATE = 0, -1, -2, -3
 SADMM_E_HIP, SADMM_E_NOMEM, SADMM_E_NUMERIC = -4, -5, -6
 SADMM_C128, SADMM_C64 = 0, 1
-ST_FP64, ST_FP32, ST_FP16P, ST_BF16P = 0, 1, 2, 3
-STORAGE = {"fp64": ST_FP64, "fp32": ST_FP32, "fp16": ST_FP16P, "bf16": ST_BF16P}
+ST_FP64, ST_FP32, ST_FP16P, ST_BF16P, ST_MATRIX_FREE = 0, 1, 2, 3, 4
+STORAGE = {"fp64": ST_FP64, "fp32": ST_FP32, "fp16": ST_FP16P, "bf16": ST_BF16P,
+           "mf": ST_MATRIX_FREE}
 HIST = {"r": 0, "s": 1, "eps_pri": 2, "eps_dual": 3, "nmse": 4, "max_active_frac": 5}
 
 
