@@ -150,6 +150,17 @@ int sadmm_set_reference(sadmm_t h, const void* x_ref, int32_t dtype,
 int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
                 sadmm_info* info);
 
+/* Solves S independent problems (handles hs[0..S-1], all with the same
+ * storage; any sizes, sensor counts, parameters and selectors) in one
+ * iteration loop: each per-iteration kernel is launched once for every scene
+ * of the batch, one iteration is captured as a hipGraph and replayed, and each
+ * scene halts on its own (converged, max_iter, NMSE target, numeric error);
+ * pixel eliminations and re-checks are applied per scene.  ys[i] is the
+ * measurement buffer of scene i (as for sadmm_solve); infos may be NULL or
+ * hold S entries.  Results are read per handle afterwards. */
+int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dtype,
+                      int32_t on_device, sadmm_info* infos);
+
 /* Global image z (N complex) of the last solve. */
 int sadmm_get_image(sadmm_t h, void* xG, int32_t dtype, int32_t on_device);
 
@@ -246,10 +257,11 @@ enum {
   SADMM_KC_COUNT = 7
 };
 
-/* on != 0: record HIP events on the handle's stream around every launch of the
- * classes above during later solves (adds a little launch overhead); resets
- * the accumulated times. */
-int sadmm_set_profiling(sadmm_t h, int32_t on);
+/* level 0: off.  level 1: HIP events around the factor build and update
+ * launches (GRAM, INVERSE, CNN); iterations still run as a replayed hipGraph.
+ * level 2: also events around every iteration stage (FWD, WPROD, XUPD, PIXEL),
+ * launched directly instead of from the graph.  Resets the accumulated times. */
+int sadmm_set_profiling(sadmm_t h, int32_t level);
 
 /* Launch count, summed event time (ms) and algorithmic work of a kernel class
  * since the last sadmm_set_profiling call.  Work is in flops for GRAM and

@@ -96,8 +96,21 @@ struct sadmm_s {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
   bool solved = false;
 
+  // iteration-loop resources: argument table and slot table of this handle
+  // as a batch of one, its own stream for graph capture, the cached graph
+  IterArgs* args_d = nullptr;
+  int2* slots_d = nullptr;
+  hipStream_t gs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  // per-solve loop state
+  std::vector<std::pair<int, double>> frac_pts;   // (iteration, max active fraction from it on)
+  int kkt_rounds = 0, status = 1;
+  bool done = false;
+
   // optional per-kernel-class event timing (sadmm_set_profiling)
   bool prof = false;
+  int prof_level = 0;
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   std::vector<std::array<int, 3>> marks;       // (class, start event, end event)
@@ -443,7 +456,324 @@ int validate(const sadmm_params* p) {
   return SADMM_OK;
 }
 
+// ---- solve phases --------------------------------------------------------
+// Prologue: measurements, state reset, selectors (caller mask, CNN),
+// compaction, factor build, data term; uploads the iteration arguments.
+int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device) {
+  if (!y || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "solve: bad y");
+  for (int q = 0; q < h->Q; ++q)
+    if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "solve: operator of sensor %d not set", q);
+  hipStream_t s = h->s;
+  h->info = sadmm_info{};
+  h->solved = false;
+  HIPCHK(h, hipEventRecord(h->ev0, s));
+  const int Q = h->Q, N = h->N, KMp = h->KMp;
+  // ---- measurements
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  const void* ysrc = y;
+  void* ystage = nullptr;
+  if (!on_device) {
+    if (hipMalloc(&ystage, esz * (size_t)Q * h->KM) != hipSuccess) return fail_msg(h, SADMM_E_NOMEM, "solve: y staging");
+    HIPCHK(h, hipMemcpyAsync(ystage, y, esz * (size_t)Q * h->KM, hipMemcpyHostToDevice, s));
+    ysrc = ystage;
+  }
+  load_measurements(ysrc, dtype == SADMM_C128, Q, h->KM, KMp, h->y, s);
+  HIPCHK(h, hipMemcpyAsync(h->yp, h->y, 16 * (size_t)Q * KMp, hipMemcpyDeviceToDevice, s));
+  // ---- state
+  const size_t cN = h->csz * N;
+  HIPCHK(h, hipMemsetAsync(h->X, 0, cN * Q, s));
+  HIPCHK(h, hipMemsetAsync(h->dX, 0, cN * Q, s));
+  HIPCHK(h, hipMemsetAsync(h->xbar, 0, cN, s));
+  HIPCHK(h, hipMemsetAsync(h->z, 0, cN, s));
+  HIPCHK(h, hipMemsetAsync(h->u, 0, cN, s));
+  HIPCHK(h, hipMemsetAsync(h->D, 0, (h->dbl ? 8 : 4) * (size_t)h->p.Kp * Q * N, s));
+  HIPCHK(h, hipMemsetAsync(h->gone, 0, sizeof(int) * Q, s));
+  HIPCHK(h, hipMemsetAsync(h->hist, 0, sizeof(double) * 6 * (size_t)h->p.max_iter, s));
+  Ctl c0{};
+  c0.max_iter = h->p.max_iter;
+  *h->ctl_h = c0;
+  HIPCHK(h, hipMemcpyAsync(h->ctl, h->ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  // ---- learned elimination (optional): matched filter -> CNN -> shared mask
+  std::vector<uint8_t> cnn_keep;
+  h->cnn_pruned = 0;
+  if (h->cnn) {
+    TRY(push_descs(h));
+    int pe = prof_begin(h);
+    launch_matched_filter(make_args(h), h->st, h->dbl, h->y, h->mf, s);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    const float* prob = nullptr;
+    if (sadmm_cnn_prob_from_mf(h->cnn, h->mf, &prob) != SADMM_OK)
+      return fail_msg(h, SADMM_E_HIP, "solve: CNN inference failed");
+    std::vector<float> ph(N);
+    HIPCHK(h, hipMemcpyAsync(ph.data(), prob, sizeof(float) * N, hipMemcpyDeviceToHost, sadmm_cnn_stream(h->cnn)));
+    HIPCHK(h, hipStreamSynchronize(sadmm_cnn_stream(h->cnn)));
+    prof_end(h, SADMM_KC_CNN, pe);
+    cnn_keep.assign(N, 1);
+    for (int n = 0; n < N; ++n)
+      if (ph[n] >= h->cnn_thr) { cnn_keep[n] = 0; h->cnn_pruned += 1; }
+  }
+  // ---- selectors and compaction
+  std::vector<int> rebuild;
+  std::vector<int> Jh;
+  for (int q = 0; q < Q; ++q) {
+    Jh.clear();
+    std::vector<uint8_t> m(N, 1);
+    if (!h->mask0[q].empty()) m = h->mask0[q];
+    if (!cnn_keep.empty())
+      for (int n = 0; n < N; ++n) m[n] = m[n] && cnn_keep[n];
+    for (int n = 0; n < N; ++n)
+      if (m[n]) Jh.push_back(n);
+    h->nq[q] = (int)Jh.size();
+    HIPCHK(h, hipMemcpyAsync(h->mask + (size_t)q * N, m.data(), N, hipMemcpyHostToDevice, s));
+    if (!Jh.empty())
+      HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    TRY(compact_operator(h, q));
+    if (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh) rebuild.push_back(q);
+    h->facJ[q] = Jh;
+  }
+  if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
+  TRY(push_descs(h));
+  HIPCHK(h, hipEventRecord(h->evf0, s));
+  TRY(build_factors(h, rebuild));
+  launch_xy(make_args(h), h->st, h->dbl, 0, Q, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->evf1, s));
+  HIPCHK(h, hipEventSynchronize(h->evf1));
+  prof_resolve(h);
+  float fms = 0.f;
+  hipEventElapsedTime(&fms, h->evf0, h->evf1);
+  h->t_factor = fms;
+  h->frac_pts.assign(1, {1, max_active_frac(h)});
+  h->kkt_rounds = 0;
+  h->status = 1;
+  h->done = false;
+  const IterArgs a = make_args(h);
+  HIPCHK(h, hipMemcpyAsync(h->args_d, &a, sizeof(IterArgs), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return SADMM_OK;
+}
+
+// Handles the halt state of one scene after a status read.  Sets *active when
+// the scene keeps iterating.
+int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
+  *active = false;
+  hipStream_t s = h->s;
+  float fms = 0.f;
+  if (c.halt & HALT_NAN) return fail_msg(h, SADMM_E_NUMERIC, "non-finite residual at iteration %d", c.k);
+  if (!c.halt) { *active = true; return SADMM_OK; }
+  if (c.halt & HALT_PRUNE) {
+    HIPCHK(h, hipEventRecord(h->evf0, s));
+    TRY(apply_prune(h));
+    HIPCHK(h, hipEventRecord(h->evf1, s));
+    HIPCHK(h, hipEventSynchronize(h->evf1));
+    hipEventElapsedTime(&fms, h->evf0, h->evf1);
+    h->t_factor += fms;
+    h->info.prune_events += 1;
+    h->frac_pts.push_back({c.k, max_active_frac(h)});     // from the deciding iteration on
+    const int nh = c.halt & ~HALT_PRUNE;
+    *h->halt_h = nh;
+    HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (nh == 0) { *active = true; return SADMM_OK; }
+  }
+  const int hb = c.halt & ~HALT_PRUNE;
+  if (hb & HALT_NMSE) { h->status = 2; h->done = true; return SADMM_OK; }
+  if (hb & HALT_CONV) {
+    if (h->p.kkt && h->p.prune && h->kkt_rounds < KKT_ROUNDS) {
+      bool any_frozen = false;
+      for (int q = 0; q < h->Q; ++q) any_frozen = any_frozen || h->nq[q] < h->N;
+      if (any_frozen) {
+        ++h->kkt_rounds;
+        int back = 0;
+        HIPCHK(h, hipEventRecord(h->evf0, s));
+        TRY(kkt_reinstate(h, &back));
+        HIPCHK(h, hipEventRecord(h->evf1, s));
+        HIPCHK(h, hipEventSynchronize(h->evf1));
+        hipEventElapsedTime(&fms, h->evf0, h->evf1);
+        h->t_factor += fms;
+        if (back > 0) {
+          h->info.reinstated += back;
+          h->frac_pts.push_back({c.k + 1, max_active_frac(h)});
+          if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
+          *h->halt_h = 0;
+          HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+          HIPCHK(h, hipStreamSynchronize(s));
+          *active = true;
+          return SADMM_OK;
+        }
+      }
+    }
+    h->status = 0;
+    h->done = true;
+    return SADMM_OK;
+  }
+  if (hb & HALT_MAXIT) { h->status = 1; h->done = true; }
+  return SADMM_OK;
+}
+
+// Iteration loop over a batch of prepared handles (one launch per kernel for
+// every scene; a hipGraph of one iteration is replayed between status reads).
+int iterate(std::vector<sadmm_t>& hs, bool single) {
+  sadmm_t h0 = hs[0];
+  const int S = (int)hs.size();
+  hipStream_t gs = h0->gs;
+  // batch tables
+  BatchDims d{};
+  d.nscene = S;
+  std::vector<int2> slots;
+  for (int i = 0; i < S; ++i) {
+    sadmm_t h = hs[i];
+    for (int q = 0; q < h->Q; ++q) slots.push_back(make_int2(i, q));
+    d.KMp_max = std::max(d.KMp_max, h->KMp);
+    d.nchunk_max = std::max(d.nchunk_max, h->nchunk);
+    d.N_max = std::max(d.N_max, h->N);
+    d.nblk_max = std::max(d.nblk_max, h->nblk);
+  }
+  d.nslot = (int)slots.size();
+  IterArgs* args_d = h0->args_d;
+  int2* slots_d = h0->slots_d;
+  Ctl** ctlp_d = nullptr;
+  Ctl* ctl_all_d = nullptr;
+  std::vector<Ctl> ctl_all(S);
+  std::vector<void*> tmp;
+  auto cleanup = [&]() { for (void* p : tmp) hipFree(p); };
+  if (!single) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(IterArgs) * S) != hipSuccess) return fail_msg(h0, SADMM_E_NOMEM, "batch tables");
+    tmp.push_back(p); args_d = static_cast<IterArgs*>(p);
+    if (hipMalloc(&p, sizeof(int2) * slots.size()) != hipSuccess) { cleanup(); return fail_msg(h0, SADMM_E_NOMEM, "batch tables"); }
+    tmp.push_back(p); slots_d = static_cast<int2*>(p);
+    if (hipMalloc(&p, sizeof(Ctl*) * S) != hipSuccess) { cleanup(); return fail_msg(h0, SADMM_E_NOMEM, "batch tables"); }
+    tmp.push_back(p); ctlp_d = static_cast<Ctl**>(p);
+    if (hipMalloc(&p, sizeof(Ctl) * S) != hipSuccess) { cleanup(); return fail_msg(h0, SADMM_E_NOMEM, "batch tables"); }
+    tmp.push_back(p); ctl_all_d = static_cast<Ctl*>(p);
+    std::vector<IterArgs> av(S);
+    std::vector<Ctl*> cp(S);
+    for (int i = 0; i < S; ++i) { av[i] = make_args(hs[i]); cp[i] = hs[i]->ctl; }
+    if (hipMemcpy(args_d, av.data(), sizeof(IterArgs) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(slots_d, slots.data(), sizeof(int2) * slots.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctlp_d, cp.data(), sizeof(Ctl*) * S, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail_msg(h0, SADMM_E_HIP, "batch tables: copy failed");
+    }
+  }
+  const BatchView bv{args_d, slots_d};
+  const bool staged = single && h0->prof_level >= 2;
+  // graph of one iteration (captured once per handle, or per batch call)
+  hipGraphExec_t ge = single ? h0->gexec : nullptr;
+  hipGraph_t gr = nullptr;
+  if (!staged && !ge) {
+    bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      launch_iteration_batch(bv, d, h0->st, gs, nullptr);
+      ok = hipStreamEndCapture(gs, &gr) == hipSuccess && gr;
+      ok = ok && hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0) == hipSuccess;
+    }
+    if (!ok) { ge = nullptr; (void)hipGetLastError(); }
+    if (single && ge) { h0->gexec = ge; h0->graph = gr; gr = nullptr; }
+  }
+  const int check = h0->p.check_every;
+  int rc = SADMM_OK;
+  for (;;) {
+    for (int i = 0; i < check; ++i) {
+      if (ge) {
+        if (hipGraphLaunch(ge, gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "graph launch failed"); break; }
+      } else if (staged) {
+        sadmm_t h = h0;
+        int ev[IT_NSTAGE];
+        for (int k = 0; k < IT_NSTAGE; ++k) ev[k] = -1;
+        if (h->evnext + 2 * IT_NSTAGE <= h->evpool.size()) {
+          for (int k = 0; k < IT_NSTAGE; ++k) ev[k] = (int)(h->evnext + 2 * k);
+          h->evnext += 2 * IT_NSTAGE;
+        }
+        {
+          // algorithmic bytes of one iteration, per stage
+          const double ob = op_bytes(h), cz = (double)h->csz;
+          double nqs = 0;
+          for (int q = 0; q < h->Q; ++q) nqs += h->nq[q];
+          const double KM = h->KM, Q = h->Q, N = h->N;
+          prof_work(h, SADMM_KC_FWD, nqs * KM * ob + nqs * 4 * cz + Q * KM * cz);
+          prof_work(h, SADMM_KC_WPROD, Q * (KM * KM * 16.0 + 2 * KM * cz));
+          prof_work(h, SADMM_KC_XUPD, nqs * KM * ob + Q * KM * cz + nqs * (7 * cz + cz / 2));
+          prof_work(h, SADMM_KC_PIXEL, Q * N * 2 * cz + N * 6 * cz);
+        }
+        std::function<void(int, bool)> hook = [&](int stage, bool begin) {
+          if (ev[0] < 0) return;
+          hipEventRecord(h->evpool[ev[stage] + (begin ? 0 : 1)], gs);
+          if (!begin) h->marks.push_back({SADMM_KC_FWD + stage, ev[stage], ev[stage] + 1});
+        };
+        launch_iteration_batch(bv, d, h0->st, gs, &hook);
+      } else {
+        launch_iteration_batch(bv, d, h0->st, gs, nullptr);
+      }
+    }
+    if (rc != SADMM_OK) break;
+    if (hipGetLastError() != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "iteration launch failed"); break; }
+    if (single) {
+      if (hipMemcpyAsync(h0->ctl_h, h0->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, gs) != hipSuccess ||
+          hipStreamSynchronize(gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "status read failed"); break; }
+      ctl_all[0] = *h0->ctl_h;
+      prof_resolve(h0);
+    } else {
+      gather_ctl(ctlp_d, ctl_all_d, S, gs);
+      if (hipMemcpyAsync(ctl_all.data(), ctl_all_d, sizeof(Ctl) * S, hipMemcpyDeviceToHost, gs) != hipSuccess ||
+          hipStreamSynchronize(gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "status read failed"); break; }
+    }
+    bool any = false;
+    for (int i = 0; i < S && rc == SADMM_OK; ++i) {
+      sadmm_t h = hs[i];
+      if (h->done) continue;
+      *h->ctl_h = ctl_all[i];
+      bool active = false;
+      rc = handle_halt(h, ctl_all[i], &active);
+      if (rc != SADMM_OK && h != h0) h0->err = h->err;
+      any = any || active;
+    }
+    if (rc != SADMM_OK || !any) break;
+  }
+  if (!single) {
+    if (ge) hipGraphExecDestroy(ge);
+    if (gr) hipGraphDestroy(gr);
+  }
+  hipStreamSynchronize(gs);
+  cleanup();
+  return rc;
+}
+
+// Epilogue: timing, history, info.
+int solve_epilogue(sadmm_t h, sadmm_info* info) {
+  hipStream_t s = h->s;
+  float fms = 0.f;
+  HIPCHK(h, hipEventRecord(h->ev1, s));
+  HIPCHK(h, hipEventSynchronize(h->ev1));
+  hipEventElapsedTime(&fms, h->ev0, h->ev1);
+  h->t_total = fms;
+  h->t_iter = h->t_total - h->t_factor;
+  HIPCHK(h, hipMemcpy(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  const Ctl c = *h->ctl_h;
+  h->hist_count = c.k;
+  h->hist_h.assign(6 * (size_t)h->p.max_iter, 0.0);
+  HIPCHK(h, hipMemcpy(h->hist_h.data(), h->hist, sizeof(double) * 5 * h->p.max_iter, hipMemcpyDeviceToHost));
+  for (int k = 1; k <= c.k; ++k) {
+    double f = h->frac_pts[0].second;
+    for (auto& pt : h->frac_pts)
+      if (pt.first <= k) f = pt.second;
+    h->hist_h[5 * (size_t)h->p.max_iter + k - 1] = f;
+  }
+  h->info.iters = c.k;
+  h->info.status = h->status;
+  h->info.r = c.r; h->info.s = c.s; h->info.eps_pri = c.eps_pri; h->info.eps_dual = c.eps_dual;
+  h->info.nmse = c.nmse;
+  h->info.max_active_frac = max_active_frac(h);
+  h->solved = true;
+  if (info) *info = h->info;
+  return SADMM_OK;
+}
+
 }  // namespace
+
 
 // ====================================================================== C ABI
 extern "C" {
@@ -530,6 +860,8 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   A_(dalloc_t(h, &h->lst, sizeof(int) * N));
   A_(dalloc_t(h, &h->lst2, sizeof(int) * N));
   A_(dalloc_t(h, &h->ctl, sizeof(Ctl)));
+  A_(dalloc_t(h, &h->args_d, sizeof(IterArgs)));
+  A_(dalloc_t(h, &h->slots_d, sizeof(int2) * Q));
   A_(dalloc_t(h, &h->sens_d, sizeof(SensorDesc) * Q));
   A_(dalloc_t(h, &h->gemm_d, sizeof(GemmDesc) * std::max(Q, 4)));
   A_(dalloc_t(h, &h->hpd_d, sizeof(HpdDesc) * Q));
@@ -546,6 +878,15 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
     g_create_err = "pinned host allocation failed";
     sadmm_destroy(h);
     return SADMM_E_NOMEM;
+  }
+  {
+    std::vector<int2> sl(Q);
+    for (int q = 0; q < Q; ++q) sl[q] = make_int2(0, q);
+    if (hipMemcpy(h->slots_d, sl.data(), sizeof(int2) * Q, hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreate(&h->gs) != hipSuccess) {
+      sadmm_destroy(h);
+      return SADMM_E_HIP;
+    }
   }
   if (hipMemsetAsync(h->fail, 0, sizeof(int), h->s) != hipSuccess ||
       hipMemsetAsync(h->gone, 0, sizeof(int) * Q, h->s) != hipSuccess ||
@@ -667,203 +1008,26 @@ int sadmm_set_reference(sadmm_t h, const void* x_ref, int32_t dtype, int32_t on_
 
 int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadmm_info* info) {
   if (!h) return SADMM_E_ARG;
-  if (!y || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "solve: bad y");
-  for (int q = 0; q < h->Q; ++q)
-    if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "solve: operator of sensor %d not set", q);
-  const int Q = h->Q, N = h->N, KMp = h->KMp;
-  hipStream_t s = h->s;
-  h->info = sadmm_info{};
-  h->solved = false;
-  HIPCHK(h, hipEventRecord(h->ev0, s));
-  // ---- measurements
-  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
-  const void* ysrc = y;
-  void* ystage = nullptr;
-  if (!on_device) {
-    if (hipMalloc(&ystage, esz * (size_t)Q * h->KM) != hipSuccess) return fail_msg(h, SADMM_E_NOMEM, "solve: y staging");
-    HIPCHK(h, hipMemcpyAsync(ystage, y, esz * (size_t)Q * h->KM, hipMemcpyHostToDevice, s));
-    ysrc = ystage;
+  TRY(solve_prologue(h, y, dtype, on_device));
+  std::vector<sadmm_t> hs{h};
+  TRY(iterate(hs, /*single=*/true));
+  return solve_epilogue(h, info);
+}
+
+int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dtype, int32_t on_device,
+                      sadmm_info* infos) {
+  if (!hs || S < 1 || !ys) return SADMM_E_ARG;
+  for (int i = 0; i < S; ++i) {
+    if (!hs[i]) return SADMM_E_ARG;
+    if (hs[i]->st != hs[0]->st)
+      return fail_msg(hs[0], SADMM_E_ARG, "solve_batch: every handle must use the same storage");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail_msg(hs[0], SADMM_E_ARG, "solve_batch: handle repeated");
   }
-  load_measurements(ysrc, dtype == SADMM_C128, Q, h->KM, KMp, h->y, s);
-  HIPCHK(h, hipMemcpyAsync(h->yp, h->y, 16 * (size_t)Q * KMp, hipMemcpyDeviceToDevice, s));
-  // ---- state
-  const size_t cN = h->csz * N;
-  HIPCHK(h, hipMemsetAsync(h->X, 0, cN * Q, s));
-  HIPCHK(h, hipMemsetAsync(h->dX, 0, cN * Q, s));
-  HIPCHK(h, hipMemsetAsync(h->xbar, 0, cN, s));
-  HIPCHK(h, hipMemsetAsync(h->z, 0, cN, s));
-  HIPCHK(h, hipMemsetAsync(h->u, 0, cN, s));
-  HIPCHK(h, hipMemsetAsync(h->D, 0, (h->dbl ? 8 : 4) * (size_t)h->p.Kp * Q * N, s));
-  HIPCHK(h, hipMemsetAsync(h->gone, 0, sizeof(int) * Q, s));
-  HIPCHK(h, hipMemsetAsync(h->hist, 0, sizeof(double) * 6 * (size_t)h->p.max_iter, s));
-  Ctl c0{};
-  c0.max_iter = h->p.max_iter;
-  *h->ctl_h = c0;
-  HIPCHK(h, hipMemcpyAsync(h->ctl, h->ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, s));
-  // ---- learned elimination (optional): matched filter -> CNN -> shared mask
-  std::vector<uint8_t> cnn_keep;
-  h->cnn_pruned = 0;
-  if (h->cnn) {
-    TRY(push_descs(h));
-    int pe = prof_begin(h);
-    launch_matched_filter(make_args(h), h->st, h->dbl, h->y, h->mf, s);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipStreamSynchronize(s));
-    const float* prob = nullptr;
-    if (sadmm_cnn_prob_from_mf(h->cnn, h->mf, &prob) != SADMM_OK)
-      return fail_msg(h, SADMM_E_HIP, "solve: CNN inference failed");
-    std::vector<float> ph(N);
-    HIPCHK(h, hipMemcpyAsync(ph.data(), prob, sizeof(float) * N, hipMemcpyDeviceToHost, sadmm_cnn_stream(h->cnn)));
-    HIPCHK(h, hipStreamSynchronize(sadmm_cnn_stream(h->cnn)));
-    prof_end(h, SADMM_KC_CNN, pe);
-    cnn_keep.assign(N, 1);
-    for (int n = 0; n < N; ++n)
-      if (ph[n] >= h->cnn_thr) { cnn_keep[n] = 0; h->cnn_pruned += 1; }
-  }
-  // ---- selectors and compaction
-  std::vector<int> rebuild;
-  std::vector<int> Jh;
-  for (int q = 0; q < Q; ++q) {
-    Jh.clear();
-    std::vector<uint8_t> m(N, 1);
-    if (!h->mask0[q].empty()) m = h->mask0[q];
-    if (!cnn_keep.empty())
-      for (int n = 0; n < N; ++n) m[n] = m[n] && cnn_keep[n];
-    for (int n = 0; n < N; ++n)
-      if (m[n]) Jh.push_back(n);
-    h->nq[q] = (int)Jh.size();
-    HIPCHK(h, hipMemcpyAsync(h->mask + (size_t)q * N, m.data(), N, hipMemcpyHostToDevice, s));
-    if (!Jh.empty())
-      HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    TRY(compact_operator(h, q));
-    if (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh) rebuild.push_back(q);
-    h->facJ[q] = Jh;
-  }
-  if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
-  TRY(push_descs(h));
-  HIPCHK(h, hipEventRecord(h->evf0, s));
-  TRY(build_factors(h, rebuild));
-  launch_xy(make_args(h), h->st, h->dbl, 0, Q, s);
-  HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipEventRecord(h->evf1, s));
-  HIPCHK(h, hipEventSynchronize(h->evf1));
-  prof_resolve(h);
-  float fms = 0.f;
-  hipEventElapsedTime(&fms, h->evf0, h->evf1);
-  h->t_factor = fms;
-  // ---- iterations
-  std::vector<std::pair<int, double>> frac_pts;     // (iteration, max active fraction from it on)
-  frac_pts.push_back({1, max_active_frac(h)});
-  int kkt_rounds = 0;
-  int status = 1;
-  for (;;) {
-    const IterArgs a = make_args(h);
-    for (int i = 0; i < h->p.check_every; ++i) {
-      if (h->prof) {
-        int ev[IT_NSTAGE + 1];
-        for (int k = 0; k <= IT_NSTAGE; ++k) ev[k] = -1;
-        if (h->evnext + 2 * IT_NSTAGE <= h->evpool.size()) {
-          for (int k = 0; k < IT_NSTAGE; ++k) ev[k] = (int)(h->evnext + 2 * k);
-          h->evnext += 2 * IT_NSTAGE;
-        }
-        {
-          // algorithmic bytes of one iteration, per stage
-          const double ob = op_bytes(h), cz = (double)h->csz;
-          double nqs = 0;
-          for (int q = 0; q < Q; ++q) nqs += h->nq[q];
-          const double KM = h->KM;
-          prof_work(h, SADMM_KC_FWD, nqs * KM * ob + nqs * 4 * cz + Q * KM * cz);
-          prof_work(h, SADMM_KC_WPROD, Q * (KM * KM * 16.0 + 2 * KM * cz));
-          prof_work(h, SADMM_KC_XUPD, nqs * KM * ob + Q * KM * cz + nqs * (7 * cz + cz / 2));
-          prof_work(h, SADMM_KC_PIXEL, (double)Q * N * 2 * cz + (double)N * 6 * cz);
-        }
-        launch_iteration_staged(a, h->st, h->dbl, s, [&](int stage, bool begin) {
-          if (ev[0] < 0) return;
-          hipEventRecord(h->evpool[ev[stage] + (begin ? 0 : 1)], s);
-          if (!begin) h->marks.push_back({SADMM_KC_FWD + stage, ev[stage], ev[stage] + 1});
-        });
-      } else {
-        launch_iteration(a, h->st, h->dbl, s);
-      }
-    }
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    prof_resolve(h);
-    const Ctl c = *h->ctl_h;
-    if (c.halt & HALT_NAN) return fail_msg(h, SADMM_E_NUMERIC, "non-finite residual at iteration %d", c.k);
-    if (!c.halt) continue;
-    if (c.halt & HALT_PRUNE) {
-      HIPCHK(h, hipEventRecord(h->evf0, s));
-      TRY(apply_prune(h));
-      HIPCHK(h, hipEventRecord(h->evf1, s));
-      HIPCHK(h, hipEventSynchronize(h->evf1));
-      hipEventElapsedTime(&fms, h->evf0, h->evf1);
-      h->t_factor += fms;
-      h->info.prune_events += 1;
-      // the new selector counts from the iteration that decided it
-      frac_pts.push_back({c.k, max_active_frac(h)});
-      const int nh = c.halt & ~HALT_PRUNE;
-      *h->halt_h = nh;
-      HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
-      HIPCHK(h, hipStreamSynchronize(s));
-      if (nh == 0) continue;
-    }
-    const int hb = c.halt & ~HALT_PRUNE;
-    if (hb & HALT_NMSE) { status = 2; break; }
-    if (hb & HALT_CONV) {
-      if (h->p.kkt && h->p.prune && kkt_rounds < KKT_ROUNDS) {
-        bool any_frozen = false;
-        for (int q = 0; q < Q; ++q) any_frozen = any_frozen || h->nq[q] < N;
-        if (any_frozen) {
-          ++kkt_rounds;
-          int back = 0;
-          HIPCHK(h, hipEventRecord(h->evf0, s));
-          TRY(kkt_reinstate(h, &back));
-          HIPCHK(h, hipEventRecord(h->evf1, s));
-          HIPCHK(h, hipEventSynchronize(h->evf1));
-          hipEventElapsedTime(&fms, h->evf0, h->evf1);
-          h->t_factor += fms;
-          if (back > 0) {
-            h->info.reinstated += back;
-            frac_pts.push_back({c.k + 1, max_active_frac(h)});
-            if (c.k >= h->p.max_iter) { status = 1; break; }
-            *h->halt_h = 0;
-            HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
-            HIPCHK(h, hipStreamSynchronize(s));
-            continue;
-          }
-        }
-      }
-      status = 0;
-      break;
-    }
-    if (hb & HALT_MAXIT) { status = 1; break; }
-  }
-  HIPCHK(h, hipEventRecord(h->ev1, s));
-  HIPCHK(h, hipEventSynchronize(h->ev1));
-  hipEventElapsedTime(&fms, h->ev0, h->ev1);
-  h->t_total = fms;
-  h->t_iter = h->t_total - h->t_factor;
-  const Ctl c = *h->ctl_h;
-  // ---- history
-  h->hist_count = c.k;
-  h->hist_h.assign(6 * (size_t)h->p.max_iter, 0.0);
-  HIPCHK(h, hipMemcpy(h->hist_h.data(), h->hist, sizeof(double) * 5 * h->p.max_iter, hipMemcpyDeviceToHost));
-  for (int k = 1; k <= c.k; ++k) {
-    double f = frac_pts[0].second;
-    for (auto& pt : frac_pts)
-      if (pt.first <= k) f = pt.second;
-    h->hist_h[5 * (size_t)h->p.max_iter + k - 1] = f;
-  }
-  h->info.iters = c.k;
-  h->info.status = status;
-  h->info.r = c.r; h->info.s = c.s; h->info.eps_pri = c.eps_pri; h->info.eps_dual = c.eps_dual;
-  h->info.nmse = c.nmse;
-  h->info.max_active_frac = max_active_frac(h);
-  h->solved = true;
-  if (info) *info = h->info;
+  for (int i = 0; i < S; ++i) TRY(solve_prologue(hs[i], ys[i], dtype, on_device));
+  std::vector<sadmm_t> v(hs, hs + S);
+  TRY(iterate(v, S == 1));
+  for (int i = 0; i < S; ++i) TRY(solve_epilogue(hs[i], infos ? &infos[i] : nullptr));
   return SADMM_OK;
 }
 
@@ -1000,7 +1164,9 @@ int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold) {
 
 int sadmm_set_profiling(sadmm_t h, int32_t on) {
   if (!h) return SADMM_E_ARG;
+  if (on < 0 || on > 2) return fail_msg(h, SADMM_E_ARG, "set_profiling: level 0, 1 or 2");
   h->prof = on != 0;
+  h->prof_level = on;
   if (h->prof && h->evpool.empty()) {
     h->evpool.resize(8192);
     for (auto& e : h->evpool)
@@ -1043,6 +1209,9 @@ void sadmm_destroy(sadmm_t h) {
   if (h->evf0) hipEventDestroy(h->evf0);
   if (h->evf1) hipEventDestroy(h->evf1);
   for (auto& e : h->evpool) hipEventDestroy(e);
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  if (h->gs) { hipStreamSynchronize(h->gs); hipStreamDestroy(h->gs); }
   delete h;
 }
 

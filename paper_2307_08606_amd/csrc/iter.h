@@ -48,19 +48,33 @@ struct IterArgs {
   int* gone;           // Q: pixels to eliminate per sensor
 };
 
+// A batch of independent problems ("scenes") iterated by one launch per
+// kernel: per-scene arguments in device memory, and a slot table mapping each
+// work slot to (scene, sensor).  A single solve is a batch of one.
+struct BatchView {
+  const IterArgs* args;   // nscene entries (device)
+  const int2* slots;      // nslot entries (device): x = scene, y = sensor
+};
+struct BatchDims {
+  int nscene, nslot;
+  int KMp_max, nchunk_max, N_max, nblk_max;
+};
+
 constexpr int FWD_THREADS = 256;
 constexpr int DOT_COLS_PER_WAVE = 4;
 
 // Launchers.  `st` is the operator storage (sadmm_storage), `dbl` selects FP64
 // compute (only with ST_FP64).
-void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s);
-
-// The same launches with a hook called before (begin = true) and after each
-// stage: 0 forward + partial reduce, 1 W product, 2 adjoint + x-update,
+// One iteration of every scene of a batch (all scenes share the storage st).
+// The optional hook is called before (begin = true) and after each stage:
+// 0 forward + partial reduce, 1 W product, 2 adjoint + x-update,
 // 3 pixel update + finalize + SSC check.
 constexpr int IT_NSTAGE = 4;
-void launch_iteration_staged(const IterArgs& a, int st, bool dbl, hipStream_t s,
-                             const std::function<void(int, bool)>& hook);
+void launch_iteration_batch(const BatchView& b, const BatchDims& d, int st, hipStream_t s,
+                            const std::function<void(int, bool)>* hook);
+
+// Copies the control blocks of a batch (ptrs: nscene device pointers) into out.
+void gather_ctl(Ctl* const* ptrs, Ctl* out, int nscene, hipStream_t s);
 int fwd_row_tile(int st);   // rows covered by one forward work-group
 
 // xy_q = Ahat_q^H (W_q y'_q) for the sensors in [q0, q1), FP64 arithmetic

@@ -67,11 +67,13 @@ __device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* col
 }
 
 template <int ST>
-__global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(IterArgs a) {
+__global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(BatchView bv) {
   using T = typename Store<ST>::T;
   constexpr int R = Store<ST>::RPT;
+  const int2 sl = bv.slots[blockIdx.z];
+  const IterArgs& a = bv.args[sl.x];
   if (a.ctl->halt) return;
-  const int q = blockIdx.z, ch = blockIdx.y;
+  const int q = sl.y, ch = blockIdx.y;
   const SensorDesc sd = a.sens[q];
   const int p0 = ch * a.chunk;
   if (p0 >= sd.nq) return;
@@ -94,9 +96,11 @@ __global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(IterArgs a) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void fwd_reduce_kernel(IterArgs a) {
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(BatchView bv) {
+  const int2 sl = bv.slots[blockIdx.y];
+  const IterArgs& a = bv.args[sl.x];
   if (a.ctl->halt) return;
-  const int q = blockIdx.y;
+  const int q = sl.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.KMp) return;
   const int nq = a.sens[q].nq;
@@ -191,13 +195,11 @@ template <int ST, int EPI> struct DotAcc {
 // The W product always reads the FP64 factor and accumulates in FP64: W_q has
 // condition number (c/mu + s_max^2)/(c/mu) and rounding it to FP32 would put a
 // relative error of about 6e-8 * s_max^2 / (c/mu) on every x-update.
-template <int ST, int EPI, class TS = typename Store<ST>::T>
-__global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
+template <int ST, int EPI, class TS>
+__device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) {
   using T = TS;                               // compute precision of the state
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
-  const int q = (EPI == EPI_KKT) ? x.q
-              : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
   const SensorDesc sd = a.sens[q];
   int ncols;
   if constexpr (EPI == EPI_W || EPI == EPI_WY) ncols = a.KMp;
@@ -270,10 +272,26 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
   }
 }
 
+template <int ST, int EPI, class TS = typename Store<ST>::T>
+__global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
+  const int q = (EPI == EPI_KKT) ? x.q
+              : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
+  coldot_body<ST, EPI, TS>(a, x, q);
+}
+
+// Per-iteration column dots over a batch: blockIdx.y is the work slot.
+template <int ST, int EPI, class TS = typename Store<ST>::T>
+__global__ __launch_bounds__(256) void coldot_batch_kernel(BatchView bv) {
+  const int2 sl = bv.slots[blockIdx.y];
+  DotExtra x{};
+  coldot_body<ST, EPI, TS>(bv.args[sl.x], x, sl.y);
+}
+
 // ------------------------------------------------------------------ pixel update
 template <class T>
-__global__ __launch_bounds__(256) void pixel_kernel(IterArgs a) {
-  if (a.ctl->halt) return;
+__global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
+  const IterArgs& a = bv.args[blockIdx.y];
+  if (a.ctl->halt || (int)blockIdx.x >= a.nblk) return;
   __shared__ double sm[4 * 8];
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int n = blockIdx.x * 256 + threadIdx.x;
@@ -320,7 +338,8 @@ __global__ __launch_bounds__(256) void pixel_kernel(IterArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void finalize_kernel(IterArgs a) {
+__global__ __launch_bounds__(256) void finalize_kernel(BatchView bv) {
+  const IterArgs& a = bv.args[blockIdx.x];
   Ctl* ctl = a.ctl;
   if (ctl->halt) return;
   __shared__ double sm[4 * 8];
@@ -364,12 +383,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(IterArgs a) {
 // differences exist.  Runs at the last permitted iteration too (max_iter),
 // but not once converged.
 template <class T>
-__global__ __launch_bounds__(256) void ssc_kernel(IterArgs a) {
+__global__ __launch_bounds__(256) void ssc_kernel(BatchView bv) {
+  const int2 sl = bv.slots[blockIdx.y];
+  const IterArgs& a = bv.args[sl.x];
   Ctl* ctl = a.ctl;
+  if (!a.prune) return;
   if (ctl->halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_PRUNE)) return;
   const int k = ctl->k;
   if (k < a.Kp || !ctl->gate) return;
-  const int q = blockIdx.y;
+  const int q = sl.y;
   const SensorDesc sd = a.sens[q];
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= sd.nq) return;
@@ -384,9 +406,10 @@ __global__ __launch_bounds__(256) void ssc_kernel(IterArgs a) {
 }
 
 // Raises the prune halt bit when the SSC check removed anything.
-__global__ void ssc_flag_kernel(IterArgs a) {
+__global__ void ssc_flag_kernel(BatchView bv) {
+  const IterArgs& a = bv.args[blockIdx.x];
   Ctl* ctl = a.ctl;
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || !a.prune) return;
   if (ctl->halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_PRUNE)) return;
   int tot = 0;
   for (int q = 0; q < a.Q; ++q) tot += a.gone[q];
@@ -396,32 +419,35 @@ __global__ void ssc_flag_kernel(IterArgs a) {
   }
 }
 
+__global__ void gather_ctl_kernel(Ctl* const* ptrs, Ctl* out, int n) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < n) out[i] = *ptrs[i];
+}
+
 template <int ST>
-void run_iteration(const IterArgs& a, hipStream_t s, const std::function<void(int, bool)>* hook) {
+void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
+                         const std::function<void(int, bool)>* hook) {
   using T = typename Store<ST>::T;
   auto mark = [&](int stage, bool begin) { if (hook) (*hook)(stage, begin); };
   const int rows = FWD_THREADS * Store<ST>::RPT;
-  dim3 gf((a.KMp + rows - 1) / rows, a.nchunk, a.Q);
-  mark(0, true);
-  fwd_iter_kernel<ST><<<gf, FWD_THREADS, 0, s>>>(a);
-  fwd_reduce_kernel<T><<<dim3((a.KMp + 255) / 256, a.Q), 256, 0, s>>>(a);
-  mark(0, false);
   const int cpb = 4 * DOT_COLS_PER_WAVE;
-  const size_t smem = (size_t)a.KMp * sizeof(C2<T>);
-  DotExtra x{};
+  mark(0, true);
+  fwd_iter_kernel<ST><<<dim3((d.KMp_max + rows - 1) / rows, d.nchunk_max, d.nslot), FWD_THREADS, 0, s>>>(b);
+  fwd_reduce_kernel<T><<<dim3((d.KMp_max + 255) / 256, d.nslot), 256, 0, s>>>(b);
+  mark(0, false);
   mark(1, true);
-  coldot_kernel<ST_FP64, EPI_W, T><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256, a.KMp * sizeof(cd), s>>>(a, x);
+  coldot_batch_kernel<ST_FP64, EPI_W, T><<<dim3((d.KMp_max + cpb - 1) / cpb, d.nslot), 256,
+                                           (size_t)d.KMp_max * sizeof(cd), s>>>(b);
   mark(1, false);
   mark(2, true);
-  coldot_kernel<ST, EPI_XUPD><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
+  coldot_batch_kernel<ST, EPI_XUPD><<<dim3((d.N_max + cpb - 1) / cpb, d.nslot), 256,
+                                      (size_t)d.KMp_max * sizeof(C2<T>), s>>>(b);
   mark(2, false);
   mark(3, true);
-  pixel_kernel<T><<<a.nblk, 256, 0, s>>>(a);
-  finalize_kernel<<<1, 256, 0, s>>>(a);
-  if (a.prune) {
-    ssc_kernel<T><<<dim3((a.N + 255) / 256, a.Q), 256, 0, s>>>(a);
-    ssc_flag_kernel<<<1, 64, 0, s>>>(a);
-  }
+  pixel_kernel<T><<<dim3(d.nblk_max, d.nscene), 256, 0, s>>>(b);
+  finalize_kernel<<<d.nscene, 256, 0, s>>>(b);
+  ssc_kernel<T><<<dim3((d.N_max + 255) / 256, d.nslot), 256, 0, s>>>(b);
+  ssc_flag_kernel<<<d.nscene, 64, 0, s>>>(b);
   mark(3, false);
 }
 
@@ -436,27 +462,19 @@ int fwd_row_tile(int st) {
   }
 }
 
-void launch_iteration(const IterArgs& a, int st, bool dbl, hipStream_t s) {
-  (void)dbl;
+void launch_iteration_batch(const BatchView& b, const BatchDims& d, int st, hipStream_t s,
+                            const std::function<void(int, bool)>* hook) {
   switch (st) {
-    case ST_FP64: run_iteration<ST_FP64>(a, s, nullptr); break;
-    case ST_FP32: run_iteration<ST_FP32>(a, s, nullptr); break;
-    case ST_FP16P: run_iteration<ST_FP16P>(a, s, nullptr); break;
-    case ST_BF16P: run_iteration<ST_BF16P>(a, s, nullptr); break;
-    case ST_MF: run_iteration<ST_MF>(a, s, nullptr); break;
+    case ST_FP64: run_iteration_batch<ST_FP64>(b, d, s, hook); break;
+    case ST_FP32: run_iteration_batch<ST_FP32>(b, d, s, hook); break;
+    case ST_FP16P: run_iteration_batch<ST_FP16P>(b, d, s, hook); break;
+    case ST_BF16P: run_iteration_batch<ST_BF16P>(b, d, s, hook); break;
+    case ST_MF: run_iteration_batch<ST_MF>(b, d, s, hook); break;
   }
 }
 
-void launch_iteration_staged(const IterArgs& a, int st, bool dbl, hipStream_t s,
-                             const std::function<void(int, bool)>& hook) {
-  (void)dbl;
-  switch (st) {
-    case ST_FP64: run_iteration<ST_FP64>(a, s, &hook); break;
-    case ST_FP32: run_iteration<ST_FP32>(a, s, &hook); break;
-    case ST_FP16P: run_iteration<ST_FP16P>(a, s, &hook); break;
-    case ST_BF16P: run_iteration<ST_BF16P>(a, s, &hook); break;
-    case ST_MF: run_iteration<ST_MF>(a, s, &hook); break;
-  }
+void gather_ctl(Ctl* const* ptrs, Ctl* out, int nscene, hipStream_t s) {
+  gather_ctl_kernel<<<(nscene + 63) / 64, 64, 0, s>>>(ptrs, out, nscene);
 }
 
 template <int ST>

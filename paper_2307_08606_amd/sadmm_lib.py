@@ -83,6 +83,8 @@ sadmm_set_active_mask = _sig("sadmm_set_active_mask", C.c_int, _H, C.c_int32, _P
 sadmm_set_reference = _sig("sadmm_set_reference", C.c_int, _H, _P, C.c_int32, C.c_int32,
                            C.c_double)
 sadmm_solve = _sig("sadmm_solve", C.c_int, _H, _P, C.c_int32, C.c_int32, C.POINTER(sadmm_info))
+sadmm_solve_batch = _sig("sadmm_solve_batch", C.c_int, C.POINTER(_H), C.c_int32,
+                         C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.POINTER(sadmm_info))
 sadmm_get_image = _sig("sadmm_get_image", C.c_int, _H, _P, C.c_int32, C.c_int32)
 sadmm_get_sensor_image = _sig("sadmm_get_sensor_image", C.c_int, _H, C.c_int32, _P, C.c_int32,
                               C.c_int32)
@@ -289,8 +291,8 @@ class Solver:
         self._cnn = cnn
         self._check(sadmm_set_pruning_cnn(self._h, cnn._h if cnn is not None else None, threshold))
 
-    def set_profiling(self, on=True):
-        self._check(sadmm_set_profiling(self._h, int(bool(on))))
+    def set_profiling(self, level=1):
+        self._check(sadmm_set_profiling(self._h, int(level)))
 
     def kernel_stats(self) -> dict:
         """{class: (launches, total_ms, work)}; work in flops (gram, inverse) or bytes."""
@@ -311,6 +313,20 @@ class Solver:
             self._check(sadmm_get_timing(self._h, i, C.byref(v)))
             out[k] = v.value
         return out
+
+
+def solve_batch(solvers, ys):
+    """Solve several handles in one batched iteration loop (sadmm_solve_batch).
+    ys: list of measurement arrays/tensors (same dtype, all host or all device)."""
+    S = len(solvers)
+    ys = [np.ascontiguousarray(y) if isinstance(y, np.ndarray) else y for y in ys]
+    hs = (_H * S)(*[s._h for s in solvers])
+    ptrs = (C.c_void_p * S)(*[_ptr(y) for y in ys])
+    infos = (sadmm_info * S)()
+    rc = sadmm_solve_batch(hs, S, ptrs, _dtype_code(ys[0]), _on_device(ys[0]), infos)
+    if rc != SADMM_OK:
+        raise SadmmError(rc, sadmm_last_error(solvers[0]._h).decode())
+    return [infos[i].as_dict() for i in range(S)]
 
 
 # ---------------------------------------------------------------- CNN
