@@ -662,7 +662,7 @@ int iterate(std::vector<sadmm_t>& hs, bool single) {
   const BatchView bv{args_d, slots_d};
   const bool staged = single && h0->prof_level >= 2;
   // graph of one iteration (captured once per handle, or per batch call)
-  hipGraphExec_t ge = single ? h0->gexec : nullptr;
+  hipGraphExec_t ge = (single && !staged) ? h0->gexec : nullptr;
   hipGraph_t gr = nullptr;
   if (!staged && !ge) {
     bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;

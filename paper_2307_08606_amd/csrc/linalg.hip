@@ -1,12 +1,16 @@
-// FP64 complex GEMM (batched, tiled through LDS) and blocked Gauss-Jordan
+// FP64 complex linear algebra on the device: batched GEMM, the Hermitian Gram
+// of the operator on the FP64 matrix instructions, and the Cholesky-based
 // inverse of Hermitian positive definite matrices.
 //
 // These build W_q = ((c/mu) I + Ahat_q Ahat_q^H)^{-1}, the factor through which
 // the ridge x-update of eq. (3) is applied in Woodbury form, and apply the
 // low-rank corrections of W_q when SSC (Alg. 1) removes columns of Ahat_q or
-// the optimality re-check puts them back.  MI355X runs FP64 FMA on the vector
-// units at the same peak as FP64 matrix instructions, so these are plain
-// register-blocked FMA kernels.
+// the optimality re-check puts them back.  MI355X has the same FP64 peak on
+// the vector units as on the matrix units, but a register-blocked vector FMA
+// tile needs one 16-byte LDS read per two FMAs and is capped by LDS bandwidth;
+// the 16x16x4 FP64 instruction needs 8x fewer operand reads, so the Gram (the
+// dominant cost of a factor build) runs on it.  The smaller products keep the
+// vector kernel.
 #include <algorithm>
 
 #include "linalg.h"
@@ -417,6 +421,147 @@ __global__ void identity_pad_kernel(cd* G, int n, int n_pad, double diag_add) {
   }
 }
 
+// ------------------------------------------------------------------ Gram on MFMA
+// C = alpha * A B^H + beta * C (+ diag) for C Hermitian (B = A for the Gram of
+// the operator), on the FP64 16x16x4 matrix instruction.  Complex products are
+// split into real ones: with L = rows i of A and R = rows j of B,
+//   Re C = Lr Rr^T + Li Ri^T,   Im C = Li Rr^T - Lr Ri^T.
+// Work-group: 64 x 64 complex tile of the lower triangle (tiles enumerated
+// triangularly), four waves of 32 x 32 (2 x 2 blocks of 16 x 16).  Panels of
+// HK pixel columns are staged in LDS as FP64 real/imaginary planes; the next
+// panel is fetched into registers while the current one is multiplied.
+// Operand lane layout of the instruction: lane l carries A[l % 16][l / 16] and
+// B[l / 16][l % 16]; the result block's element (4 r + l / 16, l % 16) is
+// component r of lane l.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int HM = 64, HK = 32, HLD = 80;   // HLD: padded LDS row of doubles
+constexpr int HPF = HK / 4;                  // panel elements per thread
+
+__device__ inline void tri_tile(int x, int* ti, int* tj) {
+  // x -> (ti, tj), ti >= tj, x = ti (ti + 1) / 2 + tj
+  int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= x) ++i;
+  while (i * (i + 1) / 2 > x) --i;
+  *ti = i;
+  *tj = x - i * (i + 1) / 2;
+}
+
+// Panel staging: each thread fetches HPF elements of a 64-row x HK-column panel
+// (rows contiguous across lanes) into registers, then stores them to LDS as
+// FP64 real/imaginary planes.
+template <int ST>
+__device__ inline void fetch_panel(const void* base, int64_t ld, int kmp, int r0, int rows, int p0,
+                                   int k, cd (&v)[HPF]) {
+  const int t = threadIdx.x;
+  const int gr = r0 + (t & 63);
+#pragma unroll
+  for (int e = 0; e < HPF; ++e) {
+    const int gp = p0 + (t >> 6) + 4 * e;
+    v[e] = cd{0.0, 0.0};
+    if (gr < rows && gp < k) v[e] = Store<ST>::get(col_ptr<ST>(base, ld, gp), gr, kmp);
+  }
+}
+__device__ inline void store_panel(const cd (&v)[HPF], double (*dst)[HK][HLD]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < HPF; ++e) {
+    const int pp = (t >> 6) + 4 * e;
+    dst[0][pp][t & 63] = v[e].re;
+    dst[1][pp][t & 63] = v[e].im;
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void herk_mfma_kernel(const GemmDesc* __restrict__ descs) {
+  const GemmDesc d = descs[blockIdx.y];
+  int ti, tj;
+  tri_tile(blockIdx.x, &ti, &tj);
+  const int i0 = ti * HM, j0 = tj * HM;
+  if (i0 >= d.m) return;
+  __shared__ double sL[2][HK][HLD];
+  __shared__ double sR[2][HK][HLD];
+  // a diagonal tile of a Gram reads one panel
+  const bool same = ti == tj && d.A == d.B && d.lda == d.ldb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int c16 = lane & 15, kq = lane >> 4;
+  v4d cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  double (*R)[HK][HLD] = same ? sL : sR;
+  cd vl[HPF], vr[HPF];
+  fetch_panel<ST>(d.A, d.lda, d.kmpA, i0, d.m, 0, d.k, vl);
+  if (!same) fetch_panel<ST>(d.B, d.ldb, d.kmpB, j0, d.n, 0, d.k, vr);
+  for (int p0 = 0; p0 < d.k; p0 += HK) {
+    __syncthreads();                       // previous panel consumed
+    store_panel(vl, sL);
+    if (!same) store_panel(vr, sR);
+    __syncthreads();
+    if (p0 + HK < d.k) {                   // next panel in flight during the products
+      fetch_panel<ST>(d.A, d.lda, d.kmpA, i0, d.m, p0 + HK, d.k, vl);
+      if (!same) fetch_panel<ST>(d.B, d.ldb, d.kmpB, j0, d.n, p0 + HK, d.k, vr);
+    }
+#pragma unroll
+    for (int kk = 0; kk < HK; kk += 4) {
+      double lr[2], li[2], nlr[2], rr[2], ri[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        lr[a] = sL[0][kk + kq][wr + 16 * a + c16];
+        li[a] = sL[1][kk + kq][wr + 16 * a + c16];
+        nlr[a] = -lr[a];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        rr[b] = R[0][kk + kq][wc + 16 * b + c16];
+        ri[b] = R[1][kk + kq][wc + 16 * b + c16];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lr[a], rr[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(li[a], rr[b], ci[a][b], 0, 0, 0);
+        }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(li[a], ri[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nlr[a], ri[b], ci[a][b], 0, 0, 0);
+        }
+    }
+  }
+  // ---- epilogue: lower triangle and its mirror
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + 16 * a + 4 * r + kq;
+        const int j = j0 + wc + 16 * b + c16;
+        if (i >= d.m || j >= d.n || j > i) continue;
+        const double ar = cr[a][b][r], ai = ci[a][b][r];
+        cd v = {d.alpha_re * ar - d.alpha_im * ai, d.alpha_re * ai + d.alpha_im * ar};
+        cd* cij = d.C + (int64_t)j * d.ldc + i;
+        if (d.beta != 0.0) { v.re += d.beta * cij->re; v.im += d.beta * cij->im; }
+        if (i == j) { v.re += d.diag; v.im = 0.0; }
+        *cij = v;
+        if (i != j) d.C[(int64_t)i * d.ldc + j] = cd{v.re, -v.im};
+      }
+}
+
+template <int ST>
+void launch_herk_mfma(const GemmDesc* d, int batch, int mm, hipStream_t s) {
+  const int nt = (mm + HM - 1) / HM;
+  herk_mfma_kernel<ST><<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(d);
+}
+
 template <int STA, int STB, int OPA, int OPB, bool HERM>
 void launch_gemm(const GemmDesc* d, int batch, int mm, int mn, hipStream_t s) {
   dim3 grid((mm + TM - 1) / TM, (mn + TN - 1) / TN, batch);
@@ -432,11 +577,11 @@ void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int 
   // and FP64 x FP64 products for the low-rank factor corrections.
   if (stb == sta && opa == OP_N && opb == OP_C && herm) {
     switch (sta) {
-      case ST_FP64: launch_gemm<ST_FP64, ST_FP64, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
-      case ST_FP32: launch_gemm<ST_FP32, ST_FP32, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
-      case ST_FP16P: launch_gemm<ST_FP16P, ST_FP16P, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
-      case ST_BF16P: launch_gemm<ST_BF16P, ST_BF16P, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
-      case ST_MF: launch_gemm<ST_MF, ST_MF, OP_N, OP_C, true>(d_desc, batch, max_m, max_n, s); return;
+      case ST_FP64: launch_herk_mfma<ST_FP64>(d_desc, batch, max_m, s); return;
+      case ST_FP32: launch_herk_mfma<ST_FP32>(d_desc, batch, max_m, s); return;
+      case ST_FP16P: launch_herk_mfma<ST_FP16P>(d_desc, batch, max_m, s); return;
+      case ST_BF16P: launch_herk_mfma<ST_BF16P>(d_desc, batch, max_m, s); return;
+      case ST_MF: launch_herk_mfma<ST_MF>(d_desc, batch, max_m, s); return;
     }
   }
   if (sta == ST_FP64 && stb == ST_FP64 && !herm) {

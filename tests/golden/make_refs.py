@@ -10,6 +10,12 @@ point/extended targets, 15 dB), scene seed 100:
                          iterated until the primal residual reaches the FP64
                          round-off floor (eps_rel = 1e-10 is below that floor,
                          so the run ends at max_iter)
+
+Batched uneven frames c4 (M=8, K=128, per-frame Q and grid drawn by
+scenegen.configs.c4_frames), batch seed 7, 16 frames:
+  c4_batch_seed7.json    per-frame lambda_max and lambda (= 0.2 lambda_max)
+
+    python tests/golden/make_refs.py c4
 """
 
 import json
@@ -24,6 +30,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
 from scenegen import CONFIGS, config_scene, steering  # noqa: E402
+from scenegen.configs import c4_frames, c4_scene  # noqa: E402
 
 
 def main(seed: int = 100, max_iter: int = 300):
@@ -62,5 +69,22 @@ def main(seed: int = 100, max_iter: int = 300):
     print(json.dumps(info, indent=1))
 
 
+def main_c4(seed: int = 7, n_frames: int = 16, lambda_frac: float = 0.2):
+    frames = c4_frames(n_frames, seed)
+    for fr in frames:
+        sc = c4_scene(fr)
+        A = [steering(sc.geom, q) for q in range(sc.geom.Q)]
+        fr["lambda_max"] = oracle.lambda_max(A, sc.y, 1.0, 1.0)
+        fr["lam"] = lambda_frac * fr["lambda_max"]
+    info = dict(workload="c4", seed=seed, n_frames=n_frames, lambda_frac=lambda_frac,
+                mu=1.0, beta=1.0, gamma=1.0, frames=frames)
+    with open(os.path.join(HERE, f"c4_batch_seed{seed}.json"), "w") as f:
+        json.dump(info, f, indent=1)
+    print(json.dumps(info, indent=1))
+
+
 if __name__ == "__main__":
-    main()
+    if sys.argv[1:] == ["c4"]:
+        main_c4()
+    else:
+        main()
