@@ -91,6 +91,12 @@ typedef struct {
   int32_t storage;            /* sadmm_storage */
   int32_t reuse_factor;       /* 1: a later solve reuses a factor built for the same
                                  starting selector; 0: every solve rebuilds it */
+  int32_t gram;               /* Gram Ahat Ahat^H of a factor build.  0 (default): for
+                                 FP32 / FP16P / BF16P / MATRIX_FREE storage, an exact
+                                 integer product on int8 matrix instructions of the
+                                 operator rounded to 30 bits below each row's largest
+                                 magnitude (FP64 storage always takes path 1);
+                                 1: FP64 matrix instructions on the stored values */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 

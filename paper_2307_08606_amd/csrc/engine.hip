@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/sadmm.h"
+#include "gram.h"
 #include "iter.h"
 #include "linalg.h"
 #include "util.h"
@@ -78,6 +79,9 @@ struct sadmm_s {
   std::vector<SensorDesc> sens_h;
   GemmDesc* gemm_d = nullptr;
   HpdDesc* hpd_d = nullptr;
+  GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
+  void* gi8_ws = nullptr;        // its digit-plane workspace
+  size_t gi8_ws_bytes = 0;
   cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Xg = nullptr;
   std::vector<cd*> hpdD, hpdX;                // per-sensor inverse scratch
   int rmax = 0, rpad_max = 0;
@@ -272,6 +276,47 @@ int check_fail(sadmm_t h) {
   return SADMM_OK;
 }
 
+// W64[q] = Ahat_q Ahat_q^H + rho I by the integer digit products (gram.h), in
+// groups of sensors whose digit planes fit a bounded workspace.
+int gram_integer(sadmm_t h, const std::vector<int>& qs, double rho) {
+  constexpr size_t kCap = size_t(4) << 30;
+  const size_t per = (gram_i8_workspace(h->KMp, h->N) + 255) / 256 * 256;
+  const size_t group = std::max<size_t>(1, std::min<size_t>(qs.size(), kCap / per));
+  if (h->gi8_ws_bytes < group * per) {   // owned here (not in allocs): it may grow
+    if (h->gi8_ws) {
+      HIPCHK(h, hipStreamSynchronize(h->s));
+      hipFree(h->gi8_ws);
+    }
+    h->gi8_ws = nullptr;
+    h->gi8_ws_bytes = 0;
+    const hipError_t e = hipMalloc(&h->gi8_ws, group * per);
+    if (e != hipSuccess) {
+      h->gi8_ws = nullptr;
+      return fail_msg(h, SADMM_E_NOMEM, "integer Gram workspace (%zu bytes): %s", group * per,
+                      hipGetErrorString(e));
+    }
+    h->gi8_ws_bytes = group * per;
+  }
+  for (size_t g0 = 0; g0 < qs.size(); g0 += group) {
+    const size_t n = std::min(group, qs.size() - g0);
+    std::vector<GramI8Desc> gd(n);
+    int max_k = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const int q = qs[g0 + i];
+      GramI8Desc& d = gd[i];
+      d.A = ahat_ptr(h, q); d.ldA = h->ldA; d.kmp = h->KMp;
+      d.m = h->KMp; d.k = h->nq[q];
+      d.C = h->W64[q]; d.ldc = h->KMp; d.diag = rho;
+      gram_i8_layout(d, static_cast<char*>(h->gi8_ws) + i * per);
+      max_k = std::max(max_k, d.k);
+    }
+    HIPCHK(h, hipMemcpyAsync(h->gi8_d, gd.data(), sizeof(GramI8Desc) * n, hipMemcpyHostToDevice, h->s));
+    gram_i8_batched(h->gi8_d, (int)n, h->KMp, max_k, h->st, h->s);
+    HIPCHK(h, hipGetLastError());
+  }
+  return SADMM_OK;
+}
+
 // Full factor build for the listed sensors: W64 = ((c/mu) I + Ahat Ahat^H)^{-1}
 int build_factors(sadmm_t h, const std::vector<int>& qs) {
   if (qs.empty()) return SADMM_OK;
@@ -288,10 +333,14 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
     g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta = 0.0; g.diag = rho;
     hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q]};
   }
-  HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
   HIPCHK(h, hipMemcpyAsync(h->hpd_d, hd.data(), sizeof(HpdDesc) * hd.size(), hipMemcpyHostToDevice, h->s));
   int pe = prof_begin(h);
-  zgemm_batched(h->gemm_d, (int)qs.size(), h->KMp, h->KMp, h->st, h->st, OP_N, OP_C, true, h->s);
+  if (h->p.gram == 0 && h->st != ST_FP64) {
+    TRY(gram_integer(h, qs, rho));
+  } else {
+    HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
+    zgemm_batched(h->gemm_d, (int)qs.size(), h->KMp, h->KMp, h->st, h->st, OP_N, OP_C, true, h->s);
+  }
   prof_end(h, SADMM_KC_GRAM, pe);
   for (int q : qs) {
     // Hermitian product: KM(KM+1)/2 entries, N_q complex MACs each (8 flops)
@@ -451,6 +500,7 @@ int validate(const sadmm_params* p) {
   if (p->max_iter < 1 || p->check_every < 1) return SADMM_E_ARG;
   if (p->Kp < 1 || p->Kp > 64 || !(p->eps_p >= 0)) return SADMM_E_ARG;
   if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_MATRIX_FREE) return SADMM_E_ARG;
+  if (p->gram < 0 || p->gram > 1) return SADMM_E_ARG;
   if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
   if ((int64_t)p->K * p->M > 4096) return SADMM_E_SHAPE;   // W_q and LDS staging limits
   return SADMM_OK;
@@ -865,6 +915,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   A_(dalloc_t(h, &h->sens_d, sizeof(SensorDesc) * Q));
   A_(dalloc_t(h, &h->gemm_d, sizeof(GemmDesc) * std::max(Q, 4)));
   A_(dalloc_t(h, &h->hpd_d, sizeof(HpdDesc) * Q));
+  A_(dalloc_t(h, &h->gi8_d, sizeof(GramI8Desc) * Q));
   A_(dalloc_t(h, &h->Ar, sizeof(cd) * (size_t)KMp * h->rmax));
   A_(dalloc_t(h, &h->V, sizeof(cd) * (size_t)KMp * h->rmax));
   A_(dalloc_t(h, &h->Tm, sizeof(cd) * (size_t)KMp * h->rmax));
@@ -1201,6 +1252,7 @@ void sadmm_destroy(sadmm_t h) {
   if (h->s) hipStreamSynchronize(h->s);
   else hipDeviceSynchronize();
   for (void* p : h->allocs) hipFree(p);
+  if (h->gi8_ws) hipFree(h->gi8_ws);
   if (h->ctl_h) hipHostFree(h->ctl_h);
   if (h->counts_h) hipHostFree(h->counts_h);
   if (h->halt_h) hipHostFree(h->halt_h);

@@ -1,0 +1,357 @@
+// Exact-integer Gram Ahat Ahat^H on the int8 16x16x64 matrix instruction.
+//
+// The Gram is the dense contraction of a factor build (x-update of eq. (3) in
+// Woodbury form).  MI355X runs int8 matrix products 64 times faster than FP64
+// ones, and the operator entries are bounded (|A| = 1 for the steering vectors
+// of eq. (1)), so the product is split into digit products that are exact in
+// int32 (see gram.h for the number format and the error bound).
+//
+// Complex product with L = rows i and R = rows j of Ahat:
+//   Re G = Lr Rr^T + Li Ri^T,   Im G = Li Rr^T - Lr Ri^T.
+// The subtraction uses bitwise NOT of the real digits (~d = -d - 1, exact in
+// int8 for every d) and adds back the sum of the imaginary digits of row j.
+//
+// Work-group: 64 x 64 complex tile of the lower triangle, four waves of
+// 32 x 32 (2 x 2 blocks of 16 x 16), each accumulating all 13 digit pairs with
+// s + t <= 4 into five int32 class accumulators (c = s + t).
+// Lane layout of the instruction: lane l carries A row l % 16 and B column
+// l % 16 with k-slots 16 (l / 16) + byte (any order shared by A and B gives
+// the same product); result element (4 (l / 16) + r, l % 16) is component r
+// of lane l (unlike the FP64 16x16x4 instruction, whose rows are 4 r + l / 16).
+#include <algorithm>
+
+#include "gram.h"
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));   // (uint4 arrays stay in scratch)
+
+constexpr int GT = 64;      // tile rows / columns (complex)
+constexpr int GKS = 64;     // columns per stage (k of one instruction)
+constexpr int GROW = 80;    // LDS bytes per staged row (64 + pad: no bank conflicts)
+
+inline int round_up_i(int x, int m) { return (x + m - 1) / m * m; }
+
+__global__ void clear_kernel(const GramI8Desc* __restrict__ descs) {
+  const GramI8Desc d = descs[blockIdx.y];
+  const int nch = (d.ldS + GI8_CHUNK - 1) / GI8_CHUNK;
+  const int64_t n1 = d.KMr, n2 = (int64_t)nch * 4 * d.KMr;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n1) d.rmax[i] = 0ull;
+    else d.rs[i - n1] = 0;
+  }
+}
+
+// rmax[i] = bits of max_n max(|Re A[i,n]|, |Im A[i,n]|) (non-negative doubles
+// order like their bit patterns).
+template <int ST>
+__global__ __launch_bounds__(256) void rowmax_kernel(const GramI8Desc* __restrict__ descs) {
+  const GramI8Desc d = descs[blockIdx.z];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d.m) return;
+  const int per = (d.k + gridDim.y - 1) / gridDim.y;
+  const int n0 = blockIdx.y * per, n1 = min(d.k, n0 + per);
+  double mx = 0.0;
+  for (int n = n0; n < n1; ++n) {
+    const cd v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, n), i, d.kmp);
+    mx = fmax(mx, fmax(fabs(v.re), fabs(v.im)));
+  }
+  if (n1 > n0) atomicMax(&d.rmax[i], (unsigned long long)__double_as_longlong(mx));
+}
+
+// Digit planes.  Block: 64 rows x 256 columns (four column groups of 64, each
+// thread 16 consecutive columns of one row).  Rows >= m and columns >= k get
+// zero digits.
+template <int ST>
+__global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict__ descs) {
+  const GramI8Desc d = descs[blockIdx.z];
+  const int row = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int gi = blockIdx.y * 64 + row;
+  const int cb = blockIdx.x * 256;
+  if (blockIdx.y * 64 >= d.KMr || cb >= d.ldS) return;
+  __shared__ int red[4][4][64];   // [column group][digit][row]
+  double mx = gi < d.m ? __longlong_as_double((long long)d.rmax[gi]) : 0.0;
+  int E = 0;
+  if (mx > 0.0) (void)frexp(mx, &E);
+  const double sc = ldexp(1.0, 30 - E);
+  const int64_t plane = (int64_t)d.KMr * d.ldS;
+  int rsum[4] = {0, 0, 0, 0};
+  for (int c4 = 0; c4 < 4; ++c4) {
+    const int n0 = cb + 64 * c4 + 16 * cg;
+    if (n0 >= d.ldS) break;
+    uint32_t pk[4][2][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) pk[s][p][w] = 0u;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int gn = n0 + e;
+      cd v = {0.0, 0.0};
+      if (gi < d.m && gn < d.k) v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
+      const long long qv[2] = {llrint(v.re * sc), llrint(v.im * sc)};
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        long long x = qv[p];
+        int dg[4];
+#pragma unroll
+        for (int s = 3; s >= 1; --s) {
+          const int lo = (int)(int8_t)(uint8_t)(x & 0xff);
+          dg[s] = lo;
+          x = (x - lo) >> 8;
+        }
+        dg[0] = (int)x;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          pk[s][p][e >> 2] |= ((uint32_t)(uint8_t)dg[s]) << (8 * (e & 3));
+          if (p == 1) rsum[s] += dg[s];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        int8_t* dst = d.S + (2 * s + p) * plane + (int64_t)gi * d.ldS + n0;
+        *reinterpret_cast<uint4*>(dst) = make_uint4(pk[s][p][0], pk[s][p][1], pk[s][p][2], pk[s][p][3]);
+      }
+  }
+  // row sums of the imaginary digits over this block's columns (one chunk)
+#pragma unroll
+  for (int s = 0; s < 4; ++s) red[cg][s][row] = rsum[s];
+  __syncthreads();
+  {
+    const int s = threadIdx.x >> 6;   // thread (s, row) adds the four column groups
+    const int v = red[0][s][row] + red[1][s][row] + red[2][s][row] + red[3][s][row];
+    const int chunk = cb / GI8_CHUNK;
+    if (v != 0) atomicAdd(&d.rs[((int64_t)chunk * 4 + s) * d.KMr + gi], v);
+  }
+}
+
+__device__ inline void tri_tile_i(int x, int* ti, int* tj) {
+  int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= x) ++i;
+  while (i * (i + 1) / 2 > x) --i;
+  *ti = i;
+  *tj = x - i * (i + 1) / 2;
+}
+
+using Panel = int8_t[2][4][2][GT][GROW];   // [L/R][digit][re/im][row][bytes]
+constexpr int NCLS = 5;                      // classes c = s + t = 0..4
+
+// Digit s of the wave's two L row blocks (real, imaginary, NOT of real).
+struct LDigit { v4i r[2], i[2], nr[2]; };
+template <int S>
+__device__ inline LDigit load_l(const Panel& sp, int wr, int r16, int kq) {
+  LDigit L;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    L.r[a] = *reinterpret_cast<const v4i*>(&sp[0][S][0][wr + 16 * a + r16][16 * kq]);
+    L.i[a] = *reinterpret_cast<const v4i*>(&sp[0][S][1][wr + 16 * a + r16][16 * kq]);
+    L.nr[a] = ~L.r[a];
+  }
+  return L;
+}
+// Accumulate the products of an L digit with R digit T into class slot C.
+template <int T, int C>
+__device__ inline void pair_mma(const Panel& sp, const LDigit& L, int wc, int r16, int kq,
+                                v4i (&re)[NCLS][2][2], v4i (&im)[NCLS][2][2]) {
+  v4i rr[2], ri[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    rr[b] = *reinterpret_cast<const v4i*>(&sp[1][T][0][wc + 16 * b + r16][16 * kq]);
+    ri[b] = *reinterpret_cast<const v4i*>(&sp[1][T][1][wc + 16 * b + r16][16 * kq]);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.r[a], rr[b], re[C][a][b], 0, 0, 0);
+      im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], rr[b], im[C][a][b], 0, 0, 0);
+      re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], ri[b], re[C][a][b], 0, 0, 0);
+      im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.nr[a], ri[b], im[C][a][b], 0, 0, 0);
+    }
+}
+
+// One stage of 64 columns: the 13 pairs grouped by L digit (one live at a time).
+__device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
+                             v4i (&re)[NCLS][2][2], v4i (&im)[NCLS][2][2]) {
+  { const LDigit L = load_l<0>(sp, wr, r16, kq);
+    pair_mma<0, 0>(sp, L, wc, r16, kq, re, im);
+    pair_mma<1, 1>(sp, L, wc, r16, kq, re, im);
+    pair_mma<2, 2>(sp, L, wc, r16, kq, re, im);
+    pair_mma<3, 3>(sp, L, wc, r16, kq, re, im); }
+  __builtin_amdgcn_sched_barrier(0);
+  { const LDigit L = load_l<1>(sp, wr, r16, kq);
+    pair_mma<0, 1>(sp, L, wc, r16, kq, re, im);
+    pair_mma<1, 2>(sp, L, wc, r16, kq, re, im);
+    pair_mma<2, 3>(sp, L, wc, r16, kq, re, im);
+    pair_mma<3, 4>(sp, L, wc, r16, kq, re, im); }
+  __builtin_amdgcn_sched_barrier(0);
+  { const LDigit L = load_l<2>(sp, wr, r16, kq);
+    pair_mma<0, 2>(sp, L, wc, r16, kq, re, im);
+    pair_mma<1, 3>(sp, L, wc, r16, kq, re, im);
+    pair_mma<2, 4>(sp, L, wc, r16, kq, re, im); }
+  __builtin_amdgcn_sched_barrier(0);
+  { const LDigit L = load_l<3>(sp, wr, r16, kq);
+    pair_mma<0, 3>(sp, L, wc, r16, kq, re, im);
+    pair_mma<1, 4>(sp, L, wc, r16, kq, re, im); }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// One chunk of columns [chunk * GI8_CHUNK, +GI8_CHUNK): chunk 0 writes
+// C = G_0 + diag I, later chunks add.
+__global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restrict__ descs, int chunk) {
+  const GramI8Desc d = descs[blockIdx.y];
+  int ti, tj;
+  tri_tile_i(blockIdx.x, &ti, &tj);
+  const int i0 = ti * GT, j0 = tj * GT;
+  if (i0 >= d.m) return;
+  const int n0 = chunk * GI8_CHUNK;
+  if (chunk > 0 && n0 >= d.ldS) return;   // nothing to add
+  const int n1 = min(n0 + GI8_CHUNK, d.ldS);
+  __shared__ __align__(16) Panel sp;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int r16 = lane & 15, kq = lane >> 4;
+  v4i re[NCLS][2][2], im[NCLS][2][2];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        re[c][a][b] = v4i{0, 0, 0, 0};
+        im[c][a][b] = v4i{0, 0, 0, 0};
+      }
+  // staging: 16 planes (L/R x digit x re/im) x 64 rows x 64 bytes per stage;
+  // thread t moves row t >> 2, quarter t & 3 of every plane (piece e = plane).
+  const int64_t plane = (int64_t)d.KMr * d.ldS;
+  const int prow = t >> 2, pq = t & 3;
+  const int8_t* srcL = d.S + (int64_t)(i0 + prow) * d.ldS + 16 * pq;
+  const int8_t* srcR = d.S + (int64_t)(j0 + prow) * d.ldS + 16 * pq;
+  int8_t* dst0 = &sp[0][0][0][prow][16 * pq];
+  constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
+  u4v pf[16];
+  if (n0 < n1) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      pf[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + n0);
+  }
+  for (int nb = n0; nb < n1; nb += GKS) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pf[e];
+    __syncthreads();
+    if (nb + GKS < n1) {   // next stage in flight during the products
+      const int nx = nb + GKS;
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        pf[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + nx);
+    }
+    kstep(sp, wr, wc, r16, kq, re, im);
+  }
+  // ---- epilogue: FP64 sum of the classes, lower triangle and its mirror
+  const int* rs = d.rs + (int64_t)chunk * 4 * d.KMr;
+  int cre[2][NCLS];   // imaginary correction: sum of rs_t over the class's pairs
+  double sj[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int j = j0 + wc + 16 * b + r16;
+    int r4[4] = {0, 0, 0, 0};
+    double mx = 0.0;
+    if (j < d.m) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r4[q] = rs[(int64_t)q * d.KMr + j];
+      mx = __longlong_as_double((long long)d.rmax[j]);
+    }
+    int E = 0;
+    if (mx > 0.0) (void)frexp(mx, &E);
+    sj[b] = ldexp(1.0, E - 6);
+    // class c holds the pairs (c - t, t), max(0, c - 3) <= t <= min(3, c)
+    cre[b][0] = r4[0];
+    cre[b][1] = r4[0] + r4[1];
+    cre[b][2] = r4[0] + r4[1] + r4[2];
+    cre[b][3] = r4[0] + r4[1] + r4[2] + r4[3];
+    cre[b][4] = r4[1] + r4[2] + r4[3];
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + wr + 16 * a + 4 * kq + r;
+      const double mx = i < d.m ? __longlong_as_double((long long)d.rmax[i]) : 0.0;
+      int E = 0;
+      if (mx > 0.0) (void)frexp(mx, &E);
+      const double si = ldexp(1.0, E - 6);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = j0 + wc + 16 * b + r16;
+        if (i >= d.m || j >= d.m || j > i) continue;
+        // smallest class first: every partial sum keeps full FP64 accuracy
+        double vr = 0.0, vi = 0.0;
+#pragma unroll
+        for (int c = NCLS - 1; c >= 0; --c) {
+          const double wgt = ldexp(1.0, -8 * c);
+          vr += (double)re[c][a][b][r] * wgt;
+          vi += ((double)im[c][a][b][r] + (double)cre[b][c]) * wgt;
+        }
+        cd v = {vr * (si * sj[b]), vi * (si * sj[b])};
+        cd* cij = d.C + (int64_t)j * d.ldc + i;
+        if (chunk > 0) { v.re += cij->re; v.im += cij->im; }
+        else if (i == j) v.re += d.diag;
+        if (i == j) v.im = 0.0;
+        *cij = v;
+        if (i != j) d.C[(int64_t)i * d.ldc + j] = cd{v.re, -v.im};
+      }
+    }
+}
+
+template <int ST>
+void launch_prep(const GramI8Desc* d, int batch, int KMr, int ldS, int max_k, hipStream_t s) {
+  const int nb = std::max(1, std::min(2048, (KMr * ((ldS + GI8_CHUNK - 1) / GI8_CHUNK) * 5 + 255) / 256));
+  clear_kernel<<<dim3(nb, batch), 256, 0, s>>>(d);
+  const int cy = std::max(1, std::min(64, max_k / 256));
+  rowmax_kernel<ST><<<dim3((KMr + 255) / 256, cy, batch), 256, 0, s>>>(d);
+  slice_kernel<ST><<<dim3((ldS + 255) / 256, KMr / 64, batch), 256, 0, s>>>(d);
+}
+
+}  // namespace
+
+size_t gram_i8_workspace(int m, int k) {
+  const size_t KMr = (size_t)round_up_i(m, 64), ldS = (size_t)round_up_i(std::max(k, 1), 64);
+  const size_t nch = (ldS + GI8_CHUNK - 1) / GI8_CHUNK;
+  return 8 * KMr * ldS + 8 * KMr + 4 * 4 * KMr * nch + 256;
+}
+
+void gram_i8_layout(GramI8Desc& d, void* base) {
+  d.KMr = round_up_i(d.m, 64);
+  d.ldS = round_up_i(std::max(d.k, 1), 64);
+  char* p = static_cast<char*>(base);
+  d.S = reinterpret_cast<int8_t*>(p);
+  p += 8 * (size_t)d.KMr * d.ldS;
+  d.rmax = reinterpret_cast<unsigned long long*>(p);
+  p += 8 * (size_t)d.KMr;
+  d.rs = reinterpret_cast<int*>(p);
+}
+
+void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
+                     hipStream_t s) {
+  if (batch <= 0 || max_m <= 0) return;
+  const int KMr = round_up_i(max_m, 64), ldS = round_up_i(std::max(max_k, 1), 64);
+  switch (st) {
+    case ST_FP32: launch_prep<ST_FP32>(d_desc, batch, KMr, ldS, max_k, s); break;
+    case ST_FP16P: launch_prep<ST_FP16P>(d_desc, batch, KMr, ldS, max_k, s); break;
+    case ST_BF16P: launch_prep<ST_BF16P>(d_desc, batch, KMr, ldS, max_k, s); break;
+    case ST_MF: launch_prep<ST_MF>(d_desc, batch, KMr, ldS, max_k, s); break;
+    default: return;
+  }
+  const int nt = KMr / GT;
+  const int nch = (ldS + GI8_CHUNK - 1) / GI8_CHUNK;
+  for (int c = 0; c < nch; ++c)
+    gram_i8_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(d_desc, c);
+}

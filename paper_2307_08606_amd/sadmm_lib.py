@@ -45,7 +45,7 @@ class sadmm_params(C.Structure):
         ("max_iter", C.c_int32), ("stop", C.c_int32), ("check_every", C.c_int32),
         ("prune", C.c_int32), ("Kp", C.c_int32), ("eps_p", C.c_double),
         ("prune_mode", C.c_int32), ("kkt", C.c_int32), ("kkt_tol", C.c_double),
-        ("storage", C.c_int32), ("reuse_factor", C.c_int32),
+        ("storage", C.c_int32), ("reuse_factor", C.c_int32), ("gram", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -152,7 +152,7 @@ class Solver:
     def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
                  eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=1e-2, storage="fp32",
-                 reuse_factor=True, stream=None):
+                 reuse_factor=True, gram="int8", stream=None):
         p = sadmm_params()
         sadmm_default_params(C.byref(p))
         p.Q, p.K, p.M, p.N = Q, K, M, N
@@ -164,6 +164,7 @@ class Solver:
         p.kkt, p.kkt_tol = int(bool(kkt)), kkt_tol
         p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         p.reuse_factor = int(bool(reuse_factor))
+        p.gram = {"int8": 0, "fp64": 1}[gram]
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
