@@ -80,6 +80,8 @@ struct sadmm_s {
   GemmDesc* gemm_d = nullptr;
   HpdDesc* hpd_d = nullptr;
   GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
+  int2* tiles_d = nullptr;       // Gram tile order (tri_tile_order)
+  int ntiles = 0;
   void* gi8_ws = nullptr;        // its digit-plane workspace
   size_t gi8_ws_bytes = 0;
   cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Xg = nullptr;
@@ -311,7 +313,7 @@ int gram_integer(sadmm_t h, const std::vector<int>& qs, double rho) {
       max_k = std::max(max_k, d.k);
     }
     HIPCHK(h, hipMemcpyAsync(h->gi8_d, gd.data(), sizeof(GramI8Desc) * n, hipMemcpyHostToDevice, h->s));
-    gram_i8_batched(h->gi8_d, (int)n, h->KMp, max_k, h->st, h->s);
+    gram_i8_batched(h->gi8_d, (int)n, h->KMp, max_k, h->st, h->tiles_d, h->ntiles, h->s);
     HIPCHK(h, hipGetLastError());
   }
   return SADMM_OK;
@@ -339,7 +341,7 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
     TRY(gram_integer(h, qs, rho));
   } else {
     HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
-    zgemm_batched(h->gemm_d, (int)qs.size(), h->KMp, h->KMp, h->st, h->st, OP_N, OP_C, true, h->s);
+    herk_batched(h->gemm_d, (int)qs.size(), h->KMp, h->st, h->tiles_d, h->ntiles, h->s);
   }
   prof_end(h, SADMM_KC_GRAM, pe);
   for (int q : qs) {
@@ -916,6 +918,13 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   A_(dalloc_t(h, &h->gemm_d, sizeof(GemmDesc) * std::max(Q, 4)));
   A_(dalloc_t(h, &h->hpd_d, sizeof(HpdDesc) * Q));
   A_(dalloc_t(h, &h->gi8_d, sizeof(GramI8Desc) * Q));
+  {
+    const std::vector<int2> order = tri_tile_order((KMp + 63) / 64);
+    h->ntiles = (int)order.size();
+    A_(dalloc_t(h, &h->tiles_d, sizeof(int2) * order.size()));
+    A_(hipMemcpy(h->tiles_d, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice) == hipSuccess
+           ? SADMM_OK : fail_msg(h, SADMM_E_HIP, "tile order upload"));
+  }
   A_(dalloc_t(h, &h->Ar, sizeof(cd) * (size_t)KMp * h->rmax));
   A_(dalloc_t(h, &h->V, sizeof(cd) * (size_t)KMp * h->rmax));
   A_(dalloc_t(h, &h->Tm, sizeof(cd) * (size_t)KMp * h->rmax));

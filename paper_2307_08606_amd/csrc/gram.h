@@ -39,6 +39,7 @@ size_t gram_i8_workspace(int m, int k);
 void gram_i8_layout(GramI8Desc& d, void* base);
 
 // C = Ahat Ahat^H + diag I for a batch of operators.  d_desc: device copy of
-// the descriptors; max_m / max_k: largest m and k in the batch.
+// the descriptors; max_m / max_k: largest m and k in the batch; tiles: device
+// copy of tri_tile_order(ceil(max_m / 64)) (linalg.h).
 void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
-                     hipStream_t s);
+                     const int2* tiles, int ntiles, hipStream_t s);

@@ -11,7 +11,8 @@
 // The subtraction uses bitwise NOT of the real digits (~d = -d - 1, exact in
 // int8 for every d) and adds back the sum of the imaginary digits of row j.
 //
-// Work-group: 64 x 64 complex tile of the lower triangle, four waves of
+// Work-group: 64 x 64 complex tile of the lower triangle (XCD-aware order, see
+// tri_tile_order), four waves of
 // 32 x 32 (2 x 2 blocks of 16 x 16), each accumulating all 13 digit pairs with
 // s + t <= 4 into five int32 class accumulators (c = s + t).
 // Lane layout of the instruction: lane l carries A row l % 16 and B column
@@ -21,6 +22,7 @@
 #include <algorithm>
 
 #include "gram.h"
+#include "linalg.h"
 
 namespace {
 
@@ -132,14 +134,6 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
   }
 }
 
-__device__ inline void tri_tile_i(int x, int* ti, int* tj) {
-  int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= x) ++i;
-  while (i * (i + 1) / 2 > x) --i;
-  *ti = i;
-  *tj = x - i * (i + 1) / 2;
-}
-
 using Panel = int8_t[2][4][2][GT][GROW];   // [L/R][digit][re/im][row][bytes]
 constexpr int NCLS = 5;                      // classes c = s + t = 0..4
 
@@ -205,10 +199,11 @@ __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
 
 // One chunk of columns [chunk * GI8_CHUNK, +GI8_CHUNK): chunk 0 writes
 // C = G_0 + diag I, later chunks add.
-__global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restrict__ descs, int chunk) {
+__global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restrict__ descs, int chunk,
+                                                       const int2* __restrict__ tiles, int ntiles) {
   const GramI8Desc d = descs[blockIdx.y];
   int ti, tj;
-  tri_tile_i(blockIdx.x, &ti, &tj);
+  if (!xcd_tile(tiles, ntiles, &ti, &tj)) return;
   const int i0 = ti * GT, j0 = tj * GT;
   if (i0 >= d.m) return;
   const int n0 = chunk * GI8_CHUNK;
@@ -340,7 +335,7 @@ void gram_i8_layout(GramI8Desc& d, void* base) {
 }
 
 void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
-                     hipStream_t s) {
+                     const int2* tiles, int ntiles, hipStream_t s) {
   if (batch <= 0 || max_m <= 0) return;
   const int KMr = round_up_i(max_m, 64), ldS = round_up_i(std::max(max_k, 1), 64);
   switch (st) {
@@ -350,8 +345,7 @@ void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, 
     case ST_MF: launch_prep<ST_MF>(d_desc, batch, KMr, ldS, max_k, s); break;
     default: return;
   }
-  const int nt = KMr / GT;
   const int nch = (ldS + GI8_CHUNK - 1) / GI8_CHUNK;
   for (int c = 0; c < nch; ++c)
-    gram_i8_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(d_desc, c);
+    gram_i8_kernel<<<dim3(8 * ((ntiles + 7) / 8), batch), 256, 0, s>>>(d_desc, c, tiles, ntiles);
 }

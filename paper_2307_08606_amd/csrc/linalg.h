@@ -1,6 +1,8 @@
 // FP64 complex linear algebra used to build and update the per-sensor factor
 // W_q = ((c/mu) I + Ahat_q Ahat_q^H)^{-1} (x-update of eq. (3) in Woodbury form).
 #pragma once
+#include <vector>
+
 #include "common.h"
 
 enum : int { OP_N = 0, OP_C = 1 };   // op(X) = X or X^H
@@ -23,6 +25,29 @@ struct GemmDesc {
 // diagonal and mirrors them (C must then be Hermitian: m == n).
 void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int sta, int stb,
                    int opa, int opb, bool herm, hipStream_t s);
+
+// Order of the lower-triangle tiles (ti >= tj) of an nt x nt tile grid for the
+// Hermitian products: blocks of 4 tile rows x 8 tile columns, so that the
+// tiles one XCD runs together (work-groups are dealt to the 8 XCDs in turn,
+// and XCD x takes a contiguous slice of this list) share row and column panels
+// in its L2.
+std::vector<int2> tri_tile_order(int nt);
+// Work-group -> tile: XCD x = b % 8 takes list entries [x P, (x + 1) P),
+// P = ceil(ntiles / 8); the grid has 8 P work-groups.
+__device__ inline bool xcd_tile(const int2* tiles, int ntiles, int* ti, int* tj) {
+  const int per = (ntiles + 7) >> 3;
+  const int p = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (p >= ntiles) return false;
+  const int2 t = tiles[p];
+  *ti = t.x;
+  *tj = t.y;
+  return true;
+}
+
+// C = A A^H + diag I (Hermitian, FP64 matrix instructions) for operators in
+// storage st; tiles: device copy of tri_tile_order(ceil(max_m / 64)).
+void herk_batched(const GemmDesc* d_desc, int batch, int max_m, int st, const int2* tiles,
+                  int ntiles, hipStream_t s);
 
 // One matrix of a batched Hermitian-positive-definite inverse.
 struct HpdDesc {

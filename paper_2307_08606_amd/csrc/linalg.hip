@@ -426,8 +426,8 @@ __global__ void identity_pad_kernel(cd* G, int n, int n_pad, double diag_add) {
 // the operator), on the FP64 16x16x4 matrix instruction.  Complex products are
 // split into real ones: with L = rows i of A and R = rows j of B,
 //   Re C = Lr Rr^T + Li Ri^T,   Im C = Li Rr^T - Lr Ri^T.
-// Work-group: 64 x 64 complex tile of the lower triangle (tiles enumerated
-// triangularly), four waves of 32 x 32 (2 x 2 blocks of 16 x 16).  Panels of
+// Work-group: 64 x 64 complex tile of the lower triangle (tile order of
+// tri_tile_order, dealt to XCDs by xcd_tile), four waves of 32 x 32 (2 x 2 blocks of 16 x 16).  Panels of
 // HK pixel columns are staged in LDS as FP64 real/imaginary planes; the next
 // panel is fetched into registers while the current one is multiplied.
 // Operand lane layout of the instruction: lane l carries A[l % 16][l / 16] and
@@ -436,15 +436,6 @@ __global__ void identity_pad_kernel(cd* G, int n, int n_pad, double diag_add) {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int HM = 64, HK = 32, HLD = 80;   // HLD: padded LDS row of doubles
 constexpr int HPF = HK / 4;                  // panel elements per thread
-
-__device__ inline void tri_tile(int x, int* ti, int* tj) {
-  // x -> (ti, tj), ti >= tj, x = ti (ti + 1) / 2 + tj
-  int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= x) ++i;
-  while (i * (i + 1) / 2 > x) --i;
-  *ti = i;
-  *tj = x - i * (i + 1) / 2;
-}
 
 // Panel staging: each thread fetches HPF elements of a 64-row x HK-column panel
 // (rows contiguous across lanes) into registers, then stores them to LDS as
@@ -472,10 +463,11 @@ __device__ inline void store_panel(const cd (&v)[HPF], double (*dst)[HK][HLD]) {
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void herk_mfma_kernel(const GemmDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void herk_mfma_kernel(const GemmDesc* __restrict__ descs,
+                                                         const int2* __restrict__ tiles, int ntiles) {
   const GemmDesc d = descs[blockIdx.y];
   int ti, tj;
-  tri_tile(blockIdx.x, &ti, &tj);
+  if (!xcd_tile(tiles, ntiles, &ti, &tj)) return;
   const int i0 = ti * HM, j0 = tj * HM;
   if (i0 >= d.m) return;
   __shared__ double sL[2][HK][HLD];
@@ -557,9 +549,8 @@ __global__ __launch_bounds__(256) void herk_mfma_kernel(const GemmDesc* __restri
 }
 
 template <int ST>
-void launch_herk_mfma(const GemmDesc* d, int batch, int mm, hipStream_t s) {
-  const int nt = (mm + HM - 1) / HM;
-  herk_mfma_kernel<ST><<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(d);
+void launch_herk_mfma(const GemmDesc* d, int batch, const int2* tiles, int ntiles, hipStream_t s) {
+  herk_mfma_kernel<ST><<<dim3(8 * ((ntiles + 7) / 8), batch), 256, 0, s>>>(d, tiles, ntiles);
 }
 
 template <int STA, int STB, int OPA, int OPB, bool HERM>
@@ -573,17 +564,8 @@ void launch_gemm(const GemmDesc* d, int batch, int mm, int mn, hipStream_t s) {
 void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int sta, int stb,
                    int opa, int opb, bool herm, hipStream_t s) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  // Instantiated combinations: Gram of the operator in its storage (N, C, herm),
-  // and FP64 x FP64 products for the low-rank factor corrections.
-  if (stb == sta && opa == OP_N && opb == OP_C && herm) {
-    switch (sta) {
-      case ST_FP64: launch_herk_mfma<ST_FP64>(d_desc, batch, max_m, s); return;
-      case ST_FP32: launch_herk_mfma<ST_FP32>(d_desc, batch, max_m, s); return;
-      case ST_FP16P: launch_herk_mfma<ST_FP16P>(d_desc, batch, max_m, s); return;
-      case ST_BF16P: launch_herk_mfma<ST_BF16P>(d_desc, batch, max_m, s); return;
-      case ST_MF: launch_herk_mfma<ST_MF>(d_desc, batch, max_m, s); return;
-    }
-  }
+  // Instantiated combinations: FP64 x FP64 products for the low-rank factor
+  // corrections (the Gram of the operator has its own launcher, herk_batched).
   if (sta == ST_FP64 && stb == ST_FP64 && !herm) {
     if (opa == OP_N && opb == OP_N) { launch_gemm<ST_FP64, ST_FP64, OP_N, OP_N, false>(d_desc, batch, max_m, max_n, s); return; }
     if (opa == OP_C && opb == OP_N) { launch_gemm<ST_FP64, ST_FP64, OP_C, OP_N, false>(d_desc, batch, max_m, max_n, s); return; }
@@ -591,6 +573,31 @@ void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int 
   }
   if (sta == ST_FP64 && stb == ST_FP64 && herm && opa == OP_C && opb == OP_N) {
     launch_gemm<ST_FP64, ST_FP64, OP_C, OP_N, true>(d_desc, batch, max_m, max_n, s); return;
+  }
+}
+
+std::vector<int2> tri_tile_order(int nt) {
+  constexpr int SR = 4, SC = 8;
+  std::vector<int2> out;
+  out.reserve((size_t)nt * (nt + 1) / 2);
+  for (int I = 0; I * SR < nt; ++I) {
+    const int r1 = std::min(nt, I * SR + SR);
+    for (int J = 0; J * SC < r1; ++J)
+      for (int ti = I * SR; ti < r1; ++ti)
+        for (int tj = J * SC; tj < std::min(J * SC + SC, ti + 1); ++tj) out.push_back(make_int2(ti, tj));
+  }
+  return out;
+}
+
+void herk_batched(const GemmDesc* d_desc, int batch, int max_m, int st, const int2* tiles,
+                  int ntiles, hipStream_t s) {
+  if (batch <= 0 || max_m <= 0 || ntiles <= 0) return;
+  switch (st) {
+    case ST_FP64: launch_herk_mfma<ST_FP64>(d_desc, batch, tiles, ntiles, s); return;
+    case ST_FP32: launch_herk_mfma<ST_FP32>(d_desc, batch, tiles, ntiles, s); return;
+    case ST_FP16P: launch_herk_mfma<ST_FP16P>(d_desc, batch, tiles, ntiles, s); return;
+    case ST_BF16P: launch_herk_mfma<ST_BF16P>(d_desc, batch, tiles, ntiles, s); return;
+    case ST_MF: launch_herk_mfma<ST_MF>(d_desc, batch, tiles, ntiles, s); return;
   }
 }
 
