@@ -33,6 +33,32 @@ METRIC = ("time-to-NMSE≤1e-3 vs FP64 oracle: learned+pruned vs plain SADMM; "
           "iters/s; HBM GB/s")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+INT8_PEAK_TOPS = 5000.0        # dense int8 matrix peak, tera-ops/s
+# int8 operations per complex multiply-add of the integer Gram: 13 digit pairs
+# x 4 real products x 2 (multiply + add)
+INT8_OPS_PER_CMAC = 13 * 4 * 2
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "gram_i8_c2_pmc.json")
+GRAM_SOURCES = ("paper_2307_08606_amd/csrc/gram_i8.hip", "paper_2307_08606_amd/csrc/gram.h")
+
+
+def gram_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in GRAM_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the integer Gram kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since."""
+    try:
+        pm = json.load(open(PMC_SUMMARY))
+    except (OSError, ValueError):
+        return None
+    if pm.get("source_sha256") != gram_source_hash():
+        return None
+    return pm.get("traffic_bytes_per_launch")
 
 
 def parse():
@@ -212,24 +238,28 @@ def main():
 
     head = results[variants[0][0]]
     st = head["stats"]
-    # dominant kernel class of the headline solve
-    dom = max(st, key=lambda k: st[k][1])
-    n, ms, work = st[dom]
-    if dom in ("gram", "inverse"):
-        achieved = work / (ms * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None)
+    # Roofline of the dominant kernel of the headline solve: the Gram of the
+    # factor build (the integer int8 kernel for non-FP64 storage).
+    n, ms, work = st["gram"]
+    integer = args.storage != "fp64"
+    if integer:
+        ops = work / 8.0 * INT8_OPS_PER_CMAC          # work: FP64-equivalent flops
+        achieved = ops / (ms * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 1), peak=INT8_PEAK_TOPS, unit="TOP/s",
+                    frac=round(achieved / INT8_PEAK_TOPS, 4), traffic=measured_traffic(),
+                    kernel="gram_i8_kernel (exact integer Gram Ahat Ahat^H, int8 16x16x64 MFMA)",
+                    fp64_equivalent_tflops=round(work / (ms * 1e-3) / 1e12, 1))
+        per_launch = ops / max(n, 1)
     else:
-        achieved = work / (ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
-    roof["kernel"] = {"gram": "herk_mfma_kernel (FP64 Gram Ahat Ahat^H on 16x16x4 FP64 MFMA)",
-                      "inverse": "chol/trtri/xhx kernels", "fwd": "fwd_iter_kernel",
-                      "xupd": "coldot_kernel<EPI_XUPD>", "wprod": "coldot_kernel<EPI_W>",
-                      "pixel": "pixel/finalize/ssc kernels"}[dom]
+        achieved = work / (ms * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
+                    kernel="herk_mfma_kernel (FP64 Gram Ahat Ahat^H on 16x16x4 FP64 MFMA)")
+        per_launch = work / max(n, 1)
     roof["launches"] = n
     roof["avg_launch_ms"] = round(ms / max(n, 1), 4)
-    roof["work_per_launch"] = work / max(n, 1)
+    roof["work_per_launch"] = per_launch
+    roof["class_ms_per_solve"] = {k: round(v[1] / args.steps, 3) for k, v in st.items() if v[0]}
 
     # matrix-free operator at 512 x 512 pixels (c5 geometry): steady-state rate
     if not args.only:

@@ -253,14 +253,16 @@ int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold);
 
 /* Kernel classes timed when profiling is on. */
 enum {
-  SADMM_KC_GRAM = 0,     /* FP64 Gram Ahat Ahat^H of a factor build */
+  SADMM_KC_GRAM = 0,     /* Gram Ahat Ahat^H of a factor build (matrix-instruction kernel;
+                            one launch per 8192-column chunk on the integer path) */
   SADMM_KC_INVERSE = 1,  /* Cholesky, triangular inverse and W = X^H X */
   SADMM_KC_FWD = 2,      /* forward product Ahat v (+ partial-sum reduction) */
   SADMM_KC_WPROD = 3,    /* W t */
   SADMM_KC_XUPD = 4,     /* adjoint product Ahat^H w with the fused x-update */
   SADMM_KC_PIXEL = 5,    /* image/dual update, residuals, SSC check */
   SADMM_KC_CNN = 6,      /* matched filter + CNN inference before a solve */
-  SADMM_KC_COUNT = 7
+  SADMM_KC_SLICE = 7,    /* integer Gram: row scales and digit planes of the operator */
+  SADMM_KC_COUNT = 8
 };
 
 /* level 0: off.  level 1: HIP events around the factor build and update
@@ -272,8 +274,9 @@ int sadmm_set_profiling(sadmm_t h, int32_t level);
 /* Launch count, summed event time (ms) and algorithmic work of a kernel class
  * since the last sadmm_set_profiling call.  Work is in flops for GRAM and
  * INVERSE (complex multiply-add = 8 flops; Hermitian product counts one
- * triangle) and in bytes for the others (operator, factor and state bytes each
- * launch must move at least once). */
+ * triangle; the integer Gram reports the same FP64-equivalent count) and in
+ * bytes for the others (operator, factor and state bytes each launch must move
+ * at least once). */
 int sadmm_get_kernel_stats(sadmm_t h, int32_t kclass, int32_t* launches, double* total_ms,
                            double* work);
 

@@ -313,7 +313,16 @@ int gram_integer(sadmm_t h, const std::vector<int>& qs, double rho) {
       max_k = std::max(max_k, d.k);
     }
     HIPCHK(h, hipMemcpyAsync(h->gi8_d, gd.data(), sizeof(GramI8Desc) * n, hipMemcpyHostToDevice, h->s));
-    gram_i8_batched(h->gi8_d, (int)n, h->KMp, max_k, h->st, h->tiles_d, h->ntiles, h->s);
+    int pe = prof_begin(h);
+    gram_i8_prepare(h->gi8_d, (int)n, h->KMp, max_k, h->st, h->s);
+    prof_end(h, SADMM_KC_SLICE, pe);
+    for (size_t i = 0; i < n; ++i)   // operator read once, digit planes written once
+      prof_work(h, SADMM_KC_SLICE, (double)h->nq[qs[g0 + i]] * h->KMp * (op_bytes(h) + 8.0));
+    for (int c = 0; c < gram_i8_chunks(max_k); ++c) {
+      pe = prof_begin(h);
+      gram_i8_chunk(h->gi8_d, (int)n, c, h->tiles_d, h->ntiles, h->s);
+      prof_end(h, SADMM_KC_GRAM, pe);
+    }
     HIPCHK(h, hipGetLastError());
   }
   return SADMM_OK;
@@ -336,14 +345,15 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
     hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q]};
   }
   HIPCHK(h, hipMemcpyAsync(h->hpd_d, hd.data(), sizeof(HpdDesc) * hd.size(), hipMemcpyHostToDevice, h->s));
-  int pe = prof_begin(h);
+  int pe = -1;
   if (h->p.gram == 0 && h->st != ST_FP64) {
     TRY(gram_integer(h, qs, rho));
   } else {
     HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
+    pe = prof_begin(h);
     herk_batched(h->gemm_d, (int)qs.size(), h->KMp, h->st, h->tiles_d, h->ntiles, h->s);
+    prof_end(h, SADMM_KC_GRAM, pe);
   }
-  prof_end(h, SADMM_KC_GRAM, pe);
   for (int q : qs) {
     // Hermitian product: KM(KM+1)/2 entries, N_q complex MACs each (8 flops)
     prof_work(h, SADMM_KC_GRAM, 8.0 * 0.5 * h->KM * (h->KM + 1.0) * h->nq[q]);

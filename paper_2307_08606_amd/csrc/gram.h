@@ -38,8 +38,15 @@ size_t gram_i8_workspace(int m, int k);
 // Carve the workspace at `base` into d.S, d.rmax, d.rs (sets KMr, ldS).
 void gram_i8_layout(GramI8Desc& d, void* base);
 
-// C = Ahat Ahat^H + diag I for a batch of operators.  d_desc: device copy of
-// the descriptors; max_m / max_k: largest m and k in the batch; tiles: device
-// copy of tri_tile_order(ceil(max_m / 64)) (linalg.h).
-void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
-                     const int2* tiles, int ntiles, hipStream_t s);
+// C = Ahat Ahat^H + diag I for a batch of operators, in two phases.
+// gram_i8_prepare: row scales and digit planes (reads the operator once).
+// gram_i8_chunk:   the int8 products of columns [c * GI8_CHUNK, +GI8_CHUNK);
+//                  chunk 0 writes C, later chunks add to it (launch them in
+//                  order, c < gram_i8_chunks(max_k)).
+// d_desc: device copy of the descriptors; max_m / max_k: largest m and k in
+// the batch; tiles: device copy of tri_tile_order(ceil(max_m / 64)) (linalg.h).
+void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
+                     hipStream_t s);
+int gram_i8_chunks(int max_k);
+void gram_i8_chunk(const GramI8Desc* d_desc, int batch, int chunk, const int2* tiles, int ntiles,
+                   hipStream_t s);

@@ -334,8 +334,8 @@ void gram_i8_layout(GramI8Desc& d, void* base) {
   d.rs = reinterpret_cast<int*>(p);
 }
 
-void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
-                     const int2* tiles, int ntiles, hipStream_t s) {
+void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
+                     hipStream_t s) {
   if (batch <= 0 || max_m <= 0) return;
   const int KMr = round_up_i(max_m, 64), ldS = round_up_i(std::max(max_k, 1), 64);
   switch (st) {
@@ -345,7 +345,14 @@ void gram_i8_batched(const GramI8Desc* d_desc, int batch, int max_m, int max_k, 
     case ST_MF: launch_prep<ST_MF>(d_desc, batch, KMr, ldS, max_k, s); break;
     default: return;
   }
-  const int nch = (ldS + GI8_CHUNK - 1) / GI8_CHUNK;
-  for (int c = 0; c < nch; ++c)
-    gram_i8_kernel<<<dim3(8 * ((ntiles + 7) / 8), batch), 256, 0, s>>>(d_desc, c, tiles, ntiles);
+}
+
+int gram_i8_chunks(int max_k) {
+  return (round_up_i(std::max(max_k, 1), 64) + GI8_CHUNK - 1) / GI8_CHUNK;
+}
+
+void gram_i8_chunk(const GramI8Desc* d_desc, int batch, int chunk, const int2* tiles, int ntiles,
+                   hipStream_t s) {
+  if (batch <= 0 || ntiles <= 0) return;
+  gram_i8_kernel<<<dim3(8 * ((ntiles + 7) / 8), batch), 256, 0, s>>>(d_desc, chunk, tiles, ntiles);
 }

@@ -98,7 +98,8 @@ sadmm_get_timing = _sig("sadmm_get_timing", C.c_int, _H, C.c_int32, C.POINTER(C.
 sadmm_set_profiling = _sig("sadmm_set_profiling", C.c_int, _H, C.c_int32)
 sadmm_get_kernel_stats = _sig("sadmm_get_kernel_stats", C.c_int, _H, C.c_int32, _P, _P, _P)
 sadmm_destroy = _sig("sadmm_destroy", None, _H)
-KERNEL_CLASSES = {"gram": 0, "inverse": 1, "fwd": 2, "wprod": 3, "xupd": 4, "pixel": 5, "cnn": 6}
+KERNEL_CLASSES = {"gram": 0, "inverse": 1, "fwd": 2, "wprod": 3, "xupd": 4, "pixel": 5, "cnn": 6,
+                  "slice": 7}
 
 sadmm_cnn_create = _sig("sadmm_cnn_create", C.c_int, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                         C.c_void_p, C.POINTER(_H))
