@@ -305,6 +305,8 @@ def main():
         extra["c5_matrix_free_factor_ms"] = round(r5["factor_ms"], 1)
         extra["c5_matrix_free_iter_ms"] = round(r5["iter_ms"], 3)
         extra["c5_matrix_free_Gelem_per_s"] = round(r5["elems_per_iter"] / (r5["iter_ms"] * 1e-3) / 1e9, 1)
+        extra["c5_matrix_free_stage_ms"] = {k: round(v[1] / max(v[0], 1), 3)
+                                            for k, v in r5["stats"].items() if v[0]}
     if "c4" in results:
         r4 = results["c4"]
         for k in ("sequential", "batched"):

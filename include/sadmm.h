@@ -62,8 +62,9 @@ typedef enum { SADMM_C128 = 0, SADMM_C64 = 1 } sadmm_dtype;
  * build.  FP16P / BF16P: operator stored as separate real and imaginary half /
  * bfloat16 planes per column, FP32 arithmetic, FP64 factor build.
  * MATRIX_FREE: no operator entries are stored; every product regenerates the
- * LFM steering entries of eq. (1) from per-pixel phase records (FP64 phase
- * fraction, FP32 complex exponential); operators must be given by
+ * LFM steering entries of eq. (1) from per-pixel phase records (an FP64 phase
+ * fraction and FP32 complex exponential every 8 rows, FP32 rotation by the
+ * per-sample phase step in between); operators must be given by
  * sadmm_set_operator_geometry. */
 typedef enum {
   SADMM_ST_FP64 = 0,

@@ -109,10 +109,19 @@ template <> struct Store<ST_FP16P> : StoreP16<ST_FP16P> {};
 template <> struct Store<ST_BF16P> : StoreP16<ST_BF16P> {};
 
 // Matrix-free LFM operator (eq. (1)): instead of stored entries, each pixel has
-// a record of 2 + 2M doubles [K, M, c0_0, d_0, ..., c0_{M-1}, d_{M-1}] with
-// c0_m = frac(f0 tau_m) and d_m = frac(bw tau_m / K) (cycles, FP64), so that
-// entry (m*K + k) = exp(-j 2 pi frac(c0_m + k d_m)).  The fraction is taken in
-// FP64 (f0 tau is several thousand cycles) and the exponential in FP32.
+// a record of 2 + 4M doubles [K, M, then per receiver m: c0_m, d_m,
+// cos(2 pi d_m), sin(2 pi d_m)] with c0_m = frac(f0 tau_m) and
+// d_m = frac(bw tau_m / K) (cycles), and entry (m*K + k) =
+// exp(-j 2 pi frac(c0_m + k d_m)).
+// Entries are generated in groups of 8 consecutive rows starting at a multiple
+// of 8.  The first row of a group (and the first row of a receiver inside it)
+// is anchored: phase fraction in FP64 (f0 tau is thousands of cycles), the
+// exponential by FP32 sincospif.  The following rows are the previous entry
+// times exp(-j 2 pi d_m) in FP32 (at most 7 steps, each a few units of 2^-24).
+// The arithmetic is written with explicit round-to-nearest operations and
+// get() replays its row's group, so every product and the Gram see identical
+// entries.
+constexpr int MF_REC_BASE = 2, MF_REC_PER_RX = 4;
 __device__ inline void mf_entry(double c0, double d, int k, float* re, float* im) {
   const double cyc = fma((double)k, d, c0);
   const float fr = (float)(cyc - floor(cyc));
@@ -125,31 +134,68 @@ template <> struct Store<ST_MF> {
   using T = float;
   static constexpr int RPT = 8;
   static constexpr int BYTES = 0;   // nothing stored per entry
+  // rows i .. i+7, i a multiple of 8
   __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
     (void)KM;
     const double* rec = reinterpret_cast<const double*>(col);
     const int K = (int)rec[0], M = (int)rec[1];
     int m = i / K, k = i - m * K;
+    float er = 0.f, ei = 0.f, rc = 0.f, rs = 0.f;
+    if ((K & (RPT - 1)) == 0) {   // the group stays within one receiver
+      if (m < M) {
+        const double* p = rec + MF_REC_BASE + MF_REC_PER_RX * m;
+        mf_entry(p[0], p[1], k, &er, &ei);
+        rc = (float)p[2];
+        rs = (float)p[3];
+      }
+      re[0] = er;
+      im[0] = ei;
+#pragma unroll
+      for (int r = 1; r < RPT; ++r) {
+        const float nr = __fmaf_rn(er, rc, __fmul_rn(ei, rs));
+        const float ni = __fmaf_rn(ei, rc, -__fmul_rn(er, rs));
+        er = nr;
+        ei = ni;
+        re[r] = er;
+        im[r] = ei;
+      }
+      return;
+    }
+    bool anchored = false;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       if (m < M) {
-        mf_entry(rec[2 + 2 * m], rec[3 + 2 * m], k, &re[r], &im[r]);
+        if (!anchored) {
+          const double* p = rec + MF_REC_BASE + MF_REC_PER_RX * m;
+          mf_entry(p[0], p[1], k, &er, &ei);
+          rc = (float)p[2];
+          rs = (float)p[3];
+          anchored = true;
+        } else {
+          // (er + j ei) * (rc - j rs)
+          const float nr = __fmaf_rn(er, rc, __fmul_rn(ei, rs));
+          const float ni = __fmaf_rn(ei, rc, -__fmul_rn(er, rs));
+          er = nr;
+          ei = ni;
+        }
+        re[r] = er;
+        im[r] = ei;
       } else {
         re[r] = 0.f;
         im[r] = 0.f;
       }
-      if (++k == K) { k = 0; ++m; }
+      if (++k == K) { k = 0; ++m; anchored = false; }
     }
   }
   __device__ static inline cd get(const void* col, int i, int KM) {
-    (void)KM;
-    const double* rec = reinterpret_cast<const double*>(col);
-    const int K = (int)rec[0], M = (int)rec[1];
-    const int m = i / K, k = i - m * K;
-    if (m >= M) return {0.0, 0.0};
-    float re, im;
-    mf_entry(rec[2 + 2 * m], rec[3 + 2 * m], k, &re, &im);
-    return {(double)re, (double)im};
+    const int g = i & ~(RPT - 1);
+    float re[RPT], im[RPT];
+    load(col, g, KM, re, im);
+    float vr = re[0], vi = im[0];
+#pragma unroll
+    for (int r = 1; r < RPT; ++r)
+      if (i - g == r) { vr = re[r]; vi = im[r]; }
+    return {(double)vr, (double)vi};
   }
 };
 

@@ -193,7 +193,7 @@ void prof_work(sadmm_t h, int cls, double w) {
 }
 // bytes per stored complex operator entry
 double op_bytes(sadmm_t h) {
-  if (h->st == ST_MF) return 8.0 * (2.0 + 2.0 * h->M) / h->KM;   // record bytes per entry
+  if (h->st == ST_MF) return 8.0 * (MF_REC_BASE + MF_REC_PER_RX * h->M) / h->KM;   // record bytes per entry
   return h->st == ST_FP64 ? 16.0 : (h->st == ST_FP32 ? 8.0 : 4.0);
 }
 
@@ -869,7 +869,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   h->s = static_cast<hipStream_t>(p->stream);
   if (h->st == ST_FP64) { h->ldA = h->KMp; h->slot = 16; }
   else if (h->st == ST_FP32) { h->ldA = h->KMp; h->slot = 8; }
-  else if (h->st == ST_MF) { h->ldA = 2 + 2 * (int64_t)h->M; h->slot = 8; }
+  else if (h->st == ST_MF) { h->ldA = MF_REC_BASE + MF_REC_PER_RX * (int64_t)h->M; h->slot = 8; }
   else { h->ldA = 2 * (int64_t)h->KMp; h->slot = 2; }
   h->chunk = 256;
   h->nchunk = (h->N + h->chunk - 1) / h->chunk;

@@ -15,8 +15,9 @@ void geometry_operator(const double* tx, const double* rx, const double* pix, in
                        double f0, double bw, int st, void* dst, int64_t ldA, int KMp,
                        hipStream_t s);
 
-// Matrix-free operator records (per pixel: K, M, frac(f0 tau_m), frac(bw tau_m / K)),
-// column stride ld doubles (>= 2 + 2M).
+// Matrix-free operator records (per pixel: K, M, then per receiver frac(f0 tau_m),
+// frac(bw tau_m / K) and the cosine and sine of 2 pi times the latter), column
+// stride ld doubles (>= 2 + 4M).
 void mf_records(const double* tx, const double* rx, const double* pix, int M, int K, int N, double f0,
                 double bw, double* rec, int64_t ld, hipStream_t s);
 

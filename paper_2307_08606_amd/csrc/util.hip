@@ -79,8 +79,13 @@ __global__ void mf_records_kernel(const double* tx, const double* rx, const doub
   for (int m = 0; m < M; ++m) {
     const double tau = (dt + hypot(px - rx[2 * m], py - rx[2 * m + 1])) / 299792458.0;
     const double a = f0 * tau, b = bw * tau / (double)K;
-    r[2 + 2 * m] = a - floor(a);
-    r[3 + 2 * m] = b - floor(b);
+    double* p = r + MF_REC_BASE + MF_REC_PER_RX * m;
+    p[0] = a - floor(a);
+    p[1] = b - floor(b);
+    double sn, cs;
+    sincospi(2.0 * p[1], &sn, &cs);   // rotation from row k to k + 1
+    p[2] = cs;
+    p[3] = sn;
   }
 }
 
