@@ -84,8 +84,10 @@ struct sadmm_s {
   int ntiles = 0;
   void* gi8_ws = nullptr;        // its digit-plane workspace
   size_t gi8_ws_bytes = 0;
-  cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Xg = nullptr;
-  std::vector<cd*> hpdD, hpdX;                // per-sensor inverse scratch
+  cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Xg = nullptr,
+     *Tg = nullptr;
+  MmDesc* mm_d = nullptr;     // GEMM descriptors of the factorisations
+  std::vector<cd*> hpdD, hpdX, hpdT;          // per-sensor inverse scratch
   int rmax = 0, rpad_max = 0;
   int chunk = 256, nchunk = 0, nblk = 0;
   double xref_norm2 = 0.0, nmse_target = 0.0;
@@ -342,7 +344,7 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
     g.kmpA = h->KMp; g.kmpB = h->KMp;
     g.lda = h->ldA; g.ldb = h->ldA; g.ldc = h->KMp;
     g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta = 0.0; g.diag = rho;
-    hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q]};
+    hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q], h->hpdT[q]};
   }
   HIPCHK(h, hipMemcpyAsync(h->hpd_d, hd.data(), sizeof(HpdDesc) * hd.size(), hipMemcpyHostToDevice, h->s));
   int pe = -1;
@@ -362,7 +364,7 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
   }
   HIPCHK(h, hipGetLastError());
   pe = prof_begin(h);
-  hpd_inverse_batched(h->hpd_d, (int)qs.size(), h->KMp, h->fail, h->s);
+  hpd_inverse_batched(hd.data(), h->hpd_d, (int)qs.size(), h->KMp, h->fail, h->mm_d, h->s);
   prof_end(h, SADMM_KC_INVERSE, pe);
   HIPCHK(h, hipGetLastError());
   for (int q : qs) h->fac_valid[q] = true;
@@ -387,14 +389,14 @@ int lowrank_update(sadmm_t h, int q, const int* d_list, int r, int sign) {
   g[2] = GemmDesc{h->V, h->Cm, h->Tm, KMp, r, r, KMp, KMp, KMp, rp, KMp, 1.0, 0.0, 0.0, 0.0};
   // W += -sign * Tm V^H
   g[3] = GemmDesc{h->Tm, h->V, h->W64[q], KMp, KMp, r, KMp, KMp, KMp, KMp, KMp, -(double)sign, 0.0, 1.0, 0.0};
-  HpdDesc hd{h->Cm, rp, h->Dg, h->Xg};
+  HpdDesc hd{h->Cm, rp, h->Dg, h->Xg, h->Tg};
   HIPCHK(h, hipMemcpyAsync(h->gemm_d, g.data(), sizeof(GemmDesc) * 4, hipMemcpyHostToDevice, h->s));
   HIPCHK(h, hipMemcpyAsync(h->hpd_d, &hd, sizeof hd, hipMemcpyHostToDevice, h->s));
   zgemm_batched(h->gemm_d, 1, KMp, r, ST_FP64, ST_FP64, OP_N, OP_N, false, h->s);
   HIPCHK(h, hipMemsetAsync(h->Cm, 0, sizeof(cd) * (size_t)rp * rp, h->s));
   set_identity_pad(h->Cm, 0, rp, 0.0, h->s);
   zgemm_batched(h->gemm_d + 1, 1, r, r, ST_FP64, ST_FP64, OP_C, OP_N, false, h->s);
-  hpd_inverse_batched(h->hpd_d, 1, rp, h->fail, h->s);
+  hpd_inverse_batched(&hd, h->hpd_d, 1, rp, h->fail, h->mm_d, h->s);
   zgemm_batched(h->gemm_d + 2, 1, KMp, r, ST_FP64, ST_FP64, OP_N, OP_N, false, h->s);
   zgemm_batched(h->gemm_d + 3, 1, KMp, KMp, ST_FP64, ST_FP64, OP_N, OP_C, false, h->s);
   hermitian_inplace(h->W64[q], KMp, KMp, h->s);
@@ -881,7 +883,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   h->J.assign(Q, nullptr); h->Jnew.assign(Q, nullptr); h->xy.assign(Q, nullptr);
   h->nq.assign(Q, N); h->op_set.assign(Q, false); h->fac_valid.assign(Q, false);
   h->facJ.assign(Q, {}); h->mask0.assign(Q, {});
-  h->hpdD.assign(Q, nullptr); h->hpdX.assign(Q, nullptr);
+  h->hpdD.assign(Q, nullptr); h->hpdX.assign(Q, nullptr); h->hpdT.assign(Q, nullptr);
   h->sens_h.assign(Q, SensorDesc{});
   h->rmax = std::min(KMp, 1024);
   h->rpad_max = round_up(h->rmax, HPD_NB);
@@ -894,6 +896,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
     A_(dalloc(h, &h->xy[q], cN));
     A_(dalloc_t(h, &h->hpdD[q], sizeof(cd) * (size_t)HPD_NB * KMp));
     A_(dalloc_t(h, &h->hpdX[q], sizeof(cd) * (size_t)KMp * KMp));
+    A_(dalloc_t(h, &h->hpdT[q], sizeof(cd) * ((size_t)KMp * KMp / 4 + 1)));
   }
   A_(dalloc(h, &h->X, cN * Q));
   A_(dalloc(h, &h->dX, cN * Q));
@@ -941,6 +944,9 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   A_(dalloc_t(h, &h->Cm, sizeof(cd) * (size_t)h->rpad_max * h->rpad_max));
   A_(dalloc_t(h, &h->Dg, sizeof(cd) * (size_t)HPD_NB * h->rpad_max));
   A_(dalloc_t(h, &h->Xg, sizeof(cd) * (size_t)h->rpad_max * h->rpad_max));
+  A_(dalloc_t(h, &h->Tg, sizeof(cd) * ((size_t)h->rpad_max * h->rpad_max / 4 + 1)));
+  A_(dalloc_t(h, &h->mm_d, sizeof(MmDesc) * std::max((size_t)Q * hpd_mm_count(KMp),
+                                                     hpd_mm_count(h->rpad_max))));
   g_create_err.clear();
   if (hipHostMalloc((void**)&h->ctl_h, sizeof(Ctl)) != hipSuccess ||
       hipHostMalloc((void**)&h->counts_h, 2 * sizeof(int)) != hipSuccess ||

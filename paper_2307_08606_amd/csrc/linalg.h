@@ -49,6 +49,17 @@ __device__ inline bool xcd_tile(const int2* tiles, int ntiles, int* ti, int* tj)
 void herk_batched(const GemmDesc* d_desc, int batch, int max_m, int st, const int2* tiles,
                   int ntiles, hipStream_t s);
 
+// One product of a batched FP64 complex GEMM on the matrix instructions,
+// C = alpha op(A) op(B) + beta C, all column-major complex128.
+struct MmDesc {
+  const cd* A;
+  const cd* B;
+  cd* C;
+  int m, n, k;
+  int lda, ldb, ldc;
+  double alpha_re, alpha_im, beta;
+};
+
 // One matrix of a batched Hermitian-positive-definite inverse.
 struct HpdDesc {
   cd* G;        // n_pad x n_pad column-major, ld = n_pad; rows/cols >= n hold identity.
@@ -56,12 +67,21 @@ struct HpdDesc {
   int n_pad;    // multiple of HPD_NB
   cd* D;        // scratch NB x n_pad: inverses of the diagonal Cholesky blocks
   cd* X;        // scratch n_pad x n_pad: X = L^{-1}
+  cd* T;        // scratch n_pad * n_pad / 4: products of the triangular inverse
 };
 constexpr int HPD_NB = 32;
+// Descriptors one matrix of order n_pad needs in the scratch d_mm below.
+size_t hpd_mm_count(int n_pad);
 // G <- G^{-1} through the Cholesky factor G = L L^H: X = L^{-1}, G^{-1} = X^H X.
-// *d_fail is set non-zero if a pivot is not positive (loss of definiteness).
-void hpd_inverse_batched(const HpdDesc* d_desc, int batch, int max_npad, int* d_fail,
-                         hipStream_t s);
+// Blocked right-looking Cholesky (NB x NB diagonal blocks factored in LDS,
+// panel and trailing update as matrix-instruction GEMMs), X by recursive
+// doubling (X21 = -X22 L21 X11 over blocks of 32, 64, ...), X^H X over the
+// nonzero k-range of each tile.  All matrices of the batch have order n_pad.
+// h_desc: host copies of the descriptors (d_desc on the device); d_mm: device
+// scratch for batch * hpd_mm_count(n_pad) descriptors.  *d_fail is set
+// non-zero if a pivot is not positive (loss of definiteness).
+void hpd_inverse_batched(const HpdDesc* h_desc, const HpdDesc* d_desc, int batch, int n_pad,
+                         int* d_fail, MmDesc* d_mm, hipStream_t s);
 
 // dst (T-complex, ld_dst) = (src + src^H) / 2 for n x n, src complex128 ld_src.
 void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, int n,

@@ -112,9 +112,11 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 
 // ------------------------------------------------------------------ HPD inverse
 // W = G^{-1} for Hermitian positive definite G through its Cholesky factor:
-//   1. blocked right-looking Cholesky G = L L^H (NB x NB diagonal blocks
-//      factored in LDS, panel solve, rank-NB trailing update of the lower part)
-//   2. X = L^{-1} by blocked forward substitution, block row by block row
+//   1. blocked right-looking Cholesky G = L L^H: NB x NB diagonal blocks
+//      factored in LDS (with their inverses), the panel L21 = G21 Lkk^{-H} and
+//      the trailing update G22 -= L21 L21^H as matrix-instruction GEMMs
+//   2. X = L^{-1} by recursive doubling: with X11, X22 the inverses of two
+//      adjacent diagonal blocks, the block below X11 is -X22 (L21 X11)
 //   3. W = X^H X
 // All steps in FP64.  (Gauss-Jordan elimination without pivoting is
 // unstable on the strongly correlated Gram matrices of radar operators.)
@@ -179,143 +181,6 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const HpdDesc* __restric
   }
 }
 
-// Panel: L[i, kb] = G[i, kb] Lkk^{-H} for rows i >= k0 + NB (in place).
-__global__ __launch_bounds__(256) void chol_panel_kernel(const HpdDesc* __restrict__ descs, int k0) {
-  const HpdDesc h = descs[blockIdx.y];
-  constexpr int NB = HPD_NB;
-  if (k0 >= h.n_pad) return;
-  __shared__ cd Ls[NB][NB + 1];   // Ls[c][r] = element (r, c) of Lkk^{-1}
-  const int t = threadIdx.x;
-  for (int e = t; e < NB * NB; e += 256) Ls[e / NB][e % NB] = h.D[(int64_t)k0 * NB + e];
-  __syncthreads();
-  const int i = k0 + NB + blockIdx.x * 256 + t;
-  if (i >= h.n_pad) return;
-  cd g[NB];
-  for (int s2 = 0; s2 < NB; ++s2) g[s2] = h.G[(int64_t)(k0 + s2) * h.n_pad + i];
-  for (int c = 0; c < NB; ++c) {
-    cd acc = {0.0, 0.0};
-    for (int s2 = 0; s2 <= c; ++s2) cfmac(acc, Ls[s2][c], g[s2]);   // g[s2] * conj(Linv(c, s2))
-    h.G[(int64_t)(k0 + c) * h.n_pad + i] = acc;
-  }
-}
-
-// Trailing update of the lower part: G[i, j] -= L[i, kb] L[j, kb]^H,
-// i >= j >= k0 + NB.  K = NB in two halves (33 KB of LDS).
-__global__ __launch_bounds__(256) void chol_update_kernel(const HpdDesc* __restrict__ descs, int k0) {
-  const HpdDesc h = descs[blockIdx.z];
-  constexpr int NB = HPD_NB;
-  constexpr int HB = NB / 2;
-  const int ti = blockIdx.x, tj = blockIdx.y;
-  if (tj > ti) return;
-  const int base = k0 + NB;
-  const int i0 = base + ti * TM, j0 = base + tj * TN;
-  if (i0 >= h.n_pad || j0 >= h.n_pad) return;
-  __shared__ cd sC[HB][TM + 1];
-  __shared__ cd sR[HB][TN + 1];
-  const int t = threadIdx.x;
-  const int tx = t & 15, ty = t >> 4;
-  cd acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = {0.0, 0.0};
-  for (int h0 = 0; h0 < NB; h0 += HB) {
-    for (int e = t; e < HB * TM; e += 256) {
-      const int ii = e % TM, c = e / TM;
-      const int gi = i0 + ii;
-      sC[c][ii] = gi < h.n_pad ? h.G[(int64_t)(k0 + h0 + c) * h.n_pad + gi] : cd{0.0, 0.0};
-    }
-    for (int e = t; e < HB * TN; e += 256) {
-      const int jj = e % TN, c = e / TN;
-      const int gj = j0 + jj;
-      cd v = gj < h.n_pad ? h.G[(int64_t)(k0 + h0 + c) * h.n_pad + gj] : cd{0.0, 0.0};
-      v.im = -v.im;
-      sR[c][jj] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int c = 0; c < HB; ++c) {
-      cd av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sC[c][tx + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sR[c][ty + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + tx + 16 * a;
-    if (i >= h.n_pad) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = j0 + ty + 16 * b;
-      if (j >= h.n_pad || j > i) continue;
-      cd* g = h.G + (int64_t)j * h.n_pad + i;
-      *g = csub(*g, acc[a][b]);
-    }
-  }
-}
-
-// Block row ib of X = L^{-1} (X zero-initialised, lower triangular):
-//   X[ib, jb] = -Lib,ib^{-1} sum_{k = jb..ib-1} L[ib, k] X[k, jb]   (jb < ib)
-//   X[ib, ib] = Lib,ib^{-1}
-// One work-group per NB x NB output tile.
-__global__ __launch_bounds__(256) void trtri_row_kernel(const HpdDesc* __restrict__ descs, int i0) {
-  const HpdDesc h = descs[blockIdx.y];
-  constexpr int NB = HPD_NB;
-  if (i0 >= h.n_pad) return;
-  const int j0 = blockIdx.x * NB;
-  if (j0 > i0) return;
-  __shared__ cd sL[NB][NB + 1];   // sL[k][r] = L(i0 + r, k0 + k)
-  __shared__ cd sX[NB][NB + 1];   // sX[c][k] = X(k0 + k, j0 + c)
-  __shared__ cd sT[NB][NB + 1];   // sT[c][r] = T(r, c)
-  const int t = threadIdx.x;
-  cd* X = h.X;
-  if (j0 == i0) {
-    for (int e = t; e < NB * NB; e += 256) {
-      const int r = e % NB, c = e / NB;
-      X[(int64_t)(i0 + c) * h.n_pad + i0 + r] = h.D[(int64_t)(i0 + c) * NB + r];
-    }
-    return;
-  }
-  // each thread owns 4 outputs: rows r = t % NB, columns c = t / NB + 8 * q4
-  const int r = t % NB, cb = t / NB;
-  cd acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-  for (int k0 = j0; k0 < i0; k0 += NB) {
-    for (int e = t; e < NB * NB; e += 256) {
-      const int rr = e % NB, cc = e / NB;
-      sL[cc][rr] = h.G[(int64_t)(k0 + cc) * h.n_pad + i0 + rr];
-      sX[cc][rr] = X[(int64_t)(j0 + cc) * h.n_pad + k0 + rr];
-    }
-    __syncthreads();
-    for (int k = 0; k < NB; ++k) {
-      const cd lv = sL[k][r];
-#pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) cfma(acc[q4], lv, sX[cb + 8 * q4][k]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q4 = 0; q4 < 4; ++q4) sT[cb + 8 * q4][r] = acc[q4];
-  for (int e = t; e < NB * NB; e += 256) {
-    const int rr = e % NB, cc = e / NB;
-    sL[cc][rr] = h.D[(int64_t)(i0 + cc) * NB + rr];     // Lii^{-1}
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q4 = 0; q4 < 4; ++q4) {
-    const int c = cb + 8 * q4;
-    cd v = {0.0, 0.0};
-    for (int s2 = 0; s2 <= r; ++s2) cfma(v, sL[s2][r], sT[c][s2]);
-    X[(int64_t)(j0 + c) * h.n_pad + i0 + r] = {-v.re, -v.im};
-  }
-}
-
 __global__ void zero_x_kernel(const HpdDesc* __restrict__ descs) {
   const HpdDesc h = descs[blockIdx.y];
   const int64_t n2 = (int64_t)h.n_pad * h.n_pad;
@@ -323,67 +188,20 @@ __global__ void zero_x_kernel(const HpdDesc* __restrict__ descs) {
     h.X[e] = {0.0, 0.0};
 }
 
-// W = X^H X into G (lower tiles computed, mirrored to the upper part).
-__global__ __launch_bounds__(256) void xhx_kernel(const HpdDesc* __restrict__ descs) {
-  const HpdDesc h = descs[blockIdx.z];
-  const int ti = blockIdx.x, tj = blockIdx.y;
-  if (tj > ti) return;
-  const int i0 = ti * TM, j0 = tj * TN;
-  if (i0 >= h.n_pad || j0 >= h.n_pad) return;
-  __shared__ cd sA[TK][TM + 1];
-  __shared__ cd sB[TK][TN + 1];
-  const int t = threadIdx.x;
-  const int tx = t & 15, ty = t >> 4;
-  cd acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = {0.0, 0.0};
-  // W[i, j] = sum_k conj(X[k, i]) X[k, j]; X lower triangular: k >= max(i, j) >= j0
-  for (int p0 = (j0 / TK) * TK; p0 < h.n_pad; p0 += TK) {
-    for (int e = t; e < TK * TM; e += 256) {
-      const int pp = e % TK, ii = e / TK;
-      const int gi = i0 + ii, gp = p0 + pp;
-      cd v = (gi < h.n_pad && gp < h.n_pad) ? h.X[(int64_t)gi * h.n_pad + gp] : cd{0.0, 0.0};
-      v.im = -v.im;
-      sA[pp][ii] = v;
-    }
-    for (int e = t; e < TK * TN; e += 256) {
-      const int pp = e % TK, jj = e / TK;
-      const int gj = j0 + jj, gp = p0 + pp;
-      sB[pp][jj] = (gj < h.n_pad && gp < h.n_pad) ? h.X[(int64_t)gj * h.n_pad + gp] : cd{0.0, 0.0};
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < TK; ++kk) {
-      cd av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sA[kk][tx + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sB[kk][ty + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + tx + 16 * a;
-    if (i >= h.n_pad) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = j0 + ty + 16 * b;
-      if (j >= h.n_pad || j > i) continue;
-      cd v = acc[a][b];
-      if (i == j) v.im = 0.0;
-      h.G[(int64_t)j * h.n_pad + i] = v;
-      if (i != j) h.G[(int64_t)i * h.n_pad + j] = {v.re, -v.im};
-    }
+// Diagonal blocks of X = L^{-1} are the inverses of the diagonal Cholesky
+// blocks (from chol_diag_kernel).  One work-group per block.
+__global__ void x_diag_kernel(const HpdDesc* __restrict__ descs) {
+  const HpdDesc h = descs[blockIdx.y];
+  constexpr int NB = HPD_NB;
+  const int i0 = blockIdx.x * NB;
+  if (i0 >= h.n_pad) return;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e % NB, c = e / NB;
+    h.X[(int64_t)(i0 + c) * h.n_pad + i0 + r] = h.D[(int64_t)(i0 + c) * NB + r];
   }
 }
 
+// W = X^H X into G (lower tiles computed, mirrored to the upper part).
 __global__ void cast_herm_kernel(const cd* __restrict__ src, int64_t lds, void* dst, int64_t ldd,
                                  int n, int to_float) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -548,6 +366,163 @@ __global__ __launch_bounds__(256) void herk_mfma_kernel(const GemmDesc* __restri
       }
 }
 
+// ------------------------------------------------------------------ FP64 GEMM on MFMA
+// C = alpha op(A) op(B) + beta C on the FP64 16x16x4 instruction, same tile
+// structure as the Gram kernel (64 x 64 complex tile, four waves of 32 x 32).
+// op(A) panels are staged as [re/im][k][i], op(B) panels as [re/im][k][j];
+// the conjugate of an OP_C operand is taken while staging, so the products are
+//   Re C += Ar Br - Ai Bi,   Im C += Ar Bi + Ai Br.
+// KR restricts the k-range of a tile to where both operands can be nonzero:
+//   KR_B_LOWER: op(B)[k][j] = 0 for k < j   (kb = j0)
+//   KR_A_LOWER: op(A)[i][k] = 0 for k > i   (ke = i0 + 64)
+//   KR_GE_MAX:  op(A)[i][k] = 0 for k < i and op(B)[k][j] = 0 for k < j
+// OUT: MM_FULL writes every tile; MM_LOWER only entries i >= j (tiles of the
+// lower triangle); MM_HERM also writes the conjugate mirror (C Hermitian).
+enum : int { KR_ALL = 0, KR_B_LOWER = 1, KR_A_LOWER = 2, KR_GE_MAX = 4 };
+enum : int { MM_FULL = 0, MM_LOWER = 1, MM_HERM = 2 };
+
+__device__ inline void tri_of(int x, int* ti, int* tj) {
+  // x -> (ti, tj), ti >= tj, x = ti (ti + 1) / 2 + tj
+  int i = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= x) ++i;
+  while (i * (i + 1) / 2 > x) --i;
+  *ti = i;
+  *tj = x - i * (i + 1) / 2;
+}
+
+// Element (r, c) of op(X) for the staged panel: `rows` indexes the 64-wide
+// side (i of A, j of B), k the inner dimension.  ROWSMAJ: the 64-wide index is
+// contiguous in memory (OP_N for A, OP_C for B); otherwise k is.
+template <bool ROWSMAJ>
+__device__ inline void mm_fetch(const cd* X, int ld, bool conj, int r0, int rows, int p0, int ke,
+                                cd (&v)[HPF]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < HPF; ++e) {
+    int r, k;
+    if constexpr (ROWSMAJ) { r = r0 + (t & 63); k = p0 + (t >> 6) + 4 * e; }
+    else { k = p0 + (t & 31); r = r0 + (t >> 5) + 8 * e; }
+    cd x = {0.0, 0.0};
+    if (r < rows && k < ke) {
+      x = ROWSMAJ ? X[(int64_t)k * ld + r] : X[(int64_t)r * ld + k];
+      if (conj) x.im = -x.im;
+    }
+    v[e] = x;
+  }
+}
+template <bool ROWSMAJ>
+__device__ inline void mm_store(const cd (&v)[HPF], double (*dst)[HK][HLD]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < HPF; ++e) {
+    int r, k;
+    if constexpr (ROWSMAJ) { r = t & 63; k = (t >> 6) + 4 * e; }
+    else { k = t & 31; r = (t >> 5) + 8 * e; }
+    dst[0][k][r] = v[e].re;
+    dst[1][k][r] = v[e].im;
+  }
+}
+
+template <int OPA, int OPB, int KR, int OUT>
+__global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ descs) {
+  const MmDesc d = descs[blockIdx.z];
+  int ti, tj;
+  if constexpr (OUT == MM_FULL) { ti = blockIdx.x; tj = blockIdx.y; }
+  else tri_of(blockIdx.x, &ti, &tj);
+  const int i0 = ti * HM, j0 = tj * HM;
+  if (i0 >= d.m || j0 >= d.n) return;
+  int kb = 0, ke = d.k;
+  if constexpr ((KR & KR_B_LOWER) != 0) kb = max(kb, j0);
+  if constexpr ((KR & KR_A_LOWER) != 0) ke = min(ke, i0 + HM);
+  if constexpr ((KR & KR_GE_MAX) != 0) kb = max(kb, max(i0, j0));
+  // A: op N -> element (i, k) at A[k lda + i] (i contiguous); op C -> conj(A[i lda + k]).
+  // B: op N -> element (k, j) at B[j ldb + k] (k contiguous); op C -> conj(B[k ldb + j]).
+  constexpr bool AROWS = OPA == OP_N, BROWS = OPB == OP_C;
+  __shared__ double sA[2][HK][HLD];
+  __shared__ double sB[2][HK][HLD];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int c16 = lane & 15, kq = lane >> 4;
+  v4d cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  cd va[HPF], vb[HPF];
+  if (kb < ke) {
+    mm_fetch<AROWS>(d.A, d.lda, OPA == OP_C, i0, d.m, kb, ke, va);
+    mm_fetch<BROWS>(d.B, d.ldb, OPB == OP_C, j0, d.n, kb, ke, vb);
+  }
+  for (int p0 = kb; p0 < ke; p0 += HK) {
+    __syncthreads();
+    mm_store<AROWS>(va, sA);
+    mm_store<BROWS>(vb, sB);
+    __syncthreads();
+    if (p0 + HK < ke) {
+      mm_fetch<AROWS>(d.A, d.lda, OPA == OP_C, i0, d.m, p0 + HK, ke, va);
+      mm_fetch<BROWS>(d.B, d.ldb, OPB == OP_C, j0, d.n, p0 + HK, ke, vb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < HK; kk += 4) {
+      double ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = sA[0][kk + kq][wr + 16 * a + c16];
+        ai[a] = sA[1][kk + kq][wr + 16 * a + c16];
+        nai[a] = -ai[a];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        br[b] = sB[0][kk + kq][wc + 16 * b + c16];
+        bi[b] = sB[1][kk + kq][wc + 16 * b + c16];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+        }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[a], bi[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + 16 * a + 4 * r + kq;
+        const int j = j0 + wc + 16 * b + c16;
+        if (i >= d.m || j >= d.n) continue;
+        if (OUT != MM_FULL && j > i) continue;
+        const double xr = cr[a][b][r], xi = ci[a][b][r];
+        cd v = {d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr};
+        cd* cij = d.C + (int64_t)j * d.ldc + i;
+        if (d.beta != 0.0) { v.re += d.beta * cij->re; v.im += d.beta * cij->im; }
+        if (OUT == MM_HERM && i == j) v.im = 0.0;
+        *cij = v;
+        if (OUT == MM_HERM && i != j) d.C[(int64_t)i * d.ldc + j] = cd{v.re, -v.im};
+      }
+}
+
+template <int OPA, int OPB, int KR, int OUT>
+void launch_zmm(const MmDesc* d, int count, int max_m, int max_n, hipStream_t s) {
+  if (count <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int mt = (max_m + HM - 1) / HM, nt = (max_n + HM - 1) / HM;
+  const dim3 grid = OUT == MM_FULL ? dim3(mt, nt, count) : dim3(mt * (mt + 1) / 2, 1, count);
+  zmm_kernel<OPA, OPB, KR, OUT><<<grid, 256, 0, s>>>(d);
+}
+
 template <int ST>
 void launch_herk_mfma(const GemmDesc* d, int batch, const int2* tiles, int ntiles, hipStream_t s) {
   herk_mfma_kernel<ST><<<dim3(8 * ((ntiles + 7) / 8), batch), 256, 0, s>>>(d, tiles, ntiles);
@@ -601,23 +576,104 @@ void herk_batched(const GemmDesc* d_desc, int batch, int max_m, int st, const in
   }
 }
 
-void hpd_inverse_batched(const HpdDesc* d_desc, int batch, int max_npad, int* d_fail,
-                         hipStream_t s) {
-  if (batch <= 0 || max_npad <= 0) return;
-  zero_x_kernel<<<dim3(std::min<int64_t>(((int64_t)max_npad * max_npad + 255) / 256, 4096), batch), 256, 0, s>>>(d_desc);
-  for (int k0 = 0; k0 < max_npad; k0 += HPD_NB) {
-    chol_diag_kernel<<<batch, 256, 0, s>>>(d_desc, k0, d_fail);
-    const int rest = max_npad - k0 - HPD_NB;
-    if (rest > 0) {
-      chol_panel_kernel<<<dim3((rest + 255) / 256, batch), 256, 0, s>>>(d_desc, k0);
-      const int tiles = (rest + TM - 1) / TM;
-      chol_update_kernel<<<dim3(tiles, tiles, batch), 256, 0, s>>>(d_desc, k0);
+size_t hpd_mm_count(int n) {
+  const int nb = n / HPD_NB;
+  size_t c = 2 * (size_t)std::max(nb - 1, 0);              // panel + trailing per step
+  for (int b = HPD_NB; b < n; b *= 2) c += 2 * (size_t)((n - b + 2 * b - 1) / (2 * b));
+  return c + 1;                                            // X^H X
+}
+
+void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, int n, int* d_fail,
+                         MmDesc* d_mm, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  constexpr int NB = HPD_NB;
+  // Plan every GEMM of the factorisation (descriptors grouped per launch,
+  // all matrices of the batch together), upload once, then launch in order.
+  enum Kind { PANEL, TRAIL, TRI1, TRI2, XHX, DIAG };
+  struct Launch { Kind kind; int off, count, m, n, k0; };
+  std::vector<MmDesc> mm;
+  std::vector<Launch> plan;
+  mm.reserve((size_t)batch * hpd_mm_count(n));
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    plan.push_back({DIAG, 0, batch, 0, 0, k0});
+    const int rest = n - k0 - NB;
+    if (rest <= 0) continue;
+    Launch lp{PANEL, (int)mm.size(), batch, rest, NB, k0};
+    for (int i = 0; i < batch; ++i) {
+      cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
+      mm.push_back(MmDesc{L21, hd[i].D + (int64_t)k0 * NB, L21, rest, NB, NB, n, NB, n,
+                          1.0, 0.0, 0.0});
+    }
+    plan.push_back(lp);
+    Launch lt{TRAIL, (int)mm.size(), batch, rest, rest, k0};
+    for (int i = 0; i < batch; ++i) {
+      const cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
+      mm.push_back(MmDesc{L21, L21, hd[i].G + (int64_t)(k0 + NB) * n + k0 + NB, rest, rest, NB,
+                          n, n, n, -1.0, 0.0, 1.0});
+    }
+    plan.push_back(lt);
+  }
+  for (int b = NB; b < n; b *= 2) {
+    Launch l1{TRI1, (int)mm.size(), 0, b, b, 0};
+    for (int i = 0; i < batch; ++i) {
+      int64_t toff = 0;
+      for (int o = 0; o + b < n; o += 2 * b) {
+        const int rows = std::min(b, n - o - b);
+        // T = L21 X11
+        mm.push_back(MmDesc{hd[i].G + (int64_t)o * n + o + b, hd[i].X + (int64_t)o * n + o,
+                            hd[i].T + toff, rows, b, b, n, n, rows, 1.0, 0.0, 0.0});
+        toff += (int64_t)rows * b;
+      }
+    }
+    l1.count = (int)mm.size() - l1.off;
+    plan.push_back(l1);
+    Launch l2{TRI2, (int)mm.size(), 0, b, b, 0};
+    for (int i = 0; i < batch; ++i) {
+      int64_t toff = 0;
+      for (int o = 0; o + b < n; o += 2 * b) {
+        const int rows = std::min(b, n - o - b);
+        // X21 = -X22 T
+        mm.push_back(MmDesc{hd[i].X + (int64_t)(o + b) * n + o + b, hd[i].T + toff,
+                            hd[i].X + (int64_t)o * n + o + b, rows, b, rows, n, rows, n,
+                            -1.0, 0.0, 0.0});
+        toff += (int64_t)rows * b;
+      }
+    }
+    l2.count = (int)mm.size() - l2.off;
+    plan.push_back(l2);
+  }
+  Launch lx{XHX, (int)mm.size(), batch, n, n, 0};
+  for (int i = 0; i < batch; ++i)
+    mm.push_back(MmDesc{hd[i].X, hd[i].X, hd[i].G, n, n, n, n, n, n, 1.0, 0.0, 0.0});
+  plan.push_back(lx);
+  if (hipMemcpyAsync(d_mm, mm.data(), sizeof(MmDesc) * mm.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return;
+
+  zero_x_kernel<<<dim3(std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096), batch), 256, 0, s>>>(d_desc);
+  bool diag_done = false;
+  for (const Launch& l : plan) {
+    const MmDesc* p = d_mm + l.off;
+    switch (l.kind) {
+      case DIAG: chol_diag_kernel<<<batch, 256, 0, s>>>(d_desc, l.k0, d_fail); break;
+      case PANEL: launch_zmm<OP_N, OP_C, KR_ALL, MM_FULL>(p, l.count, l.m, l.n, s); break;
+      case TRAIL: launch_zmm<OP_N, OP_C, KR_ALL, MM_LOWER>(p, l.count, l.m, l.n, s); break;
+      case TRI1:
+        if (!diag_done) {   // X's diagonal blocks, once the Cholesky is complete
+          x_diag_kernel<<<dim3(n / NB, batch), 256, 0, s>>>(d_desc);
+          diag_done = true;
+        }
+        launch_zmm<OP_N, OP_N, KR_B_LOWER, MM_FULL>(p, l.count, l.m, l.n, s);
+        break;
+      case TRI2: launch_zmm<OP_N, OP_N, KR_A_LOWER, MM_FULL>(p, l.count, l.m, l.n, s); break;
+      case XHX:
+        if (!diag_done) {
+          x_diag_kernel<<<dim3(n / NB, batch), 256, 0, s>>>(d_desc);
+          diag_done = true;
+        }
+        launch_zmm<OP_C, OP_N, KR_GE_MAX, MM_HERM>(p, l.count, l.m, l.n, s);
+        break;
     }
   }
-  for (int i0 = 0; i0 < max_npad; i0 += HPD_NB)
-    trtri_row_kernel<<<dim3(i0 / HPD_NB + 1, batch), 256, 0, s>>>(d_desc, i0);
-  const int tiles = (max_npad + TM - 1) / TM;
-  xhx_kernel<<<dim3(tiles, tiles, batch), 256, 0, s>>>(d_desc);
 }
 
 void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, int n, bool to_float,
