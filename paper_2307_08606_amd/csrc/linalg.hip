@@ -123,35 +123,38 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 
 // Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS; write
 // Lkk into G (upper part zeroed) and Lkk^{-1} into Dinv[:, k0:k0+NB].
-__global__ __launch_bounds__(256) void chol_diag_kernel(const HpdDesc* __restrict__ descs, int k0,
-                                                        int* fail) {
+// The inverse rides along the column steps: with Y = I, step c sets row c of
+// X = Lkk^{-1} to Y[c, :] / L[c, c] and removes L[r, c] X[c, :] from the rows
+// r > c below, in parallel with the trailing update of the factor.
+constexpr int DIAG_THREADS = 256;
+__global__ __launch_bounds__(DIAG_THREADS) void chol_diag_kernel(const HpdDesc* __restrict__ descs,
+                                                                 int k0, int* fail) {
   const HpdDesc h = descs[blockIdx.x];
   if (k0 >= h.n_pad) return;
   constexpr int NB = HPD_NB;
   __shared__ cd P[NB][NB + 1];    // P[c][r] = element (r, c)
-  __shared__ cd Li[NB][NB + 1];   // Li[c][r] = element (r, c) of Lkk^{-1}
-  __shared__ double sdiag;
+  __shared__ cd Li[NB][NB + 1];   // Li[c][r] = element (r, c) of Y, then of Lkk^{-1}
   const int t = threadIdx.x;
-  for (int e = t; e < NB * NB; e += 256) {
+  for (int e = t; e < NB * NB; e += DIAG_THREADS) {
     const int r = e % NB, c = e / NB;
     P[c][r] = h.G[(int64_t)(k0 + c) * h.n_pad + k0 + r];
+    Li[c][r] = {r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
   for (int c = 0; c < NB; ++c) {
-    if (t == 0) {
-      const double d = P[c][c].re;
-      if (!(d > 0.0)) atomicOr(fail, 1);
-      sdiag = sqrt(fmax(d, 1e-300));
-    }
+    const double d = P[c][c].re;   // every thread reads the pivot
+    if (t == 0 && !(d > 0.0)) atomicOr(fail, 1);
+    const double sd = sqrt(fmax(d, 1e-300)), rs = 1.0 / sd;
     __syncthreads();
-    const double sd = sdiag;
-    if (t > c && t < NB) P[c][t] = cscale(P[c][t], 1.0 / sd);   // column c below the diagonal
+    if (t > c && t < NB) P[c][t] = cscale(P[c][t], rs);      // column c of L below the diagonal
     if (t == c) P[c][c] = {sd, 0.0};
+    if (t >= NB && t - NB <= c) Li[t - NB][c] = cscale(Li[t - NB][c], rs);   // row c of X
     __syncthreads();
-    for (int e = t; e < NB * NB; e += 256) {
-      const int r = e % NB, s2 = e / NB;
-      if (s2 > c && r >= s2) {
-        // (r, s2) -= L(r, c) conj(L(s2, c))
+    const int m = NB - 1 - c;   // rows below c
+    // factor: (r, s2) -= L(r, c) conj(L(s2, c)), c < s2 <= r
+    for (int e = t; e < m * m; e += DIAG_THREADS) {
+      const int r = c + 1 + e % m, s2 = c + 1 + e / m;
+      if (r >= s2) {
         const cd a = P[c][r], b = P[c][s2];
         cd v = P[s2][r];
         v.re -= a.re * b.re + a.im * b.im;
@@ -159,22 +162,18 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const HpdDesc* __restric
         P[s2][r] = v;
       }
     }
+    // inverse: Y(r, j) -= L(r, c) X(c, j), r > c, j <= c
+    for (int e = t; e < m * (c + 1); e += DIAG_THREADS) {
+      const int r = c + 1 + e % m, j = e / m;
+      const cd l = P[c][r], x = Li[j][c];
+      cd v = Li[j][r];
+      v.re -= l.re * x.re - l.im * x.im;
+      v.im -= l.re * x.im + l.im * x.re;
+      Li[j][r] = v;
+    }
     __syncthreads();
   }
-  // column j of Lkk^{-1} by forward substitution (one thread per column)
-  if (t < NB) {
-    const int j = t;
-    for (int r = 0; r < j; ++r) Li[j][r] = {0.0, 0.0};
-    const double djj = P[j][j].re;
-    Li[j][j] = {1.0 / djj, 0.0};
-    for (int r = j + 1; r < NB; ++r) {
-      cd acc = {0.0, 0.0};
-      for (int k = j; k < r; ++k) cfma(acc, P[k][r], Li[j][k]);
-      Li[j][r] = cscale(acc, -1.0 / P[r][r].re);
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < NB * NB; e += 256) {
+  for (int e = t; e < NB * NB; e += DIAG_THREADS) {
     const int r = e % NB, c = e / NB;
     h.G[(int64_t)(k0 + c) * h.n_pad + k0 + r] = (r >= c) ? P[c][r] : cd{0.0, 0.0};
     h.D[(int64_t)(k0 + c) * NB + r] = Li[c][r];
@@ -410,8 +409,9 @@ __device__ inline void mm_fetch(const cd* X, int ld, bool conj, int r0, int rows
     v[e] = x;
   }
 }
+constexpr int HLDZ = 65;   // odd row length: k-contiguous staging stores hit distinct banks
 template <bool ROWSMAJ>
-__device__ inline void mm_store(const cd (&v)[HPF], double (*dst)[HK][HLD]) {
+__device__ inline void mm_store(const cd (&v)[HPF], double (*dst)[HK][HLDZ]) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int e = 0; e < HPF; ++e) {
@@ -438,8 +438,8 @@ __global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ des
   // A: op N -> element (i, k) at A[k lda + i] (i contiguous); op C -> conj(A[i lda + k]).
   // B: op N -> element (k, j) at B[j ldb + k] (k contiguous); op C -> conj(B[k ldb + j]).
   constexpr bool AROWS = OPA == OP_N, BROWS = OPB == OP_C;
-  __shared__ double sA[2][HK][HLD];
-  __shared__ double sB[2][HK][HLD];
+  __shared__ double sA[2][HK][HLDZ];
+  __shared__ double sB[2][HK][HLDZ];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
   const int c16 = lane & 15, kq = lane >> 4;
@@ -654,7 +654,7 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
   for (const Launch& l : plan) {
     const MmDesc* p = d_mm + l.off;
     switch (l.kind) {
-      case DIAG: chol_diag_kernel<<<batch, 256, 0, s>>>(d_desc, l.k0, d_fail); break;
+      case DIAG: chol_diag_kernel<<<batch, DIAG_THREADS, 0, s>>>(d_desc, l.k0, d_fail); break;
       case PANEL: launch_zmm<OP_N, OP_C, KR_ALL, MM_FULL>(p, l.count, l.m, l.n, s); break;
       case TRAIL: launch_zmm<OP_N, OP_C, KR_ALL, MM_LOWER>(p, l.count, l.m, l.n, s); break;
       case TRI1:
