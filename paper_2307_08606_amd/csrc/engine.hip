@@ -280,96 +280,154 @@ int check_fail(sadmm_t h) {
   return SADMM_OK;
 }
 
-// W64[q] = Ahat_q Ahat_q^H + rho I by the integer digit products (gram.h), in
-// groups of sensors whose digit planes fit a bounded workspace.
-int gram_integer(sadmm_t h, const std::vector<int>& qs, double rho) {
+// One factor to build: sensor q of handle h.
+struct FacItem {
+  sadmm_t h;
+  int q;
+};
+
+double factor_rho(sadmm_t h) { return (h->p.beta + h->p.gamma) / h->p.mu; }
+bool integer_gram(sadmm_t h) { return h->p.gram == 0 && h->st != ST_FP64; }
+
+// Device table of `need` descriptors: h0's own when it is large enough, else a
+// temporary one (freed by the caller through tmp after the stream syncs).
+template <class T>
+int desc_table(sadmm_t h0, T* own, size_t own_cap, size_t need, std::vector<void*>& tmp, T** out) {
+  if (need <= own_cap) { *out = own; return SADMM_OK; }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * need) != hipSuccess)
+    return fail_msg(h0, SADMM_E_NOMEM, "factor build: descriptor table");
+  tmp.push_back(p);
+  *out = static_cast<T*>(p);
+  return SADMM_OK;
+}
+
+// W64 = Ahat Ahat^H + rho I by the integer digit products (gram.h) for the
+// items, in groups whose digit planes fit a bounded workspace owned by h0.
+int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void*>& tmp) {
   constexpr size_t kCap = size_t(4) << 30;
-  const size_t per = (gram_i8_workspace(h->KMp, h->N) + 255) / 256 * 256;
-  const size_t group = std::max<size_t>(1, std::min<size_t>(qs.size(), kCap / per));
-  if (h->gi8_ws_bytes < group * per) {   // owned here (not in allocs): it may grow
-    if (h->gi8_ws) {
-      HIPCHK(h, hipStreamSynchronize(h->s));
-      hipFree(h->gi8_ws);
+  int max_n = 0;
+  for (const FacItem& it : items) max_n = std::max(max_n, it.h->N);
+  const size_t per = (gram_i8_workspace(h0->KMp, max_n) + 255) / 256 * 256;
+  const size_t group = std::max<size_t>(1, std::min<size_t>(items.size(), kCap / per));
+  if (h0->gi8_ws_bytes < group * per) {   // owned here (not in allocs): it may grow
+    if (h0->gi8_ws) {
+      HIPCHK(h0, hipStreamSynchronize(h0->s));
+      hipFree(h0->gi8_ws);
     }
-    h->gi8_ws = nullptr;
-    h->gi8_ws_bytes = 0;
-    const hipError_t e = hipMalloc(&h->gi8_ws, group * per);
+    h0->gi8_ws = nullptr;
+    h0->gi8_ws_bytes = 0;
+    const hipError_t e = hipMalloc(&h0->gi8_ws, group * per);
     if (e != hipSuccess) {
-      h->gi8_ws = nullptr;
-      return fail_msg(h, SADMM_E_NOMEM, "integer Gram workspace (%zu bytes): %s", group * per,
+      h0->gi8_ws = nullptr;
+      return fail_msg(h0, SADMM_E_NOMEM, "integer Gram workspace (%zu bytes): %s", group * per,
                       hipGetErrorString(e));
     }
-    h->gi8_ws_bytes = group * per;
+    h0->gi8_ws_bytes = group * per;
   }
-  for (size_t g0 = 0; g0 < qs.size(); g0 += group) {
-    const size_t n = std::min(group, qs.size() - g0);
+  GramI8Desc* dd = nullptr;
+  TRY(desc_table(h0, h0->gi8_d, (size_t)h0->Q, group, tmp, &dd));
+  for (size_t g0 = 0; g0 < items.size(); g0 += group) {
+    const size_t n = std::min(group, items.size() - g0);
     std::vector<GramI8Desc> gd(n);
     int max_k = 0;
     for (size_t i = 0; i < n; ++i) {
-      const int q = qs[g0 + i];
+      const sadmm_t h = items[g0 + i].h;
+      const int q = items[g0 + i].q;
       GramI8Desc& d = gd[i];
       d.A = ahat_ptr(h, q); d.ldA = h->ldA; d.kmp = h->KMp;
       d.m = h->KMp; d.k = h->nq[q];
-      d.C = h->W64[q]; d.ldc = h->KMp; d.diag = rho;
-      gram_i8_layout(d, static_cast<char*>(h->gi8_ws) + i * per);
+      d.C = h->W64[q]; d.ldc = h->KMp; d.diag = factor_rho(h);
+      gram_i8_layout(d, static_cast<char*>(h0->gi8_ws) + i * per);
       max_k = std::max(max_k, d.k);
+      prof_work(h0, SADMM_KC_SLICE, (double)h->nq[q] * h->KMp * (op_bytes(h) + 8.0));
     }
-    HIPCHK(h, hipMemcpyAsync(h->gi8_d, gd.data(), sizeof(GramI8Desc) * n, hipMemcpyHostToDevice, h->s));
-    int pe = prof_begin(h);
-    gram_i8_prepare(h->gi8_d, (int)n, h->KMp, max_k, h->st, h->s);
-    prof_end(h, SADMM_KC_SLICE, pe);
-    for (size_t i = 0; i < n; ++i)   // operator read once, digit planes written once
-      prof_work(h, SADMM_KC_SLICE, (double)h->nq[qs[g0 + i]] * h->KMp * (op_bytes(h) + 8.0));
+    // (stream order keeps a later group's upload behind the kernels reading this one)
+    HIPCHK(h0, hipMemcpyAsync(dd, gd.data(), sizeof(GramI8Desc) * n, hipMemcpyHostToDevice, h0->s));
+    int pe = prof_begin(h0);
+    gram_i8_prepare(dd, (int)n, h0->KMp, max_k, h0->st, h0->s);
+    prof_end(h0, SADMM_KC_SLICE, pe);
     for (int c = 0; c < gram_i8_chunks(max_k); ++c) {
-      pe = prof_begin(h);
-      gram_i8_chunk(h->gi8_d, (int)n, c, h->tiles_d, h->ntiles, h->s);
-      prof_end(h, SADMM_KC_GRAM, pe);
+      pe = prof_begin(h0);
+      gram_i8_chunk(dd, (int)n, c, h0->tiles_d, h0->ntiles, h0->s);
+      prof_end(h0, SADMM_KC_GRAM, pe);
     }
-    HIPCHK(h, hipGetLastError());
+    HIPCHK(h0, hipGetLastError());
   }
   return SADMM_OK;
 }
 
-// Full factor build for the listed sensors: W64 = ((c/mu) I + Ahat Ahat^H)^{-1}
-int build_factors(sadmm_t h, const std::vector<int>& qs) {
-  if (qs.empty()) return SADMM_OK;
-  const double rho = (h->p.beta + h->p.gamma) / h->p.mu;
-  std::vector<GemmDesc> gd(qs.size());
-  std::vector<HpdDesc> hd(qs.size());
-  for (size_t i = 0; i < qs.size(); ++i) {
-    const int q = qs[i];
+// Full factor build W64 = ((c/mu) I + Ahat Ahat^H)^{-1} of the items, which
+// share KMp, storage and Gram path; runs on h0's stream.  Used for the sensors
+// of one handle, and by sadmm_solve_batch for the sensors of every handle at
+// once (one Gram and one inverse chain for the whole batch).
+int build_factors_items(sadmm_t h0, const std::vector<FacItem>& items) {
+  if (items.empty()) return SADMM_OK;
+  const size_t n = items.size();
+  std::vector<void*> tmp;
+  auto cleanup = [&]() {
+    if (!tmp.empty()) hipStreamSynchronize(h0->s);
+    for (void* p : tmp) hipFree(p);
+  };
+  std::vector<GemmDesc> gd(n);
+  std::vector<HpdDesc> hd(n);
+  for (size_t i = 0; i < n; ++i) {
+    const sadmm_t h = items[i].h;
+    const int q = items[i].q;
     GemmDesc& g = gd[i];
     g.A = ahat_ptr(h, q); g.B = ahat_ptr(h, q); g.C = h->W64[q];
     g.m = h->KMp; g.n = h->KMp; g.k = h->nq[q];
     g.kmpA = h->KMp; g.kmpB = h->KMp;
     g.lda = h->ldA; g.ldb = h->ldA; g.ldc = h->KMp;
-    g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta = 0.0; g.diag = rho;
+    g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta = 0.0; g.diag = factor_rho(h);
     hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q], h->hpdT[q]};
-  }
-  HIPCHK(h, hipMemcpyAsync(h->hpd_d, hd.data(), sizeof(HpdDesc) * hd.size(), hipMemcpyHostToDevice, h->s));
-  int pe = -1;
-  if (h->p.gram == 0 && h->st != ST_FP64) {
-    TRY(gram_integer(h, qs, rho));
-  } else {
-    HIPCHK(h, hipMemcpyAsync(h->gemm_d, gd.data(), sizeof(GemmDesc) * gd.size(), hipMemcpyHostToDevice, h->s));
-    pe = prof_begin(h);
-    herk_batched(h->gemm_d, (int)qs.size(), h->KMp, h->st, h->tiles_d, h->ntiles, h->s);
-    prof_end(h, SADMM_KC_GRAM, pe);
-  }
-  for (int q : qs) {
     // Hermitian product: KM(KM+1)/2 entries, N_q complex MACs each (8 flops)
-    prof_work(h, SADMM_KC_GRAM, 8.0 * 0.5 * h->KM * (h->KM + 1.0) * h->nq[q]);
+    prof_work(h0, SADMM_KC_GRAM, 8.0 * 0.5 * h->KM * (h->KM + 1.0) * h->nq[q]);
     // Cholesky n^3/3, triangular inverse n^3/6, X^H X n^3/3 complex MACs
-    prof_work(h, SADMM_KC_INVERSE, 8.0 * (5.0 / 6.0) * (double)h->KM * h->KM * h->KM);
+    prof_work(h0, SADMM_KC_INVERSE, 8.0 * (5.0 / 6.0) * (double)h->KM * h->KM * h->KM);
   }
-  HIPCHK(h, hipGetLastError());
-  pe = prof_begin(h);
-  hpd_inverse_batched(hd.data(), h->hpd_d, (int)qs.size(), h->KMp, h->fail, h->mm_d, h->s);
-  prof_end(h, SADMM_KC_INVERSE, pe);
-  HIPCHK(h, hipGetLastError());
-  for (int q : qs) h->fac_valid[q] = true;
-  HIPCHK(h, hipGetLastError());
-  return check_fail(h);
+  int rc = SADMM_OK;
+  HpdDesc* hpd = nullptr;
+  MmDesc* mm = nullptr;
+  GemmDesc* gemm = nullptr;
+  const size_t mm_need = n * hpd_mm_count(h0->KMp);
+  const size_t mm_own = std::max((size_t)h0->Q * hpd_mm_count(h0->KMp), hpd_mm_count(h0->rpad_max));
+  if ((rc = desc_table(h0, h0->hpd_d, (size_t)h0->Q, n, tmp, &hpd)) != SADMM_OK ||
+      (rc = desc_table(h0, h0->mm_d, mm_own, mm_need, tmp, &mm)) != SADMM_OK ||
+      (rc = desc_table(h0, h0->gemm_d, (size_t)std::max(h0->Q, 4), n, tmp, &gemm)) != SADMM_OK) {
+    cleanup();
+    return rc;
+  }
+  if (hipMemcpyAsync(hpd, hd.data(), sizeof(HpdDesc) * n, hipMemcpyHostToDevice, h0->s) != hipSuccess) {
+    cleanup();
+    return fail_msg(h0, SADMM_E_HIP, "factor build: descriptor upload");
+  }
+  if (integer_gram(h0)) {
+    rc = gram_integer(h0, items, tmp);
+  } else {
+    if (hipMemcpyAsync(gemm, gd.data(), sizeof(GemmDesc) * n, hipMemcpyHostToDevice, h0->s) != hipSuccess)
+      rc = fail_msg(h0, SADMM_E_HIP, "factor build: descriptor upload");
+    const int pe = prof_begin(h0);
+    if (rc == SADMM_OK) herk_batched(gemm, (int)n, h0->KMp, h0->st, h0->tiles_d, h0->ntiles, h0->s);
+    prof_end(h0, SADMM_KC_GRAM, pe);
+  }
+  if (rc == SADMM_OK) {
+    const int pe = prof_begin(h0);
+    hpd_inverse_batched(hd.data(), hpd, (int)n, h0->KMp, h0->fail, mm, h0->s);
+    prof_end(h0, SADMM_KC_INVERSE, pe);
+    if (hipGetLastError() != hipSuccess) rc = fail_msg(h0, SADMM_E_HIP, "factor build: launch failed");
+  }
+  if (rc == SADMM_OK) rc = check_fail(h0);   // synchronises h0's stream
+  cleanup();
+  if (rc != SADMM_OK) return rc;
+  for (const FacItem& it : items) it.h->fac_valid[it.q] = true;
+  return SADMM_OK;
+}
+
+int build_factors(sadmm_t h, const std::vector<int>& qs) {
+  std::vector<FacItem> items;
+  for (int q : qs) items.push_back({h, q});
+  return build_factors_items(h, items);
 }
 
 // Low-rank correction of W64[q] for r columns (pixel list lst) leaving
@@ -523,7 +581,11 @@ int validate(const sadmm_params* p) {
 // ---- solve phases --------------------------------------------------------
 // Prologue: measurements, state reset, selectors (caller mask, CNN),
 // compaction, factor build, data term; uploads the iteration arguments.
-int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device) {
+// With rebuild_out, stops before the factor build and returns the sensors to
+// rebuild (the caller builds them and then calls solve_prologue_finish).
+int solve_prologue_finish(sadmm_t h);
+int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
+                   std::vector<int>* rebuild_out = nullptr) {
   if (!y || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "solve: bad y");
   for (int q = 0; q < h->Q; ++q)
     if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "solve: operator of sensor %d not set", q);
@@ -600,7 +662,18 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device) {
   if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
   TRY(push_descs(h));
   HIPCHK(h, hipEventRecord(h->evf0, s));
+  if (rebuild_out) {
+    *rebuild_out = rebuild;
+    return SADMM_OK;
+  }
   TRY(build_factors(h, rebuild));
+  return solve_prologue_finish(h);
+}
+
+// Prologue, second part (factors built): data term, timing, arguments.
+int solve_prologue_finish(sadmm_t h) {
+  hipStream_t s = h->s;
+  const int Q = h->Q;
   launch_xy(make_args(h), h->st, h->dbl, 0, Q, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->evf1, s));
@@ -1100,7 +1173,27 @@ int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dty
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail_msg(hs[0], SADMM_E_ARG, "solve_batch: handle repeated");
   }
-  for (int i = 0; i < S; ++i) TRY(solve_prologue(hs[i], ys[i], dtype, on_device));
+  // inputs of every scene, then the factors of every (scene, sensor) in one
+  // build per group of equal order and Gram path, then the data terms
+  std::vector<std::vector<int>> rebuild(S);
+  for (int i = 0; i < S; ++i) TRY(solve_prologue(hs[i], ys[i], dtype, on_device, &rebuild[i]));
+  std::vector<bool> built(S, false);
+  for (int i = 0; i < S; ++i) {
+    if (built[i]) continue;
+    std::vector<FacItem> items;
+    for (int j = i; j < S; ++j) {
+      if (built[j] || hs[j]->KMp != hs[i]->KMp || integer_gram(hs[j]) != integer_gram(hs[i])) continue;
+      built[j] = true;
+      for (int q : rebuild[j]) items.push_back({hs[j], q});
+    }
+    const int rc = build_factors_items(hs[i], items);
+    if (rc != SADMM_OK) {
+      for (int j = 0; j < S; ++j)
+        if (hs[j] != hs[i]) hs[j]->err = hs[i]->err;
+      return rc;
+    }
+  }
+  for (int i = 0; i < S; ++i) TRY(solve_prologue_finish(hs[i]));
   std::vector<sadmm_t> v(hs, hs + S);
   TRY(iterate(v, S == 1));
   for (int i = 0; i < S; ++i) TRY(solve_epilogue(hs[i], infos ? &infos[i] : nullptr));
