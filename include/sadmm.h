@@ -122,6 +122,20 @@ void sadmm_default_params(sadmm_params* p);
  * device memory sized for Q, K*M and N.  Errors: E_ARG on invalid params. */
 int sadmm_create(const sadmm_params* p, sadmm_t* out);
 
+/* Creates a handle that borrows the operators A_q and factors W_q of src
+ * (frames of one array geometry: the same eq. (1) operator, different
+ * measurements).  It allocates only its own state (x_q, z, u, y, data terms).
+ * Requirements: same Q, K, M, N, storage, mu, beta, gamma as src; plain SADMM
+ * (prune = 0, kkt = 0 on both handles); src has no pixel selector and borrows
+ * from no one.  set_operator* and set_active_mask on the new handle return
+ * E_STATE.  src must outlive every handle created from it; a later
+ * set_operator on src changes the operator of all of them.  A solve_batch
+ * whose handles all use one FP32 operator (src and/or its borrowers, 2..64
+ * scenes) runs the forward and adjoint products of all scenes as
+ * multi-right-hand-side products on FP32 matrix instructions.
+ * Errors: E_ARG (message from sadmm_last_error(NULL)). */
+int sadmm_create_shared(const sadmm_params* p, sadmm_t src, sadmm_t* out);
+
 /* Operator of sensor q (eq. (1)): A, KM x N column-major with leading
  * dimension ld >= KM, complex128 or complex64.  Copied and converted to the
  * storage precision.  Invalidates the factor of sensor q. */

@@ -79,6 +79,8 @@ struct sadmm_s {
   std::vector<SensorDesc> sens_h;
   GemmDesc* gemm_d = nullptr;
   HpdDesc* hpd_d = nullptr;
+  sadmm_t shared_src = nullptr;  // operator and factor borrowed from this handle
+  int n_sharers = 0;             // handles borrowing this one's operator
   GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
   int2* tiles_d = nullptr;       // Gram tile order (tri_tile_order)
   int ntiles = 0;
@@ -656,7 +658,7 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
       HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     TRY(compact_operator(h, q));
-    if (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh) rebuild.push_back(q);
+    if (!h->shared_src && (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh)) rebuild.push_back(q);
     h->facJ[q] = Jh;
   }
   if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
@@ -752,7 +754,7 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
 
 // Iteration loop over a batch of prepared handles (one launch per kernel for
 // every scene; a hipGraph of one iteration is replayed between status reads).
-int iterate(std::vector<sadmm_t>& hs, bool single) {
+int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = nullptr) {
   sadmm_t h0 = hs[0];
   const int S = (int)hs.size();
   hipStream_t gs = h0->gs;
@@ -804,7 +806,8 @@ int iterate(std::vector<sadmm_t>& hs, bool single) {
   if (!staged && !ge) {
     bool ok = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-      launch_iteration_batch(bv, d, h0->st, gs, nullptr);
+      if (shared) launch_iteration_shared(bv, d, *shared, gs, nullptr);
+      else launch_iteration_batch(bv, d, h0->st, gs, nullptr);
       ok = hipStreamEndCapture(gs, &gr) == hipSuccess && gr;
       ok = ok && hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0) == hipSuccess;
     }
@@ -841,9 +844,11 @@ int iterate(std::vector<sadmm_t>& hs, bool single) {
           hipEventRecord(h->evpool[ev[stage] + (begin ? 0 : 1)], gs);
           if (!begin) h->marks.push_back({SADMM_KC_FWD + stage, ev[stage], ev[stage] + 1});
         };
-        launch_iteration_batch(bv, d, h0->st, gs, &hook);
+        if (shared) launch_iteration_shared(bv, d, *shared, gs, &hook);
+        else launch_iteration_batch(bv, d, h0->st, gs, &hook);
       } else {
-        launch_iteration_batch(bv, d, h0->st, gs, nullptr);
+        if (shared) launch_iteration_shared(bv, d, *shared, gs, nullptr);
+        else launch_iteration_batch(bv, d, h0->st, gs, nullptr);
       }
     }
     if (rc != SADMM_OK) break;
@@ -928,12 +933,36 @@ void sadmm_default_params(sadmm_params* p) {
   p->stream = nullptr;
 }
 
-int sadmm_create(const sadmm_params* p, sadmm_t* out) {
+static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out);
+
+int sadmm_create(const sadmm_params* p, sadmm_t* out) { return create_impl(p, nullptr, out); }
+
+int sadmm_create_shared(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
+  if (!out || !p || !src) return SADMM_E_ARG;
+  *out = nullptr;
+  auto bad = [&](const char* why) {
+    g_create_err = std::string("create_shared: ") + why;
+    return SADMM_E_ARG;
+  };
+  if (src->shared_src) return bad("the source borrows its operator itself");
+  if (p->Q != src->Q || p->K != src->K || p->M != src->M || p->N != src->N || p->storage != src->p.storage)
+    return bad("shape or storage differs from the source");
+  if (p->mu != src->p.mu || p->beta != src->p.beta || p->gamma != src->p.gamma)
+    return bad("mu, beta, gamma must equal the source's (the factor is shared)");
+  if (p->prune || p->kkt || src->p.prune || src->p.kkt)
+    return bad("shared operators need plain SADMM (prune = 0, kkt = 0) on both handles");
+  for (int q = 0; q < src->Q; ++q)
+    if (!src->mask0[q].empty()) return bad("the source has a pixel selector");
+  return create_impl(p, src, out);
+}
+
+static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   if (!out) return SADMM_E_ARG;
   *out = nullptr;
   int rc = validate(p);
   if (rc != SADMM_OK) return rc;
   sadmm_t h = new sadmm_s();
+  h->shared_src = src;
   h->p = *p;
   h->Q = p->Q; h->K = p->K; h->M = p->M; h->N = p->N;
   h->KM = p->K * p->M;
@@ -962,14 +991,23 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
   h->rpad_max = round_up(h->rmax, HPD_NB);
 #define A_(expr) do { int r_ = (expr); if (r_ != SADMM_OK) { sadmm_destroy(h); return r_; } } while (0)
   for (int q = 0; q < Q; ++q) {
-    A_(dalloc(h, &h->Afull[q], (size_t)h->ldA * h->slot * N));
-    A_(dalloc_t(h, &h->W64[q], sizeof(cd) * (size_t)KMp * KMp));
+    if (src) {   // borrowed: operator, factor and its scratch
+      h->Afull[q] = src->Afull[q];
+      h->W64[q] = src->W64[q];
+      h->hpdD[q] = src->hpdD[q];
+      h->hpdX[q] = src->hpdX[q];
+      h->hpdT[q] = src->hpdT[q];
+      h->op_set[q] = true;
+    } else {
+      A_(dalloc(h, &h->Afull[q], (size_t)h->ldA * h->slot * N));
+      A_(dalloc_t(h, &h->W64[q], sizeof(cd) * (size_t)KMp * KMp));
+      A_(dalloc_t(h, &h->hpdD[q], sizeof(cd) * (size_t)HPD_NB * KMp));
+      A_(dalloc_t(h, &h->hpdX[q], sizeof(cd) * (size_t)KMp * KMp));
+      A_(dalloc_t(h, &h->hpdT[q], sizeof(cd) * ((size_t)KMp * KMp / 4 + 1)));
+    }
     A_(dalloc_t(h, &h->J[q], sizeof(int) * N));
     A_(dalloc_t(h, &h->Jnew[q], sizeof(int) * N));
     A_(dalloc(h, &h->xy[q], cN));
-    A_(dalloc_t(h, &h->hpdD[q], sizeof(cd) * (size_t)HPD_NB * KMp));
-    A_(dalloc_t(h, &h->hpdX[q], sizeof(cd) * (size_t)KMp * KMp));
-    A_(dalloc_t(h, &h->hpdT[q], sizeof(cd) * ((size_t)KMp * KMp / 4 + 1)));
   }
   A_(dalloc(h, &h->X, cN * Q));
   A_(dalloc(h, &h->dX, cN * Q));
@@ -1046,6 +1084,7 @@ int sadmm_create(const sadmm_params* p, sadmm_t* out) {
     return SADMM_E_HIP;
   }
 #undef A_
+  if (src) src->n_sharers += 1;
   *out = h;
   return SADMM_OK;
 }
@@ -1056,6 +1095,7 @@ int sadmm_set_operator(sadmm_t h, int32_t q, const void* A, int32_t dtype, int64
   if (!A || q < 0 || q >= h->Q || (dtype != SADMM_C128 && dtype != SADMM_C64))
     return fail_msg(h, SADMM_E_ARG, "set_operator: bad argument");
   if (ld < h->KM) return fail_msg(h, SADMM_E_SHAPE, "set_operator: ld %lld < KM %d", (long long)ld, h->KM);
+  if (h->shared_src) return fail_msg(h, SADMM_E_STATE, "set_operator: the operator is borrowed");
   if (h->st == ST_MF)
     return fail_msg(h, SADMM_E_STATE, "set_operator: a matrix-free handle takes sadmm_set_operator_geometry");
   const size_t esz = dtype == SADMM_C128 ? 16 : 8;
@@ -1088,6 +1128,7 @@ int sadmm_set_operator_geometry(sadmm_t h, int32_t q, const double* tx_xy, const
   if (!h) return SADMM_E_ARG;
   if (q < 0 || q >= h->Q || !tx_xy || !rx_xy || !pix_xy)
     return fail_msg(h, SADMM_E_ARG, "set_operator_geometry: bad argument");
+  if (h->shared_src) return fail_msg(h, SADMM_E_STATE, "set_operator_geometry: the operator is borrowed");
   double* g = nullptr;
   const size_t nb = sizeof(double) * (2 + 2 * (size_t)h->M + 2 * (size_t)h->N);
   if (hipMalloc((void**)&g, nb) != hipSuccess)
@@ -1113,6 +1154,8 @@ int sadmm_set_active_mask(sadmm_t h, int32_t q, const uint8_t* mask) {
   if (!h) return SADMM_E_ARG;
   if (q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "set_active_mask: bad sensor");
   if (!mask) { h->mask0[q].clear(); return SADMM_OK; }
+  if (h->shared_src || h->n_sharers > 0)
+    return fail_msg(h, SADMM_E_STATE, "set_active_mask: the operator is shared (plain SADMM only)");
   h->mask0[q].assign(mask, mask + h->N);
   for (auto& v : h->mask0[q]) v = v ? 1 : 0;
   return SADMM_OK;
@@ -1155,8 +1198,23 @@ int sadmm_set_reference(sadmm_t h, const void* x_ref, int32_t dtype, int32_t on_
   return SADMM_OK;
 }
 
+// A handle that borrows an operator uses its source's factor: build it when
+// it is not valid (the source's own solve would).
+int ensure_source_factor(sadmm_t h) {
+  sadmm_t src = h->shared_src;
+  if (!src) return SADMM_OK;
+  std::vector<int> qs;
+  for (int q = 0; q < src->Q; ++q)
+    if (!src->fac_valid[q]) qs.push_back(q);
+  if (qs.empty()) return SADMM_OK;
+  const int rc = build_factors(src, qs);
+  if (rc != SADMM_OK) h->err = src->err;
+  return rc;
+}
+
 int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadmm_info* info) {
   if (!h) return SADMM_E_ARG;
+  TRY(ensure_source_factor(h));
   TRY(solve_prologue(h, y, dtype, on_device));
   std::vector<sadmm_t> hs{h};
   TRY(iterate(hs, /*single=*/true));
@@ -1172,6 +1230,15 @@ int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dty
       return fail_msg(hs[0], SADMM_E_ARG, "solve_batch: every handle must use the same storage");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail_msg(hs[0], SADMM_E_ARG, "solve_batch: handle repeated");
+  }
+  // scenes borrowing an operator whose source is not in the batch: the
+  // source's factor must be valid before the data terms
+  for (int i = 0; i < S; ++i) {
+    const sadmm_t src = hs[i]->shared_src;
+    if (!src) continue;
+    bool in_batch = false;
+    for (int j = 0; j < S; ++j) in_batch = in_batch || hs[j] == src;
+    if (!in_batch) TRY(ensure_source_factor(hs[i]));
   }
   // inputs of every scene, then the factors of every (scene, sensor) in one
   // build per group of equal order and Gram path, then the data terms
@@ -1195,7 +1262,49 @@ int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dty
   }
   for (int i = 0; i < S; ++i) TRY(solve_prologue_finish(hs[i]));
   std::vector<sadmm_t> v(hs, hs + S);
-  TRY(iterate(v, S == 1));
+  // every scene on one FP32 operator: multi-right-hand-side products
+  const sadmm_t root = hs[0]->shared_src ? hs[0]->shared_src : hs[0];
+  bool shared = S >= 2 && S <= 64 && root->st == ST_FP32;
+  for (int i = 0; i < S && shared; ++i)
+    shared = (hs[i]->shared_src ? hs[i]->shared_src : hs[i]) == root && !hs[i]->p.prune;
+  if (shared) {
+    const int Q = root->Q, N = root->N, KMp = root->KMp;
+    SharedBatch sb{};
+    sb.S = S;
+    sb.nch = (N + MRHS_CHUNK - 1) / MRHS_CHUNK;
+    std::vector<void*> tmp;
+    auto cleanup = [&]() { for (void* p : tmp) hipFree(p); };
+    auto grab = [&](size_t bytes) -> void* {
+      void* p = nullptr;
+      if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+      tmp.push_back(p);
+      return p;
+    };
+    sb.Vb = static_cast<float*>(grab(8 * (size_t)Q * N * S));
+    sb.Tp = static_cast<float*>(grab(8 * (size_t)sb.nch * Q * KMp * S));
+    sb.T64 = static_cast<cd*>(grab(16 * (size_t)Q * S * KMp));
+    sb.Wt64 = static_cast<cd*>(grab(16 * (size_t)Q * S * KMp));
+    MmDesc* wd = static_cast<MmDesc*>(grab(sizeof(MmDesc) * Q));
+    if (!sb.Vb || !sb.Tp || !sb.T64 || !sb.Wt64 || !wd) {
+      cleanup();
+      return fail_msg(hs[0], SADMM_E_NOMEM, "solve_batch: shared-operator buffers");
+    }
+    std::vector<MmDesc> w(Q);
+    for (int q = 0; q < Q; ++q)
+      w[q] = MmDesc{root->W64[q], sb.T64 + (int64_t)q * S * KMp, sb.Wt64 + (int64_t)q * S * KMp,
+                    KMp, S, KMp, KMp, KMp, KMp, 1.0, 0.0, 0.0};
+    if (hipMemcpy(wd, w.data(), sizeof(MmDesc) * Q, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail_msg(hs[0], SADMM_E_HIP, "solve_batch: descriptor upload");
+    }
+    sb.wdesc = wd;
+    const int rc = iterate(v, false, &sb);
+    hipStreamSynchronize(hs[0]->gs);
+    cleanup();
+    TRY(rc);
+  } else {
+    TRY(iterate(v, S == 1));
+  }
   for (int i = 0; i < S; ++i) TRY(solve_epilogue(hs[i], infos ? &infos[i] : nullptr));
   return SADMM_OK;
 }
@@ -1367,6 +1476,7 @@ int sadmm_get_timing(sadmm_t h, int32_t which, double* ms) {
 
 void sadmm_destroy(sadmm_t h) {
   if (!h) return;
+  if (h->shared_src) h->shared_src->n_sharers -= 1;
   if (h->s) hipStreamSynchronize(h->s);
   else hipDeviceSynchronize();
   for (void* p : h->allocs) hipFree(p);

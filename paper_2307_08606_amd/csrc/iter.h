@@ -73,6 +73,25 @@ constexpr int IT_NSTAGE = 4;
 void launch_iteration_batch(const BatchView& b, const BatchDims& d, int st, hipStream_t s,
                             const std::function<void(int, bool)>* hook);
 
+// Stage 3 alone (pixel update, finalize, SSC check) for every scene.
+void launch_pixel_stage(const BatchView& b, const BatchDims& d, bool dbl, hipStream_t s);
+
+// Scenes that share one FP32 operator (and so one factor, no pixel
+// elimination): the forward and adjoint products of all scenes run as
+// multi-right-hand-side products on the FP32 matrix instructions.
+struct SharedBatch {
+  int S;              // scenes (right-hand sides)
+  int nch;            // pixel chunks of the forward product
+  float* Vb;          // Q x N x S complex: v_q of every scene (pixel-major)
+  float* Tp;          // nch x Q x KMp x S complex: forward partial sums
+  cd* T64;            // Q x S x KMp: Ahat v per scene (column-major per sensor)
+  cd* Wt64;           // Q x S x KMp: W (Ahat v)
+  const void* wdesc;  // Q MmDesc products Wt = W T (device)
+};
+constexpr int MRHS_CHUNK = 1024;   // pixels per forward work-group
+void launch_iteration_shared(const BatchView& b, const BatchDims& d, const SharedBatch& sb,
+                             hipStream_t s, const std::function<void(int, bool)>* hook);
+
 // Copies the control blocks of a batch (ptrs: nscene device pointers) into out.
 void gather_ctl(Ctl* const* ptrs, Ctl* out, int nscene, hipStream_t s);
 int fwd_row_tile(int st);   // rows covered by one forward work-group

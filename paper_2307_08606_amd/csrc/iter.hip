@@ -424,6 +424,14 @@ __global__ void gather_ctl_kernel(Ctl* const* ptrs, Ctl* out, int n) {
   if (i < n) out[i] = *ptrs[i];
 }
 
+template <class T>
+void launch_pixel_stage_t(const BatchView& b, const BatchDims& d, hipStream_t s) {
+  pixel_kernel<T><<<dim3(d.nblk_max, d.nscene), 256, 0, s>>>(b);
+  finalize_kernel<<<d.nscene, 256, 0, s>>>(b);
+  ssc_kernel<T><<<dim3((d.N_max + 255) / 256, d.nslot), 256, 0, s>>>(b);
+  ssc_flag_kernel<<<d.nscene, 64, 0, s>>>(b);
+}
+
 template <int ST>
 void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
                          const std::function<void(int, bool)>* hook) {
@@ -444,14 +452,16 @@ void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
                                       (size_t)d.KMp_max * sizeof(C2<T>), s>>>(b);
   mark(2, false);
   mark(3, true);
-  pixel_kernel<T><<<dim3(d.nblk_max, d.nscene), 256, 0, s>>>(b);
-  finalize_kernel<<<d.nscene, 256, 0, s>>>(b);
-  ssc_kernel<T><<<dim3((d.N_max + 255) / 256, d.nslot), 256, 0, s>>>(b);
-  ssc_flag_kernel<<<d.nscene, 64, 0, s>>>(b);
+  launch_pixel_stage_t<T>(b, d, s);
   mark(3, false);
 }
 
 }  // namespace
+
+void launch_pixel_stage(const BatchView& b, const BatchDims& d, bool dbl, hipStream_t s) {
+  if (dbl) launch_pixel_stage_t<double>(b, d, s);
+  else launch_pixel_stage_t<float>(b, d, s);
+}
 
 int fwd_row_tile(int st) {
   switch (st) {

@@ -21,10 +21,25 @@ struct GemmDesc {
   double alpha_re, alpha_im, beta, diag;
 };
 
+// One product of a batched FP64 complex GEMM on the matrix instructions,
+// C = alpha op(A) op(B) + beta C, all column-major complex128.
+struct MmDesc {
+  const cd* A;
+  const cd* B;
+  cd* C;
+  int m, n, k;
+  int lda, ldb, ldc;
+  double alpha_re, alpha_im, beta;
+};
+
 // Batched GEMM launcher.  herm = true computes only tiles on or below the
 // diagonal and mirrors them (C must then be Hermitian: m == n).
 void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int sta, int stb,
                    int opa, int opb, bool herm, hipStream_t s);
+
+// C = alpha A B + beta C (FP64 matrix instructions, no transposes) for a batch
+// of MmDesc products; max_m / max_n bound every product's m and n.
+void zgemm_mfma_nn(const MmDesc* d_desc, int count, int max_m, int max_n, hipStream_t s);
 
 // Order of the lower-triangle tiles (ti >= tj) of an nt x nt tile grid for the
 // Hermitian products: blocks of 4 tile rows x 8 tile columns, so that the
@@ -49,16 +64,6 @@ __device__ inline bool xcd_tile(const int2* tiles, int ntiles, int* ti, int* tj)
 void herk_batched(const GemmDesc* d_desc, int batch, int max_m, int st, const int2* tiles,
                   int ntiles, hipStream_t s);
 
-// One product of a batched FP64 complex GEMM on the matrix instructions,
-// C = alpha op(A) op(B) + beta C, all column-major complex128.
-struct MmDesc {
-  const cd* A;
-  const cd* B;
-  cd* C;
-  int m, n, k;
-  int lda, ldb, ldc;
-  double alpha_re, alpha_im, beta;
-};
 
 // One matrix of a batched Hermitian-positive-definite inverse.
 struct HpdDesc {

@@ -75,6 +75,7 @@ def _sig(name, res, *args):
 
 sadmm_default_params = _sig("sadmm_default_params", None, C.POINTER(sadmm_params))
 sadmm_create = _sig("sadmm_create", C.c_int, C.POINTER(sadmm_params), C.POINTER(_H))
+sadmm_create_shared = _sig("sadmm_create_shared", C.c_int, C.POINTER(sadmm_params), _H, C.POINTER(_H))
 sadmm_set_operator = _sig("sadmm_set_operator", C.c_int, _H, C.c_int32, _P, C.c_int32,
                           C.c_int64, C.c_int32)
 sadmm_set_operator_geometry = _sig("sadmm_set_operator_geometry", C.c_int, _H, C.c_int32,
@@ -153,7 +154,7 @@ class Solver:
     def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
                  eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=1e-2, storage="fp32",
-                 reuse_factor=True, gram="int8", stream=None):
+                 reuse_factor=True, gram="int8", stream=None, share=None):
         p = sadmm_params()
         sadmm_default_params(C.byref(p))
         p.Q, p.K, p.M, p.N = Q, K, M, N
@@ -173,7 +174,11 @@ class Solver:
         self.params = p
         self.Q, self.K, self.M, self.N = Q, K, M, N
         self._h = _H()
-        self._check(sadmm_create(C.byref(p), C.byref(self._h)), create=True)
+        self._src = share          # a borrowed operator's owner must outlive this handle
+        if share is None:
+            self._check(sadmm_create(C.byref(p), C.byref(self._h)), create=True)
+        else:
+            self._check(sadmm_create_shared(C.byref(p), share._h, C.byref(self._h)), create=True)
 
     def _check(self, rc, create=False):
         if rc != SADMM_OK:
