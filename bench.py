@@ -179,6 +179,43 @@ def batch_leg(torch, lib, stream, storage, reps=3):
     return out
 
 
+def shared_leg(torch, lib, stream, info, S=32, iters=31):
+    """S frames of the c2 geometry (scene seeds 100..100+S-1) sharing one FP32
+    operator: one solve_batch iterates all of them with multi-right-hand-side
+    products.  Per-iteration time of the whole batch = (time of `iters`
+    iterations - time of 1 iteration) / (iters - 1), factor built beforehand."""
+    from scenegen import config_geometry, make_scene
+    g = config_geometry("c2")
+    hp = dict(mu=info["mu"], beta=info["beta"], gamma=info["gamma"], lam=info["lam"])
+    ys = [torch.from_numpy(np.ascontiguousarray(make_scene(g, 100 + i, 60, 15.0, extended=True).y)).to("cuda")
+          for i in range(S)]
+
+    def handles(max_iter):
+        src = lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", prune=False, reuse_factor=True,
+                         max_iter=max_iter, stop=False, check_every=max_iter, stream=stream, **hp)
+        for q in range(g.Q):
+            src.set_operator_geometry(q, g.tx[q], g.rx[q], g.pix, g.f0, g.bw)
+        return [src] + [lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", prune=False, max_iter=max_iter,
+                                   stop=False, check_every=max_iter, stream=stream, share=src, **hp)
+                        for _ in range(S - 1)]
+
+    ms = {}
+    for n in (1, iters):
+        hs = handles(n)
+        lib.solve_batch(hs, ys)              # builds the shared factor
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.solve_batch(hs, ys)
+        torch.cuda.synchronize()
+        ms[n] = (time.perf_counter() - t0) * 1e3
+        for h in reversed(hs):
+            h.close()
+    it_ms = (ms[iters] - ms[1]) / (iters - 1)
+    flops = 2 * 8.0 * g.Q * g.K * g.M * g.N * S       # forward + adjoint complex MACs
+    return dict(S=S, iter_ms=it_ms, frame_iters_per_s=S / (it_ms * 1e-3),
+                product_tflops=flops / (it_ms * 1e-3) / 1e12)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -288,6 +325,9 @@ def main():
     # one by one and as one batch (one launch per kernel for all frames)
     if not args.only:
         results["c4"] = batch_leg(torch, lib, stream, args.storage)
+    # frames of one geometry sharing the c2 operator (multi-RHS products)
+    if not args.only and args.storage == "fp32":
+        results["shared"] = shared_leg(torch, lib, stream, info)
 
     steady = results.get("steady")
     extra = {}
@@ -307,6 +347,12 @@ def main():
         extra["c5_matrix_free_Gelem_per_s"] = round(r5["elems_per_iter"] / (r5["iter_ms"] * 1e-3) / 1e9, 1)
         extra["c5_matrix_free_stage_ms"] = {k: round(v[1] / max(v[0], 1), 3)
                                             for k, v in r5["stats"].items() if v[0]}
+    if "shared" in results:
+        r = results["shared"]
+        extra["c2_shared_frames"] = r["S"]
+        extra["c2_shared_batch_iter_ms"] = round(r["iter_ms"], 3)
+        extra["c2_shared_frame_iters_per_s"] = round(r["frame_iters_per_s"], 1)
+        extra["c2_shared_product_tflops"] = round(r["product_tflops"], 1)
     if "c4" in results:
         r4 = results["c4"]
         for k in ("sequential", "batched"):

@@ -1284,8 +1284,9 @@ int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dty
     sb.Tp = static_cast<float*>(grab(8 * (size_t)sb.nch * Q * KMp * S));
     sb.T64 = static_cast<cd*>(grab(16 * (size_t)Q * S * KMp));
     sb.Wt64 = static_cast<cd*>(grab(16 * (size_t)Q * S * KMp));
+    sb.Wt32 = static_cast<float*>(grab(8 * (size_t)Q * S * KMp));
     MmDesc* wd = static_cast<MmDesc*>(grab(sizeof(MmDesc) * Q));
-    if (!sb.Vb || !sb.Tp || !sb.T64 || !sb.Wt64 || !wd) {
+    if (!sb.Vb || !sb.Tp || !sb.T64 || !sb.Wt64 || !sb.Wt32 || !wd) {
       cleanup();
       return fail_msg(hs[0], SADMM_E_NOMEM, "solve_batch: shared-operator buffers");
     }

@@ -86,6 +86,7 @@ struct SharedBatch {
   float* Tp;          // nch x Q x KMp x S complex: forward partial sums
   cd* T64;            // Q x S x KMp: Ahat v per scene (column-major per sensor)
   cd* Wt64;           // Q x S x KMp: W (Ahat v)
+  float* Wt32;        // the same as complex64 (adjoint operands)
   const void* wdesc;  // Q MmDesc products Wt = W T (device)
 };
 constexpr int MRHS_CHUNK = 1024;   // pixels per forward work-group

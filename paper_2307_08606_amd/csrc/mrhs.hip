@@ -51,21 +51,46 @@ __global__ __launch_bounds__(256) void mrhs_fwd_kernel(BatchView bv, SharedBatch
   v4f cr[SB], ci[SB];
 #pragma unroll
   for (int b = 0; b < SB; ++b) { cr[b] = v4f{0.f, 0.f, 0.f, 0.f}; ci[b] = v4f{0.f, 0.f, 0.f, 0.f}; }
+  // V is the same for the four waves (they differ by rows): blocks of 64
+  // pixels x all scenes are staged in LDS once per work-group.  Within a block,
+  // rounds of four k-steps take k = p + 4 g + i for instruction i and lane
+  // group g = lane / 16 (any assignment of k shared by both operands gives the
+  // same sum).
+  constexpr int PB = 64;
+  __shared__ float2 sV[PB][16 * SB + 1];
   const int p0 = c * MRHS_CHUNK, p1 = min(N, p0 + MRHS_CHUNK);
-  for (int p = p0; p < p1; p += 4) {
-    const int pk = p + kq;
-    float2 av = make_float2(0.f, 0.f);
-    if (pk < p1 && row < KMp) av = A[(int64_t)pk * sd.lda + row];
-    const float nai = -av.y;
+  for (int pb = p0; pb < p1; pb += PB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < PB * 16 * SB; e += 256) {
+      const int ss = e % (16 * SB), pp = e / (16 * SB);
+      const int pk = pb + pp;
+      sV[pp][ss] = (pk < p1 && ss < S) ? V[(int64_t)pk * S + ss] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int b = 0; b < SB; ++b) {
-      const int s = 16 * b + (lane & 15);
-      float2 vv = make_float2(0.f, 0.f);
-      if (pk < p1 && s < S) vv = V[(int64_t)pk * S + s];
-      cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, vv.x, cr[b], 0, 0, 0);
-      cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, vv.y, cr[b], 0, 0, 0);
-      ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, vv.y, ci[b], 0, 0, 0);
-      ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, vv.x, ci[b], 0, 0, 0);
+    for (int pr = 0; pr < PB; pr += 16) {
+      float2 av[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pk = pb + pr + 4 * kq + i;
+        av[i] = (pk < p1 && row < KMp) ? A[(int64_t)pk * sd.lda + row] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float2 vv[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) vv[b] = sV[pr + 4 * kq + i][16 * b + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, vv[b].x, cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, vv[b].y, ci[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[i].y, vv[b].y, cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, vv[b].x, ci[b], 0, 0, 0);
+        }
+      }
     }
   }
   float2* Tp = reinterpret_cast<float2*>(sb.Tp) + ((int64_t)c * gridDim.z + q) * KMp * S;
@@ -97,6 +122,14 @@ __global__ __launch_bounds__(256) void mrhs_reduce_kernel(SharedBatch sb, int Q,
   sb.T64[((int64_t)q * S + s) * KMp + row] = cd{re, im};
 }
 
+// W T to FP32 for the adjoint operands.
+__global__ __launch_bounds__(256) void mrhs_cvt_kernel(SharedBatch sb, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const cd v = sb.Wt64[i];
+  reinterpret_cast<float2*>(sb.Wt32)[i] = make_float2((float)v.re, (float)v.im);
+}
+
 // Adjoint and x-update: work-group = 64 pixels x all scenes of sensor
 // blockIdx.y; wave w owns pixels 16w..16w+15.  Y = Ahat^H (W T); the epilogue
 // is the x-update of every (pixel, scene) as in the single-scene path.
@@ -111,29 +144,50 @@ __global__ __launch_bounds__(256) void mrhs_adj_kernel(BatchView bv, SharedBatch
   const int nq = sd.nq;
   const float2* A = reinterpret_cast<const float2*>(sd.A);
   const int S = sb.S;
-  const cd* Wt = sb.Wt64 + (int64_t)q * S * KMp;
+  const float2* Wt = reinterpret_cast<const float2*>(sb.Wt32) + (int64_t)q * S * KMp;
   v4f cr[SB], ci[SB];
 #pragma unroll
   for (int b = 0; b < SB; ++b) { cr[b] = v4f{0.f, 0.f, 0.f, 0.f}; ci[b] = v4f{0.f, 0.f, 0.f, 0.f}; }
-  for (int k = 0; k < KMp; k += 4) {
-    const int kk = k + kq;
-    float2 av = make_float2(0.f, 0.f);
-    if (pa < nq) av = A[(int64_t)pa * sd.lda + kk];
-    // conj(A): real av.x, imaginary -av.y
+  // W T is the same for the four waves: blocks of 64 k x all scenes are staged
+  // in LDS ([k][scene]).  Rounds of four k-steps take k = k0 + 4 g + i
+  // (g = lane / 16): each lane reads 4 consecutive entries of its column.
+  constexpr int KB = 64;
+  __shared__ float2 sW[KB][16 * SB + 1];
+  for (int kb0 = 0; kb0 < KMp; kb0 += KB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KB * 16 * SB; e += 256) {
+      const int kk = e % KB, ss = e / KB;
+      sW[kk][ss] = (ss < S && kb0 + kk < KMp) ? Wt[(int64_t)ss * KMp + kb0 + kk] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int b = 0; b < SB; ++b) {
-      const int s = 16 * b + (lane & 15);
-      float wr = 0.f, wi = 0.f;
-      if (s < S) {
-        const cd wv = Wt[(int64_t)s * KMp + kk];
-        wr = (float)wv.re;
-        wi = (float)wv.im;
+    for (int kr = 0; kr < KB; kr += 16) {
+      const int kb = kb0 + kr + 4 * kq;
+      float4 a01 = make_float4(0.f, 0.f, 0.f, 0.f), a23 = a01;
+      if (pa < nq && kb < KMp) {   // KMp is a multiple of 32: kb + 3 < KMp
+        const float4* ap = reinterpret_cast<const float4*>(A + (int64_t)pa * sd.lda + kb);
+        a01 = ap[0];
+        a23 = ap[1];
       }
+      const float ar[4] = {a01.x, a01.z, a23.x, a23.z};
+      const float ai[4] = {a01.y, a01.w, a23.y, a23.w};
       // (ar - j ai)(wr + j wi) = (ar wr + ai wi) + j (ar wi - ai wr)
-      cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, wr, cr[b], 0, 0, 0);
-      cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, wi, cr[b], 0, 0, 0);
-      ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, wi, ci[b], 0, 0, 0);
-      ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.y, wr, ci[b], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float2 wv[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) wv[b] = sW[kr + 4 * kq + i][16 * b + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], wv[b].x, cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], wv[b].y, ci[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], wv[b].y, cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[i], wv[b].x, ci[b], 0, 0, 0);
+        }
+      }
     }
   }
 #pragma unroll
@@ -177,6 +231,7 @@ void launch_products(const BatchView& b, const BatchDims& d, const SharedBatch& 
   mark(0, false);
   mark(1, true);
   zgemm_mfma_nn(static_cast<const MmDesc*>(sb.wdesc), Q, KMp, sb.S, s);
+  mrhs_cvt_kernel<<<(unsigned)(((int64_t)Q * KMp * sb.S + 255) / 256), 256, 0, s>>>(sb, (int64_t)Q * KMp * sb.S);
   mark(1, false);
   mark(2, true);
   mrhs_adj_kernel<SB><<<dim3((N + 63) / 64, Q), 256, 0, s>>>(b, sb, KMp);

@@ -86,6 +86,23 @@ def test_shared_batch_matches_oracle(gpu_lib, frames):
     assert len(iters) > 1   # scenes stopped at different iterations
 
 
+def test_shared_batch_ragged_rows(gpu_lib):
+    """KM = 96 (the last 64-row block of the products half empty), 5 scenes."""
+    g = make_geometry(3, 2, 48, 20)
+    A = [steering(g, q) for q in range(g.Q)]
+    scenes = [make_scene(g, 70 + i, 5, 18.0) for i in range(5)]
+    lam = 0.2 * oracle.lambda_max(A, scenes[0].y, 1.0, 1.0)
+    src = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", lam=lam, max_iter=300, eps_rel=1e-4)
+    for q in range(g.Q):
+        src.set_operator(q, A[q])
+    hs = [src] + [gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", lam=lam, max_iter=300,
+                                 eps_rel=1e-4, share=src) for _ in range(4)]
+    gpu_lib.solve_batch(hs, [sc.y for sc in scenes])
+    for h, sc in zip(hs, scenes):
+        ref = oracle.solve(A, sc.y, oracle.Params(lam=lam, max_iter=300, eps_rel=1e-4))
+        assert nmse(h.image(), ref.z) <= 1e-6
+
+
 def test_create_shared_rejects_pruning_and_borrowed_setters(gpu_lib, frames):
     g, A, scenes, lam = frames
     src = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", lam=lam)
