@@ -98,6 +98,12 @@ typedef struct {
                                  operator rounded to 30 bits below each row's largest
                                  magnitude (FP64 storage always takes path 1);
                                  1: FP64 matrix instructions on the stored values */
+  int32_t direct;             /* x-update form of a sensor whose active set N_q falls
+                                 below the per-iteration bytes crossover (2.41 KM for
+                                 FP64 storage, 1.62 KM for FP32, 1.28 KM for 16-bit,
+                                 KM matrix-free): 0 (default) switches to the direct
+                                 (mu Ahat^H Ahat + cI)^{-1} of order N_q, 1 keeps the
+                                 Woodbury form (Sec. III solves the N_q system) */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 
@@ -106,11 +112,14 @@ typedef struct {
   int32_t status;             /* 0 converged, 1 max_iter reached, 2 NMSE target reached */
   int32_t prune_events;       /* iterations at which SSC removed pixels */
   int32_t reinstated;         /* pixels put back by the optimality re-check */
-  int32_t refactors;          /* full factor rebuilds (excluding the initial one) */
+  int32_t refactors;          /* full factor rebuilds after the start (Woodbury factor
+                                 or direct-form inverse) */
   int32_t updates;            /* low-rank factor up/down-dates */
   double r, s, eps_pri, eps_dual;   /* residuals of the last iteration */
   double max_active_frac;     /* max_q N_q / N at the end */
   double nmse;                /* NMSE of z vs the reference image, if one is set */
+  int32_t direct_sensors;     /* sensors whose x-update is in the direct form at the end */
+  int32_t pad;
 } sadmm_info;
 
 /* Fills *p with defaults: mu = beta = gamma = 1, eps_rel = 1e-4, Kp = 5,

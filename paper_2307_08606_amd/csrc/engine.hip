@@ -79,6 +79,13 @@ struct sadmm_s {
   std::vector<SensorDesc> sens_h;
   GemmDesc* gemm_d = nullptr;
   HpdDesc* hpd_d = nullptr;
+  // direct form (mu Ahat^H Ahat + cI)^{-1} for small active sets
+  std::vector<uint8_t> direct;   // per sensor
+  std::vector<cd*> Fd, b0d, rdir;
+  std::vector<int> fld;
+  int dir_cap = 0;               // order the direct buffers hold (0: none yet)
+  cd *A64 = nullptr, *dirD = nullptr, *dirX = nullptr, *dirT = nullptr;
+  MmDesc* dir_desc = nullptr;    // 2 products
   sadmm_t shared_src = nullptr;  // operator and factor borrowed from this handle
   int n_sharers = 0;             // handles borrowing this one's operator
   GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
@@ -256,6 +263,11 @@ int push_descs(sadmm_t h) {
     d.W64 = h->W64[q];
     d.lda = h->ldA;
     d.nq = h->nq[q];
+    d.direct = h->direct[q];
+    d.F = h->Fd[q];
+    d.b0 = h->b0d[q];
+    d.rdir = h->rdir[q];
+    d.fld = h->fld[q];
   }
   HIPCHK(h, hipMemcpyAsync(h->sens_d, h->sens_h.data(), sizeof(SensorDesc) * h->Q,
                            hipMemcpyHostToDevice, h->s));
@@ -481,6 +493,104 @@ int refresh_factor(sadmm_t h, int q, const int* d_list, int r, int sign) {
   return build_factors(h, std::vector<int>{q});
 }
 
+// Direct form: largest active set for which x = F (b0 + beta v) reads fewer
+// bytes per iteration than the Woodbury form (16 N^2 for F against
+// 2 KM N b_A + 16 KM^2 for the operator passes and W).
+int direct_threshold(sadmm_t h) {
+  double f;
+  switch (h->st) {
+    case ST_FP64: f = 1.0 + std::sqrt(2.0); break;            // b_A = 16
+    case ST_FP32: f = 0.5 * (1.0 + std::sqrt(5.0)); break;    // b_A = 8
+    case ST_MF: f = 1.0; break;                               // entries recomputed
+    default: f = 0.25 + std::sqrt(1.0625); break;             // b_A = 4
+  }
+  return (int)(f * h->KM);
+}
+// Order the direct buffers hold: the threshold rounded to the factor block.
+// Fixed per handle (params, storage, KM), so an iteration graph captured
+// before any switch already covers it.
+int direct_cap(sadmm_t h) {
+  return (h->p.direct == 0 && !h->shared_src) ? round_up(direct_threshold(h), HPD_NB) : 0;
+}
+bool want_direct(sadmm_t h, int nq) {
+  return h->p.direct == 0 && !h->shared_src && h->n_sharers == 0 && nq > 0 &&
+         nq <= direct_threshold(h);
+}
+
+// Buffers of the direct form, sized once for the largest order it can take.
+int ensure_direct_buffers(sadmm_t h, int q) {
+  const int cap = direct_cap(h);
+  auto grab = [&](void** p, size_t bytes) -> int {
+    if (*p) return SADMM_OK;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      return fail_msg(h, SADMM_E_NOMEM, "direct form: %zu bytes", bytes);
+    }
+    return SADMM_OK;
+  };
+  const size_t c2 = (size_t)cap * cap;
+  TRY(grab((void**)&h->A64, sizeof(cd) * (size_t)h->KMp * cap));
+  TRY(grab((void**)&h->dirD, sizeof(cd) * (size_t)HPD_NB * cap));
+  TRY(grab((void**)&h->dirX, sizeof(cd) * c2));
+  TRY(grab((void**)&h->dirT, sizeof(cd) * (c2 / 4 + 1)));
+  TRY(grab((void**)&h->dir_desc, sizeof(MmDesc) * 2));
+  TRY(grab((void**)&h->Fd[q], sizeof(cd) * c2));
+  TRY(grab((void**)&h->b0d[q], sizeof(cd) * cap));
+  TRY(grab((void**)&h->rdir[q], sizeof(cd) * cap));
+  h->dir_cap = cap;
+  return SADMM_OK;
+}
+
+// Sensor q to the direct form for its current active set:
+// F = (mu Ahat^H Ahat + cI)^{-1} (FP64 Gram on the matrix instructions, the
+// Cholesky inverse) and b0 = mu Ahat^H y'.
+int build_direct(sadmm_t h, int q, bool count = true) {
+  TRY(ensure_direct_buffers(h, q));
+  hipStream_t s = h->s;
+  const int nq = h->nq[q], KMp = h->KMp;
+  const int n = round_up(std::max(nq, 1), HPD_NB);
+  const double c = h->p.beta + h->p.gamma, mu = h->p.mu;
+  gather_columns_fp64(h->Afull[q], h->ldA, h->st, KMp, h->J[q], nq, h->A64, s);
+  MmDesc g[2];
+  g[0] = MmDesc{h->A64, h->A64, h->Fd[q], nq, nq, KMp, KMp, KMp, n, mu, 0.0, 0.0};
+  g[1] = MmDesc{h->A64, reinterpret_cast<const cd*>(h->yp) + (size_t)q * KMp, h->b0d[q], nq, 1, KMp,
+                KMp, KMp, n, mu, 0.0, 0.0};
+  HIPCHK(h, hipMemcpyAsync(h->dir_desc, g, sizeof g, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemsetAsync(h->Fd[q], 0, sizeof(cd) * (size_t)n * n, s));
+  zgemm_mfma_gram_cn(h->dir_desc, 1, nq, s);                   // lower + mirror
+  set_identity_pad(h->Fd[q], nq, n, c, s);                     // + cI, identity padding
+  zgemm_mfma_cn(h->dir_desc + 1, 1, nq, 1, s);                 // b0
+  HpdDesc hd{h->Fd[q], n, h->dirD, h->dirX, h->dirT};
+  std::vector<void*> tmp;
+  MmDesc* mm = nullptr;
+  const size_t own = std::max((size_t)h->Q * hpd_mm_count(KMp), hpd_mm_count(h->rpad_max));
+  TRY(desc_table(h, h->mm_d, own, hpd_mm_count(n), tmp, &mm));
+  HIPCHK(h, hipMemcpyAsync(h->hpd_d, &hd, sizeof hd, hipMemcpyHostToDevice, s));
+  hpd_inverse_batched(&hd, h->hpd_d, 1, n, h->fail, mm, s);
+  HIPCHK(h, hipGetLastError());
+  const int rc = check_fail(h);   // synchronises
+  for (void* p : tmp) hipFree(p);
+  TRY(rc);
+  h->direct[q] = 1;
+  h->fld[q] = n;
+  h->fac_valid[q] = false;        // the Woodbury factor no longer matches
+  if (count) h->info.refactors += 1;
+  return push_descs(h);
+}
+
+// Sensor q from the direct form back to the Woodbury form (its active set
+// grew past the crossover, or emptied): full factor build and data term.
+int to_woodbury(sadmm_t h, int q) {
+  h->direct[q] = 0;
+  h->info.refactors += 1;
+  TRY(build_factors(h, std::vector<int>{q}));
+  TRY(push_descs(h));
+  h->fac_valid[q] = false;
+  launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
+  HIPCHK(h, hipGetLastError());
+  return SADMM_OK;
+}
+
 int read_counts(sadmm_t h) {
   HIPCHK(h, hipMemcpyAsync(h->counts_h, h->counts, 2 * sizeof(int), hipMemcpyDeviceToHost, h->s));
   HIPCHK(h, hipStreamSynchronize(h->s));
@@ -513,6 +623,14 @@ int apply_prune(sadmm_t h) {
     h->nq[q] = kept;
     TRY(compact_operator(h, q));
     TRY(push_descs(h));
+    if (want_direct(h, kept)) {
+      TRY(build_direct(h, q));
+      continue;
+    }
+    if (h->direct[q]) {   // the active set emptied
+      TRY(to_woodbury(h, q));
+      continue;
+    }
     TRY(refresh_factor(h, q, h->lst, r, -1));
     h->fac_valid[q] = false;
     launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
@@ -552,10 +670,16 @@ int kkt_reinstate(sadmm_t h, int* n_back) {
     h->nq[q] = h->counts_h[0];
     TRY(compact_operator(h, q));
     TRY(push_descs(h));
-    TRY(refresh_factor(h, q, h->lst2, r, +1));
-    h->fac_valid[q] = false;
-    launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
-    HIPCHK(h, hipGetLastError());
+    if (want_direct(h, h->nq[q])) {
+      TRY(build_direct(h, q));
+    } else if (h->direct[q]) {   // grown past the crossover
+      TRY(to_woodbury(h, q));
+    } else {
+      TRY(refresh_factor(h, q, h->lst2, r, +1));
+      h->fac_valid[q] = false;
+      launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
+      HIPCHK(h, hipGetLastError());
+    }
     *n_back += r;
   }
   return SADMM_OK;
@@ -575,6 +699,7 @@ int validate(const sadmm_params* p) {
   if (p->Kp < 1 || p->Kp > 64 || !(p->eps_p >= 0)) return SADMM_E_ARG;
   if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_MATRIX_FREE) return SADMM_E_ARG;
   if (p->gram < 0 || p->gram > 1) return SADMM_E_ARG;
+  if (p->direct < 0 || p->direct > 1) return SADMM_E_ARG;
   if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
   if ((int64_t)p->K * p->M > 4096) return SADMM_E_SHAPE;   // W_q and LDS staging limits
   return SADMM_OK;
@@ -658,7 +783,10 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
       HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     TRY(compact_operator(h, q));
-    if (!h->shared_src && (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh)) rebuild.push_back(q);
+    h->direct[q] = want_direct(h, h->nq[q]) ? 1 : 0;   // (built in solve_prologue_finish)
+    if (!h->direct[q] && !h->shared_src &&
+        (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh))
+      rebuild.push_back(q);
     h->facJ[q] = Jh;
   }
   if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
@@ -676,7 +804,16 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
 int solve_prologue_finish(sadmm_t h) {
   hipStream_t s = h->s;
   const int Q = h->Q;
-  launch_xy(make_args(h), h->st, h->dbl, 0, Q, s);
+  bool any_direct = false;
+  for (int q = 0; q < Q; ++q) any_direct = any_direct || h->direct[q];
+  if (!any_direct) {
+    launch_xy(make_args(h), h->st, h->dbl, 0, Q, s);
+  } else {
+    for (int q = 0; q < Q; ++q) {
+      if (h->direct[q]) TRY(build_direct(h, q, false));
+      else launch_xy(make_args(h), h->st, h->dbl, q, q + 1, s);
+    }
+  }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->evf1, s));
   HIPCHK(h, hipEventSynchronize(h->evf1));
@@ -769,6 +906,7 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
     d.nchunk_max = std::max(d.nchunk_max, h->nchunk);
     d.N_max = std::max(d.N_max, h->N);
     d.nblk_max = std::max(d.nblk_max, h->nblk);
+    d.fld_max = std::max(d.fld_max, direct_cap(h));   // covers every later switch
   }
   d.nslot = (int)slots.size();
   IterArgs* args_d = h0->args_d;
@@ -909,6 +1047,8 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
   h->info.r = c.r; h->info.s = c.s; h->info.eps_pri = c.eps_pri; h->info.eps_dual = c.eps_dual;
   h->info.nmse = c.nmse;
   h->info.max_active_frac = max_active_frac(h);
+  h->info.direct_sensors = 0;
+  for (int q = 0; q < h->Q; ++q) h->info.direct_sensors += h->direct[q];
   h->solved = true;
   if (info) *info = h->info;
   return SADMM_OK;
@@ -986,6 +1126,8 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   h->nq.assign(Q, N); h->op_set.assign(Q, false); h->fac_valid.assign(Q, false);
   h->facJ.assign(Q, {}); h->mask0.assign(Q, {});
   h->hpdD.assign(Q, nullptr); h->hpdX.assign(Q, nullptr); h->hpdT.assign(Q, nullptr);
+  h->direct.assign(Q, 0); h->Fd.assign(Q, nullptr); h->b0d.assign(Q, nullptr);
+  h->rdir.assign(Q, nullptr); h->fld.assign(Q, 0);
   h->sens_h.assign(Q, SensorDesc{});
   h->rmax = std::min(KMp, 1024);
   h->rpad_max = round_up(h->rmax, HPD_NB);
@@ -1482,6 +1624,13 @@ void sadmm_destroy(sadmm_t h) {
   else hipDeviceSynchronize();
   for (void* p : h->allocs) hipFree(p);
   if (h->gi8_ws) hipFree(h->gi8_ws);
+  for (int q = 0; q < (int)h->Fd.size(); ++q) {
+    if (h->Fd[q]) hipFree(h->Fd[q]);
+    if (h->b0d[q]) hipFree(h->b0d[q]);
+    if (h->rdir[q]) hipFree(h->rdir[q]);
+  }
+  for (void* p : {(void*)h->A64, (void*)h->dirD, (void*)h->dirX, (void*)h->dirT, (void*)h->dir_desc})
+    if (p) hipFree(p);
   if (h->ctl_h) hipHostFree(h->ctl_h);
   if (h->counts_h) hipHostFree(h->counts_h);
   if (h->halt_h) hipHostFree(h->halt_h);

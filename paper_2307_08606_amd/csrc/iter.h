@@ -15,7 +15,12 @@ struct SensorDesc {
   const cd* W64;       // the same factor in complex128
   int64_t lda;         // column stride of A and Afull (storage slots)
   int nq;
-  int pad;
+  int direct;          // 1: x-update in the direct form x = F (b0 + beta v)
+  const cd* F;         // direct form: (mu Ahat^H Ahat + cI)^{-1}, nq x nq, ld = fld
+  const cd* b0;        // direct form: mu Ahat^H y', nq complex128
+  cd* rdir;            // direct form: b0 + beta v of the current iteration (fld)
+  int fld;             // leading dimension of F (multiple of 32)
+  int pad2;
 };
 
 // Everything the per-iteration kernels need; passed by value.
@@ -58,10 +63,14 @@ struct BatchView {
 struct BatchDims {
   int nscene, nslot;
   int KMp_max, nchunk_max, N_max, nblk_max;
+  int fld_max;          // largest order a sensor may take in the direct form (0: none can)
 };
 
 constexpr int FWD_THREADS = 256;
 constexpr int DOT_COLS_PER_WAVE = 4;
+// Direct-form right-hand side entries staged in LDS per pass (16 KB: within
+// the share of one of eight 256-thread work-groups on a CU).
+constexpr int XDIR_SEG = 1024;
 
 // Launchers.  `st` is the operator storage (sadmm_storage), `dbl` selects FP64
 // compute (only with ST_FP64).

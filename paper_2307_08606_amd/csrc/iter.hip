@@ -24,6 +24,8 @@
 // the solve has halted (converged, max_iter, NMSE target, numeric error, or a
 // pending pixel elimination the host must apply), so the host can queue many
 // iterations ahead and synchronise rarely.
+#include <algorithm>
+
 #include "iter.h"
 
 namespace {
@@ -75,6 +77,7 @@ __global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(BatchView bv) {
   if (a.ctl->halt) return;
   const int q = sl.y, ch = blockIdx.y;
   const SensorDesc sd = a.sens[q];
+  if (sd.direct) return;   // the direct form needs no forward product
   const int p0 = ch * a.chunk;
   if (p0 >= sd.nq) return;
   const int np = min(a.chunk, sd.nq - p0);
@@ -102,6 +105,20 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(BatchView bv) {
   if (a.ctl->halt) return;
   const int q = sl.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
+  if (a.sens[q].direct) {
+    // direct form: right-hand side b0 + beta v of this iteration (all of it
+    // before any x_q of the iteration is written)
+    const SensorDesc sd = a.sens[q];
+    if (i < sd.fld) {
+      cd r = {0.0, 0.0};
+      if (i < sd.nq) {
+        const C2<T> v = shared_v<T>(a, q, sd.J[i]);
+        r = {sd.b0[i].re + a.beta * (double)v.re, sd.b0[i].im + a.beta * (double)v.im};
+      }
+      sd.rdir[i] = r;
+    }
+    return;
+  }
   if (i >= a.KMp) return;
   const int nq = a.sens[q].nq;
   const int nch = (nq + a.chunk - 1) / a.chunk;
@@ -201,6 +218,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
+  if (EPI == EPI_W && sd.direct) return;
   int ncols;
   if constexpr (EPI == EPI_W || EPI == EPI_WY) ncols = a.KMp;
   else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) ncols = sd.nq;
@@ -280,10 +298,64 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
 }
 
 // Per-iteration column dots over a batch: blockIdx.y is the work slot.
+// x-update of a sensor in the direct form, x_q = F (b0 + beta v) with
+// F = (mu Ahat^H Ahat + cI)^{-1}: F is Hermitian, so column p of F,
+// conjugated and dotted with the right-hand side, gives x at the p-th active
+// pixel.  FP64 throughout; the right-hand side (prepared by the forward
+// reduction, zero-padded to fld) passes through LDS in XDIR_SEG segments.
+template <class T>
+__device__ inline void xdir_body(const IterArgs& a, int q) {
+  if (a.ctl->halt) return;
+  const SensorDesc sd = a.sens[q];
+  const int col0 = blockIdx.x * 4 * DOT_COLS_PER_WAVE;
+  if (col0 >= sd.nq) return;
+  extern __shared__ unsigned char smem_raw[];
+  cd* sv = reinterpret_cast<cd*>(smem_raw);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cd acc[DOT_COLS_PER_WAVE];
+#pragma unroll
+  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) acc[c] = {0.0, 0.0};
+  for (int s0 = 0; s0 < sd.fld; s0 += XDIR_SEG) {
+    const int len = min(XDIR_SEG, sd.fld - s0);
+    __syncthreads();   // the previous segment is consumed
+    for (int i = threadIdx.x; i < len; i += 256) sv[i] = sd.rdir[s0 + i];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
+      const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
+      if (p < sd.nq) {   // uniform across the wave
+        const cd d = coldot_core<ST_FP64, double>(sd.F + (int64_t)p * sd.fld + s0, sv, len, lane);
+        acc[c].re += d.re;
+        acc[c].im += d.im;
+      }
+    }
+  }
+  if (lane != 0) return;
+  const int slot = a.ctl->k % a.Kp;
+#pragma unroll
+  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
+    const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
+    if (p >= sd.nq) break;
+    const int n = sd.J[p];
+    const C2<T> xn = {(T)acc[c].re, (T)acc[c].im};
+    const int64_t o = (int64_t)q * a.N + n;
+    const C2<T> dx = csub(xn, ldc<T>(a.X, o));
+    stc<T>(a.X, o, xn);
+    stc<T>(a.dX, o, dx);
+    reinterpret_cast<T*>(a.D)[((int64_t)slot * a.Q + q) * a.N + n] = habs(dx);
+  }
+}
+
 template <int ST, int EPI, class TS = typename Store<ST>::T>
 __global__ __launch_bounds__(256) void coldot_batch_kernel(BatchView bv) {
   const int2 sl = bv.slots[blockIdx.y];
   DotExtra x{};
+  if constexpr (EPI == EPI_XUPD) {
+    if (bv.args[sl.x].sens[sl.y].direct) {
+      xdir_body<TS>(bv.args[sl.x], sl.y);
+      return;
+    }
+  }
   coldot_body<ST, EPI, TS>(bv.args[sl.x], x, sl.y);
 }
 
@@ -441,7 +513,7 @@ void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
   const int cpb = 4 * DOT_COLS_PER_WAVE;
   mark(0, true);
   fwd_iter_kernel<ST><<<dim3((d.KMp_max + rows - 1) / rows, d.nchunk_max, d.nslot), FWD_THREADS, 0, s>>>(b);
-  fwd_reduce_kernel<T><<<dim3((d.KMp_max + 255) / 256, d.nslot), 256, 0, s>>>(b);
+  fwd_reduce_kernel<T><<<dim3((std::max(d.KMp_max, d.fld_max) + 255) / 256, d.nslot), 256, 0, s>>>(b);
   mark(0, false);
   mark(1, true);
   coldot_batch_kernel<ST_FP64, EPI_W, T><<<dim3((d.KMp_max + cpb - 1) / cpb, d.nslot), 256,
@@ -449,7 +521,9 @@ void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
   mark(1, false);
   mark(2, true);
   coldot_batch_kernel<ST, EPI_XUPD><<<dim3((d.N_max + cpb - 1) / cpb, d.nslot), 256,
-                                      (size_t)d.KMp_max * sizeof(C2<T>), s>>>(b);
+                                      std::max((size_t)d.KMp_max * sizeof(C2<T>),
+                                               (size_t)std::min(d.fld_max, XDIR_SEG) * sizeof(cd)),
+                                      s>>>(b);
   mark(2, false);
   mark(3, true);
   launch_pixel_stage_t<T>(b, d, s);

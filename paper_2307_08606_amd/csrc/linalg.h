@@ -40,6 +40,10 @@ void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int 
 // C = alpha A B + beta C (FP64 matrix instructions, no transposes) for a batch
 // of MmDesc products; max_m / max_n bound every product's m and n.
 void zgemm_mfma_nn(const MmDesc* d_desc, int count, int max_m, int max_n, hipStream_t s);
+// C = alpha A^H B + beta C, and its Hermitian form (lower triangle and mirror,
+// C = alpha A^H A with B = A, m = n <= max_n).
+void zgemm_mfma_cn(const MmDesc* d_desc, int count, int max_m, int max_n, hipStream_t s);
+void zgemm_mfma_gram_cn(const MmDesc* d_desc, int count, int max_n, hipStream_t s);
 
 // Order of the lower-triangle tiles (ti >= tj) of an nt x nt tile grid for the
 // Hermitian products: blocks of 4 tile rows x 8 tile columns, so that the

@@ -554,6 +554,12 @@ void zgemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, int 
 void zgemm_mfma_nn(const MmDesc* d_desc, int count, int max_m, int max_n, hipStream_t s) {
   launch_zmm<OP_N, OP_N, KR_ALL, MM_FULL>(d_desc, count, max_m, max_n, s);
 }
+void zgemm_mfma_cn(const MmDesc* d_desc, int count, int max_m, int max_n, hipStream_t s) {
+  launch_zmm<OP_C, OP_N, KR_ALL, MM_FULL>(d_desc, count, max_m, max_n, s);
+}
+void zgemm_mfma_gram_cn(const MmDesc* d_desc, int count, int max_n, hipStream_t s) {
+  launch_zmm<OP_C, OP_N, KR_ALL, MM_HERM>(d_desc, count, max_n, max_n, s);
+}
 
 std::vector<int2> tri_tile_order(int nt) {
   constexpr int SR = 4, SC = 8;

@@ -136,6 +136,33 @@ def test_pruned_fp32_image_c1(gpu_lib):
     assert nmse(s.image(), ref.z) <= 1e-6
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_direct_form_after_pruning(gpu_lib, storage):
+    """SSC leaves every sensor about 50 of 1024 pixels, far below the bytes
+    crossover (2.41 KM = 618 for FP64 storage, 1.62 KM = 414 for FP32, KM =
+    256): the x-update switches to x = (mu Ahat^H Ahat + cI)^{-1}
+    (mu Ahat^H y' + beta v), the same minimiser as the Woodbury form.  FP64:
+    selectors, iteration count and image as the oracle (1e-8, the pruned-solve
+    bar); FP32: the FP32 image bar; both match the run kept in the Woodbury form."""
+    g, sc, A, hp = problem(seed=1, lam_frac=0.2)
+    kw = dict(max_iter=300, eps_rel=1e-4, prune=True, Kp=5, eps_p=1e-5)
+    s_d, info_d = gpu_run(gpu_lib, g, A, sc.y, hp, storage, **kw)
+    s_w, info_w = gpu_run(gpu_lib, g, A, sc.y, hp, storage, direct=False, **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, **kw))
+    assert ref.prune_events > 0
+    assert info_d["direct_sensors"] == g.Q and info_w["direct_sensors"] == 0
+    assert info_d["refactors"] >= g.Q
+    if storage == "fp64":
+        assert info_d["iters"] == ref.iters == info_w["iters"]
+        for q in range(g.Q):
+            assert np.array_equal(s_d.active_mask(q).astype(bool), ref.active[q])
+        assert rel(s_d.image(), ref.z) < 1e-8
+        assert rel(s_d.image(), s_w.image()) < 1e-8
+    else:
+        assert nmse(s_d.image(), ref.z) <= 1e-6
+        assert nmse(s_d.image(), s_w.image()) <= 1e-6
+
+
 def test_zero_mode_fp64(gpu_lib):
     g, sc, A, hp = problem(seed=6)
     kw = dict(max_iter=60, stop=False, prune=True, Kp=4, eps_p=1e-4, eps_rel=1e-3)
