@@ -104,6 +104,14 @@ typedef struct {
                                  KM matrix-free): 0 (default) switches to the direct
                                  (mu Ahat^H Ahat + cI)^{-1} of order N_q, 1 keeps the
                                  Woodbury form (Sec. III solves the N_q system) */
+  int32_t refine_every;       /* FP16P / BF16P storage only, operator set from the
+                                 geometry: every refine_every iterations (at the next
+                                 status read) and at convergence, the correction
+                                 g = mu (A^H (y - A x) - Ahat^H (y' - Ahat x)) of the
+                                 stored operator Ahat toward the accurate A (FP32
+                                 entries regenerated as in MATRIX_FREE) enters the
+                                 x-update, whose fixed point becomes that of A.
+                                 0 (default): off */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 

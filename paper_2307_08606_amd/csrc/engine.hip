@@ -86,6 +86,13 @@ struct sadmm_s {
   int dir_cap = 0;               // order the direct buffers hold (0: none yet)
   cd *A64 = nullptr, *dirD = nullptr, *dirX = nullptr, *dirT = nullptr;
   MmDesc* dir_desc = nullptr;    // 2 products
+  // correction of 16-bit storage toward the accurate (regenerated) operator
+  std::vector<double*> rec;      // per sensor: phase records of the geometry, or null
+  SensorDesc* sens_mf_d = nullptr;   // sensor table viewing rec as a matrix-free operator
+  double *gfix = nullptr, *re1 = nullptr, *re2 = nullptr, *rw = nullptr;
+  void *g32 = nullptr, *xfix = nullptr;
+  MmDesc* ref_desc = nullptr;    // Q products W_q t
+  int k_refined = 0;             // iteration of the last correction
   sadmm_t shared_src = nullptr;  // operator and factor borrowed from this handle
   int n_sharers = 0;             // handles borrowing this one's operator
   GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
@@ -245,6 +252,8 @@ IterArgs make_args(sadmm_t h) {
   a.max_iter = h->p.max_iter;
   a.ctl = h->ctl; a.hist = h->hist;
   a.keep = h->keep; a.gone = h->gone;
+  a.gfix = h->p.refine_every > 0 ? h->gfix : nullptr;
+  a.xfix = h->p.refine_every > 0 ? h->xfix : nullptr;
   return a;
 }
 
@@ -271,6 +280,15 @@ int push_descs(sadmm_t h) {
   }
   HIPCHK(h, hipMemcpyAsync(h->sens_d, h->sens_h.data(), sizeof(SensorDesc) * h->Q,
                            hipMemcpyHostToDevice, h->s));
+  if (h->sens_mf_d) {
+    std::vector<SensorDesc> m = h->sens_h;
+    for (int q = 0; q < h->Q; ++q) {
+      m[q].A = m[q].Afull = h->rec[q];
+      m[q].lda = MF_REC_BASE + MF_REC_PER_RX * (int64_t)h->M;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->sens_mf_d, m.data(), sizeof(SensorDesc) * h->Q,
+                             hipMemcpyHostToDevice, h->s));
+  }
   HIPCHK(h, hipStreamSynchronize(h->s));
   return SADMM_OK;
 }
@@ -700,6 +718,9 @@ int validate(const sadmm_params* p) {
   if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_MATRIX_FREE) return SADMM_E_ARG;
   if (p->gram < 0 || p->gram > 1) return SADMM_E_ARG;
   if (p->direct < 0 || p->direct > 1) return SADMM_E_ARG;
+  if (p->refine_every < 0) return SADMM_E_ARG;
+  if (p->refine_every > 0 && p->storage != SADMM_ST_FP16P && p->storage != SADMM_ST_BF16P)
+    return SADMM_E_ARG;   // the correction is for 16-bit storage
   if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
   if ((int64_t)p->K * p->M > 4096) return SADMM_E_SHAPE;   // W_q and LDS staging limits
   return SADMM_OK;
@@ -710,12 +731,43 @@ int validate(const sadmm_params* p) {
 // compaction, factor build, data term; uploads the iteration arguments.
 // With rebuild_out, stops before the factor build and returns the sensors to
 // rebuild (the caller builds them and then calls solve_prologue_finish).
+// Buffers of the correction (allocated at the first solve that uses it) and
+// a zero correction to start from.
+int refine_setup(sadmm_t h) {
+  for (int q = 0; q < h->Q; ++q)
+    if (!h->rec[q])
+      return fail_msg(h, SADMM_E_STATE,
+                      "solve: refine_every needs the geometry of sensor %d (sadmm_set_operator_geometry)", q);
+  const size_t QN = (size_t)h->Q * h->N;
+  auto grab = [&](void** p, size_t bytes) -> int {
+    if (*p) return SADMM_OK;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      return fail_msg(h, SADMM_E_NOMEM, "refinement buffers: %zu bytes", bytes);
+    }
+    return SADMM_OK;
+  };
+  TRY(grab((void**)&h->sens_mf_d, sizeof(SensorDesc) * h->Q));
+  TRY(grab((void**)&h->gfix, 16 * QN));
+  TRY(grab(&h->g32, h->csz * QN));
+  TRY(grab(&h->xfix, h->csz * QN));
+  TRY(grab((void**)&h->re1, 16 * (size_t)h->KMp));
+  TRY(grab((void**)&h->re2, 16 * (size_t)h->KMp));
+  TRY(grab((void**)&h->rw, 16 * (size_t)h->KMp));
+  TRY(grab((void**)&h->ref_desc, sizeof(MmDesc) * h->Q));
+  HIPCHK(h, hipMemsetAsync(h->gfix, 0, 16 * QN, h->s));
+  HIPCHK(h, hipMemsetAsync(h->g32, 0, h->csz * QN, h->s));
+  HIPCHK(h, hipMemsetAsync(h->xfix, 0, h->csz * QN, h->s));
+  return SADMM_OK;
+}
+
 int solve_prologue_finish(sadmm_t h);
 int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
                    std::vector<int>* rebuild_out = nullptr) {
   if (!y || (dtype != SADMM_C128 && dtype != SADMM_C64)) return fail_msg(h, SADMM_E_ARG, "solve: bad y");
   for (int q = 0; q < h->Q; ++q)
     if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "solve: operator of sensor %d not set", q);
+  if (h->p.refine_every > 0) TRY(refine_setup(h));
   hipStream_t s = h->s;
   h->info = sadmm_info{};
   h->solved = false;
@@ -823,11 +875,58 @@ int solve_prologue_finish(sadmm_t h) {
   h->t_factor = fms;
   h->frac_pts.assign(1, {1, max_active_frac(h)});
   h->kkt_rounds = 0;
+  h->k_refined = 0;
   h->status = 1;
   h->done = false;
   const IterArgs a = make_args(h);
   HIPCHK(h, hipMemcpyAsync(h->args_d, &a, sizeof(IterArgs), hipMemcpyHostToDevice, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  return SADMM_OK;
+}
+
+// Correction of a 16-bit stored operator Ahat toward the accurate operator A
+// (regenerated from the geometry's phase records, FP32 entries):
+//   g = mu (A^H (y - A x) - Ahat^H (y' - Ahat x))   on the active pixels,
+// with the x of the latest iteration.  The x-update then solves
+// (mu Ahat^H Ahat + cI) x = mu Ahat^H y' + beta v + g, whose fixed point is
+// the x-update of A itself.  A Woodbury sensor adds the precomputed
+// xfix = (mu Ahat^H Ahat + cI)^{-1} g = (g - Ahat^H W Ahat g) / c, a direct
+// sensor adds g to its right-hand side.  A x runs over every pixel, frozen
+// ones included (y' holds their contribution through Ahat).
+int refine(sadmm_t h, int k) {
+  hipStream_t s = h->s;
+  const int KMp = h->KMp;
+  const double mu = h->p.mu, cinv = 1.0 / (h->p.beta + h->p.gamma);
+  const IterArgs a = make_args(h);
+  IterArgs am = a;
+  am.sens = h->sens_mf_d;
+  IterArgs ag = a;
+  ag.X = h->g32;
+  std::vector<MmDesc> md(h->Q);
+  for (int q = 0; q < h->Q; ++q)
+    md[q] = MmDesc{h->W64[q], reinterpret_cast<const cd*>(h->re2), reinterpret_cast<cd*>(h->rw), KMp, 1,
+                   KMp, KMp, KMp, KMp, 1.0, 0.0, 0.0};
+  HIPCHK(h, hipMemcpyAsync(h->ref_desc, md.data(), sizeof(MmDesc) * h->Q, hipMemcpyHostToDevice, s));
+  for (int q = 0; q < h->Q; ++q) {
+    const int nq = h->nq[q];
+    if (nq == 0) continue;
+    // re1 = A x - y (every pixel), re2 = Ahat x - y' (active pixels)
+    scale_c128(h->y + 2 * (size_t)q * KMp, h->re1, KMp, -1.0, s);
+    launch_gather_fwd(am, ST_MF, false, q, nullptr, h->N, 1.0, h->re1, h->gtmp, s);
+    scale_c128(h->yp + 2 * (size_t)q * KMp, h->re2, KMp, -1.0, s);
+    launch_gather_fwd(a, h->st, false, q, h->J[q], nq, 1.0, h->re2, h->gtmp, s);
+    launch_refine_grad(am, ST_MF, q, h->J[q], nq, h->re1, -mu, false, h->gfix, h->g32, s);
+    launch_refine_grad(a, h->st, q, h->J[q], nq, h->re2, mu, true, h->gfix, h->g32, s);
+    if (h->direct[q]) continue;
+    // xfix = (g - Ahat^H W (Ahat g)) / c
+    HIPCHK(h, hipMemsetAsync(h->re2, 0, 16 * (size_t)KMp, s));
+    launch_gather_fwd(ag, h->st, false, q, h->J[q], nq, 1.0, h->re2, h->gtmp, s);
+    zgemm_mfma_nn(h->ref_desc + q, 1, KMp, 1, s);
+    launch_refine_fix(a, h->st, q, h->J[q], nq, h->rw, h->gfix, cinv, h->xfix, s);
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->k_refined = k;
   return SADMM_OK;
 }
 
@@ -842,6 +941,7 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
   if (c.halt & HALT_PRUNE) {
     HIPCHK(h, hipEventRecord(h->evf0, s));
     TRY(apply_prune(h));
+    if (h->p.refine_every > 0) TRY(refine(h, c.k));
     HIPCHK(h, hipEventRecord(h->evf1, s));
     HIPCHK(h, hipEventSynchronize(h->evf1));
     hipEventElapsedTime(&fms, h->evf0, h->evf1);
@@ -870,6 +970,7 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
         hipEventElapsedTime(&fms, h->evf0, h->evf1);
         h->t_factor += fms;
         if (back > 0) {
+          if (h->p.refine_every > 0) TRY(refine(h, c.k));
           h->info.reinstated += back;
           h->frac_pts.push_back({c.k + 1, max_active_frac(h)});
           if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
@@ -880,6 +981,15 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
           return SADMM_OK;
         }
       }
+    }
+    if (h->p.refine_every > 0 && c.k < h->p.max_iter && c.k - h->k_refined >= h->p.refine_every) {
+      // converged on a correction older than the interval: refresh it and go on
+      TRY(refine(h, c.k));
+      *h->halt_h = 0;
+      HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      *active = true;
+      return SADMM_OK;
     }
     h->status = 0;
     h->done = true;
@@ -1008,6 +1118,9 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
       *h->ctl_h = ctl_all[i];
       bool active = false;
       rc = handle_halt(h, ctl_all[i], &active);
+      if (rc == SADMM_OK && active && h->p.refine_every > 0 &&
+          ctl_all[i].k - h->k_refined >= h->p.refine_every)
+        rc = refine(h, ctl_all[i].k);
       if (rc != SADMM_OK && h != h0) h0->err = h->err;
       any = any || active;
     }
@@ -1128,6 +1241,7 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   h->hpdD.assign(Q, nullptr); h->hpdX.assign(Q, nullptr); h->hpdT.assign(Q, nullptr);
   h->direct.assign(Q, 0); h->Fd.assign(Q, nullptr); h->b0d.assign(Q, nullptr);
   h->rdir.assign(Q, nullptr); h->fld.assign(Q, 0);
+  h->rec.assign(Q, nullptr);
   h->sens_h.assign(Q, SensorDesc{});
   h->rmax = std::min(KMp, 1024);
   h->rpad_max = round_up(h->rmax, HPD_NB);
@@ -1257,6 +1371,11 @@ int sadmm_set_operator(sadmm_t h, int32_t q, const void* A, int32_t dtype, int64
     ld = h->KM;
   }
   convert_operator(src, dtype == SADMM_C128, ld, h->KM, h->N, h->st, h->Afull[q], h->ldA, h->KMp, h->s);
+  if (h->rec[q]) {   // the geometry no longer describes this operator
+    hipStreamSynchronize(h->s);
+    hipFree(h->rec[q]);
+    h->rec[q] = nullptr;
+  }
   hipError_t e = hipStreamSynchronize(h->s);
   if (stage) hipFree(stage);
   if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator: %s", hipGetErrorString(e));
@@ -1284,6 +1403,17 @@ int sadmm_set_operator_geometry(sadmm_t h, int32_t q, const double* tx_xy, const
   else
     geometry_operator(g, g + 2, g + 2 + 2 * h->M, h->M, h->K, h->N, f0, bw, h->st, h->Afull[q], h->ldA,
                       h->KMp, h->s);
+  if (h->st == ST_FP16P || h->st == ST_BF16P) {
+    // phase records of the same geometry: the accurate operator of the correction
+    const int64_t ldr = MF_REC_BASE + MF_REC_PER_RX * (int64_t)h->M;
+    if (!h->rec[q] && hipMalloc((void**)&h->rec[q], sizeof(double) * ldr * h->N) != hipSuccess) {
+      h->rec[q] = nullptr;
+      hipStreamSynchronize(h->s);
+      hipFree(g);
+      return fail_msg(h, SADMM_E_NOMEM, "set_operator_geometry: record allocation failed");
+    }
+    mf_records(g, g + 2, g + 2 + 2 * h->M, h->M, h->K, h->N, f0, bw, h->rec[q], ldr, h->s);
+  }
   hipError_t e = hipStreamSynchronize(h->s);
   hipFree(g);
   if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator_geometry: %s", hipGetErrorString(e));
@@ -1630,6 +1760,11 @@ void sadmm_destroy(sadmm_t h) {
     if (h->rdir[q]) hipFree(h->rdir[q]);
   }
   for (void* p : {(void*)h->A64, (void*)h->dirD, (void*)h->dirX, (void*)h->dirT, (void*)h->dir_desc})
+    if (p) hipFree(p);
+  for (double* p : h->rec)
+    if (p) hipFree(p);
+  for (void* p : {(void*)h->sens_mf_d, (void*)h->gfix, h->g32, h->xfix, (void*)h->re1, (void*)h->re2,
+                  (void*)h->rw, (void*)h->ref_desc})
     if (p) hipFree(p);
   if (h->ctl_h) hipHostFree(h->ctl_h);
   if (h->counts_h) hipHostFree(h->counts_h);

@@ -51,6 +51,11 @@ struct IterArgs {
   double* hist;        // 6 x max_iter
   uint8_t* keep;       // Q x N: SSC keep flag per active position
   int* gone;           // Q: pixels to eliminate per sensor
+  // Correction of a stored 16-bit operator toward the accurate one (null when
+  // off): gfix = mu (A^H (y - A x) - Ahat^H (y' - Ahat x)) at a recent x, and
+  // xfix = (mu Ahat^H Ahat + cI)^{-1} gfix, both Q x N by pixel.
+  const double* gfix;  // complex128
+  const void* xfix;    // compute precision
 };
 
 // A batch of independent problems ("scenes") iterated by one launch per
@@ -125,5 +130,15 @@ void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx
                       hipStream_t s);
 
 // |A_q^H y_q| over all pixels for every sensor, into out (Q x N doubles).
+// Refinement products of sensor q over the pixel list idx (count entries),
+// column n = idx[p] of the full operator (storage st):
+//   launch_refine_grad: g[n] = scale (A^H e)_n, or with accumulate g[n] += it,
+//                       also writing the sum in compute precision to g32[n];
+//   launch_refine_fix:  xfix[n] = cinv (g[n] - (A^H w)_n).
+// e, w: KMp complex128; g: Q x N complex128; g32, xfix: Q x N compute precision.
+void launch_refine_grad(const IterArgs& a, int st, int q, const int* idx, int count, const double* e,
+                        double scale, bool accumulate, double* g, void* g32, hipStream_t s);
+void launch_refine_fix(const IterArgs& a, int st, int q, const int* idx, int count, const double* w,
+                       const double* g, double cinv, void* xfix, hipStream_t s);
 void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,
                            hipStream_t s);

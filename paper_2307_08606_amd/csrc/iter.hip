@@ -114,6 +114,11 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(BatchView bv) {
       if (i < sd.nq) {
         const C2<T> v = shared_v<T>(a, q, sd.J[i]);
         r = {sd.b0[i].re + a.beta * (double)v.re, sd.b0[i].im + a.beta * (double)v.im};
+        if (a.gfix) {
+          const double* g = a.gfix + 2 * ((int64_t)q * a.N + sd.J[i]);
+          r.re += g[0];
+          r.im += g[1];
+        }
       }
       sd.rdir[i] = r;
     }
@@ -170,7 +175,12 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(int KMp, int nch, co
 }
 
 // ------------------------------------------------------------------ column dots
-enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5 };
+enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5,
+              EPI_GRAD = 6, EPI_FIX = 7 };
+// Column dots over a caller's pixel list of one sensor (x.q, x.idx, x.count)
+template <int EPI> constexpr bool listed_cols() {
+  return EPI == EPI_KKT || EPI == EPI_GRAD || EPI == EPI_FIX;
+}
 
 struct DotExtra {
   const int* idx;       // KKT: eliminated pixel list
@@ -180,8 +190,11 @@ struct DotExtra {
   int64_t vec_stride;   // per-sensor stride (complex entries)
   double mu, gamma, thr;
   uint8_t* flag;        // KKT
-  double* out;          // MF (|.|), WY (complex)
+  double* out;          // MF (|.|), WY (complex); GRAD / FIX: g (complex128, by pixel)
   int q0;               // WY / XY: first sensor of the launch
+  int accumulate;       // GRAD: add to out
+  void* out32;          // GRAD (accumulate): g in compute precision; FIX: xfix
+  double cinv;          // FIX: 1 / c
 };
 
 // Dot of one operator column with the LDS vector sv, accumulated in TA.
@@ -222,7 +235,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   int ncols;
   if constexpr (EPI == EPI_W || EPI == EPI_WY) ncols = a.KMp;
   else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) ncols = sd.nq;
-  else if constexpr (EPI == EPI_KKT) ncols = x.count;
+  else if constexpr (listed_cols<EPI>()) ncols = x.count;
   else ncols = a.N;
   const int cols_per_block = 4 * DOT_COLS_PER_WAVE;
   const int col0 = blockIdx.x * cols_per_block;
@@ -239,7 +252,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     else if constexpr (EPI == EPI_XUPD) v = ldc<TA>(a.w, (int64_t)q * a.KMp + i);
     else if constexpr (EPI == EPI_XY) v = {a.wy[2 * ((int64_t)q * a.KMp + i)], a.wy[2 * ((int64_t)q * a.KMp + i) + 1]};
     else {
-      const double* src = x.vec + 2 * ((EPI == EPI_KKT ? 0 : (int64_t)q * x.vec_stride) + i);
+      const double* src = x.vec + 2 * ((listed_cols<EPI>() ? 0 : (int64_t)q * x.vec_stride) + i);
       v = {(TA)src[0], (TA)src[1]};
     }
     sv[i] = v;
@@ -253,7 +266,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_WY) col = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) col = col_ptr<ST>(sd.A, sd.lda, p);
-    else if constexpr (EPI == EPI_KKT) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
+    else if constexpr (listed_cols<EPI>()) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
     else col = col_ptr<ST>(sd.Afull, sd.lda, p);
     const C2<TA> d = coldot_core<ST, TA>(col, sv, a.KMp, lane);
     if (lane != 0) continue;
@@ -264,7 +277,8 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const C2<T> v = shared_v<T>(a, q, n);
       const C2<T> xy = ldc<T>(sd.xy, p);
       const T bc = (T)a.bc;
-      const C2<T> xn = {xy.re + bc * (v.re - d.re), xy.im + bc * (v.im - d.im)};
+      C2<T> xn = {xy.re + bc * (v.re - d.re), xy.im + bc * (v.im - d.im)};
+      if (a.xfix) xn = cadd(xn, ldc<T>(a.xfix, (int64_t)q * a.N + n));
       const int64_t o = (int64_t)q * a.N + n;
       const C2<T> xo = ldc<T>(a.X, o);
       const C2<T> dx = csub(xn, xo);
@@ -284,6 +298,19 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const double gre = x.mu * d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
       const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
       x.flag[p] = hypot(gre, gim) > x.thr ? 1 : 0;
+    } else if constexpr (EPI == EPI_GRAD) {
+      const int64_t o = (int64_t)q * a.N + x.idx[p];
+      double gr = x.mu * d.re, gi = x.mu * d.im;
+      if (x.accumulate) {
+        gr += x.out[2 * o];
+        gi += x.out[2 * o + 1];
+        stc<T>(x.out32, o, C2<T>{(T)gr, (T)gi});
+      }
+      x.out[2 * o] = gr;
+      x.out[2 * o + 1] = gi;
+    } else if constexpr (EPI == EPI_FIX) {
+      const int64_t o = (int64_t)q * a.N + x.idx[p];
+      stc<T>(x.out32, o, C2<T>{(T)(x.cinv * (x.out[2 * o] - d.re)), (T)(x.cinv * (x.out[2 * o + 1] - d.im))});
     } else {
       x.out[(int64_t)q * a.N + p] = hypot(d.re, d.im);
     }
@@ -292,7 +319,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
 
 template <int ST, int EPI, class TS = typename Store<ST>::T>
 __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
-  const int q = (EPI == EPI_KKT) ? x.q
+  const int q = listed_cols<EPI>() ? x.q
               : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
   coldot_body<ST, EPI, TS>(a, x, q);
 }
@@ -639,6 +666,49 @@ void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx
     case ST_BF16P: kkt_impl<ST_BF16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
     case ST_MF: kkt_impl<ST_MF>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
   }
+}
+
+template <int ST>
+static void refine_impl(const IterArgs& a, int epi, int q, const int* idx, int count, const double* v,
+                        double scale, bool accumulate, double* g, void* out32, double cinv,
+                        hipStream_t s) {
+  if (count <= 0) return;
+  DotExtra x{};
+  x.idx = idx;
+  x.count = count;
+  x.q = q;
+  x.vec = v;
+  x.mu = scale;
+  x.accumulate = accumulate ? 1 : 0;
+  x.out = g;
+  x.out32 = out32;
+  x.cinv = cinv;
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const size_t smem = (size_t)a.KMp * sizeof(cd);
+  const dim3 grid((count + cpb - 1) / cpb, 1);
+  if (epi == EPI_GRAD) coldot_kernel<ST, EPI_GRAD><<<grid, 256, smem, s>>>(a, x);
+  else coldot_kernel<ST, EPI_FIX><<<grid, 256, smem, s>>>(a, x);
+}
+
+static void refine_dispatch(const IterArgs& a, int st, int epi, int q, const int* idx, int count,
+                            const double* v, double scale, bool accumulate, double* g, void* out32,
+                            double cinv, hipStream_t s) {
+  switch (st) {
+    case ST_FP16P: refine_impl<ST_FP16P>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
+    case ST_BF16P: refine_impl<ST_BF16P>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
+    case ST_MF: refine_impl<ST_MF>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
+    default: break;   // refinement applies to 16-bit storage only (checked by the caller)
+  }
+}
+
+void launch_refine_grad(const IterArgs& a, int st, int q, const int* idx, int count, const double* e,
+                        double scale, bool accumulate, double* g, void* g32, hipStream_t s) {
+  refine_dispatch(a, st, EPI_GRAD, q, idx, count, e, scale, accumulate, g, g32, 0.0, s);
+}
+
+void launch_refine_fix(const IterArgs& a, int st, int q, const int* idx, int count, const double* w,
+                       const double* g, double cinv, void* xfix, hipStream_t s) {
+  refine_dispatch(a, st, EPI_FIX, q, idx, count, w, 1.0, false, const_cast<double*>(g), xfix, cinv, s);
 }
 
 template <int ST>

@@ -46,7 +46,7 @@ class sadmm_params(C.Structure):
         ("prune", C.c_int32), ("Kp", C.c_int32), ("eps_p", C.c_double),
         ("prune_mode", C.c_int32), ("kkt", C.c_int32), ("kkt_tol", C.c_double),
         ("storage", C.c_int32), ("reuse_factor", C.c_int32), ("gram", C.c_int32),
-        ("direct", C.c_int32), ("stream", C.c_void_p),
+        ("direct", C.c_int32), ("refine_every", C.c_int32), ("stream", C.c_void_p),
     ]
 
 
@@ -155,7 +155,8 @@ class Solver:
     def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
                  eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=1e-2, storage="fp32",
-                 reuse_factor=True, gram="int8", direct=True, stream=None, share=None):
+                 reuse_factor=True, gram="int8", direct=True, refine_every=0, stream=None,
+                 share=None):
         p = sadmm_params()
         sadmm_default_params(C.byref(p))
         p.Q, p.K, p.M, p.N = Q, K, M, N
@@ -169,6 +170,7 @@ class Solver:
         p.reuse_factor = int(bool(reuse_factor))
         p.gram = {"int8": 0, "fp64": 1}[gram]
         p.direct = 0 if direct else 1
+        p.refine_every = int(refine_every)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

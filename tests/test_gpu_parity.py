@@ -190,6 +190,90 @@ def test_kkt_reinstates_forced_false_prune_fp64(gpu_lib):
     assert nmse(s.image(), plain.z) < 1e-6
 
 
+# ---------------------------------------------------------------- 16-bit correction
+
+def geometry_solver(lib, g, storage, hp, **kw):
+    s = lib.Solver(g.Q, g.K, g.M, g.N, storage=storage, **hp, **kw)
+    for q in range(g.Q):
+        s.set_operator_geometry(q, g.tx[q], g.rx[q], g.pix, g.f0, g.bw)
+    return s
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_refinement_of_half_precision_storage(gpu_lib, storage):
+    """16-bit stored operator corrected every 10 iterations toward the
+    operator regenerated in FP32 from the same geometry: the x-update's fixed
+    point is that of the accurate operator, so the image meets the FP32 bar
+    (NMSE 1e-6 against the FP64 optimum) that the uncorrected solve misses."""
+    g, sc, A, hp = problem(seed=19)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
+    err = {}
+    for every in (0, 10):
+        s = geometry_solver(gpu_lib, g, storage, hp, refine_every=every, max_iter=100, stop=False)
+        s.solve(sc.y)
+        err[every] = nmse(s.image(), ref.z)
+    print(storage, err)
+    assert err[10] <= 1e-6
+    assert err[10] <= 1e-2 * err[0]
+
+
+def test_refinement_with_pruning(gpu_lib):
+    """Correction on a pruned BF16 solve run to convergence (SSC elimination
+    with low-rank factor updates, a last correction at convergence): image
+    against the FP64 optimum."""
+    g, sc, A, hp = problem(seed=1, lam_frac=0.2)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
+    kw = dict(max_iter=400, eps_rel=1e-6, prune=True, Kp=5, eps_p=1e-5)
+    out = {}
+    for every in (0, 10):
+        s = geometry_solver(gpu_lib, g, "bf16", hp, refine_every=every, **kw)
+        info = s.solve(sc.y)
+        out[every] = (nmse(s.image(), ref.z), info["prune_events"], info["iters"])
+    print(out)
+    assert out[10][1] > 0
+    assert out[10][0] <= 1e-6
+    assert out[10][0] <= 1e-2 * out[0][0]
+
+
+def test_refinement_in_direct_form(gpu_lib):
+    """A caller selector leaves each sensor 300 pixels (below the 16-bit
+    crossover 1.28 KM = 327), so every sensor starts in the direct form and
+    the correction enters its right-hand side: image against the FP64 optimum
+    of the same restricted problem."""
+    g, sc, A, hp = problem(seed=1, lam_frac=0.2)
+    rng = np.random.default_rng(12)
+    plain = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
+    supp = np.flatnonzero(np.abs(plain.z) > 0)
+    mask0 = np.zeros((g.Q, g.N), bool)
+    for q in range(g.Q):
+        rest = rng.permutation(np.setdiff1d(np.arange(g.N), supp))[: 300 - supp.size]
+        mask0[q, supp] = True
+        mask0[q, rest] = True
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10), mask0=mask0)
+    out = {}
+    for every in (0, 10):
+        s = geometry_solver(gpu_lib, g, "fp16", hp, refine_every=every, max_iter=150, stop=False)
+        for q in range(g.Q):
+            s.set_active_mask(q, mask0[q].astype(np.uint8))
+        info = s.solve(sc.y)
+        out[every] = (nmse(s.image(), ref.z), info["direct_sensors"])
+    print(out)
+    assert out[10][1] == g.Q
+    assert out[10][0] <= 1e-6
+    assert out[10][0] <= 1e-2 * out[0][0]
+
+
+def test_refinement_argument_checks(gpu_lib):
+    g, sc, A, hp = problem(Q=2, M=2, K=32, n_side=8, seed=4, n_targets=2)
+    with pytest.raises(gpu_lib.SadmmError):
+        gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", refine_every=10, **hp)
+    s = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp16", refine_every=10, **hp)
+    for q in range(g.Q):
+        s.set_operator(q, A[q])           # no geometry: nothing to correct toward
+    with pytest.raises(gpu_lib.SadmmError):
+        s.solve(sc.y)
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_ragged_shapes_fp64(gpu_lib):
