@@ -213,7 +213,9 @@ int sadmm_get_dual(sadmm_t h, void* u, int32_t dtype, int32_t on_device);
 
 /* Factor W_q = ((c/mu) I + Ahat_q Ahat_q^H)^{-1} of sensor q as last built or
  * updated (complex128, KM x KM column-major, host buffer of KM*KM entries);
- * *n receives KM.  Diagnostic: lets callers check the factor directly. */
+ * *n receives KM.  For a sensor in the direct form (params.direct) it is built
+ * here for the current active set.  Diagnostic: lets callers check the factor
+ * directly. */
 int sadmm_get_factor(sadmm_t h, int32_t q, void* W, int32_t* n);
 
 /* Final selector of sensor q: mask[n] = 1 if pixel n is active (host, N bytes). */

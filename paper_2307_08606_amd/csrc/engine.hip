@@ -91,7 +91,6 @@ struct sadmm_s {
   SensorDesc* sens_mf_d = nullptr;   // sensor table viewing rec as a matrix-free operator
   double *gfix = nullptr, *re1 = nullptr, *re2 = nullptr, *rw = nullptr;
   void *g32 = nullptr, *xfix = nullptr;
-  MmDesc* ref_desc = nullptr;    // Q products W_q t
   int k_refined = 0;             // iteration of the last correction
   sadmm_t shared_src = nullptr;  // operator and factor borrowed from this handle
   int n_sharers = 0;             // handles borrowing this one's operator
@@ -754,7 +753,6 @@ int refine_setup(sadmm_t h) {
   TRY(grab((void**)&h->re1, 16 * (size_t)h->KMp));
   TRY(grab((void**)&h->re2, 16 * (size_t)h->KMp));
   TRY(grab((void**)&h->rw, 16 * (size_t)h->KMp));
-  TRY(grab((void**)&h->ref_desc, sizeof(MmDesc) * h->Q));
   HIPCHK(h, hipMemsetAsync(h->gfix, 0, 16 * QN, h->s));
   HIPCHK(h, hipMemsetAsync(h->g32, 0, h->csz * QN, h->s));
   HIPCHK(h, hipMemsetAsync(h->xfix, 0, h->csz * QN, h->s));
@@ -902,11 +900,6 @@ int refine(sadmm_t h, int k) {
   am.sens = h->sens_mf_d;
   IterArgs ag = a;
   ag.X = h->g32;
-  std::vector<MmDesc> md(h->Q);
-  for (int q = 0; q < h->Q; ++q)
-    md[q] = MmDesc{h->W64[q], reinterpret_cast<const cd*>(h->re2), reinterpret_cast<cd*>(h->rw), KMp, 1,
-                   KMp, KMp, KMp, KMp, 1.0, 0.0, 0.0};
-  HIPCHK(h, hipMemcpyAsync(h->ref_desc, md.data(), sizeof(MmDesc) * h->Q, hipMemcpyHostToDevice, s));
   for (int q = 0; q < h->Q; ++q) {
     const int nq = h->nq[q];
     if (nq == 0) continue;
@@ -921,7 +914,7 @@ int refine(sadmm_t h, int k) {
     // xfix = (g - Ahat^H W (Ahat g)) / c
     HIPCHK(h, hipMemsetAsync(h->re2, 0, 16 * (size_t)KMp, s));
     launch_gather_fwd(ag, h->st, false, q, h->J[q], nq, 1.0, h->re2, h->gtmp, s);
-    zgemm_mfma_nn(h->ref_desc + q, 1, KMp, 1, s);
+    launch_factor_vec(a, q, h->re2, h->rw, s);
     launch_refine_fix(a, h->st, q, h->J[q], nq, h->rw, h->gfix, cinv, h->xfix, s);
   }
   HIPCHK(h, hipGetLastError());
@@ -1639,6 +1632,10 @@ int sadmm_get_factor(sadmm_t h, int32_t q, void* W, int32_t* n) {
   if (!h) return SADMM_E_ARG;
   if (!W || !n || q < 0 || q >= h->Q) return fail_msg(h, SADMM_E_ARG, "get_factor: bad argument");
   if (!h->fac_valid[q] && !h->solved) return fail_msg(h, SADMM_E_STATE, "get_factor: no factor");
+  if (h->direct[q]) {   // not kept in the direct form; built for the current active set
+    TRY(build_factors(h, std::vector<int>{q}));
+    h->fac_valid[q] = false;   // (the reuse check compares against the starting set)
+  }
   *n = h->KM;
   HIPCHK(h, hipMemcpy2DAsync(W, 16 * (size_t)h->KM, h->W64[q], 16 * (size_t)h->KMp, 16 * (size_t)h->KM,
                              h->KM, hipMemcpyDeviceToHost, h->s));
@@ -1764,7 +1761,7 @@ void sadmm_destroy(sadmm_t h) {
   for (double* p : h->rec)
     if (p) hipFree(p);
   for (void* p : {(void*)h->sens_mf_d, (void*)h->gfix, h->g32, h->xfix, (void*)h->re1, (void*)h->re2,
-                  (void*)h->rw, (void*)h->ref_desc})
+                  (void*)h->rw})
     if (p) hipFree(p);
   if (h->ctl_h) hipHostFree(h->ctl_h);
   if (h->counts_h) hipHostFree(h->counts_h);

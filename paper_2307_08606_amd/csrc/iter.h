@@ -138,6 +138,8 @@ void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx
 // e, w: KMp complex128; g: Q x N complex128; g32, xfix: Q x N compute precision.
 void launch_refine_grad(const IterArgs& a, int st, int q, const int* idx, int count, const double* e,
                         double scale, bool accumulate, double* g, void* g32, hipStream_t s);
+// out = W64_q v (KMp complex128 each; W64_q Hermitian, FP64 accumulation).
+void launch_factor_vec(const IterArgs& a, int q, const double* v, double* out, hipStream_t s);
 void launch_refine_fix(const IterArgs& a, int st, int q, const int* idx, int count, const double* w,
                        const double* g, double cinv, void* xfix, hipStream_t s);
 void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,

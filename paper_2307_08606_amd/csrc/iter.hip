@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(int KMp, int nch, co
 
 // ------------------------------------------------------------------ column dots
 enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5,
-              EPI_GRAD = 6, EPI_FIX = 7 };
+              EPI_GRAD = 6, EPI_FIX = 7, EPI_WVEC = 8 };
 // Column dots over a caller's pixel list of one sensor (x.q, x.idx, x.count)
 template <int EPI> constexpr bool listed_cols() {
   return EPI == EPI_KKT || EPI == EPI_GRAD || EPI == EPI_FIX;
@@ -233,7 +233,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   const SensorDesc sd = a.sens[q];
   if (EPI == EPI_W && sd.direct) return;
   int ncols;
-  if constexpr (EPI == EPI_W || EPI == EPI_WY) ncols = a.KMp;
+  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) ncols = a.KMp;
   else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) ncols = sd.nq;
   else if constexpr (listed_cols<EPI>()) ncols = x.count;
   else ncols = a.N;
@@ -252,7 +252,8 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     else if constexpr (EPI == EPI_XUPD) v = ldc<TA>(a.w, (int64_t)q * a.KMp + i);
     else if constexpr (EPI == EPI_XY) v = {a.wy[2 * ((int64_t)q * a.KMp + i)], a.wy[2 * ((int64_t)q * a.KMp + i) + 1]};
     else {
-      const double* src = x.vec + 2 * ((listed_cols<EPI>() ? 0 : (int64_t)q * x.vec_stride) + i);
+      const double* src =
+          x.vec + 2 * ((listed_cols<EPI>() || EPI == EPI_WVEC ? 0 : (int64_t)q * x.vec_stride) + i);
       v = {(TA)src[0], (TA)src[1]};
     }
     sv[i] = v;
@@ -264,7 +265,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     if (p >= ncols) break;
     const void* col;
     if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W64, a.KMp, p);
-    else if constexpr (EPI == EPI_WY) col = col_ptr<ST>(sd.W64, a.KMp, p);
+    else if constexpr (EPI == EPI_WY || EPI == EPI_WVEC) col = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) col = col_ptr<ST>(sd.A, sd.lda, p);
     else if constexpr (listed_cols<EPI>()) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
     else col = col_ptr<ST>(sd.Afull, sd.lda, p);
@@ -298,6 +299,9 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const double gre = x.mu * d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
       const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
       x.flag[p] = hypot(gre, gim) > x.thr ? 1 : 0;
+    } else if constexpr (EPI == EPI_WVEC) {
+      x.out[2 * p] = d.re;        // (W v)_p: W Hermitian
+      x.out[2 * p + 1] = d.im;
     } else if constexpr (EPI == EPI_GRAD) {
       const int64_t o = (int64_t)q * a.N + x.idx[p];
       double gr = x.mu * d.re, gi = x.mu * d.im;
@@ -319,7 +323,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
 
 template <int ST, int EPI, class TS = typename Store<ST>::T>
 __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
-  const int q = listed_cols<EPI>() ? x.q
+  const int q = (listed_cols<EPI>() || EPI == EPI_WVEC) ? x.q
               : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
   coldot_body<ST, EPI, TS>(a, x, q);
 }
@@ -699,6 +703,16 @@ static void refine_dispatch(const IterArgs& a, int st, int epi, int q, const int
     case ST_MF: refine_impl<ST_MF>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
     default: break;   // refinement applies to 16-bit storage only (checked by the caller)
   }
+}
+
+void launch_factor_vec(const IterArgs& a, int q, const double* v, double* out, hipStream_t s) {
+  DotExtra x{};
+  x.q = q;
+  x.vec = v;
+  x.out = out;
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  coldot_kernel<ST_FP64, EPI_WVEC, float><<<dim3((a.KMp + cpb - 1) / cpb, 1), 256,
+                                             (size_t)a.KMp * sizeof(cd), s>>>(a, x);
 }
 
 void launch_refine_grad(const IterArgs& a, int st, int q, const int* idx, int count, const double* e,
