@@ -750,9 +750,9 @@ int refine_setup(sadmm_t h) {
   TRY(grab((void**)&h->gfix, 16 * QN));
   TRY(grab(&h->g32, h->csz * QN));
   TRY(grab(&h->xfix, h->csz * QN));
-  TRY(grab((void**)&h->re1, 16 * (size_t)h->KMp));
-  TRY(grab((void**)&h->re2, 16 * (size_t)h->KMp));
-  TRY(grab((void**)&h->rw, 16 * (size_t)h->KMp));
+  TRY(grab((void**)&h->re1, 16 * (size_t)h->Q * h->KMp));
+  TRY(grab((void**)&h->re2, 16 * (size_t)h->Q * h->KMp));
+  TRY(grab((void**)&h->rw, 16 * (size_t)h->Q * h->KMp));
   HIPCHK(h, hipMemsetAsync(h->gfix, 0, 16 * QN, h->s));
   HIPCHK(h, hipMemsetAsync(h->g32, 0, h->csz * QN, h->s));
   HIPCHK(h, hipMemsetAsync(h->xfix, 0, h->csz * QN, h->s));
@@ -833,7 +833,10 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
       HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     TRY(compact_operator(h, q));
-    h->direct[q] = want_direct(h, h->nq[q]) ? 1 : 0;   // (built in solve_prologue_finish)
+    // (built in solve_prologue_finish).  At the start only when F is also
+    // smaller than W (N_q < KM): the Woodbury factors of a solve are built in
+    // one batch, the direct inverses one sensor at a time.
+    h->direct[q] = (want_direct(h, h->nq[q]) && h->nq[q] < h->KM) ? 1 : 0;
     if (!h->direct[q] && !h->shared_src &&
         (!h->p.reuse_factor || !h->fac_valid[q] || h->facJ[q] != Jh))
       rebuild.push_back(q);
@@ -893,30 +896,26 @@ int solve_prologue_finish(sadmm_t h) {
 // ones included (y' holds their contribution through Ahat).
 int refine(sadmm_t h, int k) {
   hipStream_t s = h->s;
-  const int KMp = h->KMp;
+  const size_t QK = (size_t)h->Q * h->KMp;
   const double mu = h->p.mu, cinv = 1.0 / (h->p.beta + h->p.gamma);
   const IterArgs a = make_args(h);
   IterArgs am = a;
   am.sens = h->sens_mf_d;
-  IterArgs ag = a;
-  ag.X = h->g32;
-  for (int q = 0; q < h->Q; ++q) {
-    const int nq = h->nq[q];
-    if (nq == 0) continue;
-    // re1 = A x - y (every pixel), re2 = Ahat x - y' (active pixels)
-    scale_c128(h->y + 2 * (size_t)q * KMp, h->re1, KMp, -1.0, s);
-    launch_gather_fwd(am, ST_MF, false, q, nullptr, h->N, 1.0, h->re1, h->gtmp, s);
-    scale_c128(h->yp + 2 * (size_t)q * KMp, h->re2, KMp, -1.0, s);
-    launch_gather_fwd(a, h->st, false, q, h->J[q], nq, 1.0, h->re2, h->gtmp, s);
-    launch_refine_grad(am, ST_MF, q, h->J[q], nq, h->re1, -mu, false, h->gfix, h->g32, s);
-    launch_refine_grad(a, h->st, q, h->J[q], nq, h->re2, mu, true, h->gfix, h->g32, s);
-    if (h->direct[q]) continue;
-    // xfix = (g - Ahat^H W (Ahat g)) / c
-    HIPCHK(h, hipMemsetAsync(h->re2, 0, 16 * (size_t)KMp, s));
-    launch_gather_fwd(ag, h->st, false, q, h->J[q], nq, 1.0, h->re2, h->gtmp, s);
-    launch_factor_vec(a, q, h->re2, h->rw, s);
-    launch_refine_fix(a, h->st, q, h->J[q], nq, h->rw, h->gfix, cinv, h->xfix, s);
-  }
+  int max_nq = 0;
+  for (int q = 0; q < h->Q; ++q) max_nq = std::max(max_nq, h->nq[q]);
+  // re1 = A x - y (every pixel), re2 = Ahat x - y' (active pixels)
+  scale_c128(h->y, h->re1, (int)QK, -1.0, s);
+  launch_refine_fwd(am, ST_MF, false, nullptr, 1.0, h->re1, s);
+  scale_c128(h->yp, h->re2, (int)QK, -1.0, s);
+  launch_refine_fwd(a, h->st, true, nullptr, 1.0, h->re2, s);
+  // g = -mu A^H re1 + mu Ahat^H re2 on the active pixels
+  launch_refine_grad(am, ST_MF, max_nq, h->re1, -mu, false, h->gfix, h->g32, s);
+  launch_refine_grad(a, h->st, max_nq, h->re2, mu, true, h->gfix, h->g32, s);
+  // xfix = (g - Ahat^H W (Ahat g)) / c   (Woodbury sensors)
+  HIPCHK(h, hipMemsetAsync(h->re2, 0, 16 * QK, s));
+  launch_refine_fwd(a, h->st, true, h->g32, 1.0, h->re2, s);
+  launch_factor_vec(a, h->re2, h->rw, s);
+  launch_refine_fix(a, h->st, max_nq, h->rw, h->gfix, cinv, h->xfix, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
   h->k_refined = k;

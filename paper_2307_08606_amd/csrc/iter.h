@@ -130,17 +130,23 @@ void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx
                       hipStream_t s);
 
 // |A_q^H y_q| over all pixels for every sensor, into out (Q x N doubles).
-// Refinement products of sensor q over the pixel list idx (count entries),
-// column n = idx[p] of the full operator (storage st):
-//   launch_refine_grad: g[n] = scale (A^H e)_n, or with accumulate g[n] += it,
-//                       also writing the sum in compute precision to g32[n];
-//   launch_refine_fix:  xfix[n] = cinv (g[n] - (A^H w)_n).
-// e, w: KMp complex128; g: Q x N complex128; g32, xfix: Q x N compute precision.
-void launch_refine_grad(const IterArgs& a, int st, int q, const int* idx, int count, const double* e,
-                        double scale, bool accumulate, double* g, void* g32, hipStream_t s);
-// out = W64_q v (KMp complex128 each; W64_q Hermitian, FP64 accumulation).
-void launch_factor_vec(const IterArgs& a, int q, const double* v, double* out, hipStream_t s);
-void launch_refine_fix(const IterArgs& a, int st, int q, const int* idx, int count, const double* w,
-                       const double* g, double cinv, void* xfix, hipStream_t s);
+// Correction products over every sensor (one launch per step):
+//   launch_refine_fwd:  out_q += sign * A_q x_q over the active pixels J_q
+//                       (active) or all N pixels, x from xsrc (Q x N compute
+//                       precision) or X; tpart is the scratch; out Q x KMp c128;
+//   launch_factor_vec:  out_q = W64_q v_q (W Hermitian, FP64);
+//   launch_refine_grad: g[q, J_q[p]] = scale (A_q^H e_q)_p, or with accumulate
+//                       += it, also writing the sum in compute precision to g32;
+//   launch_refine_fix:  xfix[q, J_q[p]] = cinv (g - A_q^H w_q)_p.
+// e, w: Q x KMp complex128; g: Q x N complex128; g32, xfix: Q x N compute
+// precision; max_nq: the largest N_q.  Sensors in the direct form are skipped
+// by the W and fix steps.
+void launch_refine_fwd(const IterArgs& a, int st, bool active, const void* xsrc, double sign, double* out,
+                       hipStream_t s);
+void launch_factor_vec(const IterArgs& a, const double* v, double* out, hipStream_t s);
+void launch_refine_grad(const IterArgs& a, int st, int max_nq, const double* e, double scale,
+                        bool accumulate, double* g, void* g32, hipStream_t s);
+void launch_refine_fix(const IterArgs& a, int st, int max_nq, const double* w, const double* g,
+                       double cinv, void* xfix, hipStream_t s);
 void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,
                            hipStream_t s);

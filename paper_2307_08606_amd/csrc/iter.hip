@@ -174,13 +174,63 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(int KMp, int nch, co
   out[2 * i + 1] += sign * (double)s.im;
 }
 
+// Forward products of every sensor for the correction (blockIdx.z = sensor):
+// over its active pixels J_q (active = 1) or over all N pixels (active = 0),
+// coefficients from xsrc (Q x N, compute precision) or from X; partial sums
+// per column chunk into tpart (Q x nchunk x KMp).
+template <int ST>
+__global__ __launch_bounds__(FWD_THREADS) void fwd_all_kernel(IterArgs a, int active, const void* xsrc) {
+  using T = typename Store<ST>::T;
+  constexpr int R = Store<ST>::RPT;
+  const int q = blockIdx.z, ch = blockIdx.y;
+  const SensorDesc sd = a.sens[q];
+  const int count = active ? sd.nq : a.N;
+  const int* idx = active ? sd.J : nullptr;
+  const int p0 = ch * a.chunk;
+  if (p0 >= count) return;
+  const int np = min(a.chunk, count - p0);
+  const void* xs = xsrc ? xsrc : a.X;
+  __shared__ C2<T> coef[MAX_CHUNK];
+  for (int e = threadIdx.x; e < np; e += FWD_THREADS) {
+    const int n = idx ? idx[p0 + e] : p0 + e;
+    coef[e] = ldc<T>(xs, (int64_t)q * a.N + n);
+  }
+  __syncthreads();
+  const int row = (blockIdx.x * FWD_THREADS + threadIdx.x) * R;
+  if (row >= a.KMp) return;
+  C2<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = {(T)0, (T)0};
+  fwd_accumulate<ST>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
+  C2<T>* out = reinterpret_cast<C2<T>*>(a.tpart) + ((int64_t)q * a.nchunk + ch) * a.KMp + row;
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[r] = acc[r];
+}
+
+// out_q += sign * (sum of sensor q's chunk partials), complex128 Q x KMp.
+template <class T>
+__global__ __launch_bounds__(256) void fwd_all_reduce_kernel(IterArgs a, int active, double sign,
+                                                             double* out) {
+  const int q = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.KMp) return;
+  const int count = active ? a.sens[q].nq : a.N;
+  const int nch = (count + a.chunk - 1) / a.chunk;
+  const C2<T>* tp = reinterpret_cast<const C2<T>*>(a.tpart) + (int64_t)q * a.nchunk * a.KMp + i;
+  C2<T> sm = {(T)0, (T)0};
+  for (int c = 0; c < nch; ++c) sm = cadd(sm, tp[(int64_t)c * a.KMp]);
+  double* o = out + 2 * ((int64_t)q * a.KMp + i);
+  o[0] += sign * (double)sm.re;
+  o[1] += sign * (double)sm.im;
+}
+
 // ------------------------------------------------------------------ column dots
 enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5,
               EPI_GRAD = 6, EPI_FIX = 7, EPI_WVEC = 8 };
 // Column dots over a caller's pixel list of one sensor (x.q, x.idx, x.count)
-template <int EPI> constexpr bool listed_cols() {
-  return EPI == EPI_KKT || EPI == EPI_GRAD || EPI == EPI_FIX;
-}
+template <int EPI> constexpr bool listed_cols() { return EPI == EPI_KKT; }
+// Column dots over the active pixels J_q of every sensor (blockIdx.y = sensor)
+template <int EPI> constexpr bool active_cols() { return EPI == EPI_GRAD || EPI == EPI_FIX; }
 
 struct DotExtra {
   const int* idx;       // KKT: eliminated pixel list
@@ -215,6 +265,35 @@ __device__ inline C2<TA> coldot_core(const void* col, const C2<TA>* sv, int KMp,
   return acc;
 }
 
+// Dots of C operator columns with the LDS vector sv in one sweep over the
+// rows: every LDS read of the vector serves all C columns, and the C column
+// loads of a row step are in flight together.
+template <int ST, class TA, int C>
+__device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* sv, int KMp, int lane,
+                                    C2<TA> (&acc)[C]) {
+  using T = typename Store<ST>::T;
+  constexpr int R = Store<ST>::RPT;
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = {(TA)0, (TA)0};
+  for (int i0 = lane * R; i0 < KMp; i0 += SADMM_WAVE * R) {
+    C2<TA> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = sv[i0 + r];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      T re[R], im[R];
+      Store<ST>::load(col[c], i0, KMp, re, im);
+#pragma unroll
+      for (int r = 0; r < R; ++r) cfmac(acc[c], C2<TA>{(TA)re[r], (TA)im[r]}, v[r]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    acc[c].re = wave_sum(acc[c].re);
+    acc[c].im = wave_sum(acc[c].im);
+  }
+}
+
 // Accumulation precision: the per-iteration products run in the compute
 // precision; the once-per-factor data term (WY, XY) and the certificate
 // products (KKT, MF) accumulate in FP64.
@@ -231,10 +310,10 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
-  if (EPI == EPI_W && sd.direct) return;
+  if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC) && sd.direct) return;
   int ncols;
   if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) ncols = a.KMp;
-  else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) ncols = sd.nq;
+  else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY || active_cols<EPI>()) ncols = sd.nq;
   else if constexpr (listed_cols<EPI>()) ncols = x.count;
   else ncols = a.N;
   const int cols_per_block = 4 * DOT_COLS_PER_WAVE;
@@ -252,25 +331,45 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     else if constexpr (EPI == EPI_XUPD) v = ldc<TA>(a.w, (int64_t)q * a.KMp + i);
     else if constexpr (EPI == EPI_XY) v = {a.wy[2 * ((int64_t)q * a.KMp + i)], a.wy[2 * ((int64_t)q * a.KMp + i) + 1]};
     else {
-      const double* src =
-          x.vec + 2 * ((listed_cols<EPI>() || EPI == EPI_WVEC ? 0 : (int64_t)q * x.vec_stride) + i);
+      const double* src = x.vec + 2 * ((listed_cols<EPI>() ? 0 : (int64_t)q * x.vec_stride) + i);
       v = {(TA)src[0], (TA)src[1]};
     }
     sv[i] = v;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pw = col0 + wv * DOT_COLS_PER_WAVE;   // this wave's first column
+  if (pw >= ncols) return;
+  const void* cols[DOT_COLS_PER_WAVE];
+#pragma unroll
   for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
-    const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
+    const int p = min(pw + c, ncols - 1);   // past the end: repeat the last column
+    if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) cols[c] = col_ptr<ST>(sd.W64, a.KMp, p);
+    else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) cols[c] = col_ptr<ST>(sd.A, sd.lda, p);
+    else if constexpr (listed_cols<EPI>()) cols[c] = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
+    else if constexpr (active_cols<EPI>()) cols[c] = col_ptr<ST>(sd.Afull, sd.lda, sd.J[p]);
+    else cols[c] = col_ptr<ST>(sd.Afull, sd.lda, p);
+  }
+  C2<TA> dots[DOT_COLS_PER_WAVE];
+  if constexpr (ST == ST_MF) {
+    // generated entries cost registers: two columns per sweep
+    static_assert(DOT_COLS_PER_WAVE % 2 == 0, "column pairs");
+#pragma unroll
+    for (int c = 0; c < DOT_COLS_PER_WAVE; c += 2) {
+      const void* const pair[2] = {cols[c], cols[c + 1]};
+      C2<TA> d2[2];
+      coldot_multi<ST, TA, 2>(pair, sv, a.KMp, lane, d2);
+      dots[c] = d2[0];
+      dots[c + 1] = d2[1];
+    }
+  } else {
+    coldot_multi<ST, TA, DOT_COLS_PER_WAVE>(cols, sv, a.KMp, lane, dots);
+  }
+  if (lane != 0) return;
+  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
+    const int p = pw + c;
     if (p >= ncols) break;
-    const void* col;
-    if constexpr (EPI == EPI_W) col = col_ptr<ST>(sd.W64, a.KMp, p);
-    else if constexpr (EPI == EPI_WY || EPI == EPI_WVEC) col = col_ptr<ST>(sd.W64, a.KMp, p);
-    else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) col = col_ptr<ST>(sd.A, sd.lda, p);
-    else if constexpr (listed_cols<EPI>()) col = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
-    else col = col_ptr<ST>(sd.Afull, sd.lda, p);
-    const C2<TA> d = coldot_core<ST, TA>(col, sv, a.KMp, lane);
-    if (lane != 0) continue;
+    const C2<TA> d = dots[c];
     if constexpr (EPI == EPI_W) {
       stc<T>(a.w, (int64_t)q * a.KMp + p, C2<T>{(T)d.re, (T)d.im});
     } else if constexpr (EPI == EPI_XUPD) {
@@ -300,10 +399,10 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
       x.flag[p] = hypot(gre, gim) > x.thr ? 1 : 0;
     } else if constexpr (EPI == EPI_WVEC) {
-      x.out[2 * p] = d.re;        // (W v)_p: W Hermitian
-      x.out[2 * p + 1] = d.im;
+      x.out[2 * ((int64_t)q * a.KMp + p)] = d.re;        // (W v)_p: W Hermitian
+      x.out[2 * ((int64_t)q * a.KMp + p) + 1] = d.im;
     } else if constexpr (EPI == EPI_GRAD) {
-      const int64_t o = (int64_t)q * a.N + x.idx[p];
+      const int64_t o = (int64_t)q * a.N + sd.J[p];
       double gr = x.mu * d.re, gi = x.mu * d.im;
       if (x.accumulate) {
         gr += x.out[2 * o];
@@ -313,7 +412,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       x.out[2 * o] = gr;
       x.out[2 * o + 1] = gi;
     } else if constexpr (EPI == EPI_FIX) {
-      const int64_t o = (int64_t)q * a.N + x.idx[p];
+      const int64_t o = (int64_t)q * a.N + sd.J[p];
       stc<T>(x.out32, o, C2<T>{(T)(x.cinv * (x.out[2 * o] - d.re)), (T)(x.cinv * (x.out[2 * o + 1] - d.im))});
     } else {
       x.out[(int64_t)q * a.N + p] = hypot(d.re, d.im);
@@ -323,7 +422,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
 
 template <int ST, int EPI, class TS = typename Store<ST>::T>
 __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
-  const int q = (listed_cols<EPI>() || EPI == EPI_WVEC) ? x.q
+  const int q = listed_cols<EPI>() ? x.q
               : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
   coldot_body<ST, EPI, TS>(a, x, q);
 }
@@ -705,24 +804,73 @@ static void refine_dispatch(const IterArgs& a, int st, int epi, int q, const int
   }
 }
 
-void launch_factor_vec(const IterArgs& a, int q, const double* v, double* out, hipStream_t s) {
+template <int ST>
+static void refine_fwd_impl(const IterArgs& a, bool active, const void* xsrc, double sign, double* out,
+                            hipStream_t s) {
+  using T = typename Store<ST>::T;
+  const int rows = FWD_THREADS * Store<ST>::RPT;
+  fwd_all_kernel<ST><<<dim3((a.KMp + rows - 1) / rows, a.nchunk, a.Q), FWD_THREADS, 0, s>>>(
+      a, active ? 1 : 0, xsrc);
+  fwd_all_reduce_kernel<T><<<dim3((a.KMp + 255) / 256, a.Q), 256, 0, s>>>(a, active ? 1 : 0, sign, out);
+}
+
+void launch_refine_fwd(const IterArgs& a, int st, bool active, const void* xsrc, double sign, double* out,
+                       hipStream_t s) {
+  switch (st) {
+    case ST_FP16P: refine_fwd_impl<ST_FP16P>(a, active, xsrc, sign, out, s); break;
+    case ST_BF16P: refine_fwd_impl<ST_BF16P>(a, active, xsrc, sign, out, s); break;
+    case ST_MF: refine_fwd_impl<ST_MF>(a, active, xsrc, sign, out, s); break;
+    default: break;   // the correction applies to 16-bit storage (checked by the caller)
+  }
+}
+
+void launch_factor_vec(const IterArgs& a, const double* v, double* out, hipStream_t s) {
   DotExtra x{};
-  x.q = q;
   x.vec = v;
+  x.vec_stride = a.KMp;
   x.out = out;
   const int cpb = 4 * DOT_COLS_PER_WAVE;
-  coldot_kernel<ST_FP64, EPI_WVEC, float><<<dim3((a.KMp + cpb - 1) / cpb, 1), 256,
+  coldot_kernel<ST_FP64, EPI_WVEC, float><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256,
                                              (size_t)a.KMp * sizeof(cd), s>>>(a, x);
 }
 
-void launch_refine_grad(const IterArgs& a, int st, int q, const int* idx, int count, const double* e,
-                        double scale, bool accumulate, double* g, void* g32, hipStream_t s) {
-  refine_dispatch(a, st, EPI_GRAD, q, idx, count, e, scale, accumulate, g, g32, 0.0, s);
+template <int ST>
+static void refine_impl(const IterArgs& a, int epi, int max_nq, const double* v, double scale,
+                        bool accumulate, double* g, void* out32, double cinv, hipStream_t s) {
+  if (max_nq <= 0) return;
+  DotExtra x{};
+  x.vec = v;
+  x.vec_stride = a.KMp;
+  x.mu = scale;
+  x.accumulate = accumulate ? 1 : 0;
+  x.out = g;
+  x.out32 = out32;
+  x.cinv = cinv;
+  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const size_t smem = (size_t)a.KMp * sizeof(cd);
+  const dim3 grid((max_nq + cpb - 1) / cpb, a.Q);
+  if (epi == EPI_GRAD) coldot_kernel<ST, EPI_GRAD><<<grid, 256, smem, s>>>(a, x);
+  else coldot_kernel<ST, EPI_FIX><<<grid, 256, smem, s>>>(a, x);
 }
 
-void launch_refine_fix(const IterArgs& a, int st, int q, const int* idx, int count, const double* w,
-                       const double* g, double cinv, void* xfix, hipStream_t s) {
-  refine_dispatch(a, st, EPI_FIX, q, idx, count, w, 1.0, false, const_cast<double*>(g), xfix, cinv, s);
+static void refine_dispatch(const IterArgs& a, int st, int epi, int max_nq, const double* v, double scale,
+                            bool accumulate, double* g, void* out32, double cinv, hipStream_t s) {
+  switch (st) {
+    case ST_FP16P: refine_impl<ST_FP16P>(a, epi, max_nq, v, scale, accumulate, g, out32, cinv, s); break;
+    case ST_BF16P: refine_impl<ST_BF16P>(a, epi, max_nq, v, scale, accumulate, g, out32, cinv, s); break;
+    case ST_MF: refine_impl<ST_MF>(a, epi, max_nq, v, scale, accumulate, g, out32, cinv, s); break;
+    default: break;
+  }
+}
+
+void launch_refine_grad(const IterArgs& a, int st, int max_nq, const double* e, double scale,
+                        bool accumulate, double* g, void* g32, hipStream_t s) {
+  refine_dispatch(a, st, EPI_GRAD, max_nq, e, scale, accumulate, g, g32, 0.0, s);
+}
+
+void launch_refine_fix(const IterArgs& a, int st, int max_nq, const double* w, const double* g,
+                       double cinv, void* xfix, hipStream_t s) {
+  refine_dispatch(a, st, EPI_FIX, max_nq, w, 1.0, false, const_cast<double*>(g), xfix, cinv, s);
 }
 
 template <int ST>

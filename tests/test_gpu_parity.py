@@ -236,17 +236,17 @@ def test_refinement_with_pruning(gpu_lib):
 
 
 def test_refinement_in_direct_form(gpu_lib):
-    """A caller selector leaves each sensor 300 pixels (below the 16-bit
-    crossover 1.28 KM = 327), so every sensor starts in the direct form and
-    the correction enters its right-hand side: image against the FP64 optimum
-    of the same restricted problem."""
+    """A caller selector leaves each sensor 200 pixels (below KM = 256 and the
+    16-bit crossover 1.28 KM = 327), so every sensor starts in the direct form
+    and the correction enters its right-hand side: image against the FP64
+    optimum of the same restricted problem."""
     g, sc, A, hp = problem(seed=1, lam_frac=0.2)
     rng = np.random.default_rng(12)
     plain = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
     supp = np.flatnonzero(np.abs(plain.z) > 0)
     mask0 = np.zeros((g.Q, g.N), bool)
     for q in range(g.Q):
-        rest = rng.permutation(np.setdiff1d(np.arange(g.N), supp))[: 300 - supp.size]
+        rest = rng.permutation(np.setdiff1d(np.arange(g.N), supp))[: 200 - supp.size]
         mask0[q, supp] = True
         mask0[q, rest] = True
     ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10), mask0=mask0)
