@@ -250,7 +250,9 @@ int sadmm_get_timing(sadmm_t h, int32_t which, double* ms);
  * FP32 vector: W1 (C x Q x 3 x 3), b1 (C), W2 (C x C x 3 x 3), b2, W3, b3,
  * W4 (1 x C x 3 x 3), b4 (1).  Training minimises the pixel-averaged weighted
  * binary cross-entropy (positive pixels weighted by pos_weight) with Adam
- * (beta1 0.9, beta2 0.999, eps 1e-8).  The CNN only proposes eliminations: the
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Training runs in FP32; inference
+ * (sadmm_cnn_forward and the solver's selector) runs by default on the FP16
+ * matrix instructions with FP32 accumulation (sadmm_cnn_set_half).  The CNN only proposes eliminations: the
  * solver's optimality re-check (params.kkt) reinstates false ones.
  * ------------------------------------------------------------------------- */
 
@@ -267,6 +269,10 @@ int sadmm_cnn_get_params(sadmm_cnn_t c, float* params, int64_t count);
 /* Probability map (H*W floats) of the input x (Q x H x W floats). */
 int sadmm_cnn_forward(sadmm_cnn_t c, const float* x, int32_t x_on_device, float* prob,
                       int32_t prob_on_device);
+/* Inference arithmetic: on = 1 (default) FP16 operands (activations and
+ * weights rounded to binary16) on the 16x16x16 matrix instruction with FP32
+ * accumulation; 0 = FP32 direct convolutions (the training forward). */
+int sadmm_cnn_set_half(sadmm_cnn_t c, int32_t on);
 /* Loss and gradient (host buffer of param_count floats) for input x and
  * target map (H*W floats, 1 = eliminate). */
 int sadmm_cnn_gradients(sadmm_cnn_t c, const float* x, const float* target, int32_t on_device,

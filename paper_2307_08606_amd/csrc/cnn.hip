@@ -10,10 +10,14 @@
 // sensor's sub-problem before the factor build (eq. (3), initial P_q); the
 // optimality re-check after convergence reinstates false eliminations.
 //
-// The convolutions are direct: 16x16 output tiles per work-group, the input
-// tile plus halo of one channel at a time in LDS, all output channels of a
-// pixel accumulated in registers, weights in LDS.  At these channel counts
-// (<= 32) the layers are a few hundred MFLOP per 128x128 image.
+// Training runs the FP32 direct convolutions: 16x16 output tiles per
+// work-group, the input tile plus halo of one channel at a time in LDS, all
+// output channels of a pixel accumulated in registers, weights in LDS.
+// Inference (forward, and the solver's selector) runs by default on the FP16
+// matrix instructions with FP32 accumulation: each layer is a product
+// (pixels x 9 cin) . (9 cin x cout) whose left operand is gathered from an
+// LDS tile of the input (channel-last, so the four k-slots of a lane are four
+// consecutive channels of one tap).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -79,6 +83,91 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__
       float a = acc[o] + b[o];
       if (relu) a = fmaxf(a, 0.f);
       out[(int64_t)o * H * W + (int64_t)i * W + j] = a;
+    }
+  }
+}
+
+// The same layer on the 16x16x16 FP16 matrix instruction (FP32 accumulation).
+// Work-group: 16 x 16 output pixels; wave w owns rows 4w..4w+3, one 16-pixel
+// row per 16-row block of the product; output channels in blocks of 16.
+// k = tap * cinP + ci (cinP = cin rounded up to 4, tap = 3 dy + dx), padded
+// with zero weights to a multiple of 16.  Lane l supplies A[m = l % 16][k0 +
+// 4 (l / 16) + i] and B[k0 + 4 (l / 16) + i][n = l % 16], i < 4, and receives
+// C[4 (l / 16) + r][l % 16], r < 4.
+typedef _Float16 half4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+constexpr int KMAX = 9 * CMAX;   // 288, a multiple of 16
+
+__global__ __launch_bounds__(256) void conv_fwd_mfma_kernel(const float* __restrict__ in, int cin,
+                                                            const float* __restrict__ Wt,
+                                                            const float* __restrict__ b, int cout,
+                                                            int H, int W, int relu,
+                                                            float* __restrict__ out) {
+  __shared__ __align__(16) _Float16 sx[(TILE + 2) * (TILE + 2) * CMAX];   // [y][x][ci]
+  __shared__ __align__(16) _Float16 sw[CMAX * KMAX];                      // [co][k]
+  const int cinP = (cin + 3) & ~3;
+  const int Ktot = 9 * cinP, Kpad = (Ktot + 15) & ~15;
+  const int nblk = (cout + 15) >> 4;
+  for (int e = threadIdx.x; e < 16 * nblk * Kpad; e += 256) {
+    const int co = e / Kpad, k = e - co * Kpad;
+    float v = 0.f;
+    if (co < cout && k < Ktot) {
+      const int tap = k / cinP, ci = k - tap * cinP;
+      if (ci < cin) v = Wt[((int64_t)co * cin + ci) * 9 + tap];
+    }
+    sw[co * Kpad + k] = (_Float16)v;
+  }
+  const int y0 = blockIdx.y * TILE - 1, x0 = blockIdx.x * TILE - 1;
+  constexpr int NP = (TILE + 2) * (TILE + 2);
+  for (int e = threadIdx.x; e < NP * cinP; e += 256) {
+    const int ci = e / NP, pix = e - ci * NP;   // consecutive threads: consecutive pixels
+    const int gi = y0 + pix / (TILE + 2), gj = x0 + pix % (TILE + 2);
+    float v = 0.f;
+    if (ci < cin && gi >= 0 && gi < H && gj >= 0 && gj < W) v = in[(int64_t)ci * H * W + (int64_t)gi * W + gj];
+    sx[pix * cinP + ci] = (_Float16)v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  float4v acc[4][2];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = float4v{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < Kpad; k0 += 16) {
+    const int k = k0 + 4 * g;
+    half4v bv[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+      bv[nb] = nb < nblk ? *reinterpret_cast<const half4v*>(&sw[(nb * 16 + c16) * Kpad + k])
+                         : half4v{0, 0, 0, 0};
+    const bool kin = k < Ktot;
+    const int tap = kin ? k / cinP : 0, ci = kin ? k - tap * cinP : 0;
+    const int dy = tap / 3, dx = tap - 3 * dy;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const int pix = (4 * w + mb + dy) * (TILE + 2) + c16 + dx;
+      const half4v av = kin ? *reinterpret_cast<const half4v*>(&sx[pix * cinP + ci]) : half4v{0, 0, 0, 0};
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        if (nb < nblk) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv[nb], acc[mb][nb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int i = blockIdx.y * TILE + 4 * w + mb;
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int co = nb * 16 + c16;
+      if (nb >= nblk || co >= cout || i >= H) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = blockIdx.x * TILE + 4 * g + r;
+        if (j >= W) continue;
+        float a = acc[mb][nb][r] + b[co];
+        if (relu) a = fmaxf(a, 0.f);
+        out[(int64_t)co * H * W + (int64_t)i * W + j] = a;
+      }
     }
   }
 }
@@ -260,6 +349,7 @@ struct sadmm_cnn_s {
   float *tgt = nullptr, *g4 = nullptr, *gA = nullptr, *gB = nullptr, *part = nullptr;
   double *lpart = nullptr, *mx = nullptr;
   int step = 0;
+  int half = 1;               // inference on the FP16 matrix instructions
   std::vector<void*> allocs;
 };
 
@@ -278,20 +368,26 @@ int calloc_dev(sadmm_cnn_t c, void** p, size_t bytes) {
 
 dim3 tiles(int H, int W) { return dim3((W + TILE - 1) / TILE, (H + TILE - 1) / TILE); }
 
-void cnn_forward_dev(sadmm_cnn_t c) {
+void cnn_forward_dev(sadmm_cnn_t c, bool half) {
   const dim3 gr = tiles(c->H, c->W);
   const float* in[4] = {c->x, c->h1, c->h2, c->h3};
   float* out[4] = {c->h1, c->h2, c->h3, c->a4};
-  for (int l = 0; l < 4; ++l)
-    conv_fwd_kernel<<<gr, 256, 0, c->s>>>(in[l], c->L[l].cin, c->p + c->L[l].w_off, c->p + c->L[l].b_off,
-                                          c->L[l].cout, c->H, c->W, l < 3 ? 1 : 0, out[l]);
+  for (int l = 0; l < 4; ++l) {
+    if (half)
+      conv_fwd_mfma_kernel<<<gr, 256, 0, c->s>>>(in[l], c->L[l].cin, c->p + c->L[l].w_off,
+                                                 c->p + c->L[l].b_off, c->L[l].cout, c->H, c->W,
+                                                 l < 3 ? 1 : 0, out[l]);
+    else
+      conv_fwd_kernel<<<gr, 256, 0, c->s>>>(in[l], c->L[l].cin, c->p + c->L[l].w_off, c->p + c->L[l].b_off,
+                                            c->L[l].cout, c->H, c->W, l < 3 ? 1 : 0, out[l]);
+  }
 }
 
 // forward + loss + backward into c->g; returns the loss through *loss (host)
 int cnn_backward_dev(sadmm_cnn_t c, float pos_weight, double* loss) {
   const int P = c->H * c->W;
   const int nb = (P + 255) / 256;
-  cnn_forward_dev(c);
+  cnn_forward_dev(c, false);   // gradients of the FP32 forward
   bce_kernel<<<nb, 256, 0, c->s>>>(c->a4, c->tgt, P, pos_weight, c->prob, c->g4, c->lpart);
   const dim3 gr = tiles(c->H, c->W);
   const int ntiles = gr.x * gr.y;
@@ -335,7 +431,7 @@ int sadmm_cnn_prob_from_mf(sadmm_cnn_t c, const double* mf_dev, const float** pr
   const int64_t n = (int64_t)c->Q * c->H * c->W;
   max_kernel<<<1, 1024, 0, c->s>>>(mf_dev, n, c->mx);
   scale_input_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(mf_dev, n, c->mx, c->x);
-  cnn_forward_dev(c);
+  cnn_forward_dev(c, c->half != 0);
   const int P = c->H * c->W;
   bce_kernel<<<(P + 255) / 256, 256, 0, c->s>>>(c->a4, nullptr, P, 1.f, c->prob, nullptr, nullptr);
   if (hipGetLastError() != hipSuccess) return cfail(c, SADMM_E_HIP, "cnn inference launch failed");
@@ -422,12 +518,19 @@ int sadmm_cnn_forward(sadmm_cnn_t c, const float* x, int32_t x_on_device, float*
   const int64_t P = (int64_t)c->H * c->W;
   int rc = put_input(c, c->x, x, P * c->Q, x_on_device);
   if (rc) return rc;
-  cnn_forward_dev(c);
+  cnn_forward_dev(c, c->half != 0);
   bce_kernel<<<(unsigned)((P + 255) / 256), 256, 0, c->s>>>(c->a4, nullptr, (int)P, 1.f, c->prob, nullptr, nullptr);
   if (hipMemcpyAsync(prob, c->prob, 4 * P, prob_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                      c->s) != hipSuccess ||
       hipStreamSynchronize(c->s) != hipSuccess)
     return cfail(c, SADMM_E_HIP, "forward failed");
+  return SADMM_OK;
+}
+
+int sadmm_cnn_set_half(sadmm_cnn_t c, int32_t on) {
+  if (!c) return SADMM_E_ARG;
+  if (on != 0 && on != 1) return cfail(c, SADMM_E_ARG, "set_half: 0 or 1");
+  c->half = on;
   return SADMM_OK;
 }
 

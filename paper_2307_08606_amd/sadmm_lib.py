@@ -109,6 +109,7 @@ sadmm_cnn_param_count = _sig("sadmm_cnn_param_count", C.c_int64, _H)
 sadmm_cnn_set_params = _sig("sadmm_cnn_set_params", C.c_int, _H, _P, C.c_int64)
 sadmm_cnn_get_params = _sig("sadmm_cnn_get_params", C.c_int, _H, _P, C.c_int64)
 sadmm_cnn_forward = _sig("sadmm_cnn_forward", C.c_int, _H, _P, C.c_int32, _P, C.c_int32)
+sadmm_cnn_set_half = _sig("sadmm_cnn_set_half", C.c_int, _H, C.c_int32)
 sadmm_cnn_gradients = _sig("sadmm_cnn_gradients", C.c_int, _H, _P, _P, C.c_int32, C.c_float, _P,
                            C.POINTER(C.c_double))
 sadmm_cnn_train_step = _sig("sadmm_cnn_train_step", C.c_int, _H, _P, _P, C.c_int32, C.c_float,
@@ -389,6 +390,10 @@ class Cnn:
         f = np.empty(self.n, np.float32)
         self._check(sadmm_cnn_get_params(self._h, _ptr(f), self.n))
         return self.unflatten(f)
+
+    def set_half(self, on=True):
+        """Inference on FP16 matrix instructions (default) or FP32 direct convolutions."""
+        self._check(sadmm_cnn_set_half(self._h, 1 if on else 0))
 
     def forward(self, x) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float32)

@@ -1,6 +1,9 @@
 """GPU CNN kernels vs the FP64 CNN oracle, and the CNN-driven initial selector
 of the solver.  FP32 kernels: probabilities within 1e-5 absolute, gradients
-within 1e-4 relative (norm) of the FP64 reference."""
+within 1e-4 relative (norm) of the FP64 reference.  FP16 matrix-instruction
+inference: probabilities within 3e-3 absolute (a CPU model that rounds every
+layer's input and weights to binary16 and sums exactly deviates from the FP64
+network by at most 6.5e-4 on these problems)."""
 
 import numpy as np
 import pytest
@@ -28,9 +31,25 @@ def test_cnn_forward_matches_oracle(gpu_lib):
     p, x, _ = rnd_problem()
     c = gpu_lib.Cnn(3, 8, 20, 23)
     c.set_params(p)
+    c.set_half(False)
     got = c.forward(x)
     ref, _ = ocnn.forward(p, x)
     assert np.abs(got - ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("Q,C,H,W,seed", [(3, 8, 20, 23, 0), (8, 32, 40, 37, 1), (5, 32, 16, 16, 2)])
+def test_cnn_forward_fp16_matrix_instructions(gpu_lib, Q, C, H, W, seed):
+    """Default inference path: 16x16x16 FP16 products, FP32 accumulation.
+    Ragged tiles, channel counts not a multiple of 4 (Q = 3, 5) and of 16
+    (the one-channel output layer)."""
+    p, x, _ = rnd_problem(Q, C, H, W, seed=seed)
+    c = gpu_lib.Cnn(Q, C, H, W)
+    c.set_params(p)
+    got = c.forward(x)
+    ref, _ = ocnn.forward(p, x)
+    err = np.abs(got - ref).max()
+    print(Q, C, H, W, f"{err:.2e}")
+    assert err < 3e-3
 
 
 @pytest.mark.parametrize("Q,C,H,W", [(3, 8, 20, 23), (8, 32, 32, 32)])
