@@ -63,74 +63,83 @@ __global__ __launch_bounds__(256) void rowmax_kernel(const GramI8Desc* __restric
   if (n1 > n0) atomicMax(&d.rmax[i], (unsigned long long)__double_as_longlong(mx));
 }
 
-// Digit planes.  Block: 64 rows x 256 columns (four column groups of 64, each
-// thread 16 consecutive columns of one row).  Rows >= m and columns >= k get
-// zero digits.
+// Digit planes.  Block: 64 rows x SL_COLS columns.  Thread (row = t & 63,
+// column group cg = t >> 6) reads SL_COLS / 4 consecutive columns of its row
+// (the lanes of a wave read 64 consecutive rows of one column: coalesced),
+// forms the digits in FP32 / int32 (the stored values have at most 24
+// significant bits, so the power-of-two scaling and the rounding to an
+// integer are exact) and packs them into LDS; the block then writes each
+// plane's tile with the lanes along the columns (whole 128-byte lines).  Rows
+// >= m and columns >= k get zero digits.
+constexpr int SL_COLS = 128;
+constexpr int SL_W = SL_COLS / 4 + 1;   // LDS words per tile row (+1: no bank conflicts)
+
 template <int ST>
 __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict__ descs) {
   const GramI8Desc d = descs[blockIdx.z];
   const int row = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int gi = blockIdx.y * 64 + row;
-  const int cb = blockIdx.x * 256;
+  const int cb = blockIdx.x * SL_COLS;
   if (blockIdx.y * 64 >= d.KMr || cb >= d.ldS) return;
-  __shared__ int red[4][4][64];   // [column group][digit][row]
-  double mx = gi < d.m ? __longlong_as_double((long long)d.rmax[gi]) : 0.0;
+  __shared__ uint32_t sd[8][64][SL_W];   // [2 digit + re/im][row][column word]
+  __shared__ int red[4][4][64];          // [column group][digit][row]
+  const double mx = gi < d.m ? __longlong_as_double((long long)d.rmax[gi]) : 0.0;
   int E = 0;
   if (mx > 0.0) (void)frexp(mx, &E);
-  const double sc = ldexp(1.0, 30 - E);
-  const int64_t plane = (int64_t)d.KMr * d.ldS;
   int rsum[4] = {0, 0, 0, 0};
-  for (int c4 = 0; c4 < 4; ++c4) {
-    const int n0 = cb + 64 * c4 + 16 * cg;
-    if (n0 >= d.ldS) break;
-    uint32_t pk[4][2][4];
+  constexpr int PER = SL_COLS / 4;       // columns per thread
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+  for (int wd = 0; wd < PER / 4; ++wd) {   // one packed word (4 columns) per plane
+    uint32_t pk[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) pk[s][p][w] = 0u;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int gn = n0 + e;
-      cd v = {0.0, 0.0};
-      if (gi < d.m && gn < d.k) v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
-      const long long qv[2] = {llrint(v.re * sc), llrint(v.im * sc)};
+    for (int e = 0; e < 4; ++e) {
+      const int gn = cb + PER * cg + 4 * wd + e;
+      float vv[2] = {0.f, 0.f};
+      if (gi < d.m && gn < d.k) {
+        const cd v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
+        vv[0] = (float)v.re;
+        vv[1] = (float)v.im;
+      }
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        long long x = qv[p];
+        int x = (int)rintf(ldexpf(vv[p], 30 - E));   // |x| < 2^30
         int dg[4];
 #pragma unroll
-        for (int s = 3; s >= 1; --s) {
+        for (int t = 3; t >= 1; --t) {
           const int lo = (int)(int8_t)(uint8_t)(x & 0xff);
-          dg[s] = lo;
+          dg[t] = lo;
           x = (x - lo) >> 8;
         }
-        dg[0] = (int)x;
+        dg[0] = x;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          pk[s][p][e >> 2] |= ((uint32_t)(uint8_t)dg[s]) << (8 * (e & 3));
-          if (p == 1) rsum[s] += dg[s];
+        for (int t = 0; t < 4; ++t) {
+          pk[2 * t + p] |= ((uint32_t)(uint8_t)dg[t]) << (8 * e);
+          if (p == 1) rsum[t] += dg[t];
         }
       }
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        int8_t* dst = d.S + (2 * s + p) * plane + (int64_t)gi * d.ldS + n0;
-        *reinterpret_cast<uint4*>(dst) = make_uint4(pk[s][p][0], pk[s][p][1], pk[s][p][2], pk[s][p][3]);
-      }
+    for (int q = 0; q < 8; ++q) sd[q][row][(PER / 4) * cg + wd] = pk[q];
   }
-  // row sums of the imaginary digits over this block's columns (one chunk)
 #pragma unroll
-  for (int s = 0; s < 4; ++s) red[cg][s][row] = rsum[s];
+  for (int t = 0; t < 4; ++t) red[cg][t][row] = rsum[t];
   __syncthreads();
   {
-    const int s = threadIdx.x >> 6;   // thread (s, row) adds the four column groups
-    const int v = red[0][s][row] + red[1][s][row] + red[2][s][row] + red[3][s][row];
+    const int t = threadIdx.x >> 6;   // thread (t, row) adds the four column groups
+    const int v = red[0][t][row] + red[1][t][row] + red[2][t][row] + red[3][t][row];
     const int chunk = cb / GI8_CHUNK;
-    if (v != 0) atomicAdd(&d.rs[((int64_t)chunk * 4 + s) * d.KMr + gi], v);
+    if (v != 0 && gi < d.KMr) atomicAdd(&d.rs[((int64_t)chunk * 4 + t) * d.KMr + gi], v);
+  }
+  // write-out: per plane 64 rows x SL_COLS bytes as 16-byte pieces, eight
+  // lanes per row
+  const int64_t plane = (int64_t)d.KMr * d.ldS;
+  constexpr int PCS = SL_COLS / 16;   // pieces per row
+  for (int e = threadIdx.x; e < 8 * 64 * PCS; e += 256) {
+    const int q = e / (64 * PCS), r = (e / PCS) & 63, c = e % PCS;
+    if (cb + 16 * c >= d.ldS) continue;
+    const uint32_t* w = &sd[q][r][4 * c];
+    *reinterpret_cast<uint4*>(d.S + q * plane + (int64_t)(blockIdx.y * 64 + r) * d.ldS + cb + 16 * c) =
+        make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
@@ -312,7 +321,7 @@ void launch_prep(const GramI8Desc* d, int batch, int KMr, int ldS, int max_k, hi
   clear_kernel<<<dim3(nb, batch), 256, 0, s>>>(d);
   const int cy = std::max(1, std::min(64, max_k / 256));
   rowmax_kernel<ST><<<dim3((KMr + 255) / 256, cy, batch), 256, 0, s>>>(d);
-  slice_kernel<ST><<<dim3((ldS + 255) / 256, KMr / 64, batch), 256, 0, s>>>(d);
+  slice_kernel<ST><<<dim3((ldS + SL_COLS - 1) / SL_COLS, KMr / 64, batch), 256, 0, s>>>(d);
 }
 
 }  // namespace
