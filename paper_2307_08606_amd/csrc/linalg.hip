@@ -427,8 +427,14 @@ template <int OPA, int OPB, int KR, int OUT>
 __global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ descs) {
   const MmDesc d = descs[blockIdx.z];
   int ti, tj;
-  if constexpr (OUT == MM_FULL) { ti = blockIdx.x; tj = blockIdx.y; }
-  else tri_of(blockIdx.x, &ti, &tj);
+  if constexpr (OUT == MM_FULL) {
+    // A lower triangular: the k-range grows with the row tile, so the longest
+    // tiles go first (fewer of them left running at the end of the launch)
+    ti = (KR & KR_A_LOWER) != 0 ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    tj = blockIdx.y;
+  } else {
+    tri_of(blockIdx.x, &ti, &tj);
+  }
   const int i0 = ti * HM, j0 = tj * HM;
   if (i0 >= d.m || j0 >= d.n) return;
   int kb = 0, ke = d.k;
@@ -586,9 +592,23 @@ void herk_batched(const GemmDesc* d_desc, int batch, int max_m, int st, const in
   }
 }
 
+// Cholesky steps of NB columns grouped in outer blocks of HPD_OB columns: the
+// trailing update of a step covers only the rest of its outer block; the
+// columns beyond it are updated once per outer block with k = HPD_OB (one pass
+// over the trailing matrix per HPD_OB columns instead of per NB).
+constexpr int HPD_OB = 128;
+
 size_t hpd_mm_count(int n) {
-  const int nb = n / HPD_NB;
-  size_t c = 2 * (size_t)std::max(nb - 1, 0);              // panel + trailing per step
+  size_t c = 0;
+  for (int K0 = 0; K0 < n; K0 += HPD_OB) {
+    const int K1 = std::min(K0 + HPD_OB, n);
+    for (int k0 = K0; k0 < K1; k0 += HPD_NB) {
+      if (n - k0 - HPD_NB <= 0) continue;
+      c += 1;                                              // panel
+      if (K1 - k0 - HPD_NB > 0) c += 1;                    // update inside the outer block
+    }
+    if (n - K1 > 0) c += 1;                                // update beyond it
+  }
   for (int b = HPD_NB; b < n; b *= 2) c += 2 * (size_t)((n - b + 2 * b - 1) / (2 * b));
   return c + 1;                                            // X^H X
 }
@@ -604,24 +624,38 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
   std::vector<MmDesc> mm;
   std::vector<Launch> plan;
   mm.reserve((size_t)batch * hpd_mm_count(n));
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    plan.push_back({DIAG, 0, batch, 0, 0, k0});
-    const int rest = n - k0 - NB;
-    if (rest <= 0) continue;
-    Launch lp{PANEL, (int)mm.size(), batch, rest, NB, k0};
-    for (int i = 0; i < batch; ++i) {
-      cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
-      mm.push_back(MmDesc{L21, hd[i].D + (int64_t)k0 * NB, L21, rest, NB, NB, n, NB, n,
-                          1.0, 0.0, 0.0});
+  for (int K0 = 0; K0 < n; K0 += HPD_OB) {
+    const int K1 = std::min(K0 + HPD_OB, n);
+    for (int k0 = K0; k0 < K1; k0 += NB) {
+      plan.push_back({DIAG, 0, batch, 0, 0, k0});
+      const int rest = n - k0 - NB;
+      if (rest <= 0) continue;
+      Launch lp{PANEL, (int)mm.size(), batch, rest, NB, k0};
+      for (int i = 0; i < batch; ++i) {
+        cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
+        mm.push_back(MmDesc{L21, hd[i].D + (int64_t)k0 * NB, L21, rest, NB, NB, n, NB, n,
+                            1.0, 0.0, 0.0});
+      }
+      plan.push_back(lp);
+      const int nc = K1 - k0 - NB;   // columns of the outer block still to factor
+      if (nc <= 0) continue;
+      Launch lt{TRAIL, (int)mm.size(), batch, rest, nc, k0};
+      for (int i = 0; i < batch; ++i) {
+        const cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
+        mm.push_back(MmDesc{L21, L21, hd[i].G + (int64_t)(k0 + NB) * n + k0 + NB, rest, nc, NB,
+                            n, n, n, -1.0, 0.0, 1.0});
+      }
+      plan.push_back(lt);
     }
-    plan.push_back(lp);
-    Launch lt{TRAIL, (int)mm.size(), batch, rest, rest, k0};
+    const int rest2 = n - K1;   // G22 -= L21 L21^H with the outer block's columns of L
+    if (rest2 <= 0) continue;
+    Launch lo{TRAIL, (int)mm.size(), batch, rest2, rest2, K0};
     for (int i = 0; i < batch; ++i) {
-      const cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
-      mm.push_back(MmDesc{L21, L21, hd[i].G + (int64_t)(k0 + NB) * n + k0 + NB, rest, rest, NB,
+      const cd* L21 = hd[i].G + (int64_t)K0 * n + K1;
+      mm.push_back(MmDesc{L21, L21, hd[i].G + (int64_t)K1 * n + K1, rest2, rest2, K1 - K0,
                           n, n, n, -1.0, 0.0, 1.0});
     }
-    plan.push_back(lt);
+    plan.push_back(lo);
   }
   for (int b = NB; b < n; b *= 2) {
     Launch l1{TRI1, (int)mm.size(), 0, b, b, 0};
