@@ -32,6 +32,7 @@ typedef unsigned int u4v __attribute__((ext_vector_type(4)));   // (uint4 arrays
 constexpr int GT = 64;      // tile rows / columns (complex)
 constexpr int GKS = 64;     // columns per stage (k of one instruction)
 constexpr int GROW = 80;    // LDS bytes per staged row (64 + pad: no bank conflicts)
+constexpr int GLD = 2 * GKS;  // digit-plane rows padded to an even number of stages
 
 inline int round_up_i(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -159,50 +160,58 @@ __device__ inline LDigit load_l(const Panel& sp, int wr, int r16, int kq) {
   }
   return L;
 }
+// R digits of the wave's two column blocks, all four held for the stage.
+struct RDigits { v4i r[4][2], i[4][2]; };
+__device__ inline void load_r(const Panel& sp, int wc, int r16, int kq, RDigits& R) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      R.r[t][b] = *reinterpret_cast<const v4i*>(&sp[1][t][0][wc + 16 * b + r16][16 * kq]);
+      R.i[t][b] = *reinterpret_cast<const v4i*>(&sp[1][t][1][wc + 16 * b + r16][16 * kq]);
+    }
+}
 // Accumulate the products of an L digit with R digit T into class slot C.
 template <int T, int C>
-__device__ inline void pair_mma(const Panel& sp, const LDigit& L, int wc, int r16, int kq,
-                                v4i (&re)[NCLS][2][2], v4i (&im)[NCLS][2][2]) {
-  v4i rr[2], ri[2];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    rr[b] = *reinterpret_cast<const v4i*>(&sp[1][T][0][wc + 16 * b + r16][16 * kq]);
-    ri[b] = *reinterpret_cast<const v4i*>(&sp[1][T][1][wc + 16 * b + r16][16 * kq]);
-  }
+__device__ inline void pair_mma(const LDigit& L, const RDigits& R, v4i (&re)[NCLS][2][2],
+                                v4i (&im)[NCLS][2][2]) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.r[a], rr[b], re[C][a][b], 0, 0, 0);
-      im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], rr[b], im[C][a][b], 0, 0, 0);
-      re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], ri[b], re[C][a][b], 0, 0, 0);
-      im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.nr[a], ri[b], im[C][a][b], 0, 0, 0);
+      re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.r[a], R.r[T][b], re[C][a][b], 0, 0, 0);
+      im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], R.r[T][b], im[C][a][b], 0, 0, 0);
+      re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], R.i[T][b], re[C][a][b], 0, 0, 0);
+      im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.nr[a], R.i[T][b], im[C][a][b], 0, 0, 0);
     }
 }
 
-// One stage of 64 columns: the 13 pairs grouped by L digit (one live at a time).
+// One stage of 64 columns: the R digits read once, the 13 pairs grouped by L
+// digit (one live at a time).
 __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
                              v4i (&re)[NCLS][2][2], v4i (&im)[NCLS][2][2]) {
+  RDigits R;
+  load_r(sp, wc, r16, kq, R);
   { const LDigit L = load_l<0>(sp, wr, r16, kq);
-    pair_mma<0, 0>(sp, L, wc, r16, kq, re, im);
-    pair_mma<1, 1>(sp, L, wc, r16, kq, re, im);
-    pair_mma<2, 2>(sp, L, wc, r16, kq, re, im);
-    pair_mma<3, 3>(sp, L, wc, r16, kq, re, im); }
+    pair_mma<0, 0>(L, R, re, im);
+    pair_mma<1, 1>(L, R, re, im);
+    pair_mma<2, 2>(L, R, re, im);
+    pair_mma<3, 3>(L, R, re, im); }
   __builtin_amdgcn_sched_barrier(0);
   { const LDigit L = load_l<1>(sp, wr, r16, kq);
-    pair_mma<0, 1>(sp, L, wc, r16, kq, re, im);
-    pair_mma<1, 2>(sp, L, wc, r16, kq, re, im);
-    pair_mma<2, 3>(sp, L, wc, r16, kq, re, im);
-    pair_mma<3, 4>(sp, L, wc, r16, kq, re, im); }
+    pair_mma<0, 1>(L, R, re, im);
+    pair_mma<1, 2>(L, R, re, im);
+    pair_mma<2, 3>(L, R, re, im);
+    pair_mma<3, 4>(L, R, re, im); }
   __builtin_amdgcn_sched_barrier(0);
   { const LDigit L = load_l<2>(sp, wr, r16, kq);
-    pair_mma<0, 2>(sp, L, wc, r16, kq, re, im);
-    pair_mma<1, 3>(sp, L, wc, r16, kq, re, im);
-    pair_mma<2, 4>(sp, L, wc, r16, kq, re, im); }
+    pair_mma<0, 2>(L, R, re, im);
+    pair_mma<1, 3>(L, R, re, im);
+    pair_mma<2, 4>(L, R, re, im); }
   __builtin_amdgcn_sched_barrier(0);
   { const LDigit L = load_l<3>(sp, wr, r16, kq);
-    pair_mma<0, 3>(sp, L, wc, r16, kq, re, im);
-    pair_mma<1, 4>(sp, L, wc, r16, kq, re, im); }
+    pair_mma<0, 3>(L, R, re, im);
+    pair_mma<1, 4>(L, R, re, im); }
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -240,22 +249,39 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restri
   const int8_t* srcR = d.S + (int64_t)(j0 + prow) * d.ldS + 16 * pq;
   int8_t* dst0 = &sp[0][0][0][prow][16 * pq];
   constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
-  u4v pf[16];
+  // Two stages in flight: even stages load into pa, odd ones into pb, each
+  // two stages ahead of its products (every chunk has an even number of
+  // stages: the planes are padded to GLD columns).
+  u4v pa[16], pb[16];
   if (n0 < n1) {
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-      pf[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + n0);
+      pa[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + n0);
   }
-  for (int nb = n0; nb < n1; nb += GKS) {
+  if (n0 < n1) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      pb[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + n0 + GKS);
+  }
+  for (int nb = n0; nb < n1; nb += 2 * GKS) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pf[e];
+    for (int e = 0; e < 16; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
     __syncthreads();
-    if (nb + GKS < n1) {   // next stage in flight during the products
-      const int nx = nb + GKS;
+    if (nb + 2 * GKS < n1) {
 #pragma unroll
       for (int e = 0; e < 16; ++e)
-        pf[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + nx);
+        pa[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + nb + 2 * GKS);
+    }
+    kstep(sp, wr, wc, r16, kq, re, im);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pb[e];
+    __syncthreads();
+    if (nb + 3 * GKS < n1) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        pb[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + nb + 3 * GKS);
     }
     kstep(sp, wr, wc, r16, kq, re, im);
   }
@@ -327,14 +353,14 @@ void launch_prep(const GramI8Desc* d, int batch, int KMr, int ldS, int max_k, hi
 }  // namespace
 
 size_t gram_i8_workspace(int m, int k) {
-  const size_t KMr = (size_t)round_up_i(m, 64), ldS = (size_t)round_up_i(std::max(k, 1), 64);
+  const size_t KMr = (size_t)round_up_i(m, 64), ldS = (size_t)round_up_i(std::max(k, 1), GLD);
   const size_t nch = (ldS + GI8_CHUNK - 1) / GI8_CHUNK;
   return 8 * KMr * ldS + 8 * KMr + 4 * 4 * KMr * nch + 256;
 }
 
 void gram_i8_layout(GramI8Desc& d, void* base) {
   d.KMr = round_up_i(d.m, 64);
-  d.ldS = round_up_i(std::max(d.k, 1), 64);
+  d.ldS = round_up_i(std::max(d.k, 1), GLD);
   char* p = static_cast<char*>(base);
   d.S = reinterpret_cast<int8_t*>(p);
   p += 8 * (size_t)d.KMr * d.ldS;
@@ -346,7 +372,7 @@ void gram_i8_layout(GramI8Desc& d, void* base) {
 void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
                      hipStream_t s) {
   if (batch <= 0 || max_m <= 0) return;
-  const int KMr = round_up_i(max_m, 64), ldS = round_up_i(std::max(max_k, 1), 64);
+  const int KMr = round_up_i(max_m, 64), ldS = round_up_i(std::max(max_k, 1), GLD);
   switch (st) {
     case ST_FP32: launch_prep<ST_FP32>(d_desc, batch, KMr, ldS, max_k, s); break;
     case ST_FP16P: launch_prep<ST_FP16P>(d_desc, batch, KMr, ldS, max_k, s); break;
@@ -357,7 +383,7 @@ void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, 
 }
 
 int gram_i8_chunks(int max_k) {
-  return (round_up_i(std::max(max_k, 1), 64) + GI8_CHUNK - 1) / GI8_CHUNK;
+  return (round_up_i(std::max(max_k, 1), GLD) + GI8_CHUNK - 1) / GI8_CHUNK;
 }
 
 void gram_i8_chunk(const GramI8Desc* d_desc, int batch, int chunk, const int2* tiles, int ntiles,
