@@ -92,6 +92,9 @@ struct sadmm_s {
   double *gfix = nullptr, *re1 = nullptr, *re2 = nullptr, *rw = nullptr;
   void *g32 = nullptr, *xfix = nullptr;
   int k_refined = 0;             // iteration of the last correction
+  // W not formed after a build (W64 holds U = X^H, hpdX holds X = L^{-1})
+  std::vector<uint8_t> wtri;
+  double* ws = nullptr;          // Q x KMp complex128: X v of the triangular products
   sadmm_t shared_src = nullptr;  // operator and factor borrowed from this handle
   int n_sharers = 0;             // handles borrowing this one's operator
   GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
@@ -251,6 +254,7 @@ IterArgs make_args(sadmm_t h) {
   a.max_iter = h->p.max_iter;
   a.ctl = h->ctl; a.hist = h->hist;
   a.keep = h->keep; a.gone = h->gone;
+  a.ws = h->ws;
   a.gfix = h->p.refine_every > 0 ? h->gfix : nullptr;
   a.xfix = h->p.refine_every > 0 ? h->xfix : nullptr;
   return a;
@@ -276,6 +280,8 @@ int push_descs(sadmm_t h) {
     d.b0 = h->b0d[q];
     d.rdir = h->rdir[q];
     d.fld = h->fld[q];
+    d.wtri = h->wtri[q];
+    d.X = h->hpdX[q];
   }
   HIPCHK(h, hipMemcpyAsync(h->sens_d, h->sens_h.data(), sizeof(SensorDesc) * h->Q,
                            hipMemcpyHostToDevice, h->s));
@@ -414,8 +420,15 @@ int build_factors_items(sadmm_t h0, const std::vector<FacItem>& items) {
     hd[i] = HpdDesc{h->W64[q], h->KMp, h->hpdD[q], h->hpdX[q], h->hpdT[q]};
     // Hermitian product: KM(KM+1)/2 entries, N_q complex MACs each (8 flops)
     prof_work(h0, SADMM_KC_GRAM, 8.0 * 0.5 * h->KM * (h->KM + 1.0) * h->nq[q]);
-    // Cholesky n^3/3, triangular inverse n^3/6, X^H X n^3/3 complex MACs
-    prof_work(h0, SADMM_KC_INVERSE, 8.0 * (5.0 / 6.0) * (double)h->KM * h->KM * h->KM);
+  }
+  // W = X^H X is left unformed (the iterations apply X^H (X v)) unless an
+  // item's operator is shared: multi-right-hand-side products read W itself.
+  bool form_w = false;
+  for (const FacItem& it : items) form_w = form_w || it.h->shared_src || it.h->n_sharers > 0;
+  for (const FacItem& it : items) {
+    const double km = it.h->KM;
+    // Cholesky n^3/3, triangular inverse n^3/6 (+ X^H X n^3/3) complex MACs
+    prof_work(h0, SADMM_KC_INVERSE, 8.0 * (form_w ? 5.0 / 6.0 : 0.5) * km * km * km);
   }
   int rc = SADMM_OK;
   HpdDesc* hpd = nullptr;
@@ -444,15 +457,36 @@ int build_factors_items(sadmm_t h0, const std::vector<FacItem>& items) {
   }
   if (rc == SADMM_OK) {
     const int pe = prof_begin(h0);
-    hpd_inverse_batched(hd.data(), hpd, (int)n, h0->KMp, h0->fail, mm, h0->s);
+    hpd_inverse_batched(hd.data(), hpd, (int)n, h0->KMp, h0->fail, mm, h0->s, form_w);
     prof_end(h0, SADMM_KC_INVERSE, pe);
     if (hipGetLastError() != hipSuccess) rc = fail_msg(h0, SADMM_E_HIP, "factor build: launch failed");
   }
   if (rc == SADMM_OK) rc = check_fail(h0);   // synchronises h0's stream
   cleanup();
   if (rc != SADMM_OK) return rc;
-  for (const FacItem& it : items) it.h->fac_valid[it.q] = true;
+  std::vector<sadmm_t> touched;
+  for (const FacItem& it : items) {
+    it.h->fac_valid[it.q] = true;
+    it.h->wtri[it.q] = form_w ? 0 : 1;
+    if (std::find(touched.begin(), touched.end(), it.h) == touched.end()) touched.push_back(it.h);
+  }
+  for (sadmm_t h : touched) TRY(push_descs(h));
   return SADMM_OK;
+}
+
+// W64 = X^H X for a sensor whose factor was left as X (wtri), for the
+// consumers that need W itself (low-rank updates, shared operators, the
+// correction's W v, get_factor).
+int ensure_w(sadmm_t h, int q) {
+  if (!h->wtri[q]) return SADMM_OK;
+  const int n = h->KMp;
+  const MmDesc d{h->hpdX[q], h->hpdX[q], h->W64[q], n, n, n, n, n, n, 1.0, 0.0, 0.0};
+  HIPCHK(h, hipMemcpyAsync(h->mm_d, &d, sizeof d, hipMemcpyHostToDevice, h->s));
+  hpd_form_w(h->mm_d, 1, n, h->s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  h->wtri[q] = 0;
+  return push_descs(h);
 }
 
 int build_factors(sadmm_t h, const std::vector<int>& qs) {
@@ -466,6 +500,7 @@ int build_factors(sadmm_t h, const std::vector<int>& qs) {
 //   G' = G + sign * Ar Ar^H,
 //   W' = W - sign * W Ar (I + sign * Ar^H W Ar)^{-1} Ar^H W.
 int lowrank_update(sadmm_t h, int q, const int* d_list, int r, int sign) {
+  TRY(ensure_w(h, q));
   const int KMp = h->KMp;
   const int rp = round_up(r, HPD_NB);
   gather_columns_fp64(h->Afull[q], h->ldA, h->st, KMp, d_list, r, h->Ar, h->s);
@@ -895,6 +930,8 @@ int solve_prologue_finish(sadmm_t h) {
 // sensor adds g to its right-hand side.  A x runs over every pixel, frozen
 // ones included (y' holds their contribution through Ahat).
 int refine(sadmm_t h, int k) {
+  for (int q = 0; q < h->Q; ++q)
+    if (!h->direct[q]) TRY(ensure_w(h, q));   // the W v step reads W itself
   hipStream_t s = h->s;
   const size_t QK = (size_t)h->Q * h->KMp;
   const double mu = h->p.mu, cinv = 1.0 / (h->p.beta + h->p.gamma);
@@ -1208,6 +1245,7 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   if (rc != SADMM_OK) return rc;
   sadmm_t h = new sadmm_s();
   h->shared_src = src;
+  if (src) src->n_sharers += 1;   // (given back by sadmm_destroy, also on a failed create)
   h->p = *p;
   h->Q = p->Q; h->K = p->K; h->M = p->M; h->N = p->N;
   h->KM = p->K * p->M;
@@ -1234,6 +1272,7 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   h->direct.assign(Q, 0); h->Fd.assign(Q, nullptr); h->b0d.assign(Q, nullptr);
   h->rdir.assign(Q, nullptr); h->fld.assign(Q, 0);
   h->rec.assign(Q, nullptr);
+  h->wtri.assign(Q, 0);
   h->sens_h.assign(Q, SensorDesc{});
   h->rmax = std::min(KMp, 1024);
   h->rpad_max = round_up(h->rmax, HPD_NB);
@@ -1289,6 +1328,7 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   A_(dalloc_t(h, &h->sens_d, sizeof(SensorDesc) * Q));
   A_(dalloc_t(h, &h->gemm_d, sizeof(GemmDesc) * std::max(Q, 4)));
   A_(dalloc_t(h, &h->hpd_d, sizeof(HpdDesc) * Q));
+  A_(dalloc_t(h, &h->ws, 16 * (size_t)Q * KMp));
   A_(dalloc_t(h, &h->gi8_d, sizeof(GramI8Desc) * Q));
   {
     const std::vector<int2> order = tri_tile_order((KMp + 63) / 64);
@@ -1332,7 +1372,13 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
     return SADMM_E_HIP;
   }
 #undef A_
-  if (src) src->n_sharers += 1;
+  if (src) {
+    for (int q = 0; q < src->Q; ++q)   // borrowers read W itself
+      if (ensure_w(src, q) != SADMM_OK) {
+        sadmm_destroy(h);   // (gives back the share)
+        return SADMM_E_HIP;
+      }
+  }
   *out = h;
   return SADMM_OK;
 }
@@ -1635,6 +1681,7 @@ int sadmm_get_factor(sadmm_t h, int32_t q, void* W, int32_t* n) {
     TRY(build_factors(h, std::vector<int>{q}));
     h->fac_valid[q] = false;   // (the reuse check compares against the starting set)
   }
+  TRY(ensure_w(h, q));
   *n = h->KM;
   HIPCHK(h, hipMemcpy2DAsync(W, 16 * (size_t)h->KM, h->W64[q], 16 * (size_t)h->KMp, 16 * (size_t)h->KM,
                              h->KM, hipMemcpyDeviceToHost, h->s));

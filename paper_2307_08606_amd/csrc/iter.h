@@ -20,7 +20,9 @@ struct SensorDesc {
   const cd* b0;        // direct form: mu Ahat^H y', nq complex128
   cd* rdir;            // direct form: b0 + beta v of the current iteration (fld)
   int fld;             // leading dimension of F (multiple of 32)
-  int pad2;
+  int wtri;            // 1: W is not formed; W64 holds U = X^H and X = L^{-1} (lower
+                       // triangular, W = X^H X), so W v = X^H (X v)
+  const cd* X;         // with wtri: X = L^{-1}, KMp x KMp, ld = KMp, zeros above the diagonal
 };
 
 // Everything the per-iteration kernels need; passed by value.
@@ -56,6 +58,7 @@ struct IterArgs {
   // xfix = (mu Ahat^H Ahat + cI)^{-1} gfix, both Q x N by pixel.
   const double* gfix;  // complex128
   const void* xfix;    // compute precision
+  double* ws;          // Q x KMp complex128: X v of the triangular W products
 };
 
 // A batch of independent problems ("scenes") iterated by one launch per

@@ -226,7 +226,10 @@ __global__ __launch_bounds__(256) void fwd_all_reduce_kernel(IterArgs a, int act
 
 // ------------------------------------------------------------------ column dots
 enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5,
-              EPI_GRAD = 6, EPI_FIX = 7, EPI_WVEC = 8 };
+              EPI_GRAD = 6, EPI_FIX = 7, EPI_WVEC = 8, EPI_W1 = 9, EPI_WY1 = 10 };
+// W products of a sensor with wtri: EPI_W1 / EPI_WY1 form ws = X t / X y' by
+// column dots of U = X^H (column p nonzero in rows 0..p), then EPI_W / EPI_WY
+// take X^H ws by column dots of X (column p nonzero in rows p..KMp-1).
 // Column dots over a caller's pixel list of one sensor (x.q, x.idx, x.count)
 template <int EPI> constexpr bool listed_cols() { return EPI == EPI_KKT; }
 // Column dots over the active pixels J_q of every sensor (blockIdx.y = sensor)
@@ -270,12 +273,14 @@ __device__ inline C2<TA> coldot_core(const void* col, const C2<TA>* sv, int KMp,
 // loads of a row step are in flight together.
 template <int ST, class TA, int C>
 __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* sv, int KMp, int lane,
-                                    C2<TA> (&acc)[C]) {
+                                    C2<TA> (&acc)[C], int rbeg = 0, int rend = -1) {
   using T = typename Store<ST>::T;
   constexpr int R = Store<ST>::RPT;
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = {(TA)0, (TA)0};
-  for (int i0 = lane * R; i0 < KMp; i0 += SADMM_WAVE * R) {
+  // rows [rbeg, rend): rbeg a multiple of the sweep width or 0
+  const int re_ = rend < 0 ? KMp : rend;
+  for (int i0 = rbeg + lane * R; i0 < re_; i0 += SADMM_WAVE * R) {
     C2<TA> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = sv[i0 + r];
@@ -310,9 +315,11 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
-  if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC) && sd.direct) return;
+  if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC || EPI == EPI_W1) && sd.direct) return;
+  if ((EPI == EPI_W1 || EPI == EPI_WY1) && !sd.wtri) return;
   int ncols;
-  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) ncols = a.KMp;
+  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1)
+    ncols = a.KMp;
   else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY || active_cols<EPI>()) ncols = sd.nq;
   else if constexpr (listed_cols<EPI>()) ncols = x.count;
   else ncols = a.N;
@@ -324,7 +331,14 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   // stage the vector operand
   for (int i = threadIdx.x; i < a.KMp; i += 256) {
     C2<TA> v;
-    if constexpr (EPI == EPI_W) {
+    if constexpr ((EPI == EPI_W || EPI == EPI_WY) && std::is_same<TA, double>::value) {
+      if (sd.wtri) {   // second half of X^H (X v)
+        v = {(TA)a.ws[2 * ((int64_t)q * a.KMp + i)], (TA)a.ws[2 * ((int64_t)q * a.KMp + i) + 1]};
+        sv[i] = v;
+        continue;
+      }
+    }
+    if constexpr (EPI == EPI_W || EPI == EPI_W1) {
       const C2<T> tv = ldc<T>(a.t, (int64_t)q * a.KMp + i);
       v = {(TA)tv.re, (TA)tv.im};
     }
@@ -344,14 +358,28 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
 #pragma unroll
   for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
     const int p = min(pw + c, ncols - 1);   // past the end: repeat the last column
-    if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) cols[c] = col_ptr<ST>(sd.W64, a.KMp, p);
+    if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1)
+      cols[c] = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) cols[c] = col_ptr<ST>(sd.A, sd.lda, p);
     else if constexpr (listed_cols<EPI>()) cols[c] = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
     else if constexpr (active_cols<EPI>()) cols[c] = col_ptr<ST>(sd.Afull, sd.lda, sd.J[p]);
     else cols[c] = col_ptr<ST>(sd.Afull, sd.lda, p);
   }
   C2<TA> dots[DOT_COLS_PER_WAVE];
-  if constexpr (ST == ST_MF) {
+  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_W1 || EPI == EPI_WY1) {
+    int rbeg = 0, rend = -1;
+    if (sd.wtri) {
+      if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
+        rend = min(a.KMp, (pw + DOT_COLS_PER_WAVE + 63) & ~63);   // U: rows <= p
+      } else {
+#pragma unroll
+        for (int c = 0; c < DOT_COLS_PER_WAVE; ++c)                // X: rows >= p
+          cols[c] = col_ptr<ST_FP64>(sd.X, a.KMp, min(pw + c, ncols - 1));
+        rbeg = pw & ~63;
+      }
+    }
+    coldot_multi<ST, TA, DOT_COLS_PER_WAVE>(cols, sv, a.KMp, lane, dots, rbeg, rend);
+  } else if constexpr (ST == ST_MF) {
     // generated entries cost registers: two columns per sweep
     static_assert(DOT_COLS_PER_WAVE % 2 == 0, "column pairs");
 #pragma unroll
@@ -398,6 +426,9 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const double gre = x.mu * d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
       const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
       x.flag[p] = hypot(gre, gim) > x.thr ? 1 : 0;
+    } else if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
+      a.ws[2 * ((int64_t)q * a.KMp + p)] = d.re;
+      a.ws[2 * ((int64_t)q * a.KMp + p) + 1] = d.im;
     } else if constexpr (EPI == EPI_WVEC) {
       x.out[2 * ((int64_t)q * a.KMp + p)] = d.re;        // (W v)_p: W Hermitian
       x.out[2 * ((int64_t)q * a.KMp + p) + 1] = d.im;
@@ -423,7 +454,8 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
 template <int ST, int EPI, class TS = typename Store<ST>::T>
 __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
   const int q = listed_cols<EPI>() ? x.q
-              : ((EPI == EPI_WY || EPI == EPI_XY) ? x.q0 + (int)blockIdx.y : (int)blockIdx.y);
+              : ((EPI == EPI_WY || EPI == EPI_XY || EPI == EPI_WY1) ? x.q0 + (int)blockIdx.y
+                                                                      : (int)blockIdx.y);
   coldot_body<ST, EPI, TS>(a, x, q);
 }
 
@@ -646,6 +678,8 @@ void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
   fwd_reduce_kernel<T><<<dim3((std::max(d.KMp_max, d.fld_max) + 255) / 256, d.nslot), 256, 0, s>>>(b);
   mark(0, false);
   mark(1, true);
+  coldot_batch_kernel<ST_FP64, EPI_W1, T><<<dim3((d.KMp_max + cpb - 1) / cpb, d.nslot), 256,
+                                            (size_t)d.KMp_max * sizeof(cd), s>>>(b);
   coldot_batch_kernel<ST_FP64, EPI_W, T><<<dim3((d.KMp_max + cpb - 1) / cpb, d.nslot), 256,
                                            (size_t)d.KMp_max * sizeof(cd), s>>>(b);
   mark(1, false);
@@ -700,6 +734,7 @@ static void xy_impl(const IterArgs& a, int q0, int q1, hipStream_t s) {
   // W_q y'_q in FP64, then Ahat_q^H (W_q y'_q) accumulated in FP64
   x.vec = a.yp;
   x.vec_stride = a.KMp;
+  coldot_kernel<ST_FP64, EPI_WY1><<<dim3((a.KMp + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
   coldot_kernel<ST_FP64, EPI_WY><<<dim3((a.KMp + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
   coldot_kernel<ST, EPI_XY><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
 }

@@ -89,8 +89,13 @@ size_t hpd_mm_count(int n_pad);
 // h_desc: host copies of the descriptors (d_desc on the device); d_mm: device
 // scratch for batch * hpd_mm_count(n_pad) descriptors.  *d_fail is set
 // non-zero if a pivot is not positive (loss of definiteness).
+// form_w = false stops before W = X^H X: X = L^{-1} stays in the X scratch
+// and G receives U = X^H instead (W t is then X^H (X t); see hpd_form_w).
 void hpd_inverse_batched(const HpdDesc* h_desc, const HpdDesc* d_desc, int batch, int n_pad,
-                         int* d_fail, MmDesc* d_mm, hipStream_t s);
+                         int* d_fail, MmDesc* d_mm, hipStream_t s, bool form_w = true);
+// W = X^H X for `count` products C = X^H X (MmDesc: A = B = X, C = W, m = n = k
+// = n_pad, ld n_pad, alpha 1, beta 0): the last step of the inverse, run later.
+void hpd_form_w(const MmDesc* d_desc, int count, int n_pad, hipStream_t s);
 
 // dst (T-complex, ld_dst) = (src + src^H) / 2 for n x n, src complex128 ld_src.
 void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, int n,

@@ -613,8 +613,31 @@ size_t hpd_mm_count(int n) {
   return c + 1;                                            // X^H X
 }
 
+// U = X^H into G (complex conjugate transpose of the whole matrix, zeros
+// included), 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void conj_transpose_x_kernel(const HpdDesc* __restrict__ descs) {
+  const HpdDesc h = descs[blockIdx.z];
+  const int n = h.n_pad;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;   // tile of X rows i, columns j
+  if (i0 >= n || j0 >= n) return;
+  __shared__ cd tile[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int c = ty; c < 64; c += 4) {
+    const int i = i0 + tx, j = j0 + c;
+    if (i < n && j < n) tile[c][tx] = h.X[(int64_t)j * n + i];   // X(i, j)
+  }
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4) {
+    const int i = j0 + tx, j = i0 + c;   // U(i, j) = conj(X(j, i))
+    if (i < n && j < n) {
+      const cd v = tile[tx][c];
+      h.G[(int64_t)j * n + i] = cd{v.re, -v.im};
+    }
+  }
+}
+
 void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, int n, int* d_fail,
-                         MmDesc* d_mm, hipStream_t s) {
+                         MmDesc* d_mm, hipStream_t s, bool form_w) {
   if (batch <= 0 || n <= 0) return;
   constexpr int NB = HPD_NB;
   // Plan every GEMM of the factorisation (descriptors grouped per launch,
@@ -714,10 +737,19 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
           x_diag_kernel<<<dim3(n / NB, batch), 256, 0, s>>>(d_desc);
           diag_done = true;
         }
-        launch_zmm<OP_C, OP_N, KR_GE_MAX, MM_HERM>(p, l.count, l.m, l.n, s);
+        if (form_w) {
+          launch_zmm<OP_C, OP_N, KR_GE_MAX, MM_HERM>(p, l.count, l.m, l.n, s);
+        } else {
+          const dim3 g((n + 63) / 64, (n + 63) / 64, batch);
+          conj_transpose_x_kernel<<<g, 256, 0, s>>>(d_desc);
+        }
         break;
     }
   }
+}
+
+void hpd_form_w(const MmDesc* d_desc, int count, int n, hipStream_t s) {
+  launch_zmm<OP_C, OP_N, KR_GE_MAX, MM_HERM>(d_desc, count, n, n, s);
 }
 
 void cast_hermitian(const cd* src, int64_t ld_src, void* dst, int64_t ld_dst, int n, bool to_float,
