@@ -175,12 +175,19 @@ __device__ inline void load_r(const Panel& sp, int wc, int r16, int kq, RDigits&
 template <int T, int C>
 __device__ inline void pair_mma(const LDigit& L, const RDigits& R, v4i (&re)[NCLS][2][2],
                                 v4i (&im)[NCLS][2][2]) {
+  // in rounds over the four (a, b) blocks, so that the two products into one
+  // accumulator are eight instructions apart
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.r[a], R.r[T][b], re[C][a][b], 0, 0, 0);
       im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], R.r[T][b], im[C][a][b], 0, 0, 0);
+    }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
       re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], R.i[T][b], re[C][a][b], 0, 0, 0);
       im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.nr[a], R.i[T][b], im[C][a][b], 0, 0, 0);
     }
