@@ -316,6 +316,33 @@ def test_lambda_above_max_gives_zero_image(gpu_lib):
     assert np.abs(s.image()).max() == 0.0
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_unformed_and_formed_factor_agree(gpu_lib, storage):
+    """A factor build leaves W = X^H X unformed (X = L^{-1} and X^H kept, the
+    iterations apply X^H (X t)); get_factor forms W, after which a repeated
+    solve on the reused factor applies W itself.  Both solves run the same
+    60 iterations: images equal to rounding (FP64 1e-12, FP32 1e-6 relative),
+    and both match the oracle at the storage's bar."""
+    g, sc, A, hp = problem(seed=13)
+    kw = dict(max_iter=60, stop=False, reuse_factor=True)
+    s, _ = gpu_run(gpu_lib, g, A, sc.y, hp, storage, **kw)
+    z_tri = s.image()
+    W = [s.factor(q) for q in range(g.Q)]       # forms W
+    s.solve(sc.y)
+    z_full = s.image()
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=60, stop=False))
+    tol = 1e-12 if storage == "fp64" else 1e-6
+    assert rel(z_full, z_tri) < tol
+    for q in range(g.Q):
+        Aq = A[q].astype(np.complex64 if storage == "fp32" else np.complex128).astype(np.complex128)
+        Wref = np.linalg.inv(2.0 * np.eye(Aq.shape[0]) + Aq @ Aq.conj().T)
+        assert np.linalg.norm(W[q] - Wref) <= 1e-7 * np.linalg.norm(Wref)
+    if storage == "fp64":
+        assert rel(z_tri, ref.z) < 1e-8
+    else:
+        assert nmse(z_tri, ref.z) <= 1e-6
+
+
 def test_repeated_solves_reuse_factor(gpu_lib):
     """A second frame on the same handle (factor reused) equals a fresh handle."""
     g, sc, A, hp = problem(seed=13)
