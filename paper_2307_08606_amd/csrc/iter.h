@@ -75,7 +75,12 @@ struct BatchDims {
 };
 
 constexpr int FWD_THREADS = 256;
-constexpr int DOT_COLS_PER_WAVE = 4;
+// Columns per wavefront of the column-dot kernels: two for stored FP32 / FP64
+// entries (more waves in flight), four for 16-bit and generated entries (one
+// LDS read of the staged vector serves more columns).
+template <int ST> constexpr int dot_cols() {
+  return (ST == ST_FP16P || ST == ST_BF16P || ST == ST_MF) ? 4 : 2;
+}
 // Direct-form right-hand side entries staged in LDS per pass (16 KB: within
 // the share of one of eight 256-thread work-groups on a CU).
 constexpr int XDIR_SEG = 1024;

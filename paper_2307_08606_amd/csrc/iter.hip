@@ -313,6 +313,7 @@ template <int ST, int EPI, class TS>
 __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) {
   using T = TS;                               // compute precision of the state
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
+  constexpr int DC = dot_cols<ST>();
   if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
   if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC || EPI == EPI_W1) && sd.direct) return;
@@ -323,7 +324,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY || active_cols<EPI>()) ncols = sd.nq;
   else if constexpr (listed_cols<EPI>()) ncols = x.count;
   else ncols = a.N;
-  const int cols_per_block = 4 * DOT_COLS_PER_WAVE;
+  const int cols_per_block = 4 * DC;
   const int col0 = blockIdx.x * cols_per_block;
   if (col0 >= ncols) return;
   extern __shared__ unsigned char smem_raw[];
@@ -352,11 +353,11 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int pw = col0 + wv * DOT_COLS_PER_WAVE;   // this wave's first column
+  const int pw = col0 + wv * DC;   // this wave's first column
   if (pw >= ncols) return;
-  const void* cols[DOT_COLS_PER_WAVE];
+  const void* cols[DC];
 #pragma unroll
-  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
+  for (int c = 0; c < DC; ++c) {
     const int p = min(pw + c, ncols - 1);   // past the end: repeat the last column
     if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1)
       cols[c] = col_ptr<ST>(sd.W64, a.KMp, p);
@@ -365,25 +366,25 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     else if constexpr (active_cols<EPI>()) cols[c] = col_ptr<ST>(sd.Afull, sd.lda, sd.J[p]);
     else cols[c] = col_ptr<ST>(sd.Afull, sd.lda, p);
   }
-  C2<TA> dots[DOT_COLS_PER_WAVE];
+  C2<TA> dots[DC];
   if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_W1 || EPI == EPI_WY1) {
     int rbeg = 0, rend = -1;
     if (sd.wtri) {
       if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
-        rend = min(a.KMp, (pw + DOT_COLS_PER_WAVE + 63) & ~63);   // U: rows <= p
+        rend = min(a.KMp, (pw + DC + 63) & ~63);   // U: rows <= p
       } else {
 #pragma unroll
-        for (int c = 0; c < DOT_COLS_PER_WAVE; ++c)                // X: rows >= p
+        for (int c = 0; c < DC; ++c)                // X: rows >= p
           cols[c] = col_ptr<ST_FP64>(sd.X, a.KMp, min(pw + c, ncols - 1));
         rbeg = pw & ~63;
       }
     }
-    coldot_multi<ST, TA, DOT_COLS_PER_WAVE>(cols, sv, a.KMp, lane, dots, rbeg, rend);
+    coldot_multi<ST, TA, DC>(cols, sv, a.KMp, lane, dots, rbeg, rend);
   } else if constexpr (ST == ST_MF) {
     // generated entries cost registers: two columns per sweep
-    static_assert(DOT_COLS_PER_WAVE % 2 == 0, "column pairs");
+    static_assert(DC % 2 == 0, "column pairs");
 #pragma unroll
-    for (int c = 0; c < DOT_COLS_PER_WAVE; c += 2) {
+    for (int c = 0; c < DC; c += 2) {
       const void* const pair[2] = {cols[c], cols[c + 1]};
       C2<TA> d2[2];
       coldot_multi<ST, TA, 2>(pair, sv, a.KMp, lane, d2);
@@ -391,10 +392,10 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       dots[c + 1] = d2[1];
     }
   } else {
-    coldot_multi<ST, TA, DOT_COLS_PER_WAVE>(cols, sv, a.KMp, lane, dots);
+    coldot_multi<ST, TA, DC>(cols, sv, a.KMp, lane, dots);
   }
   if (lane != 0) return;
-  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
+  for (int c = 0; c < DC; ++c) {
     const int p = pw + c;
     if (p >= ncols) break;
     const C2<TA> d = dots[c];
@@ -465,26 +466,27 @@ __global__ __launch_bounds__(256) void coldot_kernel(IterArgs a, DotExtra x) {
 // conjugated and dotted with the right-hand side, gives x at the p-th active
 // pixel.  FP64 throughout; the right-hand side (prepared by the forward
 // reduction, zero-padded to fld) passes through LDS in XDIR_SEG segments.
-template <class T>
+template <int ST, class T>
 __device__ inline void xdir_body(const IterArgs& a, int q) {
+  constexpr int DC = dot_cols<ST>();   // the x-update launch's columns per wave
   if (a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
-  const int col0 = blockIdx.x * 4 * DOT_COLS_PER_WAVE;
+  const int col0 = blockIdx.x * 4 * DC;
   if (col0 >= sd.nq) return;
   extern __shared__ unsigned char smem_raw[];
   cd* sv = reinterpret_cast<cd*>(smem_raw);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  cd acc[DOT_COLS_PER_WAVE];
+  cd acc[DC];
 #pragma unroll
-  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) acc[c] = {0.0, 0.0};
+  for (int c = 0; c < DC; ++c) acc[c] = {0.0, 0.0};
   for (int s0 = 0; s0 < sd.fld; s0 += XDIR_SEG) {
     const int len = min(XDIR_SEG, sd.fld - s0);
     __syncthreads();   // the previous segment is consumed
     for (int i = threadIdx.x; i < len; i += 256) sv[i] = sd.rdir[s0 + i];
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
-      const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
+    for (int c = 0; c < DC; ++c) {
+      const int p = col0 + wv * DC + c;
       if (p < sd.nq) {   // uniform across the wave
         const cd d = coldot_core<ST_FP64, double>(sd.F + (int64_t)p * sd.fld + s0, sv, len, lane);
         acc[c].re += d.re;
@@ -495,8 +497,8 @@ __device__ inline void xdir_body(const IterArgs& a, int q) {
   if (lane != 0) return;
   const int slot = a.ctl->k % a.Kp;
 #pragma unroll
-  for (int c = 0; c < DOT_COLS_PER_WAVE; ++c) {
-    const int p = col0 + wv * DOT_COLS_PER_WAVE + c;
+  for (int c = 0; c < DC; ++c) {
+    const int p = col0 + wv * DC + c;
     if (p >= sd.nq) break;
     const int n = sd.J[p];
     const C2<T> xn = {(T)acc[c].re, (T)acc[c].im};
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(256) void coldot_batch_kernel(BatchView bv) {
   DotExtra x{};
   if constexpr (EPI == EPI_XUPD) {
     if (bv.args[sl.x].sens[sl.y].direct) {
-      xdir_body<TS>(bv.args[sl.x], sl.y);
+      xdir_body<ST, TS>(bv.args[sl.x], sl.y);
       return;
     }
   }
@@ -672,15 +674,15 @@ void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
   using T = typename Store<ST>::T;
   auto mark = [&](int stage, bool begin) { if (hook) (*hook)(stage, begin); };
   const int rows = FWD_THREADS * Store<ST>::RPT;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const int cpb64 = 4 * dot_cols<ST_FP64>(), cpb = 4 * dot_cols<ST>();
   mark(0, true);
   fwd_iter_kernel<ST><<<dim3((d.KMp_max + rows - 1) / rows, d.nchunk_max, d.nslot), FWD_THREADS, 0, s>>>(b);
   fwd_reduce_kernel<T><<<dim3((std::max(d.KMp_max, d.fld_max) + 255) / 256, d.nslot), 256, 0, s>>>(b);
   mark(0, false);
   mark(1, true);
-  coldot_batch_kernel<ST_FP64, EPI_W1, T><<<dim3((d.KMp_max + cpb - 1) / cpb, d.nslot), 256,
+  coldot_batch_kernel<ST_FP64, EPI_W1, T><<<dim3((d.KMp_max + cpb64 - 1) / cpb64, d.nslot), 256,
                                             (size_t)d.KMp_max * sizeof(cd), s>>>(b);
-  coldot_batch_kernel<ST_FP64, EPI_W, T><<<dim3((d.KMp_max + cpb - 1) / cpb, d.nslot), 256,
+  coldot_batch_kernel<ST_FP64, EPI_W, T><<<dim3((d.KMp_max + cpb64 - 1) / cpb64, d.nslot), 256,
                                            (size_t)d.KMp_max * sizeof(cd), s>>>(b);
   mark(1, false);
   mark(2, true);
@@ -729,13 +731,13 @@ template <int ST>
 static void xy_impl(const IterArgs& a, int q0, int q1, hipStream_t s) {
   DotExtra x{};
   x.q0 = q0;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const int cpb64 = 4 * dot_cols<ST_FP64>(), cpb = 4 * dot_cols<ST>();
   const size_t smem = (size_t)a.KMp * sizeof(cd);
   // W_q y'_q in FP64, then Ahat_q^H (W_q y'_q) accumulated in FP64
   x.vec = a.yp;
   x.vec_stride = a.KMp;
-  coldot_kernel<ST_FP64, EPI_WY1><<<dim3((a.KMp + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
-  coldot_kernel<ST_FP64, EPI_WY><<<dim3((a.KMp + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
+  coldot_kernel<ST_FP64, EPI_WY1><<<dim3((a.KMp + cpb64 - 1) / cpb64, q1 - q0), 256, smem, s>>>(a, x);
+  coldot_kernel<ST_FP64, EPI_WY><<<dim3((a.KMp + cpb64 - 1) / cpb64, q1 - q0), 256, smem, s>>>(a, x);
   coldot_kernel<ST, EPI_XY><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
 }
 
@@ -788,7 +790,7 @@ static void kkt_impl(const IterArgs& a, int q, const int* idx, int count, const 
   x.gamma = gamma;
   x.thr = thr;
   x.flag = flag;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const int cpb = 4 * dot_cols<ST>();
   const size_t smem = (size_t)a.KMp * sizeof(cd);
   coldot_kernel<ST, EPI_KKT><<<dim3((count + cpb - 1) / cpb, 1), 256, smem, s>>>(a, x);
 }
@@ -803,39 +805,6 @@ void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx
     case ST_FP16P: kkt_impl<ST_FP16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
     case ST_BF16P: kkt_impl<ST_BF16P>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
     case ST_MF: kkt_impl<ST_MF>(a, q, idx, count, e, mu, gamma, thr, flag, s); break;
-  }
-}
-
-template <int ST>
-static void refine_impl(const IterArgs& a, int epi, int q, const int* idx, int count, const double* v,
-                        double scale, bool accumulate, double* g, void* out32, double cinv,
-                        hipStream_t s) {
-  if (count <= 0) return;
-  DotExtra x{};
-  x.idx = idx;
-  x.count = count;
-  x.q = q;
-  x.vec = v;
-  x.mu = scale;
-  x.accumulate = accumulate ? 1 : 0;
-  x.out = g;
-  x.out32 = out32;
-  x.cinv = cinv;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
-  const size_t smem = (size_t)a.KMp * sizeof(cd);
-  const dim3 grid((count + cpb - 1) / cpb, 1);
-  if (epi == EPI_GRAD) coldot_kernel<ST, EPI_GRAD><<<grid, 256, smem, s>>>(a, x);
-  else coldot_kernel<ST, EPI_FIX><<<grid, 256, smem, s>>>(a, x);
-}
-
-static void refine_dispatch(const IterArgs& a, int st, int epi, int q, const int* idx, int count,
-                            const double* v, double scale, bool accumulate, double* g, void* out32,
-                            double cinv, hipStream_t s) {
-  switch (st) {
-    case ST_FP16P: refine_impl<ST_FP16P>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
-    case ST_BF16P: refine_impl<ST_BF16P>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
-    case ST_MF: refine_impl<ST_MF>(a, epi, q, idx, count, v, scale, accumulate, g, out32, cinv, s); break;
-    default: break;   // refinement applies to 16-bit storage only (checked by the caller)
   }
 }
 
@@ -864,7 +833,7 @@ void launch_factor_vec(const IterArgs& a, const double* v, double* out, hipStrea
   x.vec = v;
   x.vec_stride = a.KMp;
   x.out = out;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const int cpb = 4 * dot_cols<ST_FP64>();
   coldot_kernel<ST_FP64, EPI_WVEC, float><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256,
                                              (size_t)a.KMp * sizeof(cd), s>>>(a, x);
 }
@@ -881,7 +850,7 @@ static void refine_impl(const IterArgs& a, int epi, int max_nq, const double* v,
   x.out = g;
   x.out32 = out32;
   x.cinv = cinv;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const int cpb = 4 * dot_cols<ST>();
   const size_t smem = (size_t)a.KMp * sizeof(cd);
   const dim3 grid((max_nq + cpb - 1) / cpb, a.Q);
   if (epi == EPI_GRAD) coldot_kernel<ST, EPI_GRAD><<<grid, 256, smem, s>>>(a, x);
@@ -915,7 +884,7 @@ static void mf_impl(const IterArgs& a, const double* y, double* out, hipStream_t
   x.vec = y;
   x.vec_stride = a.KMp;
   x.out = out;
-  const int cpb = 4 * DOT_COLS_PER_WAVE;
+  const int cpb = 4 * dot_cols<ST>();
   const size_t smem = (size_t)a.KMp * sizeof(cd);
   coldot_kernel<ST, EPI_MF><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
 }
