@@ -1258,7 +1258,11 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   else if (h->st == ST_FP32) { h->ldA = h->KMp; h->slot = 8; }
   else if (h->st == ST_MF) { h->ldA = MF_REC_BASE + MF_REC_PER_RX * (int64_t)h->M; h->slot = 8; }
   else { h->ldA = 2 * (int64_t)h->KMp; h->slot = 2; }
-  h->chunk = 256;
+  // forward product: columns per work-group.  Long streams of stored FP32 /
+  // FP64 or generated entries (1024 columns at N = 128^2: 6.2 TB/s against
+  // 5.5 at 256), but at least 16 chunks per sensor; 16-bit planes keep 256.
+  if (h->st == ST_FP16P || h->st == ST_BF16P) h->chunk = 256;
+  else h->chunk = std::min(1024, std::max(256, (h->N / 16) / 256 * 256));
   h->nchunk = (h->N + h->chunk - 1) / h->chunk;
   h->nblk = (h->N + 255) / 256;
   const int Q = h->Q, N = h->N, KMp = h->KMp;
