@@ -57,14 +57,22 @@ __device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* col
                                       C2<typename Store<ST>::T>* acc) {
   using T = typename Store<ST>::T;
   constexpr int R = Store<ST>::RPT;
-#pragma unroll 8
-  for (int e = 0; e < np; ++e) {
+  auto step = [&](int e) {
     const int col = colidx ? colidx[p0 + e] : p0 + e;
     T re[R], im[R];
     Store<ST>::load(col_ptr<ST>(A, lda, col), row, KMp, re, im);
     const C2<T> cf = coef[e];
 #pragma unroll
     for (int r = 0; r < R; ++r) cfma(acc[r], C2<T>{re[r], im[r]}, cf);
+  };
+  if constexpr (ST == ST_MF) {
+    // generated entries: few columns in flight keep registers (and waves) for
+    // the generation arithmetic
+#pragma unroll 2
+    for (int e = 0; e < np; ++e) step(e);
+  } else {
+#pragma unroll 8
+    for (int e = 0; e < np; ++e) step(e);
   }
 }
 
