@@ -78,6 +78,12 @@ constexpr int FWD_THREADS = 256;
 // Columns per wavefront of the column-dot kernels: two for stored FP32 / FP64
 // entries (more waves in flight), four for 16-bit and generated entries (one
 // LDS read of the staged vector serves more columns).
+// Entries of the LDS copy of the vector of a column-dot kernel: stores with 8
+// rows per lane keep it lane-interleaved in blocks of 512 (see sv_slot), so
+// its length is KMp rounded up to 512.
+template <int ST> inline int sv_len(int KMp) {
+  return Store<ST>::RPT == 8 ? (KMp + 511) / 512 * 512 : KMp;
+}
 template <int ST> constexpr int dot_cols() {
   return (ST == ST_FP16P || ST == ST_BF16P || ST == ST_MF) ? 4 : 2;
 }

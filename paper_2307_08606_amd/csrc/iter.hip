@@ -276,6 +276,15 @@ __device__ inline C2<TA> coldot_core(const void* col, const C2<TA>* sv, int KMp,
   return acc;
 }
 
+// Slot of vector entry i in the LDS copy.  With 8 rows per lane, lane l of a
+// row step reads entries base + 8 l + r, r < 8: entry i is kept at
+// (i / 512) * 512 + (i % 8) * 64 + (i % 512) / 8, so the 64 lanes read 64
+// consecutive slots for each r (entries 64 bytes apart would share banks).
+template <int ST> __device__ inline int sv_slot(int i) {
+  if constexpr (Store<ST>::RPT == 8) return (i & ~511) | ((i & 7) << 6) | ((i >> 3) & 63);
+  else return i;
+}
+
 // Dots of C operator columns with the LDS vector sv in one sweep over the
 // rows: every LDS read of the vector serves all C columns, and the C column
 // loads of a row step are in flight together.
@@ -291,7 +300,7 @@ __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* s
   for (int i0 = rbeg + lane * R; i0 < re_; i0 += SADMM_WAVE * R) {
     C2<TA> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = sv[i0 + r];
+    for (int r = 0; r < R; ++r) v[r] = sv[sv_slot<ST>(i0 + r)];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       T re[R], im[R];
@@ -343,7 +352,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     if constexpr ((EPI == EPI_W || EPI == EPI_WY) && std::is_same<TA, double>::value) {
       if (sd.wtri) {   // second half of X^H (X v)
         v = {(TA)a.ws[2 * ((int64_t)q * a.KMp + i)], (TA)a.ws[2 * ((int64_t)q * a.KMp + i) + 1]};
-        sv[i] = v;
+        sv[sv_slot<ST>(i)] = v;
         continue;
       }
     }
@@ -357,7 +366,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const double* src = x.vec + 2 * ((listed_cols<EPI>() ? 0 : (int64_t)q * x.vec_stride) + i);
       v = {(TA)src[0], (TA)src[1]};
     }
-    sv[i] = v;
+    sv[sv_slot<ST>(i)] = v;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -695,7 +704,7 @@ void run_iteration_batch(const BatchView& b, const BatchDims& d, hipStream_t s,
   mark(1, false);
   mark(2, true);
   coldot_batch_kernel<ST, EPI_XUPD><<<dim3((d.N_max + cpb - 1) / cpb, d.nslot), 256,
-                                      std::max((size_t)d.KMp_max * sizeof(C2<T>),
+                                      std::max((size_t)sv_len<ST>(d.KMp_max) * sizeof(C2<T>),
                                                (size_t)std::min(d.fld_max, XDIR_SEG) * sizeof(cd)),
                                       s>>>(b);
   mark(2, false);
@@ -746,7 +755,8 @@ static void xy_impl(const IterArgs& a, int q0, int q1, hipStream_t s) {
   x.vec_stride = a.KMp;
   coldot_kernel<ST_FP64, EPI_WY1><<<dim3((a.KMp + cpb64 - 1) / cpb64, q1 - q0), 256, smem, s>>>(a, x);
   coldot_kernel<ST_FP64, EPI_WY><<<dim3((a.KMp + cpb64 - 1) / cpb64, q1 - q0), 256, smem, s>>>(a, x);
-  coldot_kernel<ST, EPI_XY><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256, smem, s>>>(a, x);
+  coldot_kernel<ST, EPI_XY><<<dim3((a.N + cpb - 1) / cpb, q1 - q0), 256,
+                             (size_t)sv_len<ST>(a.KMp) * sizeof(cd), s>>>(a, x);
 }
 
 void launch_xy(const IterArgs& a, int st, bool dbl, int q0, int q1, hipStream_t s) {
@@ -799,7 +809,7 @@ static void kkt_impl(const IterArgs& a, int q, const int* idx, int count, const 
   x.thr = thr;
   x.flag = flag;
   const int cpb = 4 * dot_cols<ST>();
-  const size_t smem = (size_t)a.KMp * sizeof(cd);
+  const size_t smem = (size_t)sv_len<ST>(a.KMp) * sizeof(cd);
   coldot_kernel<ST, EPI_KKT><<<dim3((count + cpb - 1) / cpb, 1), 256, smem, s>>>(a, x);
 }
 
@@ -859,7 +869,7 @@ static void refine_impl(const IterArgs& a, int epi, int max_nq, const double* v,
   x.out32 = out32;
   x.cinv = cinv;
   const int cpb = 4 * dot_cols<ST>();
-  const size_t smem = (size_t)a.KMp * sizeof(cd);
+  const size_t smem = (size_t)sv_len<ST>(a.KMp) * sizeof(cd);
   const dim3 grid((max_nq + cpb - 1) / cpb, a.Q);
   if (epi == EPI_GRAD) coldot_kernel<ST, EPI_GRAD><<<grid, 256, smem, s>>>(a, x);
   else coldot_kernel<ST, EPI_FIX><<<grid, 256, smem, s>>>(a, x);
@@ -893,7 +903,7 @@ static void mf_impl(const IterArgs& a, const double* y, double* out, hipStream_t
   x.vec_stride = a.KMp;
   x.out = out;
   const int cpb = 4 * dot_cols<ST>();
-  const size_t smem = (size_t)a.KMp * sizeof(cd);
+  const size_t smem = (size_t)sv_len<ST>(a.KMp) * sizeof(cd);
   coldot_kernel<ST, EPI_MF><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
 }
 
