@@ -423,18 +423,39 @@ __device__ inline void mm_store(const cd (&v)[HPF], double (*dst)[HK][HLDZ]) {
   }
 }
 
+// Triangular k-ranges (KR_A_LOWER: the k-range grows with the row tile,
+// KR_B_LOWER: it shrinks with the column tile) pair tile t with tile
+// T - 1 - t in one work-group, so every work-group does about the same work.
+template <int KR> constexpr bool paired_tiles() {
+  return (KR & (KR_A_LOWER | KR_B_LOWER)) != 0 && (KR & KR_GE_MAX) == 0;
+}
+
+template <int OPA, int OPB, int KR, int OUT>
+__device__ inline void zmm_tile(const MmDesc& d, int ti, int tj);
+
 template <int OPA, int OPB, int KR, int OUT>
 __global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ descs) {
   const MmDesc d = descs[blockIdx.z];
-  int ti, tj;
-  if constexpr (OUT == MM_FULL) {
-    // A lower triangular: the k-range grows with the row tile, so the longest
-    // tiles go first (fewer of them left running at the end of the launch)
-    ti = (KR & KR_A_LOWER) != 0 ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
-    tj = blockIdx.y;
+  if constexpr (OUT == MM_FULL && paired_tiles<KR>()) {
+    if constexpr ((KR & KR_A_LOWER) != 0) {
+      const int mt = (d.m + HM - 1) / HM, t0 = blockIdx.x, t1 = mt - 1 - (int)blockIdx.x;
+      if (t0 < mt) zmm_tile<OPA, OPB, KR, OUT>(d, t0, blockIdx.y);
+      if (t1 > t0) zmm_tile<OPA, OPB, KR, OUT>(d, t1, blockIdx.y);
+    } else {
+      const int nt = (d.n + HM - 1) / HM, t0 = blockIdx.y, t1 = nt - 1 - (int)blockIdx.y;
+      if (t0 < nt) zmm_tile<OPA, OPB, KR, OUT>(d, blockIdx.x, t0);
+      if (t1 > t0) zmm_tile<OPA, OPB, KR, OUT>(d, blockIdx.x, t1);
+    }
   } else {
-    tri_of(blockIdx.x, &ti, &tj);
+    int ti, tj;
+    if constexpr (OUT == MM_FULL) { ti = blockIdx.x; tj = blockIdx.y; }
+    else tri_of(blockIdx.x, &ti, &tj);
+    zmm_tile<OPA, OPB, KR, OUT>(d, ti, tj);
   }
+}
+
+template <int OPA, int OPB, int KR, int OUT>
+__device__ inline void zmm_tile(const MmDesc& d, int ti, int tj) {
   const int i0 = ti * HM, j0 = tj * HM;
   if (i0 >= d.m || j0 >= d.n) return;
   int kb = 0, ke = d.k;
@@ -524,7 +545,11 @@ __global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ des
 template <int OPA, int OPB, int KR, int OUT>
 void launch_zmm(const MmDesc* d, int count, int max_m, int max_n, hipStream_t s) {
   if (count <= 0 || max_m <= 0 || max_n <= 0) return;
-  const int mt = (max_m + HM - 1) / HM, nt = (max_n + HM - 1) / HM;
+  int mt = (max_m + HM - 1) / HM, nt = (max_n + HM - 1) / HM;
+  if constexpr (OUT == MM_FULL && paired_tiles<KR>()) {
+    if constexpr ((KR & KR_A_LOWER) != 0) mt = (mt + 1) / 2;
+    else nt = (nt + 1) / 2;
+  }
   const dim3 grid = OUT == MM_FULL ? dim3(mt, nt, count) : dim3(mt * (mt + 1) / 2, 1, count);
   zmm_kernel<OPA, OPB, KR, OUT><<<grid, 256, 0, s>>>(d);
 }
