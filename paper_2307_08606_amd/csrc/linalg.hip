@@ -434,7 +434,7 @@ template <int OPA, int OPB, int KR, int OUT>
 __device__ inline void zmm_tile(const MmDesc& d, int ti, int tj);
 
 template <int OPA, int OPB, int KR, int OUT>
-__global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ descs, int rect) {
   const MmDesc d = descs[blockIdx.z];
   if constexpr (OUT == MM_FULL && paired_tiles<KR>()) {
     if constexpr ((KR & KR_A_LOWER) != 0) {
@@ -448,8 +448,13 @@ __global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ des
     }
   } else {
     int ti, tj;
-    if constexpr (OUT == MM_FULL) { ti = blockIdx.x; tj = blockIdx.y; }
-    else tri_of(blockIdx.x, &ti, &tj);
+    if (OUT == MM_FULL || rect) {   // (lower output on a rectangular grid: tiles above skipped)
+      ti = blockIdx.x;
+      tj = blockIdx.y;
+      if (OUT != MM_FULL && tj > ti) return;
+    } else {
+      tri_of(blockIdx.x, &ti, &tj);
+    }
     zmm_tile<OPA, OPB, KR, OUT>(d, ti, tj);
   }
 }
@@ -550,8 +555,11 @@ void launch_zmm(const MmDesc* d, int count, int max_m, int max_n, hipStream_t s)
     if constexpr ((KR & KR_A_LOWER) != 0) mt = (mt + 1) / 2;
     else nt = (nt + 1) / 2;
   }
-  const dim3 grid = OUT == MM_FULL ? dim3(mt, nt, count) : dim3(mt * (mt + 1) / 2, 1, count);
-  zmm_kernel<OPA, OPB, KR, OUT><<<grid, 256, 0, s>>>(d);
+  // lower output: the triangle of tiles, or for a tall product (few column
+  // tiles) the rectangle of row x column tiles
+  const bool tall = OUT == MM_LOWER && 2 * nt < mt;
+  const dim3 grid = (OUT == MM_FULL || tall) ? dim3(mt, nt, count) : dim3(mt * (mt + 1) / 2, 1, count);
+  zmm_kernel<OPA, OPB, KR, OUT><<<grid, 256, 0, s>>>(d, tall ? 1 : 0);
 }
 
 template <int ST>
