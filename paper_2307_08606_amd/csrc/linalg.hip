@@ -144,7 +144,13 @@ __global__ __launch_bounds__(DIAG_THREADS) void chol_diag_kernel(const HpdDesc* 
   for (int c = 0; c < NB; ++c) {
     const double d = P[c][c].re;   // every thread reads the pivot
     if (t == 0 && !(d > 0.0)) atomicOr(fail, 1);
-    const double sd = sqrt(fmax(d, 1e-300)), rs = 1.0 / sd;
+    // 1/sqrt(d): hardware reciprocal square root, two Newton steps
+    // r <- r (3 - d r^2) / 2 (each squares the relative error), sqrt(d) = d r
+    const double dd = fmax(d, 1e-300);
+    double rs = __builtin_amdgcn_rsq(dd);
+    rs = rs * (1.5 - 0.5 * dd * rs * rs);
+    rs = rs * (1.5 - 0.5 * dd * rs * rs);
+    const double sd = dd * rs;
     __syncthreads();
     if (t > c && t < NB) P[c][t] = cscale(P[c][t], rs);      // column c of L below the diagonal
     if (t == c) P[c][c] = {sd, 0.0};
