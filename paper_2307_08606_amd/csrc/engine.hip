@@ -98,6 +98,7 @@ struct sadmm_s {
   sadmm_t shared_src = nullptr;  // operator and factor borrowed from this handle
   int n_sharers = 0;             // handles borrowing this one's operator
   GramI8Desc* gi8_d = nullptr;   // integer Gram descriptors (Q)
+  std::vector<unsigned long long*> rmaxc;   // per sensor: row maxima of the full operator
   int2* tiles_d = nullptr;       // Gram tile order (tri_tile_order)
   int ntiles = 0;
   void* gi8_ws = nullptr;        // its digit-plane workspace
@@ -368,6 +369,14 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
     const size_t n = std::min(group, items.size() - g0);
     std::vector<GramI8Desc> gd(n);
     int max_k = 0;
+    // the row maxima of the full operators (computed when they were set) bound
+    // those of the compacted ones
+    bool given = true;
+    for (size_t i = 0; i < n; ++i) {
+      const sadmm_t h = items[g0 + i].h;
+      const int q = items[g0 + i].q;
+      given = given && q < (int)h->rmaxc.size() && h->rmaxc[q];
+    }
     for (size_t i = 0; i < n; ++i) {
       const sadmm_t h = items[g0 + i].h;
       const int q = items[g0 + i].q;
@@ -376,13 +385,14 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
       d.m = h->KMp; d.k = h->nq[q];
       d.C = h->W64[q]; d.ldc = h->KMp; d.diag = factor_rho(h);
       gram_i8_layout(d, static_cast<char*>(h0->gi8_ws) + i * per);
+      if (given) d.rmax = h->rmaxc[q];
       max_k = std::max(max_k, d.k);
       prof_work(h0, SADMM_KC_SLICE, (double)h->nq[q] * h->KMp * (op_bytes(h) + 8.0));
     }
     // (stream order keeps a later group's upload behind the kernels reading this one)
     HIPCHK(h0, hipMemcpyAsync(dd, gd.data(), sizeof(GramI8Desc) * n, hipMemcpyHostToDevice, h0->s));
     int pe = prof_begin(h0);
-    gram_i8_prepare(dd, (int)n, h0->KMp, max_k, h0->st, h0->s);
+    gram_i8_prepare(dd, (int)n, h0->KMp, max_k, h0->st, given, h0->s);
     prof_end(h0, SADMM_KC_SLICE, pe);
     for (int c = 0; c < gram_i8_chunks(max_k); ++c) {
       pe = prof_begin(h0);
@@ -391,6 +401,28 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
     }
     HIPCHK(h0, hipGetLastError());
   }
+  return SADMM_OK;
+}
+
+// Row maxima of sensor q's full operator for the integer Gram (FP32, 16-bit
+// and matrix-free storage), once per operator.
+int cache_rowmax(sadmm_t h, int q) {
+  if (h->st == ST_FP64 || h->p.gram != 0 || h->shared_src) return SADMM_OK;
+  const int KMr = round_up(h->KMp, 64);
+  if ((int)h->rmaxc.size() < h->Q) h->rmaxc.assign(h->Q, nullptr);
+  if (!h->rmaxc[q] && hipMalloc((void**)&h->rmaxc[q], sizeof(unsigned long long) * KMr) != hipSuccess) {
+    h->rmaxc[q] = nullptr;
+    return fail_msg(h, SADMM_E_NOMEM, "row maxima");
+  }
+  GramI8Desc d{};
+  d.A = h->Afull[q]; d.ldA = h->ldA; d.kmp = h->KMp;
+  d.m = h->KMp; d.k = h->N;
+  d.KMr = KMr; d.ldS = round_up(h->N, 128);
+  d.rmax = h->rmaxc[q];
+  HIPCHK(h, hipMemcpyAsync(h->gi8_d, &d, sizeof d, hipMemcpyHostToDevice, h->s));
+  gram_i8_rowmax(h->gi8_d, 1, h->KMp, h->N, h->st, h->s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->s));
   return SADMM_OK;
 }
 
@@ -1421,6 +1453,7 @@ int sadmm_set_operator(sadmm_t h, int32_t q, const void* A, int32_t dtype, int64
   hipError_t e = hipStreamSynchronize(h->s);
   if (stage) hipFree(stage);
   if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator: %s", hipGetErrorString(e));
+  TRY(cache_rowmax(h, q));
   h->op_set[q] = true;
   h->fac_valid[q] = false;
   return SADMM_OK;
@@ -1459,6 +1492,7 @@ int sadmm_set_operator_geometry(sadmm_t h, int32_t q, const double* tx_xy, const
   hipError_t e = hipStreamSynchronize(h->s);
   hipFree(g);
   if (e != hipSuccess) return fail_msg(h, SADMM_E_HIP, "set_operator_geometry: %s", hipGetErrorString(e));
+  TRY(cache_rowmax(h, q));
   h->op_set[q] = true;
   h->fac_valid[q] = false;
   return SADMM_OK;
@@ -1809,6 +1843,8 @@ void sadmm_destroy(sadmm_t h) {
   for (void* p : {(void*)h->A64, (void*)h->dirD, (void*)h->dirX, (void*)h->dirT, (void*)h->dir_desc})
     if (p) hipFree(p);
   for (double* p : h->rec)
+    if (p) hipFree(p);
+  for (unsigned long long* p : h->rmaxc)
     if (p) hipFree(p);
   for (void* p : {(void*)h->sens_mf_d, (void*)h->gfix, h->g32, h->xfix, (void*)h->re1, (void*)h->re2,
                   (void*)h->rw})

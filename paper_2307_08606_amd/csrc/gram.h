@@ -45,8 +45,13 @@ void gram_i8_layout(GramI8Desc& d, void* base);
 //                  order, c < gram_i8_chunks(max_k)).
 // d_desc: device copy of the descriptors; max_m / max_k: largest m and k in
 // the batch; tiles: device copy of tri_tile_order(ceil(max_m / 64)) (linalg.h).
+// rmax_given: d.rmax already holds bounds of the rows' largest |Re| or |Im|
+// (any bound >= the maximum keeps the digits in range; the bound of the full
+// operator serves its compacted copies), so the row maxima are not recomputed.
 void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
-                     hipStream_t s);
+                     bool rmax_given, hipStream_t s);
+// Only the row maxima into d.rmax (KMr entries; d.S and d.rs are not used).
+void gram_i8_rowmax(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st, hipStream_t s);
 int gram_i8_chunks(int max_k);
 void gram_i8_chunk(const GramI8Desc* d_desc, int batch, int chunk, const int2* tiles, int ntiles,
                    hipStream_t s);

@@ -36,14 +36,18 @@ constexpr int GLD = 2 * GKS;  // digit-plane rows padded to an even number of st
 
 inline int round_up_i(int x, int m) { return (x + m - 1) / m * m; }
 
-__global__ void clear_kernel(const GramI8Desc* __restrict__ descs) {
+// Zeroes rmax (when clear_rmax) and the per-chunk digit sums rs.
+__global__ void clear_kernel(const GramI8Desc* __restrict__ descs, int clear_rmax, int clear_rs) {
   const GramI8Desc d = descs[blockIdx.y];
   const int nch = (d.ldS + GI8_CHUNK - 1) / GI8_CHUNK;
-  const int64_t n1 = d.KMr, n2 = (int64_t)nch * 4 * d.KMr;
+  const int64_t n1 = d.KMr, n2 = clear_rs ? (int64_t)nch * 4 * d.KMr : 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2;
        i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < n1) d.rmax[i] = 0ull;
-    else d.rs[i - n1] = 0;
+    if (i < n1) {
+      if (clear_rmax) d.rmax[i] = 0ull;
+    } else {
+      d.rs[i - n1] = 0;
+    }
   }
 }
 
@@ -349,12 +353,15 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restri
 }
 
 template <int ST>
-void launch_prep(const GramI8Desc* d, int batch, int KMr, int ldS, int max_k, hipStream_t s) {
+void launch_prep(const GramI8Desc* d, int batch, int KMr, int ldS, int max_k, bool rmax_given,
+                 bool planes, hipStream_t s) {
   const int nb = std::max(1, std::min(2048, (KMr * ((ldS + GI8_CHUNK - 1) / GI8_CHUNK) * 5 + 255) / 256));
-  clear_kernel<<<dim3(nb, batch), 256, 0, s>>>(d);
-  const int cy = std::max(1, std::min(64, max_k / 256));
-  rowmax_kernel<ST><<<dim3((KMr + 255) / 256, cy, batch), 256, 0, s>>>(d);
-  slice_kernel<ST><<<dim3((ldS + SL_COLS - 1) / SL_COLS, KMr / 64, batch), 256, 0, s>>>(d);
+  clear_kernel<<<dim3(nb, batch), 256, 0, s>>>(d, rmax_given ? 0 : 1, planes ? 1 : 0);
+  if (!rmax_given) {
+    const int cy = std::max(1, std::min(64, max_k / 256));
+    rowmax_kernel<ST><<<dim3((KMr + 255) / 256, cy, batch), 256, 0, s>>>(d);
+  }
+  if (planes) slice_kernel<ST><<<dim3((ldS + SL_COLS - 1) / SL_COLS, KMr / 64, batch), 256, 0, s>>>(d);
 }
 
 }  // namespace
@@ -376,17 +383,26 @@ void gram_i8_layout(GramI8Desc& d, void* base) {
   d.rs = reinterpret_cast<int*>(p);
 }
 
-void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
-                     hipStream_t s) {
+static void prep_dispatch(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
+                          bool rmax_given, bool planes, hipStream_t s) {
   if (batch <= 0 || max_m <= 0) return;
   const int KMr = round_up_i(max_m, 64), ldS = round_up_i(std::max(max_k, 1), GLD);
   switch (st) {
-    case ST_FP32: launch_prep<ST_FP32>(d_desc, batch, KMr, ldS, max_k, s); break;
-    case ST_FP16P: launch_prep<ST_FP16P>(d_desc, batch, KMr, ldS, max_k, s); break;
-    case ST_BF16P: launch_prep<ST_BF16P>(d_desc, batch, KMr, ldS, max_k, s); break;
-    case ST_MF: launch_prep<ST_MF>(d_desc, batch, KMr, ldS, max_k, s); break;
+    case ST_FP32: launch_prep<ST_FP32>(d_desc, batch, KMr, ldS, max_k, rmax_given, planes, s); break;
+    case ST_FP16P: launch_prep<ST_FP16P>(d_desc, batch, KMr, ldS, max_k, rmax_given, planes, s); break;
+    case ST_BF16P: launch_prep<ST_BF16P>(d_desc, batch, KMr, ldS, max_k, rmax_given, planes, s); break;
+    case ST_MF: launch_prep<ST_MF>(d_desc, batch, KMr, ldS, max_k, rmax_given, planes, s); break;
     default: return;
   }
+}
+
+void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st,
+                     bool rmax_given, hipStream_t s) {
+  prep_dispatch(d_desc, batch, max_m, max_k, st, rmax_given, true, s);
+}
+
+void gram_i8_rowmax(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st, hipStream_t s) {
+  prep_dispatch(d_desc, batch, max_m, max_k, st, false, false, s);
 }
 
 int gram_i8_chunks(int max_k) {
