@@ -440,7 +440,8 @@ template <int OPA, int OPB, int KR, int OUT>
 __device__ inline void zmm_tile(const MmDesc& d, int ti, int tj);
 
 template <int OPA, int OPB, int KR, int OUT>
-__global__ __launch_bounds__(256) void zmm_kernel(const MmDesc* __restrict__ descs, int rect) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void zmm_kernel(const MmDesc* __restrict__ descs, int rect) {
   const MmDesc d = descs[blockIdx.z];
   if constexpr (OUT == MM_FULL && paired_tiles<KR>()) {
     if constexpr ((KR & KR_A_LOWER) != 0) {
@@ -481,13 +482,16 @@ __device__ inline void zmm_tile(const MmDesc& d, int ti, int tj) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
   const int c16 = lane & 15, kq = lane >> 4;
-  v4d cr[2][2], ci[2][2];
+  // three real products per complex multiply-add: t1 = sum ar br,
+  // t2 = sum ai bi, t3 = sum (ar + ai)(br + bi); Re = t1 - t2, Im = t3 - t1 - t2
+  v4d t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-      ci[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      t1[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      t2[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      t3[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
     }
   cd va[HPF], vb[HPF];
   if (kb < ke) {
@@ -505,32 +509,31 @@ __device__ inline void zmm_tile(const MmDesc& d, int ti, int tj) {
     }
 #pragma unroll
     for (int kk = 0; kk < HK; kk += 4) {
-      double ar[2], ai[2], nai[2], br[2], bi[2];
+      double ar[2], ai[2], sa[2], br[2], bi[2], sb[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         ar[a] = sA[0][kk + kq][wr + 16 * a + c16];
         ai[a] = sA[1][kk + kq][wr + 16 * a + c16];
-        nai[a] = -ai[a];
+        sa[a] = ar[a] + ai[a];
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         br[b] = sB[0][kk + kq][wc + 16 * b + c16];
         bi[b] = sB[1][kk + kq][wc + 16 * b + c16];
+        sb[b] = br[b] + bi[b];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
-        }
+        for (int b = 0; b < 2; ++b) t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], t1[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[a], bi[b], cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
-        }
+        for (int b = 0; b < 2; ++b) t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], t2[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[a], sb[b], t3[a][b], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -543,7 +546,8 @@ __device__ inline void zmm_tile(const MmDesc& d, int ti, int tj) {
         const int j = j0 + wc + 16 * b + c16;
         if (i >= d.m || j >= d.n) continue;
         if (OUT != MM_FULL && j > i) continue;
-        const double xr = cr[a][b][r], xi = ci[a][b][r];
+        const double p1 = t1[a][b][r], p2 = t2[a][b][r];
+        const double xr = p1 - p2, xi = t3[a][b][r] - p1 - p2;
         cd v = {d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr};
         cd* cij = d.C + (int64_t)j * d.ldc + i;
         if (d.beta != 0.0) { v.re += d.beta * cij->re; v.im += d.beta * cij->im; }
