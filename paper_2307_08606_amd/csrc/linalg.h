@@ -82,8 +82,9 @@ constexpr int HPD_NB = 32;
 // Descriptors one matrix of order n_pad needs in the scratch d_mm below.
 size_t hpd_mm_count(int n_pad);
 // G <- G^{-1} through the Cholesky factor G = L L^H: X = L^{-1}, G^{-1} = X^H X.
-// Blocked right-looking Cholesky (NB x NB diagonal blocks factored in LDS,
-// panel and trailing update as matrix-instruction GEMMs), X by recursive
+// Blocked right-looking Cholesky (NB x NB diagonal blocks factored in LDS by
+// the kernel that also forms the panel, trailing update as matrix-instruction
+// GEMMs), X by recursive
 // doubling (X21 = -X22 L21 X11 over blocks of 32, 64, ...), X^H X over the
 // nonzero k-range of each tile.  All matrices of the batch have order n_pad.
 // h_desc: host copies of the descriptors (d_desc on the device); d_mm: device

@@ -113,27 +113,26 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 // ------------------------------------------------------------------ HPD inverse
 // W = G^{-1} for Hermitian positive definite G through its Cholesky factor:
 //   1. blocked right-looking Cholesky G = L L^H: NB x NB diagonal blocks
-//      factored in LDS (with their inverses), the panel L21 = G21 Lkk^{-H} and
-//      the trailing update G22 -= L21 L21^H as matrix-instruction GEMMs
+//      factored in LDS (with their inverses) by the kernel that also forms
+//      the panel L21 = G21 Lkk^{-H}; the trailing update G22 -= L21 L21^H as
+//      matrix-instruction GEMMs
 //   2. X = L^{-1} by recursive doubling: with X11, X22 the inverses of two
 //      adjacent diagonal blocks, the block below X11 is -X22 (L21 X11)
 //   3. W = X^H X
 // All steps in FP64.  (Gauss-Jordan elimination without pivoting is
 // unstable on the strongly correlated Gram matrices of radar operators.)
 
-// Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS; write
-// Lkk into G (upper part zeroed) and Lkk^{-1} into Dinv[:, k0:k0+NB].
-// The inverse rides along the column steps: with Y = I, step c sets row c of
-// X = Lkk^{-1} to Y[c, :] / L[c, c] and removes L[r, c] X[c, :] from the rows
-// r > c below, in parallel with the trailing update of the factor.
+// Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS, with
+// its inverse.  The inverse rides along the column steps: with Y = I, step c
+// sets row c of X = Lkk^{-1} to Y[c, :] / L[c, c] and removes L[r, c] X[c, :]
+// from the rows r > c below, in parallel with the trailing update of the
+// factor.  P[c][r] holds element (r, c) of the block, then of Lkk; Li[c][r]
+// element (r, c) of Y, then of Lkk^{-1}.
 constexpr int DIAG_THREADS = 256;
-__global__ __launch_bounds__(DIAG_THREADS) void chol_diag_kernel(const HpdDesc* __restrict__ descs,
-                                                                 int k0, int* fail) {
-  const HpdDesc h = descs[blockIdx.x];
-  if (k0 >= h.n_pad) return;
+constexpr int PANEL_ROWS = 64;   // panel rows per work-group
+__device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1], cd (*Li)[HPD_NB + 1],
+                                   int* fail) {
   constexpr int NB = HPD_NB;
-  __shared__ cd P[NB][NB + 1];    // P[c][r] = element (r, c)
-  __shared__ cd Li[NB][NB + 1];   // Li[c][r] = element (r, c) of Y, then of Lkk^{-1}
   const int t = threadIdx.x;
   for (int e = t; e < NB * NB; e += DIAG_THREADS) {
     const int r = e % NB, c = e / NB;
@@ -179,10 +178,62 @@ __global__ __launch_bounds__(DIAG_THREADS) void chol_diag_kernel(const HpdDesc* 
     }
     __syncthreads();
   }
-  for (int e = t; e < NB * NB; e += DIAG_THREADS) {
-    const int r = e % NB, c = e / NB;
-    h.G[(int64_t)(k0 + c) * h.n_pad + k0 + r] = (r >= c) ? P[c][r] : cd{0.0, 0.0};
-    h.D[(int64_t)(k0 + c) * NB + r] = Li[c][r];
+}
+
+// One column step of the Cholesky: work-group 0 factors the diagonal block and
+// writes Lkk^{-1} to D[:, k0:k0+NB]; work-group b >= 1 factors it as well (the
+// same arithmetic, so the same result) and forms panel rows
+// [k0 + NB + 64 (b - 1), +64) of L21 = G21 Lkk^{-H} in place.  The diagonal
+// block of G itself is only read (its factor lives in D; later steps use
+// only the blocks below the diagonal), so no work-group writes what another
+// may still be reading.
+__global__ __launch_bounds__(DIAG_THREADS) void chol_panel_kernel(const HpdDesc* __restrict__ descs,
+                                                                  int k0, int* fail) {
+  const HpdDesc h = descs[blockIdx.y];
+  constexpr int NB = HPD_NB;
+  if (k0 >= h.n_pad) return;
+  const int r0 = k0 + NB + PANEL_ROWS * ((int)blockIdx.x - 1);
+  if (blockIdx.x > 0 && r0 >= h.n_pad) return;
+  __shared__ cd P[NB][NB + 1];
+  __shared__ cd Li[NB][NB + 1];
+  __shared__ cd S[NB][PANEL_ROWS + 1];   // S[k][r] = G21(r0 + r, k)
+  const int t = threadIdx.x, r = t & 63, cg = t >> 6;
+  // panel rows: thread (r, cg) moves columns cg + 4 e (issued before the
+  // factorisation, stored after it)
+  cd g[NB / 4];
+  const bool row_ok = blockIdx.x > 0 && r0 + r < h.n_pad;
+#pragma unroll
+  for (int e = 0; e < NB / 4; ++e)
+    g[e] = row_ok ? h.G[(int64_t)(k0 + cg + 4 * e) * h.n_pad + r0 + r] : cd{0.0, 0.0};
+  diag_factor(h, k0, P, Li, fail);
+  if (blockIdx.x == 0) {
+    for (int e = t; e < NB * NB; e += DIAG_THREADS) {
+      const int rr = e % NB, c = e / NB;
+      h.D[(int64_t)(k0 + c) * NB + rr] = Li[c][rr];
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < NB / 4; ++e) S[cg + 4 * e][r] = g[e];
+  __syncthreads();
+  // L21(r, c) = sum_k G21(r, k) conj(X(c, k)), X = Lkk^{-1} lower triangular
+  // (Li[k][c] = X(c, k), zero for k > c); thread (r, cg) forms columns cg + 4 j
+  cd acc[NB / 4];
+#pragma unroll
+  for (int j = 0; j < NB / 4; ++j) acc[j] = {0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < NB; ++k) {
+    const cd a = S[k][r];
+#pragma unroll
+    for (int j = 0; j < NB / 4; ++j) {
+      const cd x = Li[k][cg + 4 * j];
+      acc[j].re += a.re * x.re + a.im * x.im;
+      acc[j].im += a.im * x.re - a.re * x.im;
+    }
+  }
+  if (row_ok) {
+#pragma unroll
+    for (int j = 0; j < NB / 4; ++j) h.G[(int64_t)(k0 + cg + 4 * j) * h.n_pad + r0 + r] = acc[j];
   }
 }
 
@@ -194,7 +245,7 @@ __global__ void zero_x_kernel(const HpdDesc* __restrict__ descs) {
 }
 
 // Diagonal blocks of X = L^{-1} are the inverses of the diagonal Cholesky
-// blocks (from chol_diag_kernel).  One work-group per block.
+// blocks (from chol_panel_kernel).  One work-group per block.
 __global__ void x_diag_kernel(const HpdDesc* __restrict__ descs) {
   const HpdDesc h = descs[blockIdx.y];
   constexpr int NB = HPD_NB;
@@ -647,7 +698,6 @@ size_t hpd_mm_count(int n) {
     const int K1 = std::min(K0 + HPD_OB, n);
     for (int k0 = K0; k0 < K1; k0 += HPD_NB) {
       if (n - k0 - HPD_NB <= 0) continue;
-      c += 1;                                              // panel
       if (K1 - k0 - HPD_NB > 0) c += 1;                    // update inside the outer block
     }
     if (n - K1 > 0) c += 1;                                // update beyond it
@@ -685,7 +735,7 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
   constexpr int NB = HPD_NB;
   // Plan every GEMM of the factorisation (descriptors grouped per launch,
   // all matrices of the batch together), upload once, then launch in order.
-  enum Kind { PANEL, TRAIL, TRI1, TRI2, XHX, DIAG };
+  enum Kind { TRAIL, TRI1, TRI2, XHX, DIAG };
   struct Launch { Kind kind; int off, count, m, n, k0; };
   std::vector<MmDesc> mm;
   std::vector<Launch> plan;
@@ -693,16 +743,9 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
   for (int K0 = 0; K0 < n; K0 += HPD_OB) {
     const int K1 = std::min(K0 + HPD_OB, n);
     for (int k0 = K0; k0 < K1; k0 += NB) {
-      plan.push_back({DIAG, 0, batch, 0, 0, k0});
-      const int rest = n - k0 - NB;
+      const int rest = n - k0 - NB;   // rows below the diagonal block (panel)
+      plan.push_back({DIAG, 0, batch, std::max(rest, 0), 0, k0});
       if (rest <= 0) continue;
-      Launch lp{PANEL, (int)mm.size(), batch, rest, NB, k0};
-      for (int i = 0; i < batch; ++i) {
-        cd* L21 = hd[i].G + (int64_t)k0 * n + k0 + NB;
-        mm.push_back(MmDesc{L21, hd[i].D + (int64_t)k0 * NB, L21, rest, NB, NB, n, NB, n,
-                            1.0, 0.0, 0.0});
-      }
-      plan.push_back(lp);
       const int nc = K1 - k0 - NB;   // columns of the outer block still to factor
       if (nc <= 0) continue;
       Launch lt{TRAIL, (int)mm.size(), batch, rest, nc, k0};
@@ -764,8 +807,10 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
   for (const Launch& l : plan) {
     const MmDesc* p = d_mm + l.off;
     switch (l.kind) {
-      case DIAG: chol_diag_kernel<<<batch, DIAG_THREADS, 0, s>>>(d_desc, l.k0, d_fail); break;
-      case PANEL: launch_zmm<OP_N, OP_C, KR_ALL, MM_FULL>(p, l.count, l.m, l.n, s); break;
+      case DIAG:
+        chol_panel_kernel<<<dim3(1 + (l.m + PANEL_ROWS - 1) / PANEL_ROWS, batch), DIAG_THREADS, 0, s>>>(
+            d_desc, l.k0, d_fail);
+        break;
       case TRAIL: launch_zmm<OP_N, OP_C, KR_ALL, MM_LOWER>(p, l.count, l.m, l.n, s); break;
       case TRI1:
         if (!diag_done) {   // X's diagonal blocks, once the Cholesky is complete
