@@ -122,17 +122,23 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 // All steps in FP64.  (Gauss-Jordan elimination without pivoting is
 // unstable on the strongly correlated Gram matrices of radar operators.)
 
-// Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS, with
-// its inverse.  The inverse rides along the column steps: with Y = I, step c
-// sets row c of X = Lkk^{-1} to Y[c, :] / L[c, c] and removes L[r, c] X[c, :]
-// from the rows r > c below, in parallel with the trailing update of the
-// factor.  P[c][r] holds element (r, c) of the block, then of Lkk; Li[c][r]
-// element (r, c) of Y, then of Lkk^{-1}.
+// Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS and
+// form X = Lkk^{-1} alongside: with Y = I, step c takes column c of L as
+// P[:, c] / sqrt(P[c, c]), scales row c of Y by 1 / L[c, c] (it is then row c
+// of X) and removes L[r, c] L[s, c]^* from P[r, s] (c < s <= r) and
+// L[r, c] X[c, s] from Y[r, s] (s <= c < r).  Thread (r, s0) owns the entries
+// (r, s0 + 8 j), j < 4, of both: at step c each owns either a factor entry
+// (s > c) or an inverse entry (s <= c), and no entry is written that another
+// thread reads in the same step, so all its loads go out together.  Column c
+// of L is used only in step c and is not stored (the scaling is applied on
+// read).  Only Li (Li[c][r] = element (r, c) of Y, then of X) is the result;
+// P[c][r] starts as element (r, c) of the block.
 constexpr int DIAG_THREADS = 256;
 constexpr int PANEL_ROWS = 64;   // panel rows per work-group
 __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1], cd (*Li)[HPD_NB + 1],
                                    int* fail) {
   constexpr int NB = HPD_NB;
+  static_assert(DIAG_THREADS == 8 * NB, "thread (r, s0): r < NB, s0 < 8");
   const int t = threadIdx.x;
   for (int e = t; e < NB * NB; e += DIAG_THREADS) {
     const int r = e % NB, c = e / NB;
@@ -140,41 +146,40 @@ __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1]
     Li[c][r] = {r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
+  const int r = t & (NB - 1), s0 = t / NB;
   for (int c = 0; c < NB; ++c) {
     const double d = P[c][c].re;   // every thread reads the pivot
     if (t == 0 && !(d > 0.0)) atomicOr(fail, 1);
     // 1/sqrt(d): hardware reciprocal square root, two Newton steps
-    // r <- r (3 - d r^2) / 2 (each squares the relative error), sqrt(d) = d r
+    // r <- r (3 - d r^2) / 2 (each squares the relative error)
     const double dd = fmax(d, 1e-300);
     double rs = __builtin_amdgcn_rsq(dd);
     rs = rs * (1.5 - 0.5 * dd * rs * rs);
     rs = rs * (1.5 - 0.5 * dd * rs * rs);
-    const double sd = dd * rs;
-    __syncthreads();
-    if (t > c && t < NB) P[c][t] = cscale(P[c][t], rs);      // column c of L below the diagonal
-    if (t == c) P[c][c] = {sd, 0.0};
     if (t >= NB && t - NB <= c) Li[t - NB][c] = cscale(Li[t - NB][c], rs);   // row c of X
     __syncthreads();
-    const int m = NB - 1 - c;   // rows below c
-    // factor: (r, s2) -= L(r, c) conj(L(s2, c)), c < s2 <= r
-    for (int e = t; e < m * m; e += DIAG_THREADS) {
-      const int r = c + 1 + e % m, s2 = c + 1 + e / m;
-      if (r >= s2) {
-        const cd a = P[c][r], b = P[c][s2];
-        cd v = P[s2][r];
-        v.re -= a.re * b.re + a.im * b.im;
-        v.im -= a.im * b.re - a.re * b.im;
-        P[s2][r] = v;
+    if (r > c) {
+      const cd l = cscale(P[c][r], rs);   // L(r, c)
+      cd u[4], v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sc = s0 + 8 * j;
+        u[j] = sc > c ? P[c][sc] : Li[sc][c];   // L(s, c) unscaled, or X(c, s)
+        v[j] = sc > c ? P[sc][r] : Li[sc][r];
       }
-    }
-    // inverse: Y(r, j) -= L(r, c) X(c, j), r > c, j <= c
-    for (int e = t; e < m * (c + 1); e += DIAG_THREADS) {
-      const int r = c + 1 + e % m, j = e / m;
-      const cd l = P[c][r], x = Li[j][c];
-      cd v = Li[j][r];
-      v.re -= l.re * x.re - l.im * x.im;
-      v.im -= l.re * x.im + l.im * x.re;
-      Li[j][r] = v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sc = s0 + 8 * j;
+        if (sc > c) {
+          if (sc <= r) {   // P(r, s) -= L(r, c) conj(L(s, c))
+            const cd b = cscale(u[j], rs);
+            P[sc][r] = cd{v[j].re - (l.re * b.re + l.im * b.im), v[j].im - (l.im * b.re - l.re * b.im)};
+          }
+        } else {           // Y(r, s) -= L(r, c) X(c, s)
+          Li[sc][r] = cd{v[j].re - (l.re * u[j].re - l.im * u[j].im),
+                         v[j].im - (l.re * u[j].im + l.im * u[j].re)};
+        }
+      }
     }
     __syncthreads();
   }
