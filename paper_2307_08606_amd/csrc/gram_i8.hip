@@ -12,9 +12,9 @@
 // int8 for every d) and adds back the sum of the imaginary digits of row j.
 //
 // Work-group: 64 x 64 complex tile of the lower triangle (XCD-aware order, see
-// tri_tile_order), four waves of
-// 32 x 32 (2 x 2 blocks of 16 x 16), each accumulating all 13 digit pairs with
-// s + t <= 4 into five int32 class accumulators (c = s + t).
+// tri_tile_order), eight waves of 32 x 16 (2 x 1 blocks of 16 x 16, two waves
+// per SIMD), each accumulating all 13 digit pairs with s + t <= 4 into five
+// int32 class accumulators (c = s + t).
 // Lane layout of the instruction: lane l carries A row l % 16 and B column
 // l % 16 with k-slots 16 (l / 16) + byte (any order shared by A and B gives
 // the same product); result element (4 (l / 16) + r, l % 16) is component r
@@ -150,6 +150,12 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
 
 using Panel = int8_t[2][4][2][GT][GROW];   // [L/R][digit][re/im][row][bytes]
 constexpr int NCLS = 5;                      // classes c = s + t = 0..4
+// Eight waves per work-group (two per SIMD, so one wave's LDS reads overlap
+// the other's matrix instructions): wave w owns rows 32 (w & 1) + [0, 32)
+// (two 16-row blocks a) and columns 16 (w >> 1) + [0, 16) (one block).
+constexpr int GWAVES = 8;
+constexpr int GTHREADS = 64 * GWAVES;
+constexpr int BB = 1;                        // 16-column blocks per wave
 
 // Digit s of the wave's two L row blocks (real, imaginary, NOT of real).
 struct LDigit { v4i r[2], i[2], nr[2]; };
@@ -164,34 +170,34 @@ __device__ inline LDigit load_l(const Panel& sp, int wr, int r16, int kq) {
   }
   return L;
 }
-// R digits of the wave's two column blocks, all four held for the stage.
-struct RDigits { v4i r[4][2], i[4][2]; };
+// R digits of the wave's column block(s), all four held for the stage.
+struct RDigits { v4i r[4][BB], i[4][BB]; };
 __device__ inline void load_r(const Panel& sp, int wc, int r16, int kq, RDigits& R) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < BB; ++b) {
       R.r[t][b] = *reinterpret_cast<const v4i*>(&sp[1][t][0][wc + 16 * b + r16][16 * kq]);
       R.i[t][b] = *reinterpret_cast<const v4i*>(&sp[1][t][1][wc + 16 * b + r16][16 * kq]);
     }
 }
 // Accumulate the products of an L digit with R digit T into class slot C.
 template <int T, int C>
-__device__ inline void pair_mma(const LDigit& L, const RDigits& R, v4i (&re)[NCLS][2][2],
-                                v4i (&im)[NCLS][2][2]) {
-  // in rounds over the four (a, b) blocks, so that the two products into one
-  // accumulator are eight instructions apart
+__device__ inline void pair_mma(const LDigit& L, const RDigits& R, v4i (&re)[NCLS][2][BB],
+                                v4i (&im)[NCLS][2][BB]) {
+  // in rounds over the (a, b) blocks, so that the two products into one
+  // accumulator are apart
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < BB; ++b) {
       re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.r[a], R.r[T][b], re[C][a][b], 0, 0, 0);
       im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], R.r[T][b], im[C][a][b], 0, 0, 0);
     }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < BB; ++b) {
       re[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.i[a], R.i[T][b], re[C][a][b], 0, 0, 0);
       im[C][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L.nr[a], R.i[T][b], im[C][a][b], 0, 0, 0);
     }
@@ -200,7 +206,7 @@ __device__ inline void pair_mma(const LDigit& L, const RDigits& R, v4i (&re)[NCL
 // One stage of 64 columns: the R digits read once, the 13 pairs grouped by L
 // digit (one live at a time).
 __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
-                             v4i (&re)[NCLS][2][2], v4i (&im)[NCLS][2][2]) {
+                             v4i (&re)[NCLS][2][BB], v4i (&im)[NCLS][2][BB]) {
   RDigits R;
   load_r(sp, wc, r16, kq, R);
   { const LDigit L = load_l<0>(sp, wr, r16, kq);
@@ -228,8 +234,8 @@ __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
 
 // One chunk of columns [chunk * GI8_CHUNK, +GI8_CHUNK): chunk 0 writes
 // C = G_0 + diag I, later chunks add.
-__global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restrict__ descs, int chunk,
-                                                       const int2* __restrict__ tiles, int ntiles) {
+__global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __restrict__ descs, int chunk,
+                                                             const int2* __restrict__ tiles, int ntiles) {
   const GramI8Desc d = descs[blockIdx.y];
   int ti, tj;
   if (!xcd_tile(tiles, ntiles, &ti, &tj)) return;
@@ -240,68 +246,63 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restri
   const int n1 = min(n0 + GI8_CHUNK, d.ldS);
   __shared__ __align__(16) Panel sp;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  const int wr = 32 * (w & 1), wc = 16 * BB * (w >> 1);
   const int r16 = lane & 15, kq = lane >> 4;
-  v4i re[NCLS][2][2], im[NCLS][2][2];
+  v4i re[NCLS][2][BB], im[NCLS][2][BB];
 #pragma unroll
   for (int c = 0; c < NCLS; ++c)
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < BB; ++b) {
         re[c][a][b] = v4i{0, 0, 0, 0};
         im[c][a][b] = v4i{0, 0, 0, 0};
       }
   // staging: 16 planes (L/R x digit x re/im) x 64 rows x 64 bytes per stage;
-  // thread t moves row t >> 2, quarter t & 3 of every plane (piece e = plane).
+  // thread t moves row (t >> 2) & 63, quarter t & 3 of the eight planes
+  // 8 (t >> 8) + e of the L/R x digit x re/im order (L for t < 256, R above).
+  constexpr int PPT = 16 * 256 / GTHREADS;   // planes per thread
   const int64_t plane = (int64_t)d.KMr * d.ldS;
-  const int prow = t >> 2, pq = t & 3;
-  const int8_t* srcL = d.S + (int64_t)(i0 + prow) * d.ldS + 16 * pq;
-  const int8_t* srcR = d.S + (int64_t)(j0 + prow) * d.ldS + 16 * pq;
-  int8_t* dst0 = &sp[0][0][0][prow][16 * pq];
+  const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
+  const int8_t* src = d.S + (int64_t)((side ? j0 : i0) + prow) * d.ldS + 16 * pq;
+  int8_t* dst0 = &sp[side][0][0][prow][16 * pq];
   constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
   // Two stages in flight: even stages load into pa, odd ones into pb, each
   // two stages ahead of its products (every chunk has an even number of
   // stages: the planes are padded to GLD columns).
-  u4v pa[16], pb[16];
+  u4v pa[PPT], pb[PPT];
   if (n0 < n1) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-      pa[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + n0);
-  }
-  if (n0 < n1) {
+    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0);
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-      pb[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + n0 + GKS);
+    for (int e = 0; e < PPT; ++e) pb[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0 + GKS);
   }
   for (int nb = n0; nb < n1; nb += 2 * GKS) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
     __syncthreads();
     if (nb + 2 * GKS < n1) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        pa[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + nb + 2 * GKS);
+      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 2 * GKS);
     }
     kstep(sp, wr, wc, r16, kq, re, im);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pb[e];
+    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pb[e];
     __syncthreads();
     if (nb + 3 * GKS < n1) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        pb[e] = *reinterpret_cast<const u4v*>((e < 8 ? srcL : srcR) + (e & 7) * plane + nb + 3 * GKS);
+      for (int e = 0; e < PPT; ++e) pb[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 3 * GKS);
     }
     kstep(sp, wr, wc, r16, kq, re, im);
   }
   // ---- epilogue: FP64 sum of the classes, lower triangle and its mirror
   const int* rs = d.rs + (int64_t)chunk * 4 * d.KMr;
-  int cre[2][NCLS];   // imaginary correction: sum of rs_t over the class's pairs
-  double sj[2];
+  int cre[BB][NCLS];   // imaginary correction: sum of rs_t over the class's pairs
+  double sj[BB];
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
+  for (int b = 0; b < BB; ++b) {
     const int j = j0 + wc + 16 * b + r16;
     int r4[4] = {0, 0, 0, 0};
     double mx = 0.0;
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(const GramI8Desc* __restri
       if (mx > 0.0) (void)frexp(mx, &E);
       const double si = ldexp(1.0, E - 6);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < BB; ++b) {
         const int j = j0 + wc + 16 * b + r16;
         if (i >= d.m || j >= d.m || j > i) continue;
         // smallest class first: every partial sum keeps full FP64 accuracy
@@ -412,5 +413,5 @@ int gram_i8_chunks(int max_k) {
 void gram_i8_chunk(const GramI8Desc* d_desc, int batch, int chunk, const int2* tiles, int ntiles,
                    hipStream_t s) {
   if (batch <= 0 || ntiles <= 0) return;
-  gram_i8_kernel<<<dim3(8 * ((ntiles + 7) / 8), batch), 256, 0, s>>>(d_desc, chunk, tiles, ntiles);
+  gram_i8_kernel<<<dim3(8 * ((ntiles + 7) / 8), batch), GTHREADS, 0, s>>>(d_desc, chunk, tiles, ntiles);
 }
