@@ -204,7 +204,8 @@ __device__ inline void pair_mma(const LDigit& L, const RDigits& R, v4i (&re)[NCL
 }
 
 // One stage of 64 columns: the R digits read once, the 13 pairs grouped by L
-// digit (one live at a time).
+// digit (the compiler may load the next L digit during the current group's
+// products).
 __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
                              v4i (&re)[NCLS][2][BB], v4i (&im)[NCLS][2][BB]) {
   RDigits R;
@@ -214,22 +215,18 @@ __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
     pair_mma<1, 1>(L, R, re, im);
     pair_mma<2, 2>(L, R, re, im);
     pair_mma<3, 3>(L, R, re, im); }
-  __builtin_amdgcn_sched_barrier(0);
   { const LDigit L = load_l<1>(sp, wr, r16, kq);
     pair_mma<0, 1>(L, R, re, im);
     pair_mma<1, 2>(L, R, re, im);
     pair_mma<2, 3>(L, R, re, im);
     pair_mma<3, 4>(L, R, re, im); }
-  __builtin_amdgcn_sched_barrier(0);
   { const LDigit L = load_l<2>(sp, wr, r16, kq);
     pair_mma<0, 2>(L, R, re, im);
     pair_mma<1, 3>(L, R, re, im);
     pair_mma<2, 4>(L, R, re, im); }
-  __builtin_amdgcn_sched_barrier(0);
   { const LDigit L = load_l<3>(sp, wr, r16, kq);
     pair_mma<0, 3>(L, R, re, im);
     pair_mma<1, 4>(L, R, re, im); }
-  __builtin_amdgcn_sched_barrier(0);
 }
 
 // One chunk of columns [chunk * GI8_CHUNK, +GI8_CHUNK): chunk 0 writes
