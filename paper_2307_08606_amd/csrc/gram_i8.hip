@@ -241,7 +241,7 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
   const int n0 = chunk * GI8_CHUNK;
   if (chunk > 0 && n0 >= d.ldS) return;   // nothing to add
   const int n1 = min(n0 + GI8_CHUNK, d.ldS);
-  __shared__ __align__(16) Panel sp;
+  __shared__ __align__(16) Panel sp[2];   // double buffer: stage 2 s in sp[0], 2 s + 1 in sp[1]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = 32 * (w & 1), wc = 16 * BB * (w >> 1);
   const int r16 = lane & 15, kq = lane >> 4;
@@ -262,37 +262,42 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
   const int64_t plane = (int64_t)d.KMr * d.ldS;
   const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
   const int8_t* src = d.S + (int64_t)((side ? j0 : i0) + prow) * d.ldS + 16 * pq;
-  int8_t* dst0 = &sp[side][0][0][prow][16 * pq];
+  int8_t* dst0 = &sp[0][side][0][0][prow][16 * pq];
+  int8_t* dst1 = &sp[1][side][0][0][prow][16 * pq];
   constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
-  // Two stages in flight: even stages load into pa, odd ones into pb, each
-  // two stages ahead of its products (every chunk has an even number of
-  // stages: the planes are padded to GLD columns).
-  u4v pa[PPT], pb[PPT];
+  // Stage s is staged in sp[s & 1]; its loads are issued one stage ahead (in
+  // flight during the products of the stage before) and stored to LDS after
+  // those products.  One barrier per stage: a buffer is refilled only after
+  // the barrier that follows the products reading it.
+  u4v pa[PPT];
   if (n0 < n1) {
 #pragma unroll
     for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0);
 #pragma unroll
-    for (int e = 0; e < PPT; ++e) pb[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0 + GKS);
-  }
-  for (int nb = n0; nb < n1; nb += 2 * GKS) {
+    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0 + GKS);
+  }
+  for (int nb = n0; nb < n1; nb += 2 * GKS) {
+    kstep(sp[0], wr, wc, r16, kq, re, im);                      // stage nb
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst1 + e * kPlaneLds) = pa[e];
     __syncthreads();
     if (nb + 2 * GKS < n1) {
 #pragma unroll
       for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 2 * GKS);
     }
-    kstep(sp, wr, wc, r16, kq, re, im);
-    __syncthreads();
+    kstep(sp[1], wr, wc, r16, kq, re, im);                      // stage nb + GKS
+    if (nb + 2 * GKS < n1) {
 #pragma unroll
-    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pb[e];
+      for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    }
     __syncthreads();
     if (nb + 3 * GKS < n1) {
 #pragma unroll
-      for (int e = 0; e < PPT; ++e) pb[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 3 * GKS);
+      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 3 * GKS);
     }
-    kstep(sp, wr, wc, r16, kq, re, im);
   }
   // ---- epilogue: FP64 sum of the classes, lower triangle and its mirror
   const int* rs = d.rs + (int64_t)chunk * 4 * d.KMr;
