@@ -498,25 +498,32 @@ __device__ inline void zmm_tile(const MmDesc& d, int ti, int tj);
 template <int OPA, int OPB, int KR, int OUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void zmm_kernel(const MmDesc* __restrict__ descs, int rect) {
-  const MmDesc d = descs[blockIdx.z];
+  // Work-groups are dealt to the 8 XCDs by linear id modulo 8; taking the
+  // product index as the linear id modulo the number of products keeps each
+  // product (one sensor's matrix in a batch of 8) on one XCD, so its panels
+  // stay in that XCD's L2 instead of being fetched by all eight.
+  const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned rest = lin / gridDim.z;
+  const int bz = (int)(lin % gridDim.z), bx = (int)(rest % gridDim.x), by = (int)(rest / gridDim.x);
+  const MmDesc d = descs[bz];
   if constexpr (OUT == MM_FULL && paired_tiles<KR>()) {
     if constexpr ((KR & KR_A_LOWER) != 0) {
-      const int mt = (d.m + HM - 1) / HM, t0 = blockIdx.x, t1 = mt - 1 - (int)blockIdx.x;
-      if (t0 < mt) zmm_tile<OPA, OPB, KR, OUT>(d, t0, blockIdx.y);
-      if (t1 > t0) zmm_tile<OPA, OPB, KR, OUT>(d, t1, blockIdx.y);
+      const int mt = (d.m + HM - 1) / HM, t0 = bx, t1 = mt - 1 - bx;
+      if (t0 < mt) zmm_tile<OPA, OPB, KR, OUT>(d, t0, by);
+      if (t1 > t0) zmm_tile<OPA, OPB, KR, OUT>(d, t1, by);
     } else {
-      const int nt = (d.n + HM - 1) / HM, t0 = blockIdx.y, t1 = nt - 1 - (int)blockIdx.y;
-      if (t0 < nt) zmm_tile<OPA, OPB, KR, OUT>(d, blockIdx.x, t0);
-      if (t1 > t0) zmm_tile<OPA, OPB, KR, OUT>(d, blockIdx.x, t1);
+      const int nt = (d.n + HM - 1) / HM, t0 = by, t1 = nt - 1 - by;
+      if (t0 < nt) zmm_tile<OPA, OPB, KR, OUT>(d, bx, t0);
+      if (t1 > t0) zmm_tile<OPA, OPB, KR, OUT>(d, bx, t1);
     }
   } else {
     int ti, tj;
     if (OUT == MM_FULL || rect) {   // (lower output on a rectangular grid: tiles above skipped)
-      ti = blockIdx.x;
-      tj = blockIdx.y;
+      ti = bx;
+      tj = by;
       if (OUT != MM_FULL && tj > ti) return;
     } else {
-      tri_of(blockIdx.x, &ti, &tj);
+      tri_of(bx, &ti, &tj);
     }
     zmm_tile<OPA, OPB, KR, OUT>(d, ti, tj);
   }
