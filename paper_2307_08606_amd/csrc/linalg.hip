@@ -123,22 +123,36 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 // unstable on the strongly correlated Gram matrices of radar operators.)
 
 // Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS and
-// form X = Lkk^{-1} alongside: with Y = I, step c takes column c of L as
-// P[:, c] / sqrt(P[c, c]), scales row c of Y by 1 / L[c, c] (it is then row c
-// of X) and removes L[r, c] L[s, c]^* from P[r, s] (c < s <= r) and
-// L[r, c] X[c, s] from Y[r, s] (s <= c < r).  Thread (r, s0) owns the entries
-// (r, s0 + 8 j), j < 4, of both: at step c each owns either a factor entry
-// (s > c) or an inverse entry (s <= c), and no entry is written that another
-// thread reads in the same step, so all its loads go out together.  Column c
-// of L is used only in step c and is not stored (the scaling is applied on
-// read).  Only Li (Li[c][r] = element (r, c) of Y, then of X) is the result;
-// P[c][r] starts as element (r, c) of the block.
+// form X = Lkk^{-1} alongside, two columns c, c + 1 per step.  Every thread
+// derives the 2 x 2 pivot block: L[c, c] = sqrt(P[c, c]), l = L[c + 1, c] =
+// P[c + 1, c] / L[c, c], L[c + 1, c + 1] = sqrt(P[c + 1, c + 1] - |l|^2).
+// Phase 1: thread NB + j turns rows c, c + 1 of Y (Y = I at the start) into
+// rows of X: X[c, j] = Y[c, j] / L[c, c], X[c + 1, j] = (Y[c + 1, j] -
+// l X[c, j]) / L[c + 1, c + 1].  Phase 2: thread (r, s0) owns the entries
+// (r, s0 + 8 j), j < 4, of both matrices, each either a factor entry (s > c
+// + 1: P[r, s] -= L[r, c] L[s, c]^* + L[r, c + 1] L[s, c + 1]^*) or an
+// inverse entry (s <= c + 1: Y[r, s] -= L[r, c] X[c, s] + L[r, c + 1]
+// X[c + 1, s]), for r > c + 1; columns c, c + 1 of L are formed on read
+// (L[r, c] = P[r, c] / L[c, c], L[r, c + 1] = (P[r, c + 1] - L[r, c] l^*) /
+// L[c + 1, c + 1]) and not stored.  No entry is written that another thread
+// reads in the same phase, so each thread's loads go out together.  Only Li
+// (Li[c][r] = element (r, c) of Y, then of X) is the result; P[c][r] starts
+// as element (r, c) of the block.
 constexpr int DIAG_THREADS = 256;
 constexpr int PANEL_ROWS = 64;   // panel rows per work-group
+// 1 / sqrt(d): hardware reciprocal square root, two Newton steps
+// r <- r (3 - d r^2) / 2 (each squares the relative error)
+__device__ inline double rsqrt_nr(double d) {
+  const double dd = fmax(d, 1e-300);
+  double rs = __builtin_amdgcn_rsq(dd);
+  rs = rs * (1.5 - 0.5 * dd * rs * rs);
+  return rs * (1.5 - 0.5 * dd * rs * rs);
+}
+__device__ inline cd cmulc(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }   // a conj(b)
 __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1], cd (*Li)[HPD_NB + 1],
                                    int* fail) {
   constexpr int NB = HPD_NB;
-  static_assert(DIAG_THREADS == 8 * NB, "thread (r, s0): r < NB, s0 < 8");
+  static_assert(DIAG_THREADS == 8 * NB && NB % 2 == 0, "thread (r, s0): r < NB, s0 < 8");
   const int t = threadIdx.x;
   for (int e = t; e < NB * NB; e += DIAG_THREADS) {
     const int r = e % NB, c = e / NB;
@@ -147,37 +161,51 @@ __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1]
   }
   __syncthreads();
   const int r = t & (NB - 1), s0 = t / NB;
-  for (int c = 0; c < NB; ++c) {
-    const double d = P[c][c].re;   // every thread reads the pivot
-    if (t == 0 && !(d > 0.0)) atomicOr(fail, 1);
-    // 1/sqrt(d): hardware reciprocal square root, two Newton steps
-    // r <- r (3 - d r^2) / 2 (each squares the relative error)
-    const double dd = fmax(d, 1e-300);
-    double rs = __builtin_amdgcn_rsq(dd);
-    rs = rs * (1.5 - 0.5 * dd * rs * rs);
-    rs = rs * (1.5 - 0.5 * dd * rs * rs);
-    if (t >= NB && t - NB <= c) Li[t - NB][c] = cscale(Li[t - NB][c], rs);   // row c of X
+  for (int c = 0; c < NB; c += 2) {
+    const double d0 = P[c][c].re;   // every thread reads the pivot block
+    const cd e = P[c][c + 1];
+    const double d1 = P[c + 1][c + 1].re;
+    const double rs0 = rsqrt_nr(d0);
+    const cd l = cscale(e, rs0);
+    const double d1r = d1 - cabs2(l);
+    if (t == 0 && !(d0 > 0.0 && d1r > 0.0)) atomicOr(fail, 1);
+    const double rs1 = rsqrt_nr(d1r);
+    if (t >= NB && t - NB <= c + 1) {   // rows c, c + 1 of X, column j
+      const int j = t - NB;
+      const cd xc = cscale(Li[j][c], rs0);
+      const cd y = Li[j][c + 1];
+      const cd lx = cmul(l, xc);
+      Li[j][c] = xc;
+      Li[j][c + 1] = cscale(csub(y, lx), rs1);
+    }
     __syncthreads();
-    if (r > c) {
-      const cd l = cscale(P[c][r], rs);   // L(r, c)
-      cd u[4], v[4];
+    if (r > c + 1) {
+      const cd a0 = cscale(P[c][r], rs0);                      // L(r, c)
+      const cd pa = P[c + 1][r], al = cmulc(a0, l);
+      const cd a1 = cscale(csub(pa, al), rs1);   // L(r, c + 1)
+      cd u0[4], u1[4], v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int sc = s0 + 8 * j;
-        u[j] = sc > c ? P[c][sc] : Li[sc][c];   // L(s, c) unscaled, or X(c, s)
-        v[j] = sc > c ? P[sc][r] : Li[sc][r];
+        const bool f = sc > c + 1;
+        u0[j] = f ? P[c][sc] : Li[sc][c];          // column c of P at s, or X(c, s)
+        u1[j] = f ? P[c + 1][sc] : Li[sc][c + 1];  // column c + 1 of P at s, or X(c + 1, s)
+        v[j] = f ? P[sc][r] : Li[sc][r];
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int sc = s0 + 8 * j;
-        if (sc > c) {
-          if (sc <= r) {   // P(r, s) -= L(r, c) conj(L(s, c))
-            const cd b = cscale(u[j], rs);
-            P[sc][r] = cd{v[j].re - (l.re * b.re + l.im * b.im), v[j].im - (l.im * b.re - l.re * b.im)};
+        if (sc > c + 1) {
+          if (sc <= r) {   // P(r, s) -= L(r, c) conj(L(s, c)) + L(r, c + 1) conj(L(s, c + 1))
+            const cd b0 = cscale(u0[j], rs0);
+            const cd bl = cmulc(b0, l);
+            const cd b1 = cscale(csub(u1[j], bl), rs1);
+            const cd p0 = cmulc(a0, b0), p1 = cmulc(a1, b1);
+            P[sc][r] = cd{v[j].re - p0.re - p1.re, v[j].im - p0.im - p1.im};
           }
-        } else {           // Y(r, s) -= L(r, c) X(c, s)
-          Li[sc][r] = cd{v[j].re - (l.re * u[j].re - l.im * u[j].im),
-                         v[j].im - (l.re * u[j].im + l.im * u[j].re)};
+        } else {           // Y(r, s) -= L(r, c) X(c, s) + L(r, c + 1) X(c + 1, s)
+          const cd p0 = cmul(a0, u0[j]), p1 = cmul(a1, u1[j]);
+          Li[sc][r] = cd{v[j].re - p0.re - p1.re, v[j].im - p0.im - p1.im};
         }
       }
     }
