@@ -31,7 +31,7 @@ typedef unsigned int u4v __attribute__((ext_vector_type(4)));   // (uint4 arrays
 
 constexpr int GT = 64;      // tile rows / columns (complex)
 constexpr int GKS = 64;     // columns per stage (k of one instruction)
-constexpr int GROW = 80;    // LDS bytes per staged row (64 + pad: no bank conflicts)
+constexpr int GROW = 64;    // LDS bytes per staged row (16-byte quarters swizzled, see swz)
 constexpr int GLD = 2 * GKS;  // digit-plane rows padded to an even number of stages
 
 inline int round_up_i(int x, int m) { return (x + m - 1) / m * m; }
@@ -149,6 +149,14 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
 }
 
 using Panel = int8_t[2][4][2][GT][GROW];   // [L/R][digit][re/im][row][bytes]
+// Quarter q of staged row `row` sits at 16 (q ^ swz(row)).  The 16 lanes
+// reading one operand block take rows 16 m + [0, 16) at one quarter, and the
+// lanes of a store take four consecutive rows: with unpadded 64-byte rows
+// both land on distinct banks (32 or 64 banks of 4 bytes).
+__device__ inline int swz(int row) {
+  const int r = row & 15;
+  return ((r >> 1) + (r >> 3)) & 3;
+}
 constexpr int NCLS = 5;                      // classes c = s + t = 0..4
 // Eight waves per work-group (two per SIMD, so one wave's LDS reads overlap
 // the other's matrix instructions): wave w owns rows 32 (w & 1) + [0, 32)
@@ -245,6 +253,7 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = 32 * (w & 1), wc = 16 * BB * (w >> 1);
   const int r16 = lane & 15, kq = lane >> 4;
+  const int kqs = kq ^ swz(r16);   // swizzled quarter of the lane's operand rows
   v4i re[NCLS][2][BB], im[NCLS][2][BB];
 #pragma unroll
   for (int c = 0; c < NCLS; ++c)
@@ -262,8 +271,8 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
   const int64_t plane = (int64_t)d.KMr * d.ldS;
   const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
   const int8_t* src = d.S + (int64_t)((side ? j0 : i0) + prow) * d.ldS + 16 * pq;
-  int8_t* dst0 = &sp[0][side][0][0][prow][16 * pq];
-  int8_t* dst1 = &sp[1][side][0][0][prow][16 * pq];
+  int8_t* dst0 = &sp[0][side][0][0][prow][16 * (pq ^ swz(prow))];
+  int8_t* dst1 = &sp[1][side][0][0][prow][16 * (pq ^ swz(prow))];
   constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
   // Stage s is staged in sp[s & 1]; its loads are issued one stage ahead (in
   // flight during the products of the stage before) and stored to LDS after
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
     for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0 + GKS);
   }
   for (int nb = n0; nb < n1; nb += 2 * GKS) {
-    kstep(sp[0], wr, wc, r16, kq, re, im);                      // stage nb
+    kstep(sp[0], wr, wc, r16, kqs, re, im);                      // stage nb
 #pragma unroll
     for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst1 + e * kPlaneLds) = pa[e];
     __syncthreads();
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
 #pragma unroll
       for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 2 * GKS);
     }
-    kstep(sp[1], wr, wc, r16, kq, re, im);                      // stage nb + GKS
+    kstep(sp[1], wr, wc, r16, kqs, re, im);                      // stage nb + GKS
     if (nb + 2 * GKS < n1) {
 #pragma unroll
       for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
