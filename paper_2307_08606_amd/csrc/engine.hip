@@ -885,21 +885,30 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
   }
   // ---- selectors and compaction
   std::vector<int> rebuild;
-  std::vector<int> Jh;
+  // host copies of the masks and index lists stay alive until the one stream
+  // synchronisation after the loop (the uploads are asynchronous)
+  std::vector<std::vector<uint8_t>> mh(Q);
+  std::vector<std::vector<int>> Jq(Q);
   for (int q = 0; q < Q; ++q) {
-    Jh.clear();
-    std::vector<uint8_t> m(N, 1);
+    std::vector<int>& Jh = Jq[q];
+    std::vector<uint8_t>& m = mh[q];
+    m.assign(N, 1);
     if (!h->mask0[q].empty()) m = h->mask0[q];
     if (!cnn_keep.empty())
       for (int n = 0; n < N; ++n) m[n] = m[n] && cnn_keep[n];
     for (int n = 0; n < N; ++n)
       if (m[n]) Jh.push_back(n);
     h->nq[q] = (int)Jh.size();
-    HIPCHK(h, hipMemcpyAsync(h->mask + (size_t)q * N, m.data(), N, hipMemcpyHostToDevice, s));
-    if (!Jh.empty())
-      HIPCHK(h, hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    TRY(compact_operator(h, q));
+    int rc = SADMM_OK;
+    hipError_t e = hipMemcpyAsync(h->mask + (size_t)q * N, m.data(), N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !Jh.empty())
+      e = hipMemcpyAsync(h->J[q], Jh.data(), sizeof(int) * Jh.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) rc = fail_msg(h, SADMM_E_HIP, "solve: mask upload: %s", hipGetErrorString(e));
+    if (rc == SADMM_OK) rc = compact_operator(h, q);
+    if (rc != SADMM_OK) {   // (uploads already queued read mh / Jq)
+      hipStreamSynchronize(s);
+      return rc;
+    }
     // (built in solve_prologue_finish).  At the start only when F is also
     // smaller than W (N_q < KM): the Woodbury factors of a solve are built in
     // one batch, the direct inverses one sensor at a time.
@@ -909,7 +918,8 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
       rebuild.push_back(q);
     h->facJ[q] = Jh;
   }
-  if (ystage) { hipStreamSynchronize(s); hipFree(ystage); }
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (ystage) hipFree(ystage);
   TRY(push_descs(h));
   HIPCHK(h, hipEventRecord(h->evf0, s));
   if (rebuild_out) {

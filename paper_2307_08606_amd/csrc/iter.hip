@@ -331,7 +331,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   using T = TS;                               // compute precision of the state
   using TA = typename DotAcc<ST, EPI>::type;  // accumulation precision
   constexpr int DC = dot_cols<ST>();
-  if ((EPI == EPI_W || EPI == EPI_XUPD) && a.ctl->halt) return;
+  if ((EPI == EPI_W || EPI == EPI_W1 || EPI == EPI_XUPD) && a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
   if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC || EPI == EPI_W1) && sd.direct) return;
   if ((EPI == EPI_W1 || EPI == EPI_WY1) && !sd.wtri) return;
