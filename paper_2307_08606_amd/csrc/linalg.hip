@@ -123,23 +123,23 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 // unstable on the strongly correlated Gram matrices of radar operators.)
 
 // Factor the diagonal block G[k0:k0+NB, k0:k0+NB] = Lkk Lkk^H in LDS and
-// form X = Lkk^{-1} alongside, two columns c, c + 1 per step.  Every thread
-// derives the 2 x 2 pivot block: L[c, c] = sqrt(P[c, c]), l = L[c + 1, c] =
-// P[c + 1, c] / L[c, c], L[c + 1, c + 1] = sqrt(P[c + 1, c + 1] - |l|^2).
-// Phase 1: thread NB + j turns rows c, c + 1 of Y (Y = I at the start) into
-// rows of X: X[c, j] = Y[c, j] / L[c, c], X[c + 1, j] = (Y[c + 1, j] -
-// l X[c, j]) / L[c + 1, c + 1].  Phase 2: thread (r, s0) owns the entries
-// (r, s0 + 8 j), j < 4, of both matrices, each either a factor entry (s > c
-// + 1: P[r, s] -= L[r, c] L[s, c]^* + L[r, c + 1] L[s, c + 1]^*) or an
-// inverse entry (s <= c + 1: Y[r, s] -= L[r, c] X[c, s] + L[r, c + 1]
-// X[c + 1, s]), for r > c + 1; columns c, c + 1 of L are formed on read
-// (L[r, c] = P[r, c] / L[c, c], L[r, c + 1] = (P[r, c + 1] - L[r, c] l^*) /
-// L[c + 1, c + 1]) and not stored.  No entry is written that another thread
-// reads in the same phase, so each thread's loads go out together.  Only Li
-// (Li[c][r] = element (r, c) of Y, then of X) is the result; P[c][r] starts
-// as element (r, c) of the block.
+// form X = Lkk^{-1} alongside, CW = 4 columns c .. c + 3 per step.  Every
+// thread derives the CW x CW pivot block l (Cholesky of P[c:c+4, c:c+4]) and
+// the reciprocal diagonal rs.  Phase 1: thread NB + j turns rows c .. c + 3
+// of Y (Y = I at the start) into rows of X by forward substitution with l:
+// X[c + m, j] = (Y[c + m, j] - sum_{k<m} l[m, k] X[c + k, j]) rs[m].
+// Phase 2: thread (r, s0) owns the entries (r, s0 + 8 j), j < 4, of both
+// matrices, each either a factor entry (s > c + 3: P[r, s] -= sum_m L[r,
+// c + m] L[s, c + m]^*) or an inverse entry (s <= c + 3: Y[r, s] -= sum_m
+// L[r, c + m] X[c + m, s]), for r > c + 3; the rows of L in the current
+// columns are formed on read by the same substitution (L[r, c + m] =
+// (P[r, c + m] - sum_{k<m} L[r, c + k] l[m, k]^*) rs[m]) and not stored.  No
+// entry is written that another thread reads in the same phase, so each
+// thread's loads go out together.  Only Li (Li[c][r] = element (r, c) of Y,
+// then of X) is the result; P[c][r] starts as element (r, c) of the block.
 constexpr int DIAG_THREADS = 256;
 constexpr int PANEL_ROWS = 64;   // panel rows per work-group
+constexpr int CW = 4;            // columns per step of the diagonal factor
 // 1 / sqrt(d): hardware reciprocal square root, two Newton steps
 // r <- r (3 - d r^2) / 2 (each squares the relative error)
 __device__ inline double rsqrt_nr(double d) {
@@ -149,10 +149,21 @@ __device__ inline double rsqrt_nr(double d) {
   return rs * (1.5 - 0.5 * dd * rs * rs);
 }
 __device__ inline cd cmulc(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }   // a conj(b)
+// Row of L in the step's columns from the updated entries v[m] = P[row, c + m].
+__device__ inline void step_row(const cd (&v)[CW], const cd (&l)[CW][CW], const double (&rs)[CW],
+                                cd (&a)[CW]) {
+#pragma unroll
+  for (int m = 0; m < CW; ++m) {
+    cd x = v[m];
+#pragma unroll
+    for (int k = 0; k < m; ++k) x = csub(x, cmulc(a[k], l[m][k]));
+    a[m] = cscale(x, rs[m]);
+  }
+}
 __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1], cd (*Li)[HPD_NB + 1],
                                    int* fail) {
   constexpr int NB = HPD_NB;
-  static_assert(DIAG_THREADS == 8 * NB && NB % 2 == 0, "thread (r, s0): r < NB, s0 < 8");
+  static_assert(DIAG_THREADS == 8 * NB && NB % CW == 0, "thread (r, s0): r < NB, s0 < 8");
   const int t = threadIdx.x;
   for (int e = t; e < NB * NB; e += DIAG_THREADS) {
     const int r = e % NB, c = e / NB;
@@ -161,51 +172,71 @@ __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1]
   }
   __syncthreads();
   const int r = t & (NB - 1), s0 = t / NB;
-  for (int c = 0; c < NB; c += 2) {
-    const double d0 = P[c][c].re;   // every thread reads the pivot block
-    const cd e = P[c][c + 1];
-    const double d1 = P[c + 1][c + 1].re;
-    const double rs0 = rsqrt_nr(d0);
-    const cd l = cscale(e, rs0);
-    const double d1r = d1 - cabs2(l);
-    if (t == 0 && !(d0 > 0.0 && d1r > 0.0)) atomicOr(fail, 1);
-    const double rs1 = rsqrt_nr(d1r);
-    if (t >= NB && t - NB <= c + 1) {   // rows c, c + 1 of X, column j
-      const int j = t - NB;
-      const cd xc = cscale(Li[j][c], rs0);
-      const cd y = Li[j][c + 1];
-      const cd lx = cmul(l, xc);
-      Li[j][c] = xc;
-      Li[j][c + 1] = cscale(csub(y, lx), rs1);
-    }
-    __syncthreads();
-    if (r > c + 1) {
-      const cd a0 = cscale(P[c][r], rs0);                      // L(r, c)
-      const cd pa = P[c + 1][r], al = cmulc(a0, l);
-      const cd a1 = cscale(csub(pa, al), rs1);   // L(r, c + 1)
-      cd u0[4], u1[4], v[4];
+  for (int c = 0; c < NB; c += CW) {
+    // pivot block: l[i][m] = L[c + i, c + m] (i > m), rs[m] = 1 / L[c + m, c + m]
+    cd l[CW][CW];
+    double rs[CW];
+    bool ok = true;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int sc = s0 + 8 * j;
-        const bool f = sc > c + 1;
-        u0[j] = f ? P[c][sc] : Li[sc][c];          // column c of P at s, or X(c, s)
-        u1[j] = f ? P[c + 1][sc] : Li[sc][c + 1];  // column c + 1 of P at s, or X(c + 1, s)
-        v[j] = f ? P[sc][r] : Li[sc][r];
+    for (int m = 0; m < CW; ++m) {
+      double d = P[c + m][c + m].re;
+#pragma unroll
+      for (int k = 0; k < m; ++k) d -= cabs2(l[m][k]);
+      ok = ok && d > 0.0;
+      rs[m] = rsqrt_nr(d);
+#pragma unroll
+      for (int i = m + 1; i < CW; ++i) {
+        cd x = P[c + m][c + i];
+#pragma unroll
+        for (int k = 0; k < m; ++k) x = csub(x, cmulc(l[i][k], l[m][k]));
+        l[i][m] = cscale(x, rs[m]);
+      }
+    }
+    if (t == 0 && !ok) atomicOr(fail, 1);
+    if (t >= NB && t - NB < c + CW) {   // rows c .. c + 3 of X, column j
+      const int j = t - NB;
+      cd x[CW];
+#pragma unroll
+      for (int m = 0; m < CW; ++m) {
+        cd y = Li[j][c + m];
+#pragma unroll
+        for (int k = 0; k < m; ++k) y = csub(y, cmul(l[m][k], x[k]));
+        x[m] = cscale(y, rs[m]);
       }
 #pragma unroll
+      for (int m = 0; m < CW; ++m) Li[j][c + m] = x[m];
+    }
+    __syncthreads();
+    if (r >= c + CW) {
+      cd v[CW], a[CW];
+#pragma unroll
+      for (int m = 0; m < CW; ++m) v[m] = P[c + m][r];
+      cd u[4][CW], w[4];
+#pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int sc = s0 + 8 * j;
-        if (sc > c + 1) {
-          if (sc <= r) {   // P(r, s) -= L(r, c) conj(L(s, c)) + L(r, c + 1) conj(L(s, c + 1))
-            const cd b0 = cscale(u0[j], rs0);
-            const cd bl = cmulc(b0, l);
-            const cd b1 = cscale(csub(u1[j], bl), rs1);
-            const cd p0 = cmulc(a0, b0), p1 = cmulc(a1, b1);
-            P[sc][r] = cd{v[j].re - p0.re - p1.re, v[j].im - p0.im - p1.im};
+        const bool f = sc >= c + CW;
+#pragma unroll
+        for (int m = 0; m < CW; ++m) u[j][m] = f ? P[c + m][sc] : Li[sc][c + m];   // P[s, c + m] or X[c + m, s]
+        w[j] = f ? P[sc][r] : Li[sc][r];
+      }
+      step_row(v, l, rs, a);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sc = s0 + 8 * j;
+        cd acc = w[j];
+        if (sc >= c + CW) {
+          if (sc <= r) {   // P(r, s) -= sum_m L(r, c + m) conj(L(s, c + m))
+            cd b[CW];
+            step_row(u[j], l, rs, b);
+#pragma unroll
+            for (int m = 0; m < CW; ++m) acc = csub(acc, cmulc(a[m], b[m]));
+            P[sc][r] = acc;
           }
-        } else {           // Y(r, s) -= L(r, c) X(c, s) + L(r, c + 1) X(c + 1, s)
-          const cd p0 = cmul(a0, u0[j]), p1 = cmul(a1, u1[j]);
-          Li[sc][r] = cd{v[j].re - p0.re - p1.re, v[j].im - p0.im - p1.im};
+        } else {           // Y(r, s) -= sum_m L(r, c + m) X(c + m, s)
+#pragma unroll
+          for (int m = 0; m < CW; ++m) acc = csub(acc, cmul(a[m], u[j][m]));
+          Li[sc][r] = acc;
         }
       }
     }
@@ -213,10 +244,10 @@ __device__ inline void diag_factor(const HpdDesc& h, int k0, cd (*P)[HPD_NB + 1]
   }
 }
 
-// One column step of the Cholesky: work-group 0 factors the diagonal block and
-// writes Lkk^{-1} to D[:, k0:k0+NB]; work-group b >= 1 factors it as well (the
-// same arithmetic, so the same result) and forms panel rows
-// [k0 + NB + 64 (b - 1), +64) of L21 = G21 Lkk^{-H} in place.  The diagonal
+// One column step of the Cholesky: every work-group b factors the diagonal
+// block (the same arithmetic, so the same result) and forms panel rows
+// [k0 + NB + 64 b, +64) of L21 = G21 Lkk^{-H} in place; work-group 0 also
+// writes Lkk^{-1} to D[:, k0:k0+NB].  The diagonal
 // block of G itself is only read (its factor lives in D; later steps use
 // only the blocks below the diagonal), so no work-group writes what another
 // may still be reading.
@@ -225,7 +256,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void chol_panel_kernel(const HpdDesc*
   const HpdDesc h = descs[blockIdx.y];
   constexpr int NB = HPD_NB;
   if (k0 >= h.n_pad) return;
-  const int r0 = k0 + NB + PANEL_ROWS * ((int)blockIdx.x - 1);
+  const int r0 = k0 + NB + PANEL_ROWS * (int)blockIdx.x;
   if (blockIdx.x > 0 && r0 >= h.n_pad) return;
   __shared__ cd P[NB][NB + 1];
   __shared__ cd Li[NB][NB + 1];
@@ -234,7 +265,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void chol_panel_kernel(const HpdDesc*
   // panel rows: thread (r, cg) moves columns cg + 4 e (issued before the
   // factorisation, stored after it)
   cd g[NB / 4];
-  const bool row_ok = blockIdx.x > 0 && r0 + r < h.n_pad;
+  const bool row_ok = r0 + r < h.n_pad;
 #pragma unroll
   for (int e = 0; e < NB / 4; ++e)
     g[e] = row_ok ? h.G[(int64_t)(k0 + cg + 4 * e) * h.n_pad + r0 + r] : cd{0.0, 0.0};
@@ -244,7 +275,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void chol_panel_kernel(const HpdDesc*
       const int rr = e % NB, c = e / NB;
       h.D[(int64_t)(k0 + c) * NB + rr] = Li[c][rr];
     }
-    return;
+    if (r0 >= h.n_pad) return;   // last diagonal block: no panel
   }
 #pragma unroll
   for (int e = 0; e < NB / 4; ++e) S[cg + 4 * e][r] = g[e];
@@ -848,7 +879,7 @@ void hpd_inverse_batched(const HpdDesc* hd, const HpdDesc* d_desc, int batch, in
     const MmDesc* p = d_mm + l.off;
     switch (l.kind) {
       case DIAG:
-        chol_panel_kernel<<<dim3(1 + (l.m + PANEL_ROWS - 1) / PANEL_ROWS, batch), DIAG_THREADS, 0, s>>>(
+        chol_panel_kernel<<<dim3(std::max(1, (l.m + PANEL_ROWS - 1) / PANEL_ROWS), batch), DIAG_THREADS, 0, s>>>(
             d_desc, l.k0, d_fail);
         break;
       case TRAIL: launch_zmm<OP_N, OP_C, KR_ALL, MM_LOWER>(p, l.count, l.m, l.n, s); break;
