@@ -24,8 +24,9 @@ struct GramI8Desc {
   int m;             // rows of Ahat (= order of the Gram), <= kmp
   int k;             // columns (active pixels)
   int KMr;           // m rounded up to 64: rows of the digit planes
-  int ldS;           // bytes per digit-plane row: k rounded up to 64
-  int8_t* S;         // 8 planes [digit s][re, im], each KMr x ldS bytes
+  int ldS;           // columns of the digit planes: k rounded up to 128
+  int8_t* S;         // 8 planes [digit s][re, im] of KMr x ldS bytes, stored in
+                     // 32 KB blocks per (64-row block, 64-column stage)
   unsigned long long* rmax;   // KMr: bits of the row's largest |Re| or |Im| (FP64)
   int* rs;           // [chunk][digit t][KMr]: sum over the chunk of imaginary digits
   cd* C;             // output, m x m, column-major, ld = ldc

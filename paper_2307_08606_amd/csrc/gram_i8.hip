@@ -36,6 +36,14 @@ constexpr int GLD = 2 * GKS;  // digit-plane rows padded to an even number of st
 
 inline int round_up_i(int x, int m) { return (x + m - 1) / m * m; }
 
+// Digit planes are stored stage-blocked: for row block rb (64 rows) and stage
+// st (64 columns), the 8 planes' 64 x 64-byte tiles lie in one contiguous
+// 32 KB block, so a work-group's stage of a panel is one contiguous read.
+constexpr int64_t kStageBlock = 8 * 64 * 64;
+__host__ __device__ inline int64_t stage_block(int rb, int st, int ldS) {
+  return ((int64_t)rb * (ldS / 64) + st) * kStageBlock;
+}
+
 // Zeroes rmax (when clear_rmax) and the per-chunk digit sums rs.
 __global__ void clear_kernel(const GramI8Desc* __restrict__ descs, int clear_rmax, int clear_rs) {
   const GramI8Desc d = descs[blockIdx.y];
@@ -137,14 +145,16 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
   }
   // write-out: per plane 64 rows x SL_COLS bytes as 16-byte pieces, eight
   // lanes per row
-  const int64_t plane = (int64_t)d.KMr * d.ldS;
   constexpr int PCS = SL_COLS / 16;   // pieces per row
   for (int e = threadIdx.x; e < 8 * 64 * PCS; e += 256) {
-    const int q = e / (64 * PCS), r = (e / PCS) & 63, c = e % PCS;
-    if (cb + 16 * c >= d.ldS) continue;
-    const uint32_t* w = &sd[q][r][4 * c];
-    *reinterpret_cast<uint4*>(d.S + q * plane + (int64_t)(blockIdx.y * 64 + r) * d.ldS + cb + 16 * c) =
-        make_uint4(w[0], w[1], w[2], w[3]);
+    // consecutive threads: the 4 pieces of a stage row, then rows, then
+    // planes, then stages: contiguous stores in the stage-blocked layout
+    const int c4 = e & 3, r = (e >> 2) & 63, q = (e >> 8) & 7, sg = e >> 11;
+    const int col = cb + 64 * sg + 16 * c4;
+    if (col >= d.ldS) continue;
+    const uint32_t* w = &sd[q][r][(64 * sg + 16 * c4) / 4];
+    *reinterpret_cast<uint4*>(d.S + stage_block(blockIdx.y, col / 64, d.ldS) + (int64_t)q * 4096 + r * 64 +
+                              16 * c4) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
@@ -268,9 +278,10 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
   // thread t moves row (t >> 2) & 63, quarter t & 3 of the eight planes
   // 8 (t >> 8) + e of the L/R x digit x re/im order (L for t < 256, R above).
   constexpr int PPT = 16 * 256 / GTHREADS;   // planes per thread
-  const int64_t plane = (int64_t)d.KMr * d.ldS;
+  constexpr int64_t plane = 4096;   // between the planes of a stage block
   const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
-  const int8_t* src = d.S + (int64_t)((side ? j0 : i0) + prow) * d.ldS + 16 * pq;
+  // stage n (columns n .. n + 63) of this thread's row: src + stage_block offset
+  const int8_t* src = d.S + stage_block(side ? tj : ti, 0, d.ldS) + prow * 64 + 16 * pq;
   int8_t* dst0 = &sp[0][side][0][0][prow][16 * (pq ^ swz(prow))];
   int8_t* dst1 = &sp[1][side][0][0][prow][16 * (pq ^ swz(prow))];
   constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
@@ -281,12 +292,12 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
   u4v pa[PPT];
   if (n0 < n1) {
 #pragma unroll
-    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0);
+    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS) * kStageBlock + e * plane);
 #pragma unroll
     for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + n0 + GKS);
+    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS + 1) * kStageBlock + e * plane);
   }
   for (int nb = n0; nb < n1; nb += 2 * GKS) {
     kstep(sp[0], wr, wc, r16, kqs, re, im);                      // stage nb
@@ -295,7 +306,7 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
     __syncthreads();
     if (nb + 2 * GKS < n1) {
 #pragma unroll
-      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 2 * GKS);
+      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 2) * kStageBlock + e * plane);
     }
     kstep(sp[1], wr, wc, r16, kqs, re, im);                      // stage nb + GKS
     if (nb + 2 * GKS < n1) {
@@ -305,7 +316,7 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
     __syncthreads();
     if (nb + 3 * GKS < n1) {
 #pragma unroll
-      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + e * plane + nb + 3 * GKS);
+      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 3) * kStageBlock + e * plane);
     }
   }
   // ---- epilogue: FP64 sum of the classes, lower triangle and its mirror
