@@ -76,15 +76,19 @@ __global__ __launch_bounds__(256) void rowmax_kernel(const GramI8Desc* __restric
   if (n1 > n0) atomicMax(&d.rmax[i], (unsigned long long)__double_as_longlong(mx));
 }
 
-// Digit planes.  Block: 64 rows x SL_COLS columns.  Thread (row = t & 63,
-// column group cg = t >> 6) reads SL_COLS / 4 consecutive columns of its row
-// (the lanes of a wave read 64 consecutive rows of one column: coalesced),
-// forms the digits in FP32 / int32 (the stored values have at most 24
-// significant bits, so the power-of-two scaling and the rounding to an
-// integer are exact) and packs them into LDS; the block then writes each
-// plane's tile with the lanes along the columns (whole 128-byte lines).  Rows
-// >= m and columns >= k get zero digits.
+// Digit planes.  Block: 64 rows x SL_SUB sub-tiles of SL_COLS columns, one
+// after the other.  Thread (row = t & 63, column group cg = t >> 6) reads
+// SL_COLS / 4 consecutive columns of its row per sub-tile (the lanes of a
+// wave read 64 consecutive rows of one column: coalesced), forms the digits in
+// FP32 / int32 (the stored values have at most 24 significant bits, so the
+// power-of-two scaling and the rounding to an integer are exact) and packs
+// them into LDS; the block then writes the sub-tile's stage blocks with
+// consecutive lanes on consecutive 16-byte pieces.  The per-row digit sums of
+// the block's columns go out with one atomic add per (row, digit).  Rows >= m
+// and columns >= k get zero digits.
 constexpr int SL_COLS = 128;
+constexpr int SL_SUB = 2;   // sub-tiles of SL_COLS columns per block (GI8_CHUNK is a multiple of their width)
+static_assert(GI8_CHUNK % (SL_COLS * SL_SUB) == 0, "a block's columns stay in one chunk");
 constexpr int SL_W = SL_COLS / 4 + 1;   // LDS words per tile row (+1: no bank conflicts)
 
 template <int ST>
@@ -92,8 +96,8 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
   const GramI8Desc d = descs[blockIdx.z];
   const int row = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int gi = blockIdx.y * 64 + row;
-  const int cb = blockIdx.x * SL_COLS;
-  if (blockIdx.y * 64 >= d.KMr || cb >= d.ldS) return;
+  const int cb0 = blockIdx.x * SL_COLS * SL_SUB;
+  if (blockIdx.y * 64 >= d.KMr || cb0 >= d.ldS) return;
   __shared__ uint32_t sd[8][64][SL_W];   // [2 digit + re/im][row][column word]
   __shared__ int red[4][4][64];          // [column group][digit][row]
   const double mx = gi < d.m ? __longlong_as_double((long long)d.rmax[gi]) : 0.0;
@@ -101,60 +105,66 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
   if (mx > 0.0) (void)frexp(mx, &E);
   int rsum[4] = {0, 0, 0, 0};
   constexpr int PER = SL_COLS / 4;       // columns per thread
+  for (int sub = 0; sub < SL_SUB; ++sub) {
+    const int cb = cb0 + sub * SL_COLS;
+    if (cb >= d.ldS) break;              // (uniform across the block)
+    if (sub > 0) __syncthreads();        // the previous sub-tile is written out
 #pragma unroll
-  for (int wd = 0; wd < PER / 4; ++wd) {   // one packed word (4 columns) per plane
-    uint32_t pk[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    for (int wd = 0; wd < PER / 4; ++wd) {   // one packed word (4 columns) per plane
+      uint32_t pk[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int gn = cb + PER * cg + 4 * wd + e;
-      float vv[2] = {0.f, 0.f};
-      if (gi < d.m && gn < d.k) {
-        const cd v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
-        vv[0] = (float)v.re;
-        vv[1] = (float)v.im;
+      for (int e = 0; e < 4; ++e) {
+        const int gn = cb + PER * cg + 4 * wd + e;
+        float vv[2] = {0.f, 0.f};
+        if (gi < d.m && gn < d.k) {
+          const cd v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
+          vv[0] = (float)v.re;
+          vv[1] = (float)v.im;
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          int x = (int)rintf(ldexpf(vv[p], 30 - E));   // |x| < 2^30
+          int dg[4];
+#pragma unroll
+          for (int t = 3; t >= 1; --t) {
+            const int lo = (int)(int8_t)(uint8_t)(x & 0xff);
+            dg[t] = lo;
+            x = (x - lo) >> 8;
+          }
+          dg[0] = x;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            pk[2 * t + p] |= ((uint32_t)(uint8_t)dg[t]) << (8 * e);
+            if (p == 1) rsum[t] += dg[t];
+          }
+        }
       }
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        int x = (int)rintf(ldexpf(vv[p], 30 - E));   // |x| < 2^30
-        int dg[4];
-#pragma unroll
-        for (int t = 3; t >= 1; --t) {
-          const int lo = (int)(int8_t)(uint8_t)(x & 0xff);
-          dg[t] = lo;
-          x = (x - lo) >> 8;
-        }
-        dg[0] = x;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          pk[2 * t + p] |= ((uint32_t)(uint8_t)dg[t]) << (8 * e);
-          if (p == 1) rsum[t] += dg[t];
-        }
-      }
+      for (int q = 0; q < 8; ++q) sd[q][row][(PER / 4) * cg + wd] = pk[q];
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sd[q][row][(PER / 4) * cg + wd] = pk[q];
+    __syncthreads();
+    // write-out: consecutive threads take the 4 pieces of a stage row, then
+    // rows, then planes, then stages: contiguous stores in the stage-blocked
+    // layout
+    constexpr int PCS = SL_COLS / 16;   // pieces per row
+    for (int e = threadIdx.x; e < 8 * 64 * PCS; e += 256) {
+      const int c4 = e & 3, r = (e >> 2) & 63, q = (e >> 8) & 7, sg = e >> 11;
+      const int col = cb + 64 * sg + 16 * c4;
+      if (col >= d.ldS) continue;
+      const uint32_t* w = &sd[q][r][(64 * sg + 16 * c4) / 4];
+      *reinterpret_cast<uint4*>(d.S + stage_block(blockIdx.y, col / 64, d.ldS) + (int64_t)q * 4096 + r * 64 +
+                                16 * c4) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
   }
+  // per-row digit sums of the block's columns (all in one chunk)
 #pragma unroll
   for (int t = 0; t < 4; ++t) red[cg][t][row] = rsum[t];
   __syncthreads();
   {
     const int t = threadIdx.x >> 6;   // thread (t, row) adds the four column groups
     const int v = red[0][t][row] + red[1][t][row] + red[2][t][row] + red[3][t][row];
-    const int chunk = cb / GI8_CHUNK;
+    const int chunk = cb0 / GI8_CHUNK;
     if (v != 0 && gi < d.KMr) atomicAdd(&d.rs[((int64_t)chunk * 4 + t) * d.KMr + gi], v);
-  }
-  // write-out: per plane 64 rows x SL_COLS bytes as 16-byte pieces, eight
-  // lanes per row
-  constexpr int PCS = SL_COLS / 16;   // pieces per row
-  for (int e = threadIdx.x; e < 8 * 64 * PCS; e += 256) {
-    // consecutive threads: the 4 pieces of a stage row, then rows, then
-    // planes, then stages: contiguous stores in the stage-blocked layout
-    const int c4 = e & 3, r = (e >> 2) & 63, q = (e >> 8) & 7, sg = e >> 11;
-    const int col = cb + 64 * sg + 16 * c4;
-    if (col >= d.ldS) continue;
-    const uint32_t* w = &sd[q][r][(64 * sg + 16 * c4) / 4];
-    *reinterpret_cast<uint4*>(d.S + stage_block(blockIdx.y, col / 64, d.ldS) + (int64_t)q * 4096 + r * 64 +
-                              16 * c4) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
@@ -384,7 +394,8 @@ void launch_prep(const GramI8Desc* d, int batch, int KMr, int ldS, int max_k, bo
     const int cy = std::max(1, std::min(64, max_k / 256));
     rowmax_kernel<ST><<<dim3((KMr + 255) / 256, cy, batch), 256, 0, s>>>(d);
   }
-  if (planes) slice_kernel<ST><<<dim3((ldS + SL_COLS - 1) / SL_COLS, KMr / 64, batch), 256, 0, s>>>(d);
+  if (planes)
+    slice_kernel<ST><<<dim3((ldS + SL_COLS * SL_SUB - 1) / (SL_COLS * SL_SUB), KMr / 64, batch), 256, 0, s>>>(d);
 }
 
 }  // namespace
