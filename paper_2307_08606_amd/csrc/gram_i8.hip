@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void rowmax_kernel(const GramI8Desc* __restric
 // the block's columns go out with one atomic add per (row, digit).  Rows >= m
 // and columns >= k get zero digits.
 constexpr int SL_COLS = 128;
-constexpr int SL_SUB = 2;   // sub-tiles of SL_COLS columns per block (GI8_CHUNK is a multiple of their width)
+constexpr int SL_SUB = 1;   // sub-tiles of SL_COLS columns per block (GI8_CHUNK is a multiple of their width)
 static_assert(GI8_CHUNK % (SL_COLS * SL_SUB) == 0, "a block's columns stay in one chunk");
 constexpr int SL_W = SL_COLS / 4 + 1;   // LDS words per tile row (+1: no bank conflicts)
 
