@@ -4,15 +4,17 @@ of the same stored operator, and against a CPU FP64 inverse of the exact
 stored values.
 
 Shapes exercise the edge cases of the integer path: KM = 96 rows (the last
-64-row tile half empty), N = 8464 pixels (two 8192-column chunks, the second
-ragged), a compacted operator after pruning.
+64-row tile half empty), N = 8464 pixels (two 8192-column chunks, the
+second ragged), N = 16900 (three chunks), a compacted operator after
+pruning.
 
 Tolerance.  The integer path rounds each entry to 30 bits below its row's
 largest magnitude and drops digit pairs of weight <= 2^-40; an exact CPU
-emulation of that arithmetic on this problem gives a Gram error of ~4e-12
-relative to its largest entry and a factor error of ~2e-9 (Frobenius,
-relative), the condition number of rho I + G being ~1.4e4.  The bar 1e-7
-leaves a factor 50; dropping the s + t = 4 pairs (error 9e-6) fails it.
+emulation of that arithmetic on the N = 8464 problem gives a Gram
+error of ~4e-12 relative to its largest entry and a factor error of ~2e-9
+(Frobenius, relative), the condition number of rho I + G being ~1.4e4.  The
+bar 1e-7 leaves a factor 50; dropping the s + t = 4 pairs (error 9e-6)
+fails it.
 """
 
 import numpy as np
@@ -94,3 +96,21 @@ def test_integer_gram_on_compacted_operator(gpu_lib, problem):
         Wref = np.linalg.inv(rho * np.eye(Aq.shape[0]) + Aq @ Aq.conj().T)
         assert _rel(Wd[q], Wref) <= 1e-10
         assert _rel(Wi[q], Wref) <= 1e-7
+
+
+@pytest.mark.parametrize("storage", ["fp32", "mf"])
+def test_integer_gram_three_chunks_matches_fp64_gram(gpu_lib, storage):
+    """N = 16900: the integer products run as three column chunks (the third
+    adds 516 columns).  Same 1e-7 bar against the FP64-Gram factor of the
+    same stored operator."""
+    g = make_geometry(2, 3, 32, 130)         # KM = 96, N = 16900
+    A = [steering(g, q).astype(np.complex64) for q in range(g.Q)]
+    rng = np.random.default_rng(6)
+    y = (rng.standard_normal((g.Q, g.K * g.M)) + 1j * rng.standard_normal((g.Q, g.K * g.M)))
+    y = y.astype(np.complex64)
+    Wi = _factors(gpu_lib, g, A, y, storage, "int8")
+    Wd = _factors(gpu_lib, g, A, y, storage, "fp64")
+    for q in range(g.Q):
+        err = _rel(Wi[q], Wd[q])
+        print(storage, q, f"{err:.3e}")
+        assert err <= 1e-7, (storage, q, err)
