@@ -36,8 +36,10 @@ these points; each reading is the one that makes eq. (3) a convergent method):
 * Residuals (the paper defers them to earlier work) follow Boyd Sec. 3.3.1
   on the replicated form: r = sqrt(Q) ||xbar - z||,
   s = beta ||Z^k - Z^{k-1}||_F with Z^k[q] = x_q^k + z^k - xbar^k (Z^0 = 0),
-  eps_pri = sqrt(QN) eps_abs + eps_rel max(||X||_F, sqrt(Q) ||z||),
-  eps_dual = sqrt(QN) eps_abs + eps_rel beta sqrt(Q) ||u||.
+  eps_pri = sqrt(QN) eps_abs + eps_rel max(||X||_F, ||Z^k||_F),
+  eps_dual = sqrt(QN) eps_abs + eps_rel beta sqrt(Q) ||u||  (Boyd eq. (3.12)
+  on the stacked vectors: Z^k is the replicated shared variable and every
+  sensor holds the same scaled dual u).
 * SSC (Alg. 1) runs per sensor on that sensor's iterates x_q over its active
   set J_q, with |.| the complex modulus.  zeta_q = (1/K_p) * sum of the K_p
   most recent |x_q^(i) - x_q^(i-1)| (x^(0) = 0 counts); no SSC before K_p
@@ -152,12 +154,14 @@ class _SensorSolve:
 
 
 def residual_norms(Xn, zn, un, xbn, X, z, xb, beta):
-    """r, s, ||X||_F, ||z||, ||u|| for one iteration (replicated-form residuals)."""
+    """r, s, ||X||_F, ||Z||_F, ||u|| for one iteration (replicated-form
+    residuals; Z[q] = x_q + z - xbar is sensor q's copy of the shared variable)."""
     Q = Xn.shape[0]
     r = np.sqrt(Q) * np.linalg.norm(xbn - zn)
-    dZ = (Xn + (zn - xbn)[None, :]) - (X + (z - xb)[None, :])
+    Zn = Xn + (zn - xbn)[None, :]
+    dZ = Zn - (X + (z - xb)[None, :])
     s = beta * np.linalg.norm(dZ)
-    return r, s, np.linalg.norm(Xn), np.linalg.norm(zn), np.linalg.norm(un)
+    return r, s, np.linalg.norm(Xn), np.linalg.norm(Zn), np.linalg.norm(un)
 
 
 def kkt_gradient(A: List[np.ndarray], y: np.ndarray, X: np.ndarray, u: np.ndarray,
@@ -234,8 +238,8 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
         xbn = Xn.mean(axis=0)
         zn = soft_threshold(xbn + u, tau)                 # eq. (3), row 2
         un = u + xbn - zn                                 # eq. (3), row 3
-        r, s, nX, nz, nu = residual_norms(Xn, zn, un, xbn, X, z, xb, beta)
-        eps_pri = sqQN * p.eps_abs + p.eps_rel * max(nX, np.sqrt(Q) * nz)
+        r, s, nX, nZ, nu = residual_norms(Xn, zn, un, xbn, X, z, xb, beta)
+        eps_pri = sqQN * p.eps_abs + p.eps_rel * max(nX, nZ)
         eps_dual = sqQN * p.eps_abs + p.eps_rel * beta * np.sqrt(Q) * nu
         # history of per-pixel changes over the active set (Alg. 1, step 1)
         slot = (k - 1) % D.shape[0]

@@ -564,17 +564,22 @@ __global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
     }
     const C2<T> un = csub(cadd(uo, xb), zn);
     const C2<T> dz = csub(csub(zn, xb), csub(zo, xbo));
-    double s2 = 0.0, nx2 = 0.0;
+    // replicated shared variable Z[q] = x_q + z - xbar: s from its change,
+    // its norm for the primal tolerance
+    const C2<T> zx = csub(zn, xb);
+    double s2 = 0.0, nx2 = 0.0, nz2 = 0.0;
     for (int q = 0; q < a.Q; ++q) {
       const int64_t o = (int64_t)q * a.N + n;
       const C2<T> d = cadd(ldc<T>(a.dX, o), dz);
+      const C2<T> xq = ldc<T>(a.X, o);
       s2 += (double)cabs2(d);
-      nx2 += (double)cabs2(ldc<T>(a.X, o));
+      nx2 += (double)cabs2(xq);
+      nz2 += (double)cabs2(cadd(xq, zx));
     }
     part[0] = (double)cabs2(csub(xb, zn));
     part[1] = s2;
     part[2] = nx2;
-    part[3] = (double)cabs2(zn);
+    part[3] = nz2;
     part[4] = (double)cabs2(un);
     if (a.xref) {
       const C2<T> r = ldc<T>(a.xref, n);
@@ -608,7 +613,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchView bv) {
   const double r = sqrt(Q) * sqrt(part[0]);
   const double s = a.beta * sqrt(part[1]);
   const double sqQN = sqrt(Q * (double)a.N);
-  const double eps_pri = sqQN * a.eps_abs + a.eps_rel * fmax(sqrt(part[2]), sqrt(Q) * sqrt(part[3]));
+  const double eps_pri = sqQN * a.eps_abs + a.eps_rel * fmax(sqrt(part[2]), sqrt(part[3]));
   const double eps_dual = sqQN * a.eps_abs + a.eps_rel * a.beta * sqrt(Q) * sqrt(part[4]);
   const double nmse = a.xref ? part[5] / a.xref_norm2 : 0.0;
   int halt = 0;

@@ -107,3 +107,68 @@ def lasso_admm_boyd(A, y, mu, beta, gamma, lam, iters, eps_abs, eps_rel):
         ed = np.sqrt(N) * eps_abs + eps_rel * np.linalg.norm(beta * u)
         out.append((z.copy(), r, s, ep, ed))
     return out
+
+
+def sharing_admm_replicated(A, y, mu, beta, gamma, lam, iters, eps_abs, eps_rel):
+    """Boyd et al. 2011 Sec. 7.3 sharing problem written in the general
+    two-block form of Sec. 3 with the shared variable replicated per sensor:
+
+        min sum_i f_i(x_i) + g(sum_i z_i)   s.t.  x_i - z_i = 0,
+        f_i(x) = mu/2||y_i - A_i x||^2 + gamma/2||x||^2,  g(s) = lam ||s||_1
+
+    (the l1 term on the sum of sub-images).  Every block keeps its own z_i and
+    u_i (Q copies, no averaging shortcut).  The x-step is a dense solve per
+    sensor; the z-step is the joint prox of lam||sum z_i||_1 over the stacked
+    z, solved per pixel in closed form (for a fixed sum s the stacked
+    minimiser is z_i = v_i + (s - V)/Q with V = sum_i v_i, and s itself is the
+    prox of lam Q/beta |.| at V).  Residuals and tolerances are Sec. 3.3.1's,
+    eq. (3.12), on the stacked vectors with A = I, B = -I, c = 0:
+    r = ||x - z||, s = beta ||z^k - z^{k-1}||, eps_pri = sqrt(p) eps_abs +
+    eps_rel max(||x||, ||z||), eps_dual = sqrt(n) eps_abs + eps_rel ||beta u||,
+    with p = n = Q N (complex entries).
+
+    Returns per iteration (x, zbar, r, s, eps_pri, eps_dual), zbar = mean_i z_i.
+    """
+    Q = len(A)
+    N = A[0].shape[1]
+    Ms = [mu * a.conj().T @ a + (gamma + beta) * np.eye(N) for a in A]
+    rhs0 = [mu * a.conj().T @ yy for a, yy in zip(A, y)]
+    x = np.zeros((Q, N), complex)
+    z = np.zeros((Q, N), complex)
+    u = np.zeros((Q, N), complex)
+    out = []
+    for _ in range(iters):
+        x = np.stack([np.linalg.solve(Ms[i], rhs0[i] + beta * (z[i] - u[i])) for i in range(Q)])
+        v = x + u
+        V = v.sum(axis=0)
+        t = lam * Q / beta
+        m = np.abs(V)
+        S = np.where(m > t, V * (1.0 - t / np.maximum(m, 1e-300)), 0.0)
+        zn = v + (S - V)[None, :] / Q
+        u = u + x - zn
+        r = np.linalg.norm((x - zn).ravel())
+        s = beta * np.linalg.norm((zn - z).ravel())
+        z = zn
+        dim = Q * N
+        ep = np.sqrt(dim) * eps_abs + eps_rel * max(np.linalg.norm(x.ravel()), np.linalg.norm(z.ravel()))
+        ed = np.sqrt(dim) * eps_abs + eps_rel * np.linalg.norm((beta * u).ravel())
+        out.append((x.copy(), z.mean(axis=0), r, s, ep, ed))
+    return out
+
+
+def misfit_gradient_fd(A, y, h=1e-3):
+    """Gradient of the data misfit f(x) = 1/2 ||y - A x||^2 at x = 0 by central
+    differences along the real and imaginary unit directions of each pixel
+    (exact up to rounding for a quadratic).  Returns the complex gradient
+    df/dRe(x_n) + i df/dIm(x_n), whose modulus is |a_n^H y|."""
+    N = A.shape[1]
+    g = np.zeros(N, complex)
+    f = lambda x: 0.5 * np.linalg.norm(y - A @ x) ** 2
+    for n in range(N):
+        e = np.zeros(N, complex)
+        e[n] = h
+        gr = (f(e) - f(-e)) / (2 * h)
+        e[n] = 1j * h
+        gi = (f(e) - f(-e)) / (2 * h)
+        g[n] = gr + 1j * gi
+    return g

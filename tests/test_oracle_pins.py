@@ -11,8 +11,9 @@ import pytest
 
 import oracle
 from oracle.sadmm import _SensorSolve
-from tests.pin_helpers import (cd_quadratic_l1, lasso_admm_boyd, prox_bruteforce,
-                               sharing_reduction, tiny_problem)
+from tests.pin_helpers import (cd_quadratic_l1, lasso_admm_boyd, misfit_gradient_fd,
+                               prox_bruteforce, sharing_admm_replicated, sharing_reduction,
+                               tiny_problem)
 
 
 # ---------------------------------------------------------------- z-update (eq. (3), row 2)
@@ -69,6 +70,58 @@ def test_single_sensor_equals_boyd_lasso_admm():
         assert R.history["s"][k] == pytest.approx(s, rel=1e-9, abs=1e-14)
         assert R.history["eps_pri"][k] == pytest.approx(ep, rel=1e-12)
         assert R.history["eps_dual"][k] == pytest.approx(ed, rel=1e-12)
+
+
+@pytest.mark.parametrize("Q,KM,N,seed", [(3, 8, 14, 3), (4, 6, 16, 4)])
+def test_multi_sensor_iterates_and_residuals_equal_replicated_form(Q, KM, N, seed):
+    """Q > 1: the oracle's iterates, residuals r and s, and tolerances eps_pri
+    and eps_dual equal those of the sharing problem run as general two-block
+    ADMM with the shared variable replicated per sensor (Boyd Sec. 7.3 set up
+    in the form of Sec. 3, residuals and eq. (3.12) on the stacked vectors).
+    Both tolerance terms are non-zero, so a missing sqrt(Q) in r, in eps_pri's
+    absolute term or in eps_dual, or sqrt(N) in place of sqrt(QN), all fail."""
+    A, y = tiny_problem(Q=Q, KM=KM, N=N, seed=seed)
+    mu, beta, gamma = 1.3, 0.7, 0.9
+    lam = 0.3 * oracle.lambda_max(A, y, mu, gamma)
+    eps_abs, eps_rel = 2e-3, 3e-2
+    p = oracle.Params(mu=mu, beta=beta, gamma=gamma, lam=lam, eps_abs=eps_abs, eps_rel=eps_rel,
+                      max_iter=30, stop=False)
+    R = oracle.solve(A, y, p, record_iterates=True)
+    ref = sharing_admm_replicated(A, y, mu, beta, gamma, lam, 30, eps_abs, eps_rel)
+    nz = 0
+    for k in range(30):
+        x, zb, r, s, ep, ed = ref[k]
+        assert np.allclose(R.history["X"][k], x, rtol=0, atol=1e-12)
+        assert np.allclose(R.history["z"][k], zb, rtol=0, atol=1e-12)
+        assert R.history["r"][k] == pytest.approx(r, rel=1e-9, abs=1e-14)
+        assert R.history["s"][k] == pytest.approx(s, rel=1e-9, abs=1e-14)
+        assert R.history["eps_pri"][k] == pytest.approx(ep, rel=1e-12)
+        assert R.history["eps_dual"][k] == pytest.approx(ed, rel=1e-12)
+        nz += np.count_nonzero(zb)
+        # |u_j| <= lam/beta after every z-update, so |z_j| <= |xbar_j| and
+        # ||Z||_F <= ||X||_F: the tolerance's max is always ||X||_F
+        Xk = R.history["X"][k]
+        assert R.history["eps_pri"][k] == pytest.approx(
+            np.sqrt(Q * N) * eps_abs + eps_rel * np.linalg.norm(Xk), rel=1e-12)
+        assert np.all(np.abs(R.history["u"][k]) <= lam / beta * (1 + 1e-12))
+    assert nz > 0                                   # the l1 term is active
+
+
+def test_matched_filter_is_misfit_gradient_modulus():
+    """The matched filter |A_q^H y_q| is the modulus of the gradient of
+    1/2||y_q - A_q x||^2 at x = 0 (central differences, exact for a
+    quadratic), and equals a scalar double loop over rows and pixels."""
+    A, y = tiny_problem(Q=3, KM=7, N=9, seed=8)
+    mf = oracle.matched_filter(A, y)
+    assert mf.shape == (3, 9)
+    for q in range(3):
+        g = misfit_gradient_fd(A[q], y[q])
+        assert np.allclose(mf[q], np.abs(g), rtol=1e-9, atol=1e-12)
+        for n in range(9):
+            acc = 0j
+            for i in range(7):
+                acc += A[q][i, n].conjugate() * y[q][i]
+            assert mf[q, n] == pytest.approx(abs(acc), rel=1e-13)
 
 
 def test_single_sensor_optimum_equals_coordinate_descent():
