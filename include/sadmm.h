@@ -87,7 +87,11 @@ typedef struct {
   double eps_p;               /* SSC tolerance on the mean |change| */
   int32_t prune_mode;         /* 0: freeze eliminated pixels; 1: zero them */
   int32_t kkt;                /* 1: after convergence, re-check eliminated pixels
-                                 against the optimality condition and reinstate */
+                                 against the optimality condition and reinstate
+                                 (when prune = 1, or when the solve started with
+                                 eliminated pixels: caller mask or CNN); at most 8
+                                 rounds, after which remaining violations end the
+                                 solve with status 3 */
   double kkt_tol;             /* reinstate when |g| > kkt_tol * lambda */
   int32_t storage;            /* sadmm_storage */
   int32_t reuse_factor;       /* 1: a later solve reuses a factor built for the same
@@ -105,19 +109,25 @@ typedef struct {
                                  (mu Ahat^H Ahat + cI)^{-1} of order N_q, 1 keeps the
                                  Woodbury form (Sec. III solves the N_q system) */
   int32_t refine_every;       /* FP16P / BF16P storage only, operator set from the
-                                 geometry: every refine_every iterations (at the next
-                                 status read) and at convergence, the correction
-                                 g = mu (A^H (y - A x) - Ahat^H (y' - Ahat x)) of the
-                                 stored operator Ahat toward the accurate A (FP32
-                                 entries regenerated as in MATRIX_FREE) enters the
-                                 x-update, whose fixed point becomes that of A.
-                                 0 (default): off */
+                                 geometry: every refine_every iterations (a batch:
+                                 at the first status read at or after that) the
+                                 correction g = mu (A^H (y - A x) - Ahat^H (y' - Ahat x))
+                                 of the stored operator Ahat toward the accurate A
+                                 (FP32 entries regenerated as in MATRIX_FREE) enters
+                                 the x-update, whose fixed point becomes that of A.
+                                 When the stop test passes on a correction taken at
+                                 an earlier x, g is retaken at the converged x and
+                                 the solve stops only if |g_new - g_old| / (beta +
+                                 gamma) <= eps_pri (the bound on the x-update's
+                                 change), else it iterates on.  0 (default): off */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 
 typedef struct {
   int32_t iters;              /* iterations run */
-  int32_t status;             /* 0 converged, 1 max_iter reached, 2 NMSE target reached */
+  int32_t status;             /* 0 converged, 1 max_iter reached, 2 NMSE target reached,
+                                 3 converged on the restricted problem but the
+                                 optimality re-check's round cap left violations */
   int32_t prune_events;       /* iterations at which SSC removed pixels */
   int32_t reinstated;         /* pixels put back by the optimality re-check */
   int32_t refactors;          /* full factor rebuilds after the start (Woodbury factor
@@ -288,7 +298,9 @@ const char* sadmm_cnn_last_error(sadmm_cnn_t c);
  * sensor, before the factor build, the pixels whose probability is >=
  * threshold (combined with any mask set by sadmm_set_active_mask).  The CNN's
  * image size must be N pixels and its input channels Q; it must use the
- * solver's stream.  Eliminated pixels are frozen at x = 0. */
+ * solver's stream.  Eliminated pixels are frozen at x = 0.  The solver must
+ * have kkt = 1 (else SADMM_E_ARG): the optimality re-check judges every
+ * learned elimination after convergence and reinstates false ones. */
 int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold);
 
 /* Kernel classes timed when profiling is on. */

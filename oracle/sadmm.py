@@ -60,7 +60,11 @@ g_q = mu A_q^H (A_q x_q - y_q) + gamma x_q + beta u = 0 for every q and pixel.
 With `kkt=True`, after convergence every eliminated pixel with
 |g_qj| > kkt_tol * lambda is put back into J_q (its measurement contribution is
 removed from y'_q again, its history window is set to +inf so it cannot be
-eliminated for K_p iterations) and iterating resumes.
+eliminated for K_p iterations) and iterating resumes.  The re-check judges
+SSC's eliminations (prune=True) and an initial selector that already
+eliminates pixels (mask0).  After kkt_rounds reinstating rounds the next
+convergence is only checked: remaining violations leave converged=False and
+their count in kkt_violations.
 
 Each x-update is solved directly from its definition: a Cholesky factor of
 mu Ahat^H Ahat + c I when N_q <= KM, otherwise the same solve through the
@@ -107,6 +111,7 @@ class Result:
     prune_events: int
     reinstated: int
     history: dict = field(default_factory=dict)
+    kkt_violations: int = 0    # violations left when the reinstatement round cap ended it
 
     def active_indices(self, q: int) -> np.ndarray:
         return np.flatnonzero(self.active[q])
@@ -200,6 +205,7 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
     u = np.zeros(N, dtype=np.complex128)
     xb = np.zeros(N, dtype=np.complex128)
     active = np.ones((Q, N), dtype=bool) if mask0 is None else np.array(mask0, dtype=bool)
+    start_restricted = not active.all()
     yp = y.copy()                                   # y'_q: measurement minus frozen pixels
     D = np.zeros((max(p.Kp, 1), Q, N))              # ring of |x^(i) - x^(i-1)|
 
@@ -222,6 +228,7 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
     prune_events = 0
     reinstated = 0
     kkt_rounds = 0
+    violations = 0
     converged = False
     k = 0
     sqQN = np.sqrt(Q * N)
@@ -286,28 +293,39 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
             hist["u"].append(u.copy())
             hist["masks"].append(active.copy())
         if done:
-            if p.kkt and p.prune and kkt_rounds < p.kkt_rounds and (~active).any():
-                kkt_rounds += 1
-                back = _reinstate(A, y, X, u, p, active, yp, D)
-                if back:
-                    reinstated += back
-                    for q in range(Q):
-                        setup(q)
-                    continue
+            if p.kkt and (p.prune or start_restricted) and (~active).any():
+                if kkt_rounds >= p.kkt_rounds:
+                    left = _reinstate(A, y, X, u, p, active, yp, D, check_only=True)
+                    if left:
+                        violations = left
+                        break
+                else:
+                    kkt_rounds += 1
+                    back = _reinstate(A, y, X, u, p, active, yp, D)
+                    if back:
+                        reinstated += back
+                        for q in range(Q):
+                            setup(q)
+                        continue
             converged = True
             break
     return Result(z=z, X=X, u=u, active=active, iters=k, converged=converged,
-                  prune_events=prune_events, reinstated=reinstated, history=hist)
+                  prune_events=prune_events, reinstated=reinstated, history=hist,
+                  kkt_violations=violations)
 
 
-def _reinstate(A, y, X, u, p, active, yp, D) -> int:
-    """Put eliminated pixels that violate the optimality condition back."""
+def _reinstate(A, y, X, u, p, active, yp, D, check_only=False) -> int:
+    """Put eliminated pixels that violate the optimality condition back
+    (only count them when check_only)."""
     g = kkt_gradient(A, y, X, u, p)
     thr = p.kkt_tol * (p.lam if p.lam > 0 else 1.0)
     back = 0
     for q in range(len(A)):
         bad = np.flatnonzero((~active[q]) & (np.abs(g[q]) > thr))
         if bad.size == 0:
+            continue
+        if check_only:
+            back += bad.size
             continue
         if p.mode == "freeze":
             yp[q] = yp[q] + A[q][:, bad] @ X[q, bad]

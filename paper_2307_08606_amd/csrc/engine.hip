@@ -90,6 +90,7 @@ struct sadmm_s {
   std::vector<double*> rec;      // per sensor: phase records of the geometry, or null
   SensorDesc* sens_mf_d = nullptr;   // sensor table viewing rec as a matrix-free operator
   double *gfix = nullptr, *re1 = nullptr, *re2 = nullptr, *rw = nullptr;
+  double *gprev = nullptr, *dg = nullptr;   // previous correction, |g - gprev|^2
   void *g32 = nullptr, *xfix = nullptr;
   int k_refined = 0;             // iteration of the last correction
   // W not formed after a build (W64 holds U = X^H, hpdX holds X = L^{-1})
@@ -134,6 +135,8 @@ struct sadmm_s {
   std::vector<std::pair<int, double>> frac_pts;   // (iteration, max active fraction from it on)
   int kkt_rounds = 0, status = 1;
   bool done = false;
+  bool start_restricted = false;   // the solve started with eliminated pixels
+  double last_dg = 0.0;            // |g_new - g_old| of the last convergence check
 
   // optional per-kernel-class event timing (sadmm_set_profiling)
   bool prof = false;
@@ -724,9 +727,9 @@ int apply_prune(sadmm_t h) {
   return SADMM_OK;
 }
 
-// Optimality re-check of eliminated pixels after convergence; returns the
-// number of pixels reinstated (negative on error).
-int kkt_reinstate(sadmm_t h, int* n_back) {
+// Optimality re-check of eliminated pixels after convergence; *n_back = the
+// number of violating pixels, which are reinstated unless check_only.
+int kkt_reinstate(sadmm_t h, int* n_back, bool check_only = false) {
   *n_back = 0;
   const double thr = h->p.kkt_tol * (h->p.lambda > 0 ? h->p.lambda : 1.0);
   for (int q = 0; q < h->Q; ++q) {
@@ -745,6 +748,7 @@ int kkt_reinstate(sadmm_t h, int* n_back) {
     TRY(read_counts(h));
     const int r = h->counts_h[0];
     if (r == 0) continue;
+    if (check_only) { *n_back += r; continue; }
     if (h->p.prune_mode == 0)
       launch_gather_fwd(a, h->st, h->dbl, q, h->lst2, r, 1.0, h->yp + 2 * (size_t)q * h->KMp, h->gtmp, h->s);
     set_bytes_at(h->mask + (size_t)q * h->N, h->lst2, r, 1, h->s);
@@ -815,6 +819,8 @@ int refine_setup(sadmm_t h) {
   };
   TRY(grab((void**)&h->sens_mf_d, sizeof(SensorDesc) * h->Q));
   TRY(grab((void**)&h->gfix, 16 * QN));
+  TRY(grab((void**)&h->gprev, 16 * QN));
+  TRY(grab((void**)&h->dg, sizeof(double)));
   TRY(grab(&h->g32, h->csz * QN));
   TRY(grab(&h->xfix, h->csz * QN));
   TRY(grab((void**)&h->re1, 16 * (size_t)h->Q * h->KMp));
@@ -885,6 +891,7 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
   }
   // ---- selectors and compaction
   std::vector<int> rebuild;
+  h->start_restricted = false;
   // host copies of the masks and index lists stay alive until the one stream
   // synchronisation after the loop (the uploads are asynchronous)
   std::vector<std::vector<uint8_t>> mh(Q);
@@ -899,6 +906,7 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
     for (int n = 0; n < N; ++n)
       if (m[n]) Jh.push_back(n);
     h->nq[q] = (int)Jh.size();
+    if (h->nq[q] < N) h->start_restricted = true;
     int rc = SADMM_OK;
     hipError_t e = hipMemcpyAsync(h->mask + (size_t)q * N, m.data(), N, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !Jh.empty())
@@ -1028,39 +1036,59 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
   const int hb = c.halt & ~HALT_PRUNE;
   if (hb & HALT_NMSE) { h->status = 2; h->done = true; return SADMM_OK; }
   if (hb & HALT_CONV) {
-    if (h->p.kkt && h->p.prune && h->kkt_rounds < KKT_ROUNDS) {
-      bool any_frozen = false;
-      for (int q = 0; q < h->Q; ++q) any_frozen = any_frozen || h->nq[q] < h->N;
-      if (any_frozen) {
-        ++h->kkt_rounds;
-        int back = 0;
-        HIPCHK(h, hipEventRecord(h->evf0, s));
-        TRY(kkt_reinstate(h, &back));
-        HIPCHK(h, hipEventRecord(h->evf1, s));
-        HIPCHK(h, hipEventSynchronize(h->evf1));
-        hipEventElapsedTime(&fms, h->evf0, h->evf1);
-        h->t_factor += fms;
-        if (back > 0) {
-          if (h->p.refine_every > 0) TRY(refine(h, c.k));
-          h->info.reinstated += back;
-          h->frac_pts.push_back({c.k + 1, max_active_frac(h)});
-          if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
-          *h->halt_h = 0;
-          HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
-          HIPCHK(h, hipStreamSynchronize(s));
-          *active = true;
-          return SADMM_OK;
-        }
+    bool any_frozen = false;
+    for (int q = 0; q < h->Q; ++q) any_frozen = any_frozen || h->nq[q] < h->N;
+    // the re-check judges every elimination: SSC's, and the selector the
+    // solve started from (caller mask or CNN)
+    const bool judge = h->p.kkt && (h->p.prune || h->start_restricted) && any_frozen;
+    if (judge && h->kkt_rounds >= KKT_ROUNDS) {
+      // round cap reached: certify without reinstating
+      int bad = 0;
+      TRY(kkt_reinstate(h, &bad, true));
+      if (bad > 0) { h->status = 3; h->done = true; return SADMM_OK; }
+    }
+    if (judge && h->kkt_rounds < KKT_ROUNDS) {
+      ++h->kkt_rounds;
+      int back = 0;
+      HIPCHK(h, hipEventRecord(h->evf0, s));
+      TRY(kkt_reinstate(h, &back));
+      HIPCHK(h, hipEventRecord(h->evf1, s));
+      HIPCHK(h, hipEventSynchronize(h->evf1));
+      hipEventElapsedTime(&fms, h->evf0, h->evf1);
+      h->t_factor += fms;
+      if (back > 0) {
+        if (h->p.refine_every > 0) TRY(refine(h, c.k));
+        h->info.reinstated += back;
+        h->frac_pts.push_back({c.k + 1, max_active_frac(h)});
+        if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
+        *h->halt_h = 0;
+        HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        *active = true;
+        return SADMM_OK;
       }
     }
-    if (h->p.refine_every > 0 && c.k < h->p.max_iter && c.k - h->k_refined >= h->p.refine_every) {
-      // converged on a correction older than the interval: refresh it and go on
+    if (h->p.refine_every > 0 && h->k_refined != c.k) {
+      // The correction in use was taken at an earlier x.  Retake it at the
+      // converged x; the solve stops only if the x-update moves by at most
+      // the primal tolerance under the new one (|dx| <= |dg| / c, since
+      // (mu Ahat^H Ahat + cI)^{-1} has norm <= 1/c), else it goes on.
+      if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
+      const size_t QN = (size_t)h->Q * h->N;
+      HIPCHK(h, hipMemcpyAsync(h->gprev, h->gfix, 16 * QN, hipMemcpyDeviceToDevice, s));
       TRY(refine(h, c.k));
-      *h->halt_h = 0;
-      HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+      diff_norm2_c128(h->gfix, h->gprev, (int64_t)QN, h->dg, s);
+      double dg2 = 0.0;
+      HIPCHK(h, hipMemcpyAsync(&dg2, h->dg, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(h, hipStreamSynchronize(s));
-      *active = true;
-      return SADMM_OK;
+      h->last_dg = std::sqrt(dg2);
+      if (!(h->last_dg / (h->p.beta + h->p.gamma) <= c.eps_pri)) {
+        *h->halt_h = 0;
+        HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        *active = true;
+        return SADMM_OK;
+      }
     }
     h->status = 0;
     h->done = true;
@@ -1136,7 +1164,12 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
   const int check = h0->p.check_every;
   int rc = SADMM_OK;
   for (;;) {
-    for (int i = 0; i < check; ++i) {
+    // a single scene reads its status exactly where a correction is due
+    // (a batch corrects at the first status read at or after it)
+    int nq_iter = check;
+    if (single && h0->p.refine_every > 0)
+      nq_iter = std::max(1, std::min(check, h0->k_refined + h0->p.refine_every - h0->ctl_h->k));
+    for (int i = 0; i < nq_iter; ++i) {
       if (ge) {
         if (hipGraphLaunch(ge, gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "graph launch failed"); break; }
       } else if (staged) {
@@ -1799,6 +1832,8 @@ int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold) {
   if (cq != h->Q || (int64_t)ch * cw != h->N)
     return fail_msg(h, SADMM_E_SHAPE, "set_pruning_cnn: CNN shape does not match Q x N");
   if (!(threshold > 0.0 && threshold <= 1.0)) return fail_msg(h, SADMM_E_ARG, "set_pruning_cnn: threshold");
+  if (!h->p.kkt)
+    return fail_msg(h, SADMM_E_ARG, "set_pruning_cnn: learned eliminations need the KKT re-check (kkt = 1)");
   h->cnn = cnn;
   h->cnn_thr = threshold;
   return SADMM_OK;
@@ -1857,7 +1892,7 @@ void sadmm_destroy(sadmm_t h) {
   for (unsigned long long* p : h->rmaxc)
     if (p) hipFree(p);
   for (void* p : {(void*)h->sens_mf_d, (void*)h->gfix, h->g32, h->xfix, (void*)h->re1, (void*)h->re2,
-                  (void*)h->rw})
+                  (void*)h->rw, (void*)h->gprev, (void*)h->dg})
     if (p) hipFree(p);
   if (h->ctl_h) hipHostFree(h->ctl_h);
   if (h->counts_h) hipHostFree(h->counts_h);

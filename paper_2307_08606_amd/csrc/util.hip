@@ -231,9 +231,33 @@ __global__ void load_meas_kernel(const void* src, int c128, int KM, int KMp, dou
   dst[2 * ((int64_t)q * KMp + i) + 1] = im;
 }
 
+// out[0] = sum_i |a_i - b_i|^2 over n complex128 entries; one work-group of
+// 1024 threads, fixed reduction order.
+__global__ __launch_bounds__(1024) void diff_norm2_kernel(const double* a, const double* b, int64_t n,
+                                                          double* out) {
+  __shared__ double sm[16];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double dr = a[2 * i] - b[2 * i], di = a[2 * i + 1] - b[2 * i + 1];
+    acc += dr * dr + di * di;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += sm[w];
+    out[0] = t;
+  }
+}
+
 inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
+
+void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
+  diff_norm2_kernel<<<1, 1024, 0, s>>>(a, b, n, out);
+}
 
 void convert_operator(const void* src, bool src_c128, int64_t src_ld, int KM, int N, int st,
                       void* dst, int64_t ldA, int KMp, hipStream_t s) {

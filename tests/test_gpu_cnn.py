@@ -102,7 +102,7 @@ def test_solver_uses_cnn_selector(gpu_lib):
     mf = oracle.matched_filter(A, sc.y).reshape(3, 16, 16)
     prob = c.forward(ocnn.normalize_input(mf)).reshape(-1)
     thr = float(np.quantile(prob, 0.4))
-    s = gpu_lib.Solver(3, 32, 4, g.N, storage="fp64", lam=lam, max_iter=40, stop=False)
+    s = gpu_lib.Solver(3, 32, 4, g.N, storage="fp64", lam=lam, max_iter=40, stop=False, kkt=True)
     for q in range(3):
         s.set_operator(q, A[q])
     s.set_pruning_cnn(c, thr)
@@ -116,3 +116,52 @@ def test_solver_uses_cnn_selector(gpu_lib):
     ref = oracle.solve(A, sc.y, oracle.Params(lam=lam, max_iter=40, stop=False), mask0=masks)
     z = s.image()
     assert np.linalg.norm(z - ref.z) <= 1e-8 * np.linalg.norm(ref.z)
+
+
+def test_cnn_needs_the_optimality_recheck(gpu_lib):
+    """A learned selector is refused on a solver without the KKT re-check."""
+    c = gpu_lib.Cnn(3, 8, 16, 16)
+    c.set_params(ocnn.init_params(3, 8, seed=9))
+    s = gpu_lib.Solver(3, 32, 4, 256, storage="fp64", lam=0.1, kkt=False)
+    with pytest.raises(gpu_lib.SadmmError):
+        s.set_pruning_cnn(c, 0.5)
+
+
+def test_cnn_false_prune_is_reinstated(gpu_lib):
+    """The CNN removes 60% of the pixels (support included) before the factor
+    build with SSC off; at convergence the optimality re-check reinstates the
+    false prunes, exactly as the oracle does from the same initial selector
+    (FP64: same reinstated count, final selectors bit-exact), and the image
+    reaches the full problem's optimum."""
+    g = make_geometry(3, 4, 32, 16)
+    sc = make_scene(g, 3, 5, 20.0)
+    A = [steering(g, q) for q in range(3)]
+    lam = 0.2 * oracle.lambda_max(A, sc.y, 1.0, 1.0)
+    c = gpu_lib.Cnn(3, 8, 16, 16)
+    c.set_params(ocnn.init_params(3, 8, seed=9))
+    mf = oracle.matched_filter(A, sc.y).reshape(3, 16, 16)
+    prob = c.forward(ocnn.normalize_input(mf)).reshape(-1)
+    srt = np.sort(prob)
+    k = int(0.4 * prob.size)
+    while srt[k + 1] - srt[k] < 1e-5:       # a threshold no probability sits near
+        k += 1
+    thr = float(0.5 * (srt[k] + srt[k + 1]))
+    keep = prob < thr
+    kw = dict(lam=lam, max_iter=3000, eps_rel=1e-6, kkt=True)
+    plain = oracle.solve(A, sc.y, oracle.Params(**kw))
+    supp = np.flatnonzero(np.abs(plain.z) > 0)
+    assert (~keep[supp]).any(), "no support pixel among the learned eliminations"
+    s = gpu_lib.Solver(3, 32, 4, g.N, storage="fp64", **kw)
+    for q in range(3):
+        s.set_operator(q, A[q])
+    s.set_pruning_cnn(c, thr)
+    info = s.solve(sc.y)
+    ref = oracle.solve(A, sc.y, oracle.Params(**kw), mask0=np.tile(keep, (3, 1)))
+    print(info, ref.iters, ref.reinstated)
+    assert info["status"] == 0 and ref.converged
+    assert info["reinstated"] == ref.reinstated > 0
+    for q in range(3):
+        assert np.array_equal(s.active_mask(q).astype(bool), ref.active[q])
+    z = s.image()
+    assert np.linalg.norm(z - ref.z) <= 1e-8 * np.linalg.norm(ref.z)
+    assert np.linalg.norm(z - plain.z) ** 2 <= 1e-6 * np.linalg.norm(plain.z) ** 2

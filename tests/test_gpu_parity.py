@@ -217,6 +217,22 @@ def test_refinement_of_half_precision_storage(gpu_lib, storage):
     assert err[10] <= 1e-2 * err[0]
 
 
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_refinement_stop_rule(gpu_lib, storage):
+    """A corrected 16-bit solve run with the stop test (eps_rel = 1e-4) stops
+    only once the correction retaken at the converged x no longer moves the
+    x-update beyond the primal tolerance, so its image meets the FP32 bar
+    against the FP64 optimum (the oracle itself stops at NMSE ~4e-9 there)."""
+    g, sc, A, hp = problem(seed=19)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
+    s = geometry_solver(gpu_lib, g, storage, hp, refine_every=10, max_iter=400, eps_rel=1e-4)
+    info = s.solve(sc.y)
+    err = nmse(s.image(), ref.z)
+    print(storage, info["iters"], info["status"], err)
+    assert info["status"] == 0
+    assert err <= 1e-6
+
+
 def test_refinement_with_pruning(gpu_lib):
     """Correction on a pruned BF16 solve run to convergence (SSC elimination
     with low-rank factor updates, a last correction at convergence): image

@@ -121,3 +121,35 @@ def test_kkt_reinstates_a_forced_false_prune(radar_small):
     assert np.all(fix.z[supp[:3]] != 0)
     nmse = np.linalg.norm(fix.z - plain.z) ** 2 / np.linalg.norm(plain.z) ** 2
     assert nmse < 1e-6
+
+
+def test_kkt_judges_initial_selector_without_ssc(radar_small):
+    """An initial selector that eliminates support pixels is re-checked even
+    with SSC off (prune=False): the violations are reinstated and the optimum
+    of the full problem is reached."""
+    A, sc, base = radar_small
+    b = {**base, "eps_rel": 1e-6}
+    plain = oracle.solve(A, sc.y, oracle.Params(max_iter=5000, **b))
+    supp = np.flatnonzero(np.abs(plain.z) > 0)
+    mask0 = np.ones((len(A), A[0].shape[1]), bool)
+    mask0[:, supp[:3]] = False
+    fix = oracle.solve(A, sc.y, oracle.Params(max_iter=5000, kkt=True, **b), mask0=mask0)
+    assert fix.converged and fix.reinstated >= 3 and fix.prune_events == 0
+    nmse = np.linalg.norm(fix.z - plain.z) ** 2 / np.linalg.norm(plain.z) ** 2
+    assert nmse < 1e-6
+
+
+def test_kkt_round_cap_reports_remaining_violations(radar_small):
+    """With no reinstating round allowed, a forced false prune is only checked:
+    the solve ends unconverged and reports the violating pixels."""
+    A, sc, base = radar_small
+    b = {**base, "eps_rel": 1e-6}
+    plain = oracle.solve(A, sc.y, oracle.Params(max_iter=5000, **b))
+    supp = np.flatnonzero(np.abs(plain.z) > 0)
+    mask0 = np.ones((len(A), A[0].shape[1]), bool)
+    mask0[:, supp[:3]] = False
+    capped = oracle.solve(A, sc.y, oracle.Params(max_iter=5000, kkt=True, kkt_rounds=0, **b),
+                          mask0=mask0)
+    assert not capped.converged
+    assert capped.kkt_violations >= 3 and capped.reinstated == 0
+    assert np.all(capped.z[supp[:3]] == 0)
