@@ -117,9 +117,11 @@ typedef struct {
                                  the x-update, whose fixed point becomes that of A.
                                  When the stop test passes on a correction taken at
                                  an earlier x, g is retaken at the converged x and
-                                 the solve stops only if |g_new - g_old| / (beta +
-                                 gamma) <= eps_pri (the bound on the x-update's
-                                 change), else it iterates on.  0 (default): off */
+                                 the solve stops only if the x-update moves by at
+                                 most eps_pri under the new g (Woodbury sensors:
+                                 the change of (mu Ahat^H Ahat + cI)^{-1} g; direct
+                                 sensors: the bound |g_new - g_old| / (beta +
+                                 gamma)), else it iterates on.  0 (default): off */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 
@@ -236,7 +238,9 @@ int sadmm_get_active_mask(sadmm_t h, int32_t q, uint8_t* mask);
 int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count);
 
 /* Per-iteration history of the last solve (host buffers of capacity cap):
- * which = 0 r, 1 s, 2 eps_pri, 3 eps_dual, 4 nmse, 5 max_q N_q / N.
+ * which = 0 r, 1 s, 2 eps_pri, 3 eps_dual, 4 nmse, 5 max_q N_q / N,
+ * 6 change of the x-update when a stale 16-bit correction was retaken at a
+ * passed stop test (0 at other iterations; compared with eps_pri).
  * *count receives the number of iterations recorded. */
 int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap,
                       int32_t* count);

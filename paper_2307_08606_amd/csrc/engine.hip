@@ -90,8 +90,8 @@ struct sadmm_s {
   std::vector<double*> rec;      // per sensor: phase records of the geometry, or null
   SensorDesc* sens_mf_d = nullptr;   // sensor table viewing rec as a matrix-free operator
   double *gfix = nullptr, *re1 = nullptr, *re2 = nullptr, *rw = nullptr;
-  double *gprev = nullptr, *dg = nullptr;   // previous correction, |g - gprev|^2
-  void *g32 = nullptr, *xfix = nullptr;
+  double *gprev = nullptr, *dg = nullptr;   // previous correction, per-sensor squared changes
+  void *g32 = nullptr, *xfix = nullptr, *xprev = nullptr;
   int k_refined = 0;             // iteration of the last correction
   // W not formed after a build (W64 holds U = X^H, hpdX holds X = L^{-1})
   std::vector<uint8_t> wtri;
@@ -118,7 +118,7 @@ struct sadmm_s {
 
   // results of the last solve
   sadmm_info info{};
-  std::vector<double> hist_h;   // 6 x max_iter
+  std::vector<double> hist_h;   // 7 x max_iter
   int hist_count = 0;
   double t_total = 0, t_factor = 0, t_iter = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
@@ -136,7 +136,8 @@ struct sadmm_s {
   int kkt_rounds = 0, status = 1;
   bool done = false;
   bool start_restricted = false;   // the solve started with eliminated pixels
-  double last_dg = 0.0;            // |g_new - g_old| of the last convergence check
+  double last_dg = 0.0;            // x-update change of the last correction retake
+  std::vector<std::pair<int, double>> retake_pts;   // (iteration, that change) per retake
 
   // optional per-kernel-class event timing (sadmm_set_profiling)
   bool prof = false;
@@ -820,9 +821,10 @@ int refine_setup(sadmm_t h) {
   TRY(grab((void**)&h->sens_mf_d, sizeof(SensorDesc) * h->Q));
   TRY(grab((void**)&h->gfix, 16 * QN));
   TRY(grab((void**)&h->gprev, 16 * QN));
-  TRY(grab((void**)&h->dg, sizeof(double)));
+  TRY(grab((void**)&h->dg, sizeof(double) * h->Q));
   TRY(grab(&h->g32, h->csz * QN));
   TRY(grab(&h->xfix, h->csz * QN));
+  TRY(grab(&h->xprev, h->csz * QN));
   TRY(grab((void**)&h->re1, 16 * (size_t)h->Q * h->KMp));
   TRY(grab((void**)&h->re2, 16 * (size_t)h->Q * h->KMp));
   TRY(grab((void**)&h->rw, 16 * (size_t)h->Q * h->KMp));
@@ -962,6 +964,7 @@ int solve_prologue_finish(sadmm_t h) {
   h->frac_pts.assign(1, {1, max_active_frac(h)});
   h->kkt_rounds = 0;
   h->k_refined = 0;
+  h->retake_pts.clear();
   h->status = 1;
   h->done = false;
   const IterArgs a = make_args(h);
@@ -1071,18 +1074,37 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
     if (h->p.refine_every > 0 && h->k_refined != c.k) {
       // The correction in use was taken at an earlier x.  Retake it at the
       // converged x; the solve stops only if the x-update moves by at most
-      // the primal tolerance under the new one (|dx| <= |dg| / c, since
-      // (mu Ahat^H Ahat + cI)^{-1} has norm <= 1/c), else it goes on.
+      // the primal tolerance under the new one, else it goes on.  For a
+      // Woodbury sensor that move is the change of xfix =
+      // (mu Ahat^H Ahat + cI)^{-1} g itself (the inverse damps the part of
+      // the change of g in the range of Ahat^H, where the 16-bit error and
+      // the FP32 rounding of A^H(y - A x) sit); a direct sensor adds g to its
+      // right-hand side, and |dx| <= |dg| / c bounds its move.
       if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
       const size_t QN = (size_t)h->Q * h->N;
       HIPCHK(h, hipMemcpyAsync(h->gprev, h->gfix, 16 * QN, hipMemcpyDeviceToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(h->xprev, h->xfix, h->csz * QN, hipMemcpyDeviceToDevice, s));
       TRY(refine(h, c.k));
-      diff_norm2_c128(h->gfix, h->gprev, (int64_t)QN, h->dg, s);
-      double dg2 = 0.0;
-      HIPCHK(h, hipMemcpyAsync(&dg2, h->dg, sizeof(double), hipMemcpyDeviceToHost, s));
+      for (int q = 0; q < h->Q; ++q) {
+        const size_t o = (size_t)q * h->N;
+        if (h->direct[q])
+          diff_norm2_c128(h->gfix + 2 * o, h->gprev + 2 * o, h->N, h->dg + q, s);
+        else if (h->dbl)
+          diff_norm2_c128(static_cast<const double*>(h->xfix) + 2 * o,
+                          static_cast<const double*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
+        else
+          diff_norm2_c64(static_cast<const float*>(h->xfix) + 2 * o,
+                         static_cast<const float*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
+      }
+      std::vector<double> dq(h->Q, 0.0);
+      HIPCHK(h, hipMemcpyAsync(dq.data(), h->dg, sizeof(double) * h->Q, hipMemcpyDeviceToHost, s));
       HIPCHK(h, hipStreamSynchronize(s));
-      h->last_dg = std::sqrt(dg2);
-      if (!(h->last_dg / (h->p.beta + h->p.gamma) <= c.eps_pri)) {
+      const double cinv = 1.0 / (h->p.beta + h->p.gamma);
+      double d2 = 0.0;
+      for (int q = 0; q < h->Q; ++q) d2 += h->direct[q] ? dq[q] * cinv * cinv : dq[q];
+      h->last_dg = std::sqrt(d2);
+      h->retake_pts.push_back({c.k, h->last_dg});
+      if (!(h->last_dg <= c.eps_pri)) {
         *h->halt_h = 0;
         HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(h, hipStreamSynchronize(s));
@@ -1251,7 +1273,7 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
   HIPCHK(h, hipMemcpy(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
   const Ctl c = *h->ctl_h;
   h->hist_count = c.k;
-  h->hist_h.assign(6 * (size_t)h->p.max_iter, 0.0);
+  h->hist_h.assign(7 * (size_t)h->p.max_iter, 0.0);
   HIPCHK(h, hipMemcpy(h->hist_h.data(), h->hist, sizeof(double) * 5 * h->p.max_iter, hipMemcpyDeviceToHost));
   for (int k = 1; k <= c.k; ++k) {
     double f = h->frac_pts[0].second;
@@ -1259,6 +1281,8 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
       if (pt.first <= k) f = pt.second;
     h->hist_h[5 * (size_t)h->p.max_iter + k - 1] = f;
   }
+  for (auto& pt : h->retake_pts)
+    if (pt.first >= 1 && pt.first <= h->p.max_iter) h->hist_h[6 * (size_t)h->p.max_iter + pt.first - 1] = pt.second;
   h->info.iters = c.k;
   h->info.status = h->status;
   h->info.r = c.r; h->info.s = c.s; h->info.eps_pri = c.eps_pri; h->info.eps_dual = c.eps_dual;
@@ -1790,7 +1814,7 @@ int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count)
 
 int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap, int32_t* count) {
   if (!h) return SADMM_E_ARG;
-  if (!out || !count || which < 0 || which > 5 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
+  if (!out || !count || which < 0 || which > 6 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
   if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_history: no solve yet");
   const int n = std::min(cap, h->hist_count);
   std::memcpy(out, h->hist_h.data() + (size_t)which * h->p.max_iter, sizeof(double) * n);
@@ -1892,7 +1916,7 @@ void sadmm_destroy(sadmm_t h) {
   for (unsigned long long* p : h->rmaxc)
     if (p) hipFree(p);
   for (void* p : {(void*)h->sens_mf_d, (void*)h->gfix, h->g32, h->xfix, (void*)h->re1, (void*)h->re2,
-                  (void*)h->rw, (void*)h->gprev, (void*)h->dg})
+                  (void*)h->rw, (void*)h->gprev, (void*)h->dg, h->xprev})
     if (p) hipFree(p);
   if (h->ctl_h) hipHostFree(h->ctl_h);
   if (h->counts_h) hipHostFree(h->counts_h);

@@ -233,12 +233,15 @@ __global__ void load_meas_kernel(const void* src, int c128, int KM, int KMp, dou
 
 // out[0] = sum_i |a_i - b_i|^2 over n complex128 entries; one work-group of
 // 1024 threads, fixed reduction order.
-__global__ __launch_bounds__(1024) void diff_norm2_kernel(const double* a, const double* b, int64_t n,
+// |a - b|^2 over n interleaved complex entries (T = double or float),
+// accumulated in FP64 by one work-group.
+template <class T>
+__global__ __launch_bounds__(1024) void diff_norm2_kernel(const T* a, const T* b, int64_t n,
                                                           double* out) {
   __shared__ double sm[16];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    const double dr = a[2 * i] - b[2 * i], di = a[2 * i + 1] - b[2 * i + 1];
+    const double dr = (double)a[2 * i] - (double)b[2 * i], di = (double)a[2 * i + 1] - (double)b[2 * i + 1];
     acc += dr * dr + di * di;
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -256,7 +259,11 @@ inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 }  // namespace
 
 void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
-  diff_norm2_kernel<<<1, 1024, 0, s>>>(a, b, n, out);
+  diff_norm2_kernel<double><<<1, 1024, 0, s>>>(a, b, n, out);
+}
+
+void diff_norm2_c64(const float* a, const float* b, int64_t n, double* out, hipStream_t s) {
+  diff_norm2_kernel<float><<<1, 1024, 0, s>>>(a, b, n, out);
 }
 
 void convert_operator(const void* src, bool src_c128, int64_t src_ld, int KM, int N, int st,

@@ -228,7 +228,10 @@ def test_refinement_stop_rule(gpu_lib, storage):
     s = geometry_solver(gpu_lib, g, storage, hp, refine_every=10, max_iter=400, eps_rel=1e-4)
     info = s.solve(sc.y)
     err = nmse(s.image(), ref.z)
-    print(storage, info["iters"], info["status"], err)
+    dx, ep = s.history("retake_change"), s.history("eps_pri")
+    at = np.flatnonzero(dx)
+    print(storage, info["iters"], info["status"], err,
+          [(int(k) + 1, float(dx[k]), float(ep[k])) for k in at[:12]])
     assert info["status"] == 0
     assert err <= 1e-6
 
