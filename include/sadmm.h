@@ -283,6 +283,19 @@ int sadmm_cnn_get_params(sadmm_cnn_t c, float* params, int64_t count);
 /* Probability map (H*W floats) of the input x (Q x H x W floats). */
 int sadmm_cnn_forward(sadmm_cnn_t c, const float* x, int32_t x_on_device, float* prob,
                       int32_t prob_on_device);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the probability
+ * map of sadmm_cnn_forward for an H x W input of any size up to 512 x 512
+ * pixels (H * W <= 262144, else SADMM_E_SHAPE), with the handle's parameters
+ * and arithmetic (sadmm_cnn_set_half).  x (Q x H x W floats) and prob (H * W
+ * floats) are device pointers owned by the caller.  The activations live in
+ * a fixed 65 MiB array of the library, one per GPU, held until the process
+ * ends; the call allocates and frees nothing, enqueues its kernels on the
+ * handle's stream and returns without synchronising (prob is ready when the
+ * stream reaches that point).  Every call on one GPU uses that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller. */
+int sadmm_cnn_forward_noalloc(sadmm_cnn_t c, const float* x, int32_t H, int32_t W, float* prob);
 /* Inference arithmetic: on = 1 (default) FP16 operands (activations and
  * weights rounded to binary16) on the 16x16x16 matrix instruction with FP32
  * accumulation; 0 = FP32 direct convolutions (the training forward). */

@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -368,19 +369,56 @@ int calloc_dev(sadmm_cnn_t c, void** p, size_t bytes) {
 
 dim3 tiles(int H, int W) { return dim3((W + TILE - 1) / TILE, (H + TILE - 1) / TILE); }
 
-void cnn_forward_dev(sadmm_cnn_t c, bool half) {
-  const dim3 gr = tiles(c->H, c->W);
-  const float* in[4] = {c->x, c->h1, c->h2, c->h3};
-  float* out[4] = {c->h1, c->h2, c->h3, c->a4};
+// The four layers of an H x W input x; layer l writes out[l] (out[3] = a4).
+void cnn_layers(sadmm_cnn_t c, const float* x, int H, int W, float* const out[4], bool half) {
+  const dim3 gr = tiles(H, W);
   for (int l = 0; l < 4; ++l) {
+    const float* in = l == 0 ? x : out[l - 1];
     if (half)
-      conv_fwd_mfma_kernel<<<gr, 256, 0, c->s>>>(in[l], c->L[l].cin, c->p + c->L[l].w_off,
-                                                 c->p + c->L[l].b_off, c->L[l].cout, c->H, c->W,
+      conv_fwd_mfma_kernel<<<gr, 256, 0, c->s>>>(in, c->L[l].cin, c->p + c->L[l].w_off,
+                                                 c->p + c->L[l].b_off, c->L[l].cout, H, W,
                                                  l < 3 ? 1 : 0, out[l]);
     else
-      conv_fwd_kernel<<<gr, 256, 0, c->s>>>(in[l], c->L[l].cin, c->p + c->L[l].w_off, c->p + c->L[l].b_off,
-                                            c->L[l].cout, c->H, c->W, l < 3 ? 1 : 0, out[l]);
+      conv_fwd_kernel<<<gr, 256, 0, c->s>>>(in, c->L[l].cin, c->p + c->L[l].w_off, c->p + c->L[l].b_off,
+                                            c->L[l].cout, H, W, l < 3 ? 1 : 0, out[l]);
   }
+}
+
+void cnn_forward_dev(sadmm_cnn_t c, bool half) {
+  float* const out[4] = {c->h1, c->h2, c->h3, c->a4};
+  cnn_layers(c, c->x, c->H, c->W, out, half);
+}
+
+// Scratch of the allocation-free forward (sadmm_cnn_forward_noalloc): two
+// ping-pong activation buffers of CMAX channel planes and the pre-sigmoid
+// map, for images of at most NOALLOC_MAX_PIXELS pixels (512 x 512: 65 MiB).
+// Every entry a call reads was written by the same call, so nothing needs
+// clearing between calls.  Host code never passes this symbol to a kernel:
+// it passes the device address hipGetSymbolAddress returns for the current
+// device (noalloc_scratch).
+constexpr int64_t NOALLOC_MAX_PIXELS = 512 * 512;
+constexpr int64_t NOALLOC_FLOATS = (2 * CMAX + 1) * NOALLOC_MAX_PIXELS;
+__device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device, looked up once
+// per device.
+int noalloc_scratch(sadmm_cnn_t c, float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return cfail(c, SADMM_E_HIP, "forward_noalloc: no current device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return cfail(c, SADMM_E_HIP, "forward_noalloc: scratch symbol lookup failed");
+    g_scratch_dev[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return SADMM_OK;
 }
 
 // forward + loss + backward into c->g; returns the loss through *loss (host)
@@ -524,6 +562,24 @@ int sadmm_cnn_forward(sadmm_cnn_t c, const float* x, int32_t x_on_device, float*
                      c->s) != hipSuccess ||
       hipStreamSynchronize(c->s) != hipSuccess)
     return cfail(c, SADMM_E_HIP, "forward failed");
+  return SADMM_OK;
+}
+
+int sadmm_cnn_forward_noalloc(sadmm_cnn_t c, const float* x, int32_t H, int32_t W, float* prob) {
+  if (!c) return SADMM_E_ARG;
+  if (!x || !prob) return cfail(c, SADMM_E_ARG, "forward_noalloc: null pointer");
+  if (H < 1 || W < 1 || (int64_t)H * W > NOALLOC_MAX_PIXELS)
+    return cfail(c, SADMM_E_SHAPE, "forward_noalloc: H * W must lie in [1, 262144]");
+  float* sc = nullptr;
+  const int rc = noalloc_scratch(c, &sc);
+  if (rc) return rc;
+  const int64_t P = (int64_t)H * W;
+  float* const s0 = sc;
+  float* const s1 = sc + CMAX * P;
+  float* const out[4] = {s0, s1, s0, sc + 2 * CMAX * P};
+  cnn_layers(c, x, H, W, out, c->half != 0);
+  bce_kernel<<<(unsigned)((P + 255) / 256), 256, 0, c->s>>>(out[3], nullptr, (int)P, 1.f, prob, nullptr, nullptr);
+  if (hipGetLastError() != hipSuccess) return cfail(c, SADMM_E_HIP, "forward_noalloc: launch failed");
   return SADMM_OK;
 }
 

@@ -110,6 +110,7 @@ sadmm_cnn_param_count = _sig("sadmm_cnn_param_count", C.c_int64, _H)
 sadmm_cnn_set_params = _sig("sadmm_cnn_set_params", C.c_int, _H, _P, C.c_int64)
 sadmm_cnn_get_params = _sig("sadmm_cnn_get_params", C.c_int, _H, _P, C.c_int64)
 sadmm_cnn_forward = _sig("sadmm_cnn_forward", C.c_int, _H, _P, C.c_int32, _P, C.c_int32)
+sadmm_cnn_forward_noalloc = _sig("sadmm_cnn_forward_noalloc", C.c_int, _H, _P, C.c_int32, C.c_int32, _P)
 sadmm_cnn_set_half = _sig("sadmm_cnn_set_half", C.c_int, _H, C.c_int32)
 sadmm_cnn_gradients = _sig("sadmm_cnn_gradients", C.c_int, _H, _P, _P, C.c_int32, C.c_float, _P,
                            C.POINTER(C.c_double))
@@ -401,6 +402,16 @@ class Cnn:
         out = np.empty((self.H, self.W), np.float32)
         self._check(sadmm_cnn_forward(self._h, _ptr(x), 0, _ptr(out), 0))
         return out
+
+    def forward_noalloc(self, x, prob):
+        """Probability map of a device tensor x (Q x H x W float32, any H x W up
+        to 512 x 512) into the device tensor prob (H x W float32), on the
+        handle's stream, without allocating; the caller synchronises."""
+        assert x.is_cuda and prob.is_cuda and x.dtype == torch.float32 and prob.dtype == torch.float32
+        assert x.is_contiguous() and prob.is_contiguous() and x.dim() == 3 and x.shape[0] == self.Q
+        H, W = int(x.shape[1]), int(x.shape[2])
+        assert tuple(prob.shape) == (H, W)
+        self._check(sadmm_cnn_forward_noalloc(self._h, x.data_ptr(), H, W, prob.data_ptr()))
 
     def gradients(self, x, target, pos_weight):
         x = np.ascontiguousarray(x, dtype=np.float32)
