@@ -92,7 +92,14 @@ typedef struct {
                                  eliminated pixels: caller mask or CNN); at most 8
                                  rounds, after which remaining violations end the
                                  solve with status 3 */
-  double kkt_tol;             /* reinstate when |g| > kkt_tol * lambda */
+  double kkt_tol;             /* reinstate eliminated pixel n of sensor q when
+                                 |g_qn| / (mu |a_qn|^2 + beta + gamma) >
+                                 kkt_tol * max_m |x_q[m]|, with
+                                 g_q = mu A_q^H (A_q x_q - y_q) + gamma x_q + beta u:
+                                 the step the pixel's own coordinate of the next
+                                 x-update would take from its frozen value.
+                                 kkt_tol <= 0 (default): 10 * eps_rel, the
+                                 per-pixel precision the stop test grants */
   int32_t storage;            /* sadmm_storage */
   int32_t reuse_factor;       /* 1: a later solve reuses a factor built for the same
                                  starting selector; 0: every solve rebuilds it */
@@ -143,7 +150,7 @@ typedef struct {
 } sadmm_info;
 
 /* Fills *p with defaults: mu = beta = gamma = 1, eps_rel = 1e-4, Kp = 5,
- * eps_p = 1e-5, storage FP32, stop = 1, check_every = 8, kkt_tol = 1e-2,
+ * eps_p = 1e-5, storage FP32, stop = 1, check_every = 8, kkt_tol = 0 (10 eps_rel),
  * reuse_factor = 1. */
 void sadmm_default_params(sadmm_params* p);
 
@@ -348,6 +355,28 @@ int sadmm_set_profiling(sadmm_t h, int32_t level);
  * at least once). */
 int sadmm_get_kernel_stats(sadmm_t h, int32_t kclass, int32_t* launches, double* total_ms,
                            double* work);
+
+/* ---------------------------------------------------------------------------
+ * Roofline probes (no part of the method): the device's own bandwidth and
+ * matrix throughput, the denominators measured beside the published peaks.
+ * ------------------------------------------------------------------------- */
+
+/* Bandwidth over `bytes` (a multiple of 16) of device memory, `reps` passes
+ * after one untimed pass on the given hipStream_t; *ms receives the mean time
+ * of one pass (HIP events).  kind 0: copy src -> dst with non-temporal 16-byte
+ * loads and stores (bandwidth = 2 * bytes / time); kind 1: read src only
+ * (bandwidth = bytes / time; dst unused, may be NULL).  src and dst are
+ * caller-owned device pointers, 16-byte aligned; kind 1 allocates and frees a
+ * small result buffer. */
+int sadmm_probe_bandwidth(int32_t kind, const void* src, void* dst, int64_t bytes, int32_t reps,
+                          void* stream, double* ms);
+
+/* Register-only matrix-instruction loop over every compute unit, `iters`
+ * rounds of independent accumulators: kind 0 = int8 16x16x64 (8 waves per
+ * SIMD), 1 = FP64 16x16x4 (8 waves per SIMD), 2 = int8 32x32x32 (4 waves per
+ * SIMD).  *ops_per_s receives the achieved operations per second (multiply
+ * and add counted separately).  Allocates and frees a small result buffer. */
+int sadmm_probe_mfma(int32_t kind, int32_t iters, void* stream, double* ops_per_s);
 
 void sadmm_destroy(sadmm_t h);
 /* Message of the last failing call on h; with h = NULL, of the last failed

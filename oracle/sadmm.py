@@ -57,10 +57,18 @@ these points; each reading is the one that makes eq. (3) a convergent method):
 
 Certificate and reinstatement: at the optimum of the unpruned problem,
 g_q = mu A_q^H (A_q x_q - y_q) + gamma x_q + beta u = 0 for every q and pixel.
-With `kkt=True`, after convergence every eliminated pixel with
-|g_qj| > kkt_tol * lambda is put back into J_q (its measurement contribution is
-removed from y'_q again, its history window is set to +inf so it cannot be
-eliminated for K_p iterations) and iterating resumes.  The re-check judges
+With `kkt=True`, after convergence every eliminated pixel whose coordinate
+step |g_qj| / (mu ||a_qj||^2 + beta + gamma) exceeds kkt_tol * max_n |x_q[n]|
+(kkt_tol <= 0: 10 eps_rel, the per-pixel precision the stop test grants)
+is put back into J_q (its measurement contribution is removed from y'_q again,
+its history window is set to +inf so it cannot be eliminated for K_p
+iterations) and iterating resumes.  The step is how far the pixel's own
+coordinate of the next x-update would move it from its frozen value: the
+x-update's objective has gradient g_qj (at a fixed point x_q - v = u) and
+curvature mu ||a_qj||^2 + beta + gamma along that coordinate.  A pixel frozen
+near its optimum (SSC's eliminations) moves by about its remaining drift; a
+pixel eliminated far from it (a wrong initial selector) moves by a sizeable
+fraction of the image's peak.  The re-check judges
 SSC's eliminations (prune=True) and an initial selector that already
 eliminates pixels (mask0).  After kkt_rounds reinstating rounds the next
 convergence is only checked: remaining violations leave converged=False and
@@ -96,7 +104,7 @@ class Params:
     eps_p: float = 1e-5
     mode: str = "freeze"       # "freeze" or "zero"
     kkt: bool = False
-    kkt_tol: float = 1e-2
+    kkt_tol: float = 0.0       # <= 0: 10 * eps_rel
     kkt_rounds: int = 8
 
 
@@ -318,10 +326,12 @@ def _reinstate(A, y, X, u, p, active, yp, D, check_only=False) -> int:
     """Put eliminated pixels that violate the optimality condition back
     (only count them when check_only)."""
     g = kkt_gradient(A, y, X, u, p)
-    thr = p.kkt_tol * (p.lam if p.lam > 0 else 1.0)
     back = 0
     for q in range(len(A)):
-        bad = np.flatnonzero((~active[q]) & (np.abs(g[q]) > thr))
+        curv = p.mu * np.sum(np.abs(A[q]) ** 2, axis=0) + p.beta + p.gamma
+        step = np.abs(g[q]) / curv
+        thr = (p.kkt_tol if p.kkt_tol > 0 else 10.0 * p.eps_rel) * np.abs(X[q]).max()
+        bad = np.flatnonzero((~active[q]) & (step > thr))
         if bad.size == 0:
             continue
         if check_only:

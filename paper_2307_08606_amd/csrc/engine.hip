@@ -574,13 +574,6 @@ bool prefer_lowrank(sadmm_t h, int r, int nq_new) {
   return upd < full;
 }
 
-int refresh_factor(sadmm_t h, int q, const int* d_list, int r, int sign) {
-  if (r <= 0) return SADMM_OK;
-  if (prefer_lowrank(h, r, h->nq[q])) return lowrank_update(h, q, d_list, r, sign);
-  h->info.refactors += 1;
-  return build_factors(h, std::vector<int>{q});
-}
-
 // Direct form: largest active set for which x = F (b0 + beta v) reads fewer
 // bytes per iteration than the Woodbury form (16 N^2 for F against
 // 2 KM N b_A + 16 KM^2 for the operator passes and W).
@@ -686,7 +679,23 @@ int read_counts(sadmm_t h) {
 }
 
 // Apply the eliminations the SSC check decided at the last iteration.
+// Rebuilds the factors of the listed sensors from their current active sets
+// in one batched Gram and inverse (one chain of launches for all of them,
+// not one per sensor), then their data terms.
+int rebuild_factors(sadmm_t h, const std::vector<int>& qs) {
+  if (qs.empty()) return SADMM_OK;
+  h->info.refactors += (int)qs.size();
+  TRY(build_factors(h, qs));
+  for (int q : qs) {
+    h->fac_valid[q] = false;
+    launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
+  }
+  HIPCHK(h, hipGetLastError());
+  return SADMM_OK;
+}
+
 int apply_prune(sadmm_t h) {
+  std::vector<int> rebuild;
   std::vector<int> gone(h->Q);
   HIPCHK(h, hipMemcpyAsync(gone.data(), h->gone, sizeof(int) * h->Q, hipMemcpyDeviceToHost, h->s));
   HIPCHK(h, hipStreamSynchronize(h->s));
@@ -719,11 +728,16 @@ int apply_prune(sadmm_t h) {
       TRY(to_woodbury(h, q));
       continue;
     }
-    TRY(refresh_factor(h, q, h->lst, r, -1));
-    h->fac_valid[q] = false;
-    launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
-    HIPCHK(h, hipGetLastError());
+    if (prefer_lowrank(h, r, kept)) {
+      TRY(lowrank_update(h, q, h->lst, r, -1));
+      h->fac_valid[q] = false;
+      launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
+      HIPCHK(h, hipGetLastError());
+    } else {
+      rebuild.push_back(q);
+    }
   }
+  TRY(rebuild_factors(h, rebuild));
   HIPCHK(h, hipMemsetAsync(h->gone, 0, sizeof(int) * h->Q, h->s));
   return SADMM_OK;
 }
@@ -732,10 +746,13 @@ int apply_prune(sadmm_t h) {
 // number of violating pixels, which are reinstated unless check_only.
 int kkt_reinstate(sadmm_t h, int* n_back, bool check_only = false) {
   *n_back = 0;
-  const double thr = h->p.kkt_tol * (h->p.lambda > 0 ? h->p.lambda : 1.0);
+  std::vector<int> rebuild;
+  const double thr = h->p.kkt_tol > 0 ? h->p.kkt_tol : 10.0 * h->p.eps_rel;
   for (int q = 0; q < h->Q; ++q) {
     if (h->nq[q] == h->N) continue;
     IterArgs a = make_args(h);
+    // threshold scale: max_n |x_q[n]| (frozen pixels included)
+    maxabs_c(static_cast<const char*>(h->X) + h->csz * (size_t)q * h->N, h->dbl, h->N, h->red, h->s);
     // e = A_q x_q - y_q over all pixels (original measurement)
     scale_c128(h->y + 2 * (size_t)q * h->KMp, h->e, h->KMp, -1.0, h->s);
     launch_gather_fwd(a, h->st, h->dbl, q, nullptr, h->N, 1.0, h->e, h->gtmp, h->s);
@@ -744,7 +761,7 @@ int kkt_reinstate(sadmm_t h, int* n_back, bool check_only = false) {
     TRY(read_counts(h));
     const int ne = h->counts_h[1];
     if (ne == 0) continue;
-    launch_kkt_check(a, h->st, h->dbl, q, h->lst, ne, h->e, h->p.mu, h->p.gamma, thr, h->flag, h->s);
+    launch_kkt_check(a, h->st, h->dbl, q, h->lst, ne, h->e, h->p.mu, h->p.gamma, thr, h->red, h->flag, h->s);
     partition_flags(h->flag, h->lst, ne, h->lst2, nullptr, h->counts, h->s);
     TRY(read_counts(h));
     const int r = h->counts_h[0];
@@ -763,15 +780,17 @@ int kkt_reinstate(sadmm_t h, int* n_back, bool check_only = false) {
       TRY(build_direct(h, q));
     } else if (h->direct[q]) {   // grown past the crossover
       TRY(to_woodbury(h, q));
-    } else {
-      TRY(refresh_factor(h, q, h->lst2, r, +1));
+    } else if (prefer_lowrank(h, r, h->nq[q])) {
+      TRY(lowrank_update(h, q, h->lst2, r, +1));
       h->fac_valid[q] = false;
       launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
       HIPCHK(h, hipGetLastError());
+    } else {
+      rebuild.push_back(q);
     }
     *n_back += r;
   }
-  return SADMM_OK;
+  return rebuild_factors(h, rebuild);
 }
 
 double max_active_frac(sadmm_t h) {
@@ -1308,7 +1327,7 @@ void sadmm_default_params(sadmm_params* p) {
   p->eps_abs = 0.0; p->eps_rel = 1e-4;
   p->max_iter = 200; p->stop = 1; p->check_every = 8;
   p->prune = 0; p->Kp = 5; p->eps_p = 1e-5; p->prune_mode = 0;
-  p->kkt = 0; p->kkt_tol = 1e-2;
+  p->kkt = 0; p->kkt_tol = 0.0;
   p->storage = SADMM_ST_FP32;
   p->reuse_factor = 1;
   p->stream = nullptr;

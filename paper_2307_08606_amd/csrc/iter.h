@@ -140,8 +140,8 @@ void launch_gather_fwd(const IterArgs& a, int st, bool dbl, int q, const int* id
 // g = mu A[:,n]^H e + gamma X[q,n] + beta u[n] with e = A_q x_q - y_q
 // (complex128, KMp); flag[j] = |g| > thr.
 void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
-                      const double* e, double mu, double gamma, double thr, uint8_t* flag,
-                      hipStream_t s);
+                      const double* e, double mu, double gamma, double thr, const double* xmax,
+                      uint8_t* flag, hipStream_t s);
 
 // |A_q^H y_q| over all pixels for every sensor, into out (Q x N doubles).
 // Correction products over every sensor (one launch per step):

@@ -44,6 +44,7 @@ void iota_int(int* dst, int n, hipStream_t s);
 // out[0] (device) = sum |a_i - b_i|^2 over n complex128 entries
 void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, hipStream_t s);
 void diff_norm2_c64(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
+void maxabs_c(const void* x, bool dbl, int64_t n, double* out, hipStream_t s);
 // dst = src * scale (complex128 vectors of n entries)
 void scale_c128(const double* src, double* dst, int n, double scale, hipStream_t s);
 // complex copy with precision change: dst (T) = src (complex128) for n entries

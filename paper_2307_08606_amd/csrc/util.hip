@@ -254,12 +254,34 @@ __global__ __launch_bounds__(1024) void diff_norm2_kernel(const T* a, const T* b
   }
 }
 
+// max_i |x_i| over n interleaved complex entries (T = double or float), one
+// work-group.
+template <class T>
+__global__ __launch_bounds__(1024) void maxabs_kernel(const T* x, int64_t n, double* out) {
+  __shared__ double sm[16];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, hypot((double)x[2 * i], (double)x[2 * i + 1]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < 16; ++w) r = fmax(r, sm[w]);
+    out[0] = r;
+  }
+}
+
 inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
 
 void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
   diff_norm2_kernel<double><<<1, 1024, 0, s>>>(a, b, n, out);
+}
+
+void maxabs_c(const void* x, bool dbl, int64_t n, double* out, hipStream_t s) {
+  if (dbl) maxabs_kernel<double><<<1, 1024, 0, s>>>(static_cast<const double*>(x), n, out);
+  else maxabs_kernel<float><<<1, 1024, 0, s>>>(static_cast<const float*>(x), n, out);
 }
 
 void diff_norm2_c64(const float* a, const float* b, int64_t n, double* out, hipStream_t s) {

@@ -120,6 +120,10 @@ sadmm_cnn_destroy = _sig("sadmm_cnn_destroy", None, _H)
 sadmm_cnn_last_error = _sig("sadmm_cnn_last_error", C.c_char_p, _H)
 sadmm_set_pruning_cnn = _sig("sadmm_set_pruning_cnn", C.c_int, _H, _H, C.c_double)
 sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
+sadmm_probe_bandwidth = _sig("sadmm_probe_bandwidth", C.c_int, C.c_int32, _P, _P, C.c_int64, C.c_int32,
+                             C.c_void_p, C.POINTER(C.c_double))
+sadmm_probe_mfma = _sig("sadmm_probe_mfma", C.c_int, C.c_int32, C.c_int32, C.c_void_p,
+                        C.POINTER(C.c_double))
 
 EXPORTED = [n for n in dir() if n.startswith("sadmm_") and callable(globals()[n])
             and n not in ("sadmm_params", "sadmm_info")]
@@ -157,7 +161,7 @@ class Solver:
 
     def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
-                 eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=1e-2, storage="fp32",
+                 eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=0.0, storage="fp32",
                  reuse_factor=True, gram="int8", direct=True, refine_every=0, stream=None,
                  share=None):
         p = sadmm_params()
@@ -327,6 +331,34 @@ class Solver:
             self._check(sadmm_get_timing(self._h, i, C.byref(v)))
             out[k] = v.value
         return out
+
+
+def probe_bandwidth_gbps(kind="copy", nbytes=1 << 30, reps=10, stream=None):
+    """Device bandwidth in GB/s over nbytes: 'copy' (read + write bytes per
+    second, non-temporal) or 'read' (bytes read per second)."""
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda") if kind == "copy" else None
+    ms = C.c_double(0)
+    k = {"copy": 0, "read": 1}[kind]
+    rc = sadmm_probe_bandwidth(k, a.data_ptr(), b.data_ptr() if b is not None else 0, nbytes, reps,
+                               C_void(stream), C.byref(ms))
+    if rc != SADMM_OK:
+        raise SadmmError(rc, "sadmm_probe_bandwidth failed")
+    return (2.0 if k == 0 else 1.0) * nbytes / (ms.value * 1e-3) / 1e9
+
+
+def probe_mfma_tops(kind, iters=4096, stream=None):
+    """Register-only matrix throughput in tera-ops/s: kind 'i8' (16x16x64),
+    'f64' (16x16x4) or 'i8_32' (32x32x32)."""
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    ops = C.c_double(0)
+    rc = sadmm_probe_mfma({"i8": 0, "f64": 1, "i8_32": 2}[kind], iters, C_void(stream), C.byref(ops))
+    if rc != SADMM_OK:
+        raise SadmmError(rc, "sadmm_probe_mfma failed")
+    return ops.value / 1e12
 
 
 def solve_batch(solvers, ys):

@@ -153,3 +153,32 @@ def test_kkt_round_cap_reports_remaining_violations(radar_small):
     assert not capped.converged
     assert capped.kkt_violations >= 3 and capped.reinstated == 0
     assert np.all(capped.z[supp[:3]] == 0)
+
+
+def test_kkt_step_is_the_coordinate_move_of_a_perturbed_pixel(radar_small):
+    """At the optimum g = 0; moving x_q[j] by delta makes g_qj =
+    (mu |a_qj|^2 + gamma) delta to first order, so the re-check's step
+    |g_qj| / (mu |a_qj|^2 + beta + gamma) is |delta| times that ratio, and the
+    pixel is reinstated exactly when this exceeds kkt_tol * max |x_q|."""
+    from oracle.sadmm import _reinstate
+    A, sc, base = radar_small
+    b = {**base, "eps_rel": 1e-12}
+    p = oracle.Params(max_iter=20000, **b)
+    R = oracle.solve(A, sc.y, p)
+    q, j, delta = 1, 17, 1e-4 * (1 + 1j)
+    X = R.X.copy()
+    X[q, j] += delta
+    g = oracle.kkt_gradient(A, sc.y, X, R.u, p)
+    nrm = np.sum(np.abs(A[q][:, j]) ** 2)
+    want = abs(delta) * (b["mu"] * nrm + b["gamma"]) / (b["mu"] * nrm + b["beta"] + b["gamma"])
+    step = abs(g[q, j]) / (b["mu"] * nrm + b["beta"] + b["gamma"])
+    assert step == pytest.approx(want, rel=1e-6)
+    ratio = step / np.abs(X[q]).max()
+    for tol, expect in ((0.5 * ratio, 1), (2.0 * ratio, 0)):
+        active = np.ones_like(R.active)
+        active[q, j] = False
+        yp = sc.y.copy()
+        D = np.zeros((4,) + R.active.shape)
+        back = _reinstate(A, sc.y, X, R.u, oracle.Params(kkt_tol=tol, **b), active, yp, D,
+                          check_only=True)
+        assert back == expect
