@@ -125,10 +125,9 @@ typedef struct {
                                  When the stop test passes on a correction taken at
                                  an earlier x, g is retaken at the converged x and
                                  the solve stops only if the x-update moves by at
-                                 most eps_pri under the new g (Woodbury sensors:
-                                 the change of (mu Ahat^H Ahat + cI)^{-1} g; direct
-                                 sensors: the bound |g_new - g_old| / (beta +
-                                 gamma)), else it iterates on.  0 (default): off */
+                                 most eps_pri under the new g (the change of
+                                 (mu Ahat^H Ahat + cI)^{-1} g over the active
+                                 pixels), else it iterates on.  0 (default): off */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 
@@ -256,6 +255,26 @@ int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap,
  * measurements, over all pixels (the CNN input and the back-projection image). */
 int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
                          double* out);
+
+/* Back-projection image of Sec. IV (Fig. 1): |sum_q A_q^H y_q| per pixel,
+ * the coherent sum over the sensors of each sensor's adjoint applied to its
+ * measurements (y: Q x KM complex, sensor-major, in dtype; on_device selects
+ * a device pointer).  out: N doubles, host.  Allocates a Q x N complex128
+ * scratch for the call (and a staging copy of host measurements). */
+int sadmm_back_projection(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, double* out);
+
+/* Rendering of an image on a range_db dynamic range (Sec. IV shows every
+ * image on 30 dB): with r = |x_n| / max_m |x_m|, level
+ * floor(255 (1 + 20 log10(r) / range_db)) clipped to [0, 255], 0 where
+ * r < 10^(-range_db / 20) or the image is all zero; decided as the number of
+ * thresholds 10^((L/255 - 1) range_db / 20) * max |x|, L = 1..255, at or
+ * below |x_n|.  img: n doubles (is_complex = 0, magnitudes or real values)
+ * or n interleaved complex128 (is_complex = 1); levels: n bytes; both host
+ * or both device (on_device) pointers owned by the caller.  Runs on the given
+ * hipStream_t and returns after it; allocates small buffers (and staging for
+ * host pointers). */
+int sadmm_render_db(const void* img, int32_t is_complex, int64_t n, double range_db, int32_t on_device,
+                    uint8_t* levels, void* stream);
 
 /* Wall time of the last solve on its stream (HIP events), milliseconds:
  * which = 0 whole solve, 1 factor builds/updates, 2 iterations. */

@@ -10,11 +10,14 @@ Modules
   sadmm       plain SADMM and pruned ASADMM (eq. (3), Alg. 1), KKT certificate
   lambda_max  smallest l1 weight with an all-zero optimum image
   cnn         FP64 reference of the pixel-pruning CNN (forward, backward, BCE)
+  render      back-projection image and dynamic-range rendering (Sec. IV, Fig. 1)
 """
 
 from .sadmm import (Params, Result, solve, soft_threshold, kkt_gradient, residual_norms,
                     matched_filter)
 from .lambda_max import lambda_max
+from .render import back_projection, render_db, db_thresholds
 
 __all__ = ["Params", "Result", "solve", "soft_threshold", "kkt_gradient",
-           "residual_norms", "lambda_max", "matched_filter"]
+           "residual_norms", "lambda_max", "matched_filter", "back_projection", "render_db",
+           "db_thresholds"]

@@ -1093,12 +1093,13 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
     if (h->p.refine_every > 0 && h->k_refined != c.k) {
       // The correction in use was taken at an earlier x.  Retake it at the
       // converged x; the solve stops only if the x-update moves by at most
-      // the primal tolerance under the new one, else it goes on.  For a
-      // Woodbury sensor that move is the change of xfix =
-      // (mu Ahat^H Ahat + cI)^{-1} g itself (the inverse damps the part of
-      // the change of g in the range of Ahat^H, where the 16-bit error and
-      // the FP32 rounding of A^H(y - A x) sit); a direct sensor adds g to its
-      // right-hand side, and |dx| <= |dg| / c bounds its move.
+      // the primal tolerance under the new one, else it goes on.  That move
+      // is (mu Ahat^H Ahat + cI)^{-1} times the change of g: for a Woodbury
+      // sensor the change of xfix itself, for a direct sensor F applied to
+      // the change of g.  (The bound |dg| / c never meets the tolerance: the
+      // inverse damps the part of dg in the range of Ahat^H, where the 16-bit
+      // error and the FP32 rounding of A^H(y - A x) sit, by the operator's
+      // large singular values.)
       if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
       const size_t QN = (size_t)h->Q * h->N;
       HIPCHK(h, hipMemcpyAsync(h->gprev, h->gfix, 16 * QN, hipMemcpyDeviceToDevice, s));
@@ -1107,7 +1108,8 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
       for (int q = 0; q < h->Q; ++q) {
         const size_t o = (size_t)q * h->N;
         if (h->direct[q])
-          diff_norm2_c128(h->gfix + 2 * o, h->gprev + 2 * o, h->N, h->dg + q, s);
+          herm_apply_norm2(reinterpret_cast<const double*>(h->Fd[q]), h->fld[q], h->nq[q], h->J[q],
+                           h->gfix + 2 * o, h->gprev + 2 * o, h->dg + q, s);
         else if (h->dbl)
           diff_norm2_c128(static_cast<const double*>(h->xfix) + 2 * o,
                           static_cast<const double*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
@@ -1118,9 +1120,8 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
       std::vector<double> dq(h->Q, 0.0);
       HIPCHK(h, hipMemcpyAsync(dq.data(), h->dg, sizeof(double) * h->Q, hipMemcpyDeviceToHost, s));
       HIPCHK(h, hipStreamSynchronize(s));
-      const double cinv = 1.0 / (h->p.beta + h->p.gamma);
       double d2 = 0.0;
-      for (int q = 0; q < h->Q; ++q) d2 += h->direct[q] ? dq[q] * cinv * cinv : dq[q];
+      for (int q = 0; q < h->Q; ++q) d2 += dq[q];
       h->last_dg = std::sqrt(d2);
       h->retake_pts.push_back({c.k, h->last_dg});
       if (!(h->last_dg <= c.eps_pri)) {
@@ -1865,6 +1866,87 @@ int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_dev
   if (ystage) hipFree(ystage);
   h->solved = false;
   return SADMM_OK;
+}
+
+int sadmm_back_projection(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, double* out) {
+  if (!h) return SADMM_E_ARG;
+  if (!y || !out || (dtype != SADMM_C128 && dtype != SADMM_C64))
+    return fail_msg(h, SADMM_E_ARG, "back_projection: bad argument");
+  for (int q = 0; q < h->Q; ++q)
+    if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "back_projection: operator %d not set", q);
+  const size_t esz = dtype == SADMM_C128 ? 16 : 8;
+  const void* ysrc = y;
+  void* ystage = nullptr;
+  double* c = nullptr;
+  auto release = [&]() {
+    if (ystage) hipFree(ystage);
+    if (c) hipFree(c);
+  };
+  if (hipMalloc((void**)&c, 16 * (size_t)h->Q * h->N) != hipSuccess) {
+    c = nullptr;
+    return fail_msg(h, SADMM_E_NOMEM, "back_projection: %zu bytes", 16 * (size_t)h->Q * h->N);
+  }
+  if (!on_device) {
+    if (hipMalloc(&ystage, esz * (size_t)h->Q * h->KM) != hipSuccess) {
+      ystage = nullptr;
+      release();
+      return fail_msg(h, SADMM_E_NOMEM, "back_projection: staging");
+    }
+    if (hipMemcpyAsync(ystage, y, esz * (size_t)h->Q * h->KM, hipMemcpyHostToDevice, h->s) != hipSuccess) {
+      release();
+      return fail_msg(h, SADMM_E_HIP, "back_projection: copy");
+    }
+    ysrc = ystage;
+  }
+  load_measurements(ysrc, dtype == SADMM_C128, h->Q, h->KM, h->KMp, h->yp, h->s);
+  for (int q = 0; q < h->Q; ++q) h->nq[q] = h->N;
+  int rc = push_descs(h);
+  if (rc == SADMM_OK) {
+    launch_matched_filter(make_args(h), h->st, h->dbl, h->yp, c, h->s, true);
+    bp_sum(c, h->Q, h->N, h->mf, h->s);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(out, h->mf, sizeof(double) * (size_t)h->N, hipMemcpyDeviceToHost, h->s) != hipSuccess ||
+        hipStreamSynchronize(h->s) != hipSuccess)
+      rc = fail_msg(h, SADMM_E_HIP, "back_projection: launch failed");
+  }
+  release();
+  h->solved = false;
+  return rc;
+}
+
+int sadmm_render_db(const void* img, int32_t is_complex, int64_t n, double range_db, int32_t on_device,
+                    uint8_t* levels, void* stream) {
+  if (!img || !levels || n < 1 || !(range_db > 0.0) || (is_complex != 0 && is_complex != 1))
+    return SADMM_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t ib = (is_complex ? 16 : 8) * (size_t)n;
+  double thr[255];
+  for (int L = 1; L <= 255; ++L) thr[L - 1] = std::pow(10.0, (L / 255.0 - 1.0) * range_db / 20.0);
+  void* dimg = nullptr;
+  double* dthr = nullptr;   // 255 thresholds + the maximum
+  uint8_t* dout = nullptr;
+  int rc = SADMM_OK;
+  if (hipMalloc((void**)&dthr, sizeof(double) * 256) != hipSuccess) return SADMM_E_NOMEM;
+  if (!on_device) {
+    if (hipMalloc(&dimg, ib) != hipSuccess || hipMalloc((void**)&dout, (size_t)n) != hipSuccess) rc = SADMM_E_NOMEM;
+    else if (hipMemcpyAsync(dimg, img, ib, hipMemcpyHostToDevice, s) != hipSuccess) rc = SADMM_E_HIP;
+  }
+  if (rc == SADMM_OK && hipMemcpyAsync(dthr, thr, sizeof(thr), hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = SADMM_E_HIP;
+  if (rc == SADMM_OK) {
+    const double* x = static_cast<const double*>(on_device ? img : dimg);
+    uint8_t* o = on_device ? levels : dout;
+    render_levels(x, is_complex != 0, n, dthr, dthr + 255, o, s);
+    if (hipGetLastError() != hipSuccess) rc = SADMM_E_HIP;
+    if (rc == SADMM_OK && !on_device &&
+        hipMemcpyAsync(levels, dout, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
+      rc = SADMM_E_HIP;
+    if (rc == SADMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = SADMM_E_HIP;
+  }
+  if (dimg) hipFree(dimg);
+  if (dout) hipFree(dout);
+  hipFree(dthr);
+  return rc;
 }
 
 int sadmm_set_pruning_cnn(sadmm_t h, sadmm_cnn_t cnn, double threshold) {

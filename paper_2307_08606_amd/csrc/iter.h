@@ -163,4 +163,4 @@ void launch_refine_grad(const IterArgs& a, int st, int max_nq, const double* e, 
 void launch_refine_fix(const IterArgs& a, int st, int max_nq, const double* w, const double* g,
                        double cinv, void* xfix, hipStream_t s);
 void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,
-                           hipStream_t s);
+                           hipStream_t s, bool cplx = false);

@@ -256,6 +256,7 @@ struct DotExtra {
   int q0;               // WY / XY: first sensor of the launch
   int accumulate;       // GRAD: add to out
   void* out32;          // GRAD (accumulate): g in compute precision; FIX: xfix
+  int cplx;             // MF: write A^H y itself (complex128) instead of |A^H y|
   double cinv;          // FIX: 1 / c
 };
 
@@ -520,6 +521,9 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     } else if constexpr (EPI == EPI_FIX) {
       const int64_t o = (int64_t)q * a.N + sd.J[p];
       stc<T>(x.out32, o, C2<T>{(T)(x.cinv * (x.out[2 * o] - d.re)), (T)(x.cinv * (x.out[2 * o + 1] - d.im))});
+    } else if (x.cplx) {
+      x.out[2 * ((int64_t)q * a.N + p)] = d.re;
+      x.out[2 * ((int64_t)q * a.N + p) + 1] = d.im;
     } else {
       x.out[(int64_t)q * a.N + p] = hypot(d.re, d.im);
     }
@@ -960,25 +964,26 @@ void launch_refine_fix(const IterArgs& a, int st, int max_nq, const double* w, c
 }
 
 template <int ST>
-static void mf_impl(const IterArgs& a, const double* y, double* out, hipStream_t s) {
+static void mf_impl(const IterArgs& a, const double* y, double* out, bool cplx, hipStream_t s) {
   using T = typename Store<ST>::T;
   DotExtra x{};
   x.vec = y;
   x.vec_stride = a.KMp;
   x.out = out;
+  x.cplx = cplx ? 1 : 0;
   const int cpb = 4 * dot_cols<ST>();
   const size_t smem = (size_t)sv_len<ST>(a.KMp) * sizeof(cd);
   coldot_kernel<ST, EPI_MF><<<dim3((a.N + cpb - 1) / cpb, a.Q), 256, smem, s>>>(a, x);
 }
 
 void launch_matched_filter(const IterArgs& a, int st, bool dbl, const double* y, double* out,
-                           hipStream_t s) {
+                           hipStream_t s, bool cplx) {
   (void)dbl;
   switch (st) {
-    case ST_FP64: mf_impl<ST_FP64>(a, y, out, s); break;
-    case ST_FP32: mf_impl<ST_FP32>(a, y, out, s); break;
-    case ST_FP16P: mf_impl<ST_FP16P>(a, y, out, s); break;
-    case ST_BF16P: mf_impl<ST_BF16P>(a, y, out, s); break;
-    case ST_MF: mf_impl<ST_MF>(a, y, out, s); break;
+    case ST_FP64: mf_impl<ST_FP64>(a, y, out, cplx, s); break;
+    case ST_FP32: mf_impl<ST_FP32>(a, y, out, cplx, s); break;
+    case ST_FP16P: mf_impl<ST_FP16P>(a, y, out, cplx, s); break;
+    case ST_BF16P: mf_impl<ST_BF16P>(a, y, out, cplx, s); break;
+    case ST_MF: mf_impl<ST_MF>(a, y, out, cplx, s); break;
   }
 }

@@ -45,6 +45,13 @@ void iota_int(int* dst, int n, hipStream_t s);
 void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, hipStream_t s);
 void diff_norm2_c64(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
 void maxabs_c(const void* x, bool dbl, int64_t n, double* out, hipStream_t s);
+void bp_sum(const double* c, int Q, int64_t N, double* out, hipStream_t s);
+// out[0] = |F (a - b)[J]|^2 (F Hermitian nq x nq, leading dimension fld)
+void herm_apply_norm2(const double* F, int fld, int nq, const int* J, const double* a, const double* b,
+                      double* out, hipStream_t s);
+// max |x| into mx[0], then out[i] = number of thr[L] * mx (L < 255) <= |x_i|
+void render_levels(const double* x, bool cplx, int64_t n, const double* thr, double* mx, uint8_t* out,
+                   hipStream_t s);
 // dst = src * scale (complex128 vectors of n entries)
 void scale_c128(const double* src, double* dst, int n, double scale, hipStream_t s);
 // complex copy with precision change: dst (T) = src (complex128) for n entries

@@ -271,12 +271,108 @@ __global__ __launch_bounds__(1024) void maxabs_kernel(const T* x, int64_t n, dou
   }
 }
 
+// out[n] = |sum_q c[q N + n]| (c complex128, Q x N).
+__global__ __launch_bounds__(256) void bp_sum_kernel(const double* __restrict__ c, int Q, int64_t N,
+                                                     double* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < Q; ++q) {
+    re += c[2 * (q * N + n)];
+    im += c[2 * (q * N + n) + 1];
+  }
+  out[n] = hypot(re, im);
+}
+
+// Rendering level of pixel n: the number of thresholds thr[L] * mx (L < 255,
+// ascending) at or below |x_n|; x real (cplx = 0) or complex128.
+__global__ __launch_bounds__(256) void level_kernel(const double* __restrict__ x, int cplx, int64_t n,
+                                                   const double* __restrict__ thr, const double* __restrict__ mx,
+                                                   uint8_t* __restrict__ out) {
+  __shared__ double t[255];
+  const double m = mx[0];
+  for (int i = threadIdx.x; i < 255; i += 256) t[i] = thr[i] * m;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = cplx ? hypot(x[2 * i], x[2 * i + 1]) : fabs(x[i]);
+  int lo = 0, hi = 255;                  // count of t[k] <= v: first k with t[k] > v
+  if (m > 0.0) {
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (t[mid] <= v) lo = mid + 1;
+      else hi = mid;
+    }
+  }
+  out[i] = (uint8_t)lo;
+}
+
+// max |x_i| over n real doubles, one work-group.
+__global__ __launch_bounds__(1024) void maxabs_real_kernel(const double* x, int64_t n, double* out) {
+  __shared__ double sm[16];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, fabs(x[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < 16; ++w) r = fmax(r, sm[w]);
+    out[0] = r;
+  }
+}
+
+// out[0] += sum_p |sum_i conj(F[i, p]) (a - b)[J[i]]|^2 over p < nq: the
+// squared norm of F (a - b) restricted to the active pixels J (F Hermitian,
+// column-major with leading dimension fld; a, b complex128 by pixel).  One
+// wave per column.
+__global__ __launch_bounds__(256) void herm_apply_norm2_kernel(const double* __restrict__ F, int fld, int nq,
+                                                              const int* __restrict__ J,
+                                                              const double* __restrict__ a,
+                                                              const double* __restrict__ b,
+                                                              double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= nq) return;
+  const double* col = F + 2 * (int64_t)p * fld;
+  double re = 0.0, im = 0.0;
+  for (int i = lane; i < nq; i += 64) {
+    const int n = J[i];
+    const double dr = a[2 * n] - b[2 * n], di = a[2 * n + 1] - b[2 * n + 1];
+    const double fr = col[2 * i], fi = col[2 * i + 1];
+    re += fr * dr + fi * di;     // conj(f) * d
+    im += fr * di - fi * dr;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  if (lane == 0) atomicAdd(out, re * re + im * im);
+}
+
 inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
 
 void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
   diff_norm2_kernel<double><<<1, 1024, 0, s>>>(a, b, n, out);
+}
+
+void herm_apply_norm2(const double* F, int fld, int nq, const int* J, const double* a, const double* b,
+                      double* out, hipStream_t s) {
+  hipMemsetAsync(out, 0, sizeof(double), s);
+  if (nq > 0) herm_apply_norm2_kernel<<<(nq + 3) / 4, 256, 0, s>>>(F, fld, nq, J, a, b, out);
+}
+
+void bp_sum(const double* c, int Q, int64_t N, double* out, hipStream_t s) {
+  bp_sum_kernel<<<blocks(N), 256, 0, s>>>(c, Q, N, out);
+}
+
+void render_levels(const double* x, bool cplx, int64_t n, const double* thr, double* mx, uint8_t* out,
+                   hipStream_t s) {
+  if (cplx) maxabs_kernel<double><<<1, 1024, 0, s>>>(x, n, mx);
+  else maxabs_real_kernel<<<1, 1024, 0, s>>>(x, n, mx);
+  level_kernel<<<blocks(n), 256, 0, s>>>(x, cplx ? 1 : 0, n, thr, mx, out);
 }
 
 void maxabs_c(const void* x, bool dbl, int64_t n, double* out, hipStream_t s) {

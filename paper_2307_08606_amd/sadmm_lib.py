@@ -120,6 +120,9 @@ sadmm_cnn_destroy = _sig("sadmm_cnn_destroy", None, _H)
 sadmm_cnn_last_error = _sig("sadmm_cnn_last_error", C.c_char_p, _H)
 sadmm_set_pruning_cnn = _sig("sadmm_set_pruning_cnn", C.c_int, _H, _H, C.c_double)
 sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
+sadmm_back_projection = _sig("sadmm_back_projection", C.c_int, _H, _P, C.c_int32, C.c_int32, _P)
+sadmm_render_db = _sig("sadmm_render_db", C.c_int, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32, _P,
+                       C.c_void_p)
 sadmm_probe_bandwidth = _sig("sadmm_probe_bandwidth", C.c_int, C.c_int32, _P, _P, C.c_int64, C.c_int32,
                              C.c_void_p, C.POINTER(C.c_double))
 sadmm_probe_mfma = _sig("sadmm_probe_mfma", C.c_int, C.c_int32, C.c_int32, C.c_void_p,
@@ -305,6 +308,14 @@ class Solver:
                                          _ptr(out)))
         return out
 
+    def back_projection(self, y) -> np.ndarray:
+        """|sum_q A_q^H y_q| (N doubles)."""
+        if isinstance(y, np.ndarray):
+            y = np.ascontiguousarray(y)
+        out = np.empty(self.N, np.float64)
+        self._check(sadmm_back_projection(self._h, _ptr(y), _dtype_code(y), _on_device(y), _ptr(out)))
+        return out
+
     def set_pruning_cnn(self, cnn, threshold=0.5):
         self._cnn = cnn
         self._check(sadmm_set_pruning_cnn(self._h, cnn._h if cnn is not None else None, threshold))
@@ -331,6 +342,21 @@ class Solver:
             self._check(sadmm_get_timing(self._h, i, C.byref(v)))
             out[k] = v.value
         return out
+
+
+def render_db(img, range_db=30.0, stream=None) -> np.ndarray:
+    """8-bit levels of |img| on a range_db dynamic range (host array in, host
+    array out; real float64 or complex128)."""
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    x = np.ascontiguousarray(img)
+    cplx = np.iscomplexobj(x)
+    x = np.ascontiguousarray(x.astype(np.complex128 if cplx else np.float64, copy=False).ravel())
+    out = np.empty(x.size, np.uint8)
+    rc = sadmm_render_db(_ptr(x), 1 if cplx else 0, x.size, float(range_db), 0, _ptr(out), C_void(stream))
+    if rc != SADMM_OK:
+        raise SadmmError(rc, "sadmm_render_db failed")
+    return out
 
 
 def probe_bandwidth_gbps(kind="copy", nbytes=1 << 30, reps=10, stream=None):
