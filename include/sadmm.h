@@ -128,6 +128,12 @@ typedef struct {
                                  most eps_pri under the new g (the change of
                                  (mu Ahat^H Ahat + cI)^{-1} g over the active
                                  pixels), else it iterates on.  0 (default): off */
+  int32_t nonneg;             /* 1: the image is a non-negative magnitude (Sec. II):
+                                 z = max(Re(xbar + u) - lambda / beta, 0) instead
+                                 of the complex soft threshold.  With a real
+                                 stacked operator (sadmm_stack_real) and real
+                                 stacked measurements, every x_q stays real.
+                                 0 (default): complex image */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 
@@ -374,6 +380,19 @@ int sadmm_set_profiling(sadmm_t h, int32_t level);
  * at least once). */
 int sadmm_get_kernel_stats(sadmm_t h, int32_t kclass, int32_t* launches, double* total_ms,
                            double* work);
+
+/* Real form of the model for a real unknown (Sec. II, x_q the magnitude):
+ * |y - A x|^2 = |[Re y; Im y] - [Re A; Im A] x|^2.  Writes the stacked real
+ * matrix [Re S; Im S] of the complex rows x cols column-major matrix S (dtype,
+ * leading dimension ld >= rows) as complex128 with zero imaginary parts,
+ * (2 rows) x cols column-major, leading dimension 2 rows, into dst.  Both are
+ * caller-owned device pointers; the work runs on the given hipStream_t and
+ * the call returns after it.  An operator A_q (KM x N) becomes one of 2 KM
+ * rows; the measurements (Q x KM, sensor-major) are the KM x Q matrix with
+ * ld = KM.  A handle for the stacked problem is created with K * M = 2 KM
+ * (for example K doubled). */
+int sadmm_stack_real(const void* src, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, void* dst,
+                     void* stream);
 
 /* ---------------------------------------------------------------------------
  * Roofline probes (no part of the method): the device's own bandwidth and

@@ -14,10 +14,10 @@ Modules
 """
 
 from .sadmm import (Params, Result, solve, soft_threshold, kkt_gradient, residual_norms,
-                    matched_filter)
+                    matched_filter, nonneg_threshold, stack_real)
 from .lambda_max import lambda_max
 from .render import back_projection, render_db, db_thresholds
 
-__all__ = ["Params", "Result", "solve", "soft_threshold", "kkt_gradient",
+__all__ = ["Params", "Result", "solve", "soft_threshold", "nonneg_threshold", "stack_real", "kkt_gradient",
            "residual_norms", "lambda_max", "matched_filter", "back_projection", "render_db",
            "db_thresholds"]

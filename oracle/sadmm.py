@@ -33,6 +33,12 @@ these points; each reading is the one that makes eq. (3) a convergent method):
   whenever the sensors' row spaces barely intersect).  With gamma > 0 the
   optimum is unique.  x-update: (mu A^H A + (beta+gamma) I) x = mu A^H y + beta v.
 * x_q is complex; S_tau(v) = v * max(0, 1 - tau/|v|), S_tau(0) = 0.
+  The magnitude variant (x_q real, the image a non-negative magnitude): the
+  real stacked model of stack_real, and with nonneg=True the z-update
+  z = max(Re(xbar + u) - tau, 0).  Non-negativity is put on the shared image
+  only: on every x_q it would make sum_q x_q >= 0 entrywise, so that
+  ||sum_q x_q||_1 = sum_q sum_n x_q[n] and the problem would split into Q
+  unrelated non-negative LASSO problems.
 * Residuals (the paper defers them to earlier work) follow Boyd Sec. 3.3.1
   on the replicated form: r = sqrt(Q) ||xbar - z||,
   s = beta ||Z^k - Z^{k-1}||_F with Z^k[q] = x_q^k + z^k - xbar^k (Z^0 = 0),
@@ -106,6 +112,7 @@ class Params:
     kkt: bool = False
     kkt_tol: float = 0.0       # <= 0: 10 * eps_rel
     kkt_rounds: int = 8
+    nonneg: bool = False       # z-update projected on the non-negative reals
 
 
 @dataclass
@@ -123,6 +130,22 @@ class Result:
 
     def active_indices(self, q: int) -> np.ndarray:
         return np.flatnonzero(self.active[q])
+
+
+def nonneg_threshold(v: np.ndarray, tau: float) -> np.ndarray:
+    """Proximal map of tau*|.| plus the indicator of the non-negative reals:
+    argmin_{z >= 0} tau z + 1/2 |z - v|^2 = max(Re v - tau, 0) (the image as
+    a magnitude, Sec. II; the imaginary part of v only adds a constant)."""
+    return np.maximum(np.real(v) - tau, 0.0).astype(np.complex128)
+
+
+def stack_real(A, y):
+    """The real form of the model for a real unknown x (Sec. II, x_q the
+    magnitude): |y - A x|^2 = |[Re y; Im y] - [Re A; Im A] x|^2, returned as
+    complex128 arrays with zero imaginary parts (2 KM rows)."""
+    As = [np.vstack([np.real(a), np.imag(a)]).astype(np.complex128) for a in A]
+    ys = np.stack([np.concatenate([np.real(v), np.imag(v)]) for v in np.asarray(y)]).astype(np.complex128)
+    return As, ys
 
 
 def soft_threshold(v: np.ndarray, tau: float) -> np.ndarray:
@@ -251,7 +274,7 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
             v = (X[q] - xb + z - u)[J]
             Xn[q, J] = sv.solve(b0[q] + beta * v)
         xbn = Xn.mean(axis=0)
-        zn = soft_threshold(xbn + u, tau)                 # eq. (3), row 2
+        zn = (nonneg_threshold if p.nonneg else soft_threshold)(xbn + u, tau)   # eq. (3), row 2
         un = u + xbn - zn                                 # eq. (3), row 3
         r, s, nX, nZ, nu = residual_norms(Xn, zn, un, xbn, X, z, xb, beta)
         eps_pri = sqQN * p.eps_abs + p.eps_rel * max(nX, nZ)

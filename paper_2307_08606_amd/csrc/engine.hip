@@ -245,6 +245,7 @@ IterArgs make_args(sadmm_t h) {
   a.c = h->p.beta + h->p.gamma;
   a.bc = a.beta / a.c;
   a.tau = h->p.lambda / h->p.beta;
+  a.nonneg = h->p.nonneg;
   a.eps_abs = h->p.eps_abs; a.eps_rel = h->p.eps_rel; a.eps_p = h->p.eps_p;
   a.inv_Q = 1.0 / h->Q;
   a.nmse_target = h->nmse_target;
@@ -809,6 +810,7 @@ int validate(const sadmm_params* p) {
   if (p->gram < 0 || p->gram > 1) return SADMM_E_ARG;
   if (p->direct < 0 || p->direct > 1) return SADMM_E_ARG;
   if (p->refine_every < 0) return SADMM_E_ARG;
+  if (p->nonneg < 0 || p->nonneg > 1) return SADMM_E_ARG;
   if (p->refine_every > 0 && p->storage != SADMM_ST_FP16P && p->storage != SADMM_ST_BF16P)
     return SADMM_E_ARG;   // the correction is for 16-bit storage
   if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
@@ -1912,6 +1914,16 @@ int sadmm_back_projection(sadmm_t h, const void* y, int32_t dtype, int32_t on_de
   release();
   h->solved = false;
   return rc;
+}
+
+int sadmm_stack_real(const void* src, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, void* dst,
+                     void* stream) {
+  if (!src || !dst || rows < 1 || cols < 1 || ld < rows || (dtype != SADMM_C128 && dtype != SADMM_C64))
+    return SADMM_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  stack_real(src, dtype == SADMM_C128, rows, cols, ld, static_cast<double*>(dst), s);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return SADMM_E_HIP;
+  return SADMM_OK;
 }
 
 int sadmm_render_db(const void* img, int32_t is_complex, int64_t n, double range_db, int32_t on_device,

@@ -29,7 +29,7 @@ struct SensorDesc {
 struct IterArgs {
   int Q, KMp, N, Kp;
   int chunk, nchunk;   // forward kernel: columns per work-group, chunks per sensor
-  int prune, stop;
+  int prune, stop, nonneg;
   double beta, c, tau, eps_abs, eps_rel, eps_p, inv_Q;
   double bc;           // beta / c
   double nmse_target, xref_norm2;

@@ -619,7 +619,9 @@ __global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
     const T mag = habs(v);
     const T tau = (T)a.tau;
     C2<T> zn = {(T)0, (T)0};
-    if (mag > tau) {
+    if (a.nonneg) {             // projection on the non-negative reals
+      if (v.re > tau) zn.re = v.re - tau;
+    } else if (mag > tau) {
       const T sc = (T)1 - tau / mag;
       zn = {v.re * sc, v.im * sc};
     }

@@ -350,6 +350,21 @@ __global__ __launch_bounds__(256) void herm_apply_norm2_kernel(const double* __r
   if (lane == 0) atomicAdd(out, re * re + im * im);
 }
 
+// dst[n (2 rows) + i] = (Re S[i, n], 0), dst[n (2 rows) + rows + i] = (Im S[i, n], 0)
+template <class T>
+__global__ __launch_bounds__(256) void stack_real_kernel(const T* __restrict__ src, int64_t rows, int64_t cols,
+                                                         int64_t ld, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t n = e / rows, i = e - n * rows;
+  const T* s = src + 2 * (n * ld + i);
+  double* d = dst + 2 * (n * 2 * rows + i);
+  d[0] = (double)s[0];
+  d[1] = 0.0;
+  d[2 * rows] = (double)s[1];
+  d[2 * rows + 1] = 0.0;
+}
+
 inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
@@ -362,6 +377,13 @@ void herm_apply_norm2(const double* F, int fld, int nq, const int* J, const doub
                       double* out, hipStream_t s) {
   hipMemsetAsync(out, 0, sizeof(double), s);
   if (nq > 0) herm_apply_norm2_kernel<<<(nq + 3) / 4, 256, 0, s>>>(F, fld, nq, J, a, b, out);
+}
+
+void stack_real(const void* src, bool c128, int64_t rows, int64_t cols, int64_t ld, double* dst, hipStream_t s) {
+  const int64_t n = rows * cols;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (c128) stack_real_kernel<double><<<g, 256, 0, s>>>(static_cast<const double*>(src), rows, cols, ld, dst);
+  else stack_real_kernel<float><<<g, 256, 0, s>>>(static_cast<const float*>(src), rows, cols, ld, dst);
 }
 
 void bp_sum(const double* c, int Q, int64_t N, double* out, hipStream_t s) {

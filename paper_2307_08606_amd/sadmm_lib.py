@@ -47,7 +47,8 @@ class sadmm_params(C.Structure):
         ("prune", C.c_int32), ("Kp", C.c_int32), ("eps_p", C.c_double),
         ("prune_mode", C.c_int32), ("kkt", C.c_int32), ("kkt_tol", C.c_double),
         ("storage", C.c_int32), ("reuse_factor", C.c_int32), ("gram", C.c_int32),
-        ("direct", C.c_int32), ("refine_every", C.c_int32), ("stream", C.c_void_p),
+        ("direct", C.c_int32), ("refine_every", C.c_int32), ("nonneg", C.c_int32),
+        ("stream", C.c_void_p),
     ]
 
 
@@ -121,6 +122,8 @@ sadmm_cnn_last_error = _sig("sadmm_cnn_last_error", C.c_char_p, _H)
 sadmm_set_pruning_cnn = _sig("sadmm_set_pruning_cnn", C.c_int, _H, _H, C.c_double)
 sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
 sadmm_back_projection = _sig("sadmm_back_projection", C.c_int, _H, _P, C.c_int32, C.c_int32, _P)
+sadmm_stack_real = _sig("sadmm_stack_real", C.c_int, _P, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P,
+                        C.c_void_p)
 sadmm_render_db = _sig("sadmm_render_db", C.c_int, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32, _P,
                        C.c_void_p)
 sadmm_probe_bandwidth = _sig("sadmm_probe_bandwidth", C.c_int, C.c_int32, _P, _P, C.c_int64, C.c_int32,
@@ -165,8 +168,8 @@ class Solver:
     def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
                  eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=0.0, storage="fp32",
-                 reuse_factor=True, gram="int8", direct=True, refine_every=0, stream=None,
-                 share=None):
+                 reuse_factor=True, gram="int8", direct=True, refine_every=0, nonneg=False,
+                 stream=None, share=None):
         p = sadmm_params()
         sadmm_default_params(C.byref(p))
         p.Q, p.K, p.M, p.N = Q, K, M, N
@@ -181,6 +184,7 @@ class Solver:
         p.gram = {"int8": 0, "fp64": 1}[gram]
         p.direct = 0 if direct else 1
         p.refine_every = int(refine_every)
+        p.nonneg = int(bool(nonneg))
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -342,6 +346,22 @@ class Solver:
             self._check(sadmm_get_timing(self._h, i, C.byref(v)))
             out[k] = v.value
         return out
+
+
+def stack_real(t, stream=None):
+    """[Re S; Im S] (complex128, zero imaginary parts) of a complex device
+    tensor S: an operator (N, KM) stored column-major as the tensor's rows
+    (pixel-major, KM contiguous) gives (N, 2 KM); measurements (Q, KM) give
+    (Q, 2 KM)."""
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    assert t.is_cuda and t.is_contiguous() and t.dim() == 2
+    cols, rows = int(t.shape[0]), int(t.shape[1])
+    out = torch.empty((cols, 2 * rows), dtype=torch.complex128, device=t.device)
+    rc = sadmm_stack_real(t.data_ptr(), _dtype_code(t), rows, cols, rows, out.data_ptr(), C_void(stream))
+    if rc != SADMM_OK:
+        raise SadmmError(rc, "sadmm_stack_real failed")
+    return out
 
 
 def render_db(img, range_db=30.0, stream=None) -> np.ndarray:
