@@ -134,6 +134,17 @@ typedef struct {
                                  stacked operator (sadmm_stack_real) and real
                                  stacked measurements, every x_q stays real.
                                  0 (default): complex image */
+  int32_t balance_every;      /* residual balancing (Boyd et al. 2011, Sec. 3.4.1):
+                                 after every balance_every-th iteration that has not
+                                 converged, beta is multiplied by balance_tau when
+                                 r > balance_mu s and divided by it when
+                                 s > balance_mu r; the scaled dual u is divided by
+                                 the same factor (beta u unchanged) and every factor
+                                 is rebuilt for c = beta + gamma (gamma, which fixes
+                                 the problem, stays).  Each later solve starts from
+                                 the beta given here.  0 (default): off */
+  double balance_mu;          /* > 1 (default 10) */
+  double balance_tau;         /* > 1 (default 2) */
   void* stream;               /* hipStream_t */
 } sadmm_params;
 
@@ -252,7 +263,8 @@ int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count)
 /* Per-iteration history of the last solve (host buffers of capacity cap):
  * which = 0 r, 1 s, 2 eps_pri, 3 eps_dual, 4 nmse, 5 max_q N_q / N,
  * 6 change of the x-update when a stale 16-bit correction was retaken at a
- * passed stop test (0 at other iterations; compared with eps_pri).
+ * passed stop test (0 at other iterations; compared with eps_pri),
+ * 7 beta in force after the iteration (residual balancing).
  * *count receives the number of iterations recorded. */
 int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap,
                       int32_t* count);

@@ -88,7 +88,7 @@ exact up to rounding; which one is used is not part of the method.
 
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import List, Optional
 
 import numpy as np
@@ -113,6 +113,9 @@ class Params:
     kkt_tol: float = 0.0       # <= 0: 10 * eps_rel
     kkt_rounds: int = 8
     nonneg: bool = False       # z-update projected on the non-negative reals
+    balance_every: int = 0     # residual balancing every this many iterations (0: off)
+    balance_mu: float = 10.0   # imbalance ratio that triggers a change
+    balance_tau: float = 2.0   # factor beta is multiplied or divided by
 
 
 @dataclass
@@ -253,7 +256,7 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
         setup(q)
 
     hist = {k: [] for k in ("r", "s", "eps_pri", "eps_dual", "max_active_frac",
-                            "active", "nmse", "pruned")}
+                            "active", "nmse", "pruned", "beta")}
     if record_iterates:
         hist["X"], hist["z"], hist["u"], hist["masks"] = [], [], [], []
     prune_events = 0
@@ -315,6 +318,24 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
             if pruned_now:
                 prune_events += 1
         hist["pruned"].append(pruned_now)
+        # residual balancing (Boyd et al. 2011, Sec. 3.4.1): beta up when the
+        # primal residual dominates, down when the dual one does; the scaled
+        # dual is rescaled so that the unscaled one (beta u) is unchanged, and
+        # every x-update is refactored for the new c = beta + gamma
+        if (not done) and p.balance_every > 0 and k % p.balance_every == 0 and k < p.max_iter:
+            f = 1.0
+            if r > p.balance_mu * s:
+                f = p.balance_tau
+            elif s > p.balance_mu * r:
+                f = 1.0 / p.balance_tau
+            if f != 1.0:
+                u = u / f
+                beta *= f
+                c = beta + gamma
+                tau = p.lam / beta
+                for q in range(Q):
+                    setup(q)
+        hist["beta"].append(beta)
         counts = active.sum(axis=1)
         hist["active"].append(counts.copy())
         hist["max_active_frac"].append(float(counts.max()) / N)
@@ -326,13 +347,13 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
         if done:
             if p.kkt and (p.prune or start_restricted) and (~active).any():
                 if kkt_rounds >= p.kkt_rounds:
-                    left = _reinstate(A, y, X, u, p, active, yp, D, check_only=True)
+                    left = _reinstate(A, y, X, u, replace(p, beta=beta), active, yp, D, check_only=True)
                     if left:
                         violations = left
                         break
                 else:
                     kkt_rounds += 1
-                    back = _reinstate(A, y, X, u, p, active, yp, D)
+                    back = _reinstate(A, y, X, u, replace(p, beta=beta), active, yp, D)
                     if back:
                         reinstated += back
                         for q in range(Q):

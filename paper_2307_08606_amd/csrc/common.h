@@ -240,7 +240,8 @@ struct Ctl {
   int nan;          // non-finite value seen
   int gone_total;   // pixels SSC decided to eliminate at the last iteration
   int max_iter;
-  int pad[2];
+  int bal;          // residual balancing at the last iteration: +1 beta up, -1 down, 0 none
+  int pad;
   double r, s, eps_pri, eps_dual, nmse;
 };
-enum : int { HALT_CONV = 1, HALT_PRUNE = 2, HALT_MAXIT = 4, HALT_NAN = 8, HALT_NMSE = 16 };
+enum : int { HALT_CONV = 1, HALT_PRUNE = 2, HALT_MAXIT = 4, HALT_NAN = 8, HALT_NMSE = 16, HALT_BAL = 32 };

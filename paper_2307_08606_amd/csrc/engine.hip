@@ -118,7 +118,7 @@ struct sadmm_s {
 
   // results of the last solve
   sadmm_info info{};
-  std::vector<double> hist_h;   // 7 x max_iter
+  std::vector<double> hist_h;   // 8 x max_iter
   int hist_count = 0;
   double t_total = 0, t_factor = 0, t_iter = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
@@ -133,6 +133,9 @@ struct sadmm_s {
   hipGraphExec_t gexec = nullptr;
   // per-solve loop state
   std::vector<std::pair<int, double>> frac_pts;   // (iteration, max active fraction from it on)
+  std::vector<std::pair<int, double>> beta_pts;   // (iteration, beta in force after it)
+  double beta0 = 1.0;              // the beta of the parameters (balancing changes p.beta in a solve)
+  bool args_dirty = false;         // the device copy of the iteration arguments is stale
   int kkt_rounds = 0, status = 1;
   bool done = false;
   bool start_restricted = false;   // the solve started with eliminated pixels
@@ -246,6 +249,8 @@ IterArgs make_args(sadmm_t h) {
   a.bc = a.beta / a.c;
   a.tau = h->p.lambda / h->p.beta;
   a.nonneg = h->p.nonneg;
+  a.bal_every = h->p.balance_every;
+  a.bal_mu = h->p.balance_mu;
   a.eps_abs = h->p.eps_abs; a.eps_rel = h->p.eps_rel; a.eps_p = h->p.eps_p;
   a.inv_Q = 1.0 / h->Q;
   a.nmse_target = h->nmse_target;
@@ -811,6 +816,8 @@ int validate(const sadmm_params* p) {
   if (p->direct < 0 || p->direct > 1) return SADMM_E_ARG;
   if (p->refine_every < 0) return SADMM_E_ARG;
   if (p->nonneg < 0 || p->nonneg > 1) return SADMM_E_ARG;
+  if (p->balance_every < 0) return SADMM_E_ARG;
+  if (p->balance_every > 0 && !(p->balance_mu > 1.0 && p->balance_tau > 1.0)) return SADMM_E_ARG;
   if (p->refine_every > 0 && p->storage != SADMM_ST_FP16P && p->storage != SADMM_ST_BF16P)
     return SADMM_E_ARG;   // the correction is for 16-bit storage
   if (p->prune_mode < 0 || p->prune_mode > 1) return SADMM_E_ARG;
@@ -862,6 +869,10 @@ int solve_prologue(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
   for (int q = 0; q < h->Q; ++q)
     if (!h->op_set[q]) return fail_msg(h, SADMM_E_STATE, "solve: operator of sensor %d not set", q);
   if (h->p.refine_every > 0) TRY(refine_setup(h));
+  if (h->p.beta != h->beta0) {   // a balanced solve left another beta: its factors do not fit
+    h->p.beta = h->beta0;
+    for (int q = 0; q < h->Q; ++q) h->fac_valid[q] = false;
+  }
   hipStream_t s = h->s;
   h->info = sadmm_info{};
   h->solved = false;
@@ -983,6 +994,7 @@ int solve_prologue_finish(sadmm_t h) {
   hipEventElapsedTime(&fms, h->evf0, h->evf1);
   h->t_factor = fms;
   h->frac_pts.assign(1, {1, max_active_frac(h)});
+  h->beta_pts.assign(1, {1, h->p.beta});
   h->kkt_rounds = 0;
   h->k_refined = 0;
   h->retake_pts.clear();
@@ -1033,6 +1045,26 @@ int refine(sadmm_t h, int k) {
   return SADMM_OK;
 }
 
+// Residual balancing (Boyd et al. 2011, Sec. 3.4.1), decided on the device at
+// the last iteration: beta times or over balance_tau, the scaled dual divided
+// by the same factor (beta u unchanged), every factor rebuilt for the new
+// c = beta + gamma (the Woodbury ones in one batch), the arguments re-sent.
+int apply_balance(sadmm_t h, int dir) {
+  if (dir == 0) return SADMM_OK;
+  const double f = dir > 0 ? h->p.balance_tau : 1.0 / h->p.balance_tau;
+  scale_cplx(h->u, h->dbl, h->N, 1.0 / f, h->s);
+  h->p.beta *= f;
+  std::vector<int> wood;
+  for (int q = 0; q < h->Q; ++q) {
+    if (h->direct[q]) TRY(build_direct(h, q));
+    else wood.push_back(q);
+  }
+  TRY(rebuild_factors(h, wood));
+  for (int q = 0; q < h->Q; ++q) h->fac_valid[q] = false;
+  h->args_dirty = true;
+  return SADMM_OK;
+}
+
 // Handles the halt state of one scene after a status read.  Sets *active when
 // the scene keeps iterating.
 int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
@@ -1041,23 +1073,29 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
   float fms = 0.f;
   if (c.halt & HALT_NAN) return fail_msg(h, SADMM_E_NUMERIC, "non-finite residual at iteration %d", c.k);
   if (!c.halt) { *active = true; return SADMM_OK; }
-  if (c.halt & HALT_PRUNE) {
+  if (c.halt & (HALT_PRUNE | HALT_BAL)) {
     HIPCHK(h, hipEventRecord(h->evf0, s));
-    TRY(apply_prune(h));
+    if (c.halt & HALT_PRUNE) {
+      TRY(apply_prune(h));
+      h->info.prune_events += 1;
+      h->frac_pts.push_back({c.k, max_active_frac(h)});     // from the deciding iteration on
+    }
+    if (c.halt & HALT_BAL) {
+      TRY(apply_balance(h, c.bal));
+      h->beta_pts.push_back({c.k, h->p.beta});
+    }
     if (h->p.refine_every > 0) TRY(refine(h, c.k));
     HIPCHK(h, hipEventRecord(h->evf1, s));
     HIPCHK(h, hipEventSynchronize(h->evf1));
     hipEventElapsedTime(&fms, h->evf0, h->evf1);
     h->t_factor += fms;
-    h->info.prune_events += 1;
-    h->frac_pts.push_back({c.k, max_active_frac(h)});     // from the deciding iteration on
-    const int nh = c.halt & ~HALT_PRUNE;
+    const int nh = c.halt & ~(HALT_PRUNE | HALT_BAL);
     *h->halt_h = nh;
     HIPCHK(h, hipMemcpyAsync(&h->ctl->halt, h->halt_h, sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (nh == 0) { *active = true; return SADMM_OK; }
   }
-  const int hb = c.halt & ~HALT_PRUNE;
+  const int hb = c.halt & ~(HALT_PRUNE | HALT_BAL);
   if (hb & HALT_NMSE) { h->status = 2; h->done = true; return SADMM_OK; }
   if (hb & HALT_CONV) {
     bool any_frozen = false;
@@ -1266,6 +1304,13 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
       *h->ctl_h = ctl_all[i];
       bool active = false;
       rc = handle_halt(h, ctl_all[i], &active);
+      if (rc == SADMM_OK && h->args_dirty) {
+        const IterArgs an = make_args(h);
+        if (hipMemcpyAsync(args_d + i, &an, sizeof(IterArgs), hipMemcpyHostToDevice, gs) != hipSuccess ||
+            hipStreamSynchronize(gs) != hipSuccess)
+          rc = fail_msg(h, SADMM_E_HIP, "argument upload failed");
+        h->args_dirty = false;
+      }
       if (rc == SADMM_OK && active && h->p.refine_every > 0 &&
           ctl_all[i].k - h->k_refined >= h->p.refine_every)
         rc = refine(h, ctl_all[i].k);
@@ -1295,7 +1340,7 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
   HIPCHK(h, hipMemcpy(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
   const Ctl c = *h->ctl_h;
   h->hist_count = c.k;
-  h->hist_h.assign(7 * (size_t)h->p.max_iter, 0.0);
+  h->hist_h.assign(8 * (size_t)h->p.max_iter, 0.0);
   HIPCHK(h, hipMemcpy(h->hist_h.data(), h->hist, sizeof(double) * 5 * h->p.max_iter, hipMemcpyDeviceToHost));
   for (int k = 1; k <= c.k; ++k) {
     double f = h->frac_pts[0].second;
@@ -1305,6 +1350,12 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
   }
   for (auto& pt : h->retake_pts)
     if (pt.first >= 1 && pt.first <= h->p.max_iter) h->hist_h[6 * (size_t)h->p.max_iter + pt.first - 1] = pt.second;
+  for (int k = 1; k <= c.k; ++k) {
+    double b = h->beta_pts[0].second;
+    for (auto& pt : h->beta_pts)
+      if (pt.first <= k) b = pt.second;
+    h->hist_h[7 * (size_t)h->p.max_iter + k - 1] = b;
+  }
   h->info.iters = c.k;
   h->info.status = h->status;
   h->info.r = c.r; h->info.s = c.s; h->info.eps_pri = c.eps_pri; h->info.eps_dual = c.eps_dual;
@@ -1331,6 +1382,7 @@ void sadmm_default_params(sadmm_params* p) {
   p->max_iter = 200; p->stop = 1; p->check_every = 8;
   p->prune = 0; p->Kp = 5; p->eps_p = 1e-5; p->prune_mode = 0;
   p->kkt = 0; p->kkt_tol = 0.0;
+  p->balance_every = 0; p->balance_mu = 10.0; p->balance_tau = 2.0;
   p->storage = SADMM_ST_FP32;
   p->reuse_factor = 1;
   p->stream = nullptr;
@@ -1368,6 +1420,7 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   h->shared_src = src;
   if (src) src->n_sharers += 1;   // (given back by sadmm_destroy, also on a failed create)
   h->p = *p;
+  h->beta0 = p->beta;
   h->Q = p->Q; h->K = p->K; h->M = p->M; h->N = p->N;
   h->KM = p->K * p->M;
   h->KMp = round_up(h->KM, 32);
@@ -1836,7 +1889,7 @@ int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count)
 
 int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap, int32_t* count) {
   if (!h) return SADMM_E_ARG;
-  if (!out || !count || which < 0 || which > 6 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
+  if (!out || !count || which < 0 || which > 7 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
   if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_history: no solve yet");
   const int n = std::min(cap, h->hist_count);
   std::memcpy(out, h->hist_h.data() + (size_t)which * h->p.max_iter, sizeof(double) * n);

@@ -30,6 +30,8 @@ struct IterArgs {
   int Q, KMp, N, Kp;
   int chunk, nchunk;   // forward kernel: columns per work-group, chunks per sensor
   int prune, stop, nonneg;
+  int bal_every;       // residual balancing period (0: off)
+  double bal_mu;       // imbalance ratio
   double beta, c, tau, eps_abs, eps_rel, eps_p, inv_Q;
   double bc;           // beta / c
   double nmse_target, xref_norm2;

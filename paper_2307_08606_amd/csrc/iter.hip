@@ -686,6 +686,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchView bv) {
   if (a.stop && r <= eps_pri && s <= eps_dual) halt |= HALT_CONV;
   if (a.xref && a.nmse_target > 0.0 && nmse <= a.nmse_target) halt |= HALT_NMSE;
   if (k >= a.max_iter) halt |= HALT_MAXIT;
+  // residual balancing (Boyd et al. 2011, Sec. 3.4.1), decided here and
+  // applied by the host after this iteration's SSC check
+  int bal = 0;
+  if (a.bal_every > 0 && !(halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_MAXIT)) && k % a.bal_every == 0) {
+    if (r > a.bal_mu * s) bal = 1;
+    else if (s > a.bal_mu * r) bal = -1;
+    if (bal) halt |= HALT_BAL;
+  }
+  ctl->bal = bal;
   double* h = a.hist;
   const int mi = a.max_iter;
   h[0 * mi + k - 1] = r;

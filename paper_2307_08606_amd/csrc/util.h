@@ -55,6 +55,8 @@ void render_levels(const double* x, bool cplx, int64_t n, const double* thr, dou
                    hipStream_t s);
 // dst = src * scale (complex128 vectors of n entries)
 void scale_c128(const double* src, double* dst, int n, double scale, hipStream_t s);
+// x *= scale over n complex entries in place (complex128 when dbl, else complex64)
+void scale_cplx(void* x, bool dbl, int64_t n, double scale, hipStream_t s);
 // complex copy with precision change: dst (T) = src (complex128) for n entries
 void c128_to_compute(const double* src, void* dst, bool dbl, int n, hipStream_t s);
 void compute_to_c128(const void* src, bool dbl, double* dst, int n, hipStream_t s);

@@ -175,6 +175,11 @@ __global__ void iota_kernel(int* dst, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) dst[i] = i;
 }
+__global__ void scale_f32_kernel(float* x, int64_t n, float sc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] *= sc;
+}
+
 __global__ void scale_c128_kernel(const double* src, double* dst, int n2, double sc) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n2) dst[i] = src[i] * sc;
@@ -474,6 +479,12 @@ void set_ring_inf(void* D, bool dbl, int Kp, int Q, int N, int q, const int* idx
 void iota_int(int* dst, int n, hipStream_t s) {
   if (n > 0) iota_kernel<<<blocks(n), 256, 0, s>>>(dst, n);
 }
+void scale_cplx(void* x, bool dbl, int64_t n, double scale, hipStream_t s) {
+  if (n <= 0) return;
+  if (dbl) scale_c128_kernel<<<blocks(2 * n), 256, 0, s>>>(static_cast<double*>(x), static_cast<double*>(x), (int)(2 * n), scale);
+  else scale_f32_kernel<<<blocks(2 * n), 256, 0, s>>>(static_cast<float*>(x), 2 * n, (float)scale);
+}
+
 void scale_c128(const double* src, double* dst, int n, double scale, hipStream_t s) {
   if (n > 0) scale_c128_kernel<<<blocks(2 * (int64_t)n), 256, 0, s>>>(src, dst, 2 * n, scale);
 }

@@ -34,7 +34,7 @@ ST_FP64, ST_FP32, ST_FP16P, ST_BF16P, ST_MATRIX_FREE = 0, 1, 2, 3, 4
 STORAGE = {"fp64": ST_FP64, "fp32": ST_FP32, "fp16": ST_FP16P, "bf16": ST_BF16P,
            "mf": ST_MATRIX_FREE}
 HIST = {"r": 0, "s": 1, "eps_pri": 2, "eps_dual": 3, "nmse": 4, "max_active_frac": 5,
-        "retake_change": 6}
+        "retake_change": 6, "beta": 7}
 
 
 class sadmm_params(C.Structure):
@@ -48,6 +48,7 @@ class sadmm_params(C.Structure):
         ("prune_mode", C.c_int32), ("kkt", C.c_int32), ("kkt_tol", C.c_double),
         ("storage", C.c_int32), ("reuse_factor", C.c_int32), ("gram", C.c_int32),
         ("direct", C.c_int32), ("refine_every", C.c_int32), ("nonneg", C.c_int32),
+        ("balance_every", C.c_int32), ("balance_mu", C.c_double), ("balance_tau", C.c_double),
         ("stream", C.c_void_p),
     ]
 
@@ -169,7 +170,7 @@ class Solver:
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
                  eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=0.0, storage="fp32",
                  reuse_factor=True, gram="int8", direct=True, refine_every=0, nonneg=False,
-                 stream=None, share=None):
+                 balance_every=0, balance_mu=10.0, balance_tau=2.0, stream=None, share=None):
         p = sadmm_params()
         sadmm_default_params(C.byref(p))
         p.Q, p.K, p.M, p.N = Q, K, M, N
@@ -185,6 +186,7 @@ class Solver:
         p.direct = 0 if direct else 1
         p.refine_every = int(refine_every)
         p.nonneg = int(bool(nonneg))
+        p.balance_every, p.balance_mu, p.balance_tau = int(balance_every), balance_mu, balance_tau
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

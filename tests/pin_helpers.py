@@ -172,3 +172,40 @@ def misfit_gradient_fd(A, y, h=1e-3):
         gi = (f(e) - f(-e)) / (2 * h)
         g[n] = gr + 1j * gi
     return g
+
+
+def lasso_admm_boyd_balanced(A, y, mu, beta, gamma, lam, iters, eps_abs, eps_rel, every,
+                             mu_b=10.0, tau_b=2.0):
+    """lasso_admm_boyd with Boyd et al. 2011 Sec. 3.4.1 residual balancing:
+    after iteration k (k a multiple of `every`), rho <- tau rho if r > mu_b s,
+    rho <- rho / tau if s > mu_b r, the scaled dual divided by the same factor
+    (the unscaled dual rho u is unchanged).  Returns per-iteration
+    (z, r, s, eps_pri, eps_dual, rho after the iteration)."""
+    N = A.shape[1]
+    AhA = mu * A.conj().T @ A
+    Aty = mu * A.conj().T @ y
+    rho = beta
+    Minv = np.linalg.inv(AhA + (gamma + rho) * np.eye(N))
+    x = np.zeros(N, complex)
+    z = np.zeros(N, complex)
+    u = np.zeros(N, complex)
+    out = []
+    for k in range(1, iters + 1):
+        x = Minv @ (Aty + rho * (z - u))
+        v = x + u
+        m = np.abs(v)
+        zn = np.where(m > lam / rho, v * (1 - (lam / rho) / np.maximum(m, 1e-300)), 0)
+        u = u + x - zn
+        r = np.linalg.norm(x - zn)
+        s = rho * np.linalg.norm(zn - z)
+        z = zn
+        ep = np.sqrt(N) * eps_abs + eps_rel * max(np.linalg.norm(x), np.linalg.norm(z))
+        ed = np.sqrt(N) * eps_abs + eps_rel * np.linalg.norm(rho * u)
+        if k % every == 0 and k < iters:
+            f = tau_b if r > mu_b * s else (1.0 / tau_b if s > mu_b * r else 1.0)
+            if f != 1.0:
+                rho *= f
+                u = u / f
+                Minv = np.linalg.inv(AhA + (gamma + rho) * np.eye(N))
+        out.append((z.copy(), r, s, ep, ed, rho))
+    return out
