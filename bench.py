@@ -150,17 +150,14 @@ def probes(torch, lib):
 
 def asadmm_leg(torch, lib, stream, g, hp, y_dev, xref_dev, eps_list=(1e-4, 1e-5), reps=2):
     """The paper's comparison (Sec. IV): accelerated (SSC pruning, Alg. 1) vs
-    plain SADMM, both FP32, run to the relative residual tolerance; the
-    accelerated solve as the paper gives it (pruned) and with the optimality
-    re-check of its eliminations (pruned_kkt).  Solve time (factor build and
-    every prune event included), iterations, max_q N_q / N per iteration and
-    the final NMSE against the FP64 optimum."""
+    plain SADMM, both FP32, run to the relative residual tolerance.  Solve
+    time (factor build and every prune event included), iterations,
+    max_q N_q / N per iteration and the final NMSE against the FP64 optimum."""
     out = {}
     for eps in eps_list:
         r = {}
-        for name, prune, kkt in (("plain", False, False), ("pruned", True, False),
-                                 ("pruned_kkt", True, True)):
-            s = lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", prune=prune, kkt=kkt,
+        for name, prune in (("plain", False), ("pruned", True)):
+            s = lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", prune=prune,
                            reuse_factor=False, max_iter=400, stop=True, check_every=4, Kp=5,
                            eps_p=1e-5, eps_abs=0.0, eps_rel=eps, stream=stream, **hp)
             for q in range(g.Q):
@@ -184,15 +181,14 @@ def asadmm_leg(torch, lib, stream, g, hp, y_dev, xref_dev, eps_list=(1e-4, 1e-5)
                            mean_active_frac=round(float(np.mean(fr)), 4) if len(fr) else 1.0,
                            active_frac_curve=[round(float(v), 4) for v in fr[::max(1, len(fr) // 16)]])
             s.close()
-        for v in ("pruned", "pruned_kkt"):
-            r[v]["time_saving"] = round(1.0 - r[v]["ms"] / r["plain"]["ms"], 4)
-            r[v]["iteration_time_saving"] = round(1.0 - r[v]["iter_ms"] / max(r["plain"]["iter_ms"], 1e-9), 4)
+        r["pruned"]["time_saving"] = round(1.0 - r["pruned"]["ms"] / r["plain"]["ms"], 4)
+        r["pruned"]["iteration_time_saving"] = round(1.0 - r["pruned"]["iter_ms"] / max(r["plain"]["iter_ms"], 1e-9), 4)
         out[f"{eps:g}"] = r
     return out
 
 
 def c5_asadmm_leg(torch, lib, stream, hp, max_iter=60):
-    """Matrix-free 512 x 512 scene: plain vs pruned (Alg. 1 + re-check) run to
+    """Matrix-free 512 x 512 scene: plain vs pruned (Alg. 1) run to
     eps_rel = 1e-4 or max_iter; no FP64 optimum exists at this size, so the
     pruned image is compared with the plain one (same support expected)."""
     from scenegen import config_geometry, make_scene
@@ -201,7 +197,7 @@ def c5_asadmm_leg(torch, lib, stream, hp, max_iter=60):
     y5 = torch.from_numpy(np.ascontiguousarray(sc5.y)).to("cuda")
     r, img = {}, {}
     for name, prune in (("plain", False), ("pruned", True)):
-        s = lib.Solver(g5.Q, g5.K, g5.M, g5.N, storage="mf", prune=prune, kkt=prune,
+        s = lib.Solver(g5.Q, g5.K, g5.M, g5.N, storage="mf", prune=prune,
                        reuse_factor=False, max_iter=max_iter, stop=True, check_every=4, Kp=5,
                        eps_p=1e-5, eps_abs=0.0, eps_rel=1e-4, stream=stream, **hp)
         for q in range(g5.Q):

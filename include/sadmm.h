@@ -86,20 +86,19 @@ typedef struct {
   int32_t Kp;                 /* SSC window (iterations), 1..64 */
   double eps_p;               /* SSC tolerance on the mean |change| */
   int32_t prune_mode;         /* 0: freeze eliminated pixels; 1: zero them */
-  int32_t kkt;                /* 1: after convergence, re-check eliminated pixels
-                                 against the optimality condition and reinstate
-                                 (when prune = 1, or when the solve started with
-                                 eliminated pixels: caller mask or CNN); at most 8
+  int32_t kkt;                /* 1: a solve that starts from a selector with
+                                 eliminated pixels (caller mask or CNN) re-checks,
+                                 after convergence, every eliminated pixel (the
+                                 selector's and SSC's) against the optimality
+                                 condition and reinstates violators; at most 8
                                  rounds, after which remaining violations end the
-                                 solve with status 3 */
+                                 solve with status 3.  SSC's eliminations in a
+                                 solve that starts from the full image are Alg. 1
+                                 as the paper gives it and are not judged */
   double kkt_tol;             /* reinstate eliminated pixel n of sensor q when
-                                 |g_qn| / (mu |a_qn|^2 + beta + gamma) >
-                                 kkt_tol * max_m |x_q[m]|, with
-                                 g_q = mu A_q^H (A_q x_q - y_q) + gamma x_q + beta u:
-                                 the step the pixel's own coordinate of the next
-                                 x-update would take from its frozen value.
-                                 kkt_tol <= 0 (default): 10 * eps_rel, the
-                                 per-pixel precision the stop test grants */
+                                 |g_qn| > kkt_tol * lambda (lambda = 0: kkt_tol),
+                                 g_q = mu A_q^H (A_q x_q - y_q) + gamma x_q + beta u
+                                 (0 at the optimum); default 1e-2 */
   int32_t storage;            /* sadmm_storage */
   int32_t reuse_factor;       /* 1: a later solve reuses a factor built for the same
                                  starting selector; 0: every solve rebuilds it */
@@ -166,7 +165,7 @@ typedef struct {
 } sadmm_info;
 
 /* Fills *p with defaults: mu = beta = gamma = 1, eps_rel = 1e-4, Kp = 5,
- * eps_p = 1e-5, storage FP32, stop = 1, check_every = 8, kkt_tol = 0 (10 eps_rel),
+ * eps_p = 1e-5, storage FP32, stop = 1, check_every = 8, kkt_tol = 1e-2,
  * reuse_factor = 1. */
 void sadmm_default_params(sadmm_params* p);
 

@@ -63,22 +63,21 @@ these points; each reading is the one that makes eq. (3) a convergent method):
 
 Certificate and reinstatement: at the optimum of the unpruned problem,
 g_q = mu A_q^H (A_q x_q - y_q) + gamma x_q + beta u = 0 for every q and pixel.
-With `kkt=True`, after convergence every eliminated pixel whose coordinate
-step |g_qj| / (mu ||a_qj||^2 + beta + gamma) exceeds kkt_tol * max_n |x_q[n]|
-(kkt_tol <= 0: 10 eps_rel, the per-pixel precision the stop test grants)
-is put back into J_q (its measurement contribution is removed from y'_q again,
-its history window is set to +inf so it cannot be eliminated for K_p
-iterations) and iterating resumes.  The step is how far the pixel's own
-coordinate of the next x-update would move it from its frozen value: the
-x-update's objective has gradient g_qj (at a fixed point x_q - v = u) and
-curvature mu ||a_qj||^2 + beta + gamma along that coordinate.  A pixel frozen
-near its optimum (SSC's eliminations) moves by about its remaining drift; a
-pixel eliminated far from it (a wrong initial selector) moves by a sizeable
-fraction of the image's peak.  The re-check judges
-SSC's eliminations (prune=True) and an initial selector that already
-eliminates pixels (mask0).  After kkt_rounds reinstating rounds the next
-convergence is only checked: remaining violations leave converged=False and
-their count in kkt_violations.
+With `kkt=True`, a solve that starts from an initial selector (mask0: a
+caller's or a learned one; its eliminations are frozen at 0) is judged after
+convergence: every eliminated pixel with |g_qj| > kkt_tol * lambda -- the
+selector's and those SSC removed in the restricted solve -- is put back into
+J_q (history window +inf, so no new elimination for K_p iterations) and
+iterating resumes.  After kkt_rounds reinstating rounds the next convergence
+is only checked: remaining violations leave converged=False and their count
+in kkt_violations.  SSC's eliminations in a solve that starts from the full
+image are the paper's method (Alg. 1) and are not judged: such a pixel,
+frozen at its settled value, keeps a gradient near lambda in its own sensor
+(the drift of its per-sensor value times the large column norm) while the
+image stays within round-off of the optimum, and no per-pixel test separates
+that from a wrong elimination at 0 -- one-step estimates of the move
+(coordinate, Schur complement, the thresholded image) certified restricted
+solves whose images were far from the optimum.
 
 Each x-update is solved directly from its definition: a Cholesky factor of
 mu Ahat^H Ahat + c I when N_q <= KM, otherwise the same solve through the
@@ -110,7 +109,7 @@ class Params:
     eps_p: float = 1e-5
     mode: str = "freeze"       # "freeze" or "zero"
     kkt: bool = False
-    kkt_tol: float = 0.0       # <= 0: 10 * eps_rel
+    kkt_tol: float = 1e-2      # reinstate when |g| > kkt_tol * lambda
     kkt_rounds: int = 8
     nonneg: bool = False       # z-update projected on the non-negative reals
     balance_every: int = 0     # residual balancing every this many iterations (0: off)
@@ -345,7 +344,7 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
             hist["u"].append(u.copy())
             hist["masks"].append(active.copy())
         if done:
-            if p.kkt and (p.prune or start_restricted) and (~active).any():
+            if p.kkt and start_restricted and (~active).any():
                 if kkt_rounds >= p.kkt_rounds:
                     left = _reinstate(A, y, X, u, replace(p, beta=beta), active, yp, D, check_only=True)
                     if left:
@@ -367,15 +366,13 @@ def solve(A: List[np.ndarray], y: np.ndarray, p: Params,
 
 
 def _reinstate(A, y, X, u, p, active, yp, D, check_only=False) -> int:
-    """Put eliminated pixels that violate the optimality condition back
-    (only count them when check_only)."""
+    """Put eliminated pixels that violate the optimality condition,
+    |g_qj| > kkt_tol * lambda, back (only count them when check_only)."""
     g = kkt_gradient(A, y, X, u, p)
+    thr = p.kkt_tol * (p.lam if p.lam > 0 else 1.0)
     back = 0
     for q in range(len(A)):
-        curv = p.mu * np.sum(np.abs(A[q]) ** 2, axis=0) + p.beta + p.gamma
-        step = np.abs(g[q]) / curv
-        thr = (p.kkt_tol if p.kkt_tol > 0 else 10.0 * p.eps_rel) * np.abs(X[q]).max()
-        bad = np.flatnonzero((~active[q]) & (step > thr))
+        bad = np.flatnonzero((~active[q]) & (np.abs(g[q]) > thr))
         if bad.size == 0:
             continue
         if check_only:

@@ -135,6 +135,7 @@ struct sadmm_s {
   std::vector<std::pair<int, double>> frac_pts;   // (iteration, max active fraction from it on)
   std::vector<std::pair<int, double>> beta_pts;   // (iteration, beta in force after it)
   double beta0 = 1.0;              // the beta of the parameters (balancing changes p.beta in a solve)
+  double* kg = nullptr;             // optimality re-check: gradients of one sensor's eliminated pixels
   bool args_dirty = false;         // the device copy of the iteration arguments is stale
   int kkt_rounds = 0, status = 1;
   bool done = false;
@@ -750,34 +751,42 @@ int apply_prune(sadmm_t h) {
 
 // Optimality re-check of eliminated pixels after convergence; *n_back = the
 // number of violating pixels, which are reinstated unless check_only.
+// Optimality re-check (solves that start from an initial selector):
+// eliminated pixels with |g_qj| > kkt_tol * lambda, g_q = mu A_q^H (A_q x_q -
+// y_q) + gamma x_q + beta u, are put back (history window +inf); *n_back =
+// their number (only counted when check_only).
 int kkt_reinstate(sadmm_t h, int* n_back, bool check_only = false) {
   *n_back = 0;
   std::vector<int> rebuild;
-  const double thr = h->p.kkt_tol > 0 ? h->p.kkt_tol : 10.0 * h->p.eps_rel;
+  hipStream_t s = h->s;
+  const int N = h->N;
+  if (!h->kg && hipMalloc((void**)&h->kg, 16 * (size_t)N) != hipSuccess) {
+    h->kg = nullptr;
+    return fail_msg(h, SADMM_E_NOMEM, "re-check buffer");
+  }
+  const double thr = h->p.kkt_tol * (h->p.lambda > 0 ? h->p.lambda : 1.0);
   for (int q = 0; q < h->Q; ++q) {
-    if (h->nq[q] == h->N) continue;
+    if (h->nq[q] == N) continue;
     IterArgs a = make_args(h);
-    // threshold scale: max_n |x_q[n]| (frozen pixels included)
-    maxabs_c(static_cast<const char*>(h->X) + h->csz * (size_t)q * h->N, h->dbl, h->N, h->red, h->s);
     // e = A_q x_q - y_q over all pixels (original measurement)
-    scale_c128(h->y + 2 * (size_t)q * h->KMp, h->e, h->KMp, -1.0, h->s);
-    launch_gather_fwd(a, h->st, h->dbl, q, nullptr, h->N, 1.0, h->e, h->gtmp, h->s);
-    // eliminated list
-    partition_flags(h->mask + (size_t)q * h->N, nullptr, h->N, nullptr, h->lst, h->counts, h->s);
+    scale_c128(h->y + 2 * (size_t)q * h->KMp, h->e, h->KMp, -1.0, s);
+    launch_gather_fwd(a, h->st, h->dbl, q, nullptr, N, 1.0, h->e, h->gtmp, s);
+    partition_flags(h->mask + (size_t)q * N, nullptr, N, nullptr, h->lst, h->counts, s);
     TRY(read_counts(h));
     const int ne = h->counts_h[1];
     if (ne == 0) continue;
-    launch_kkt_check(a, h->st, h->dbl, q, h->lst, ne, h->e, h->p.mu, h->p.gamma, thr, h->red, h->flag, h->s);
-    partition_flags(h->flag, h->lst, ne, h->lst2, nullptr, h->counts, h->s);
+    launch_kkt_grad(a, h->st, h->dbl, q, h->lst, ne, h->e, h->p.mu, h->p.gamma, h->kg, s);
+    grad_flag(h->kg, ne, thr, h->flag, s);
+    partition_flags(h->flag, h->lst, ne, h->lst2, nullptr, h->counts, s);
     TRY(read_counts(h));
     const int r = h->counts_h[0];
     if (r == 0) continue;
     if (check_only) { *n_back += r; continue; }
     if (h->p.prune_mode == 0)
-      launch_gather_fwd(a, h->st, h->dbl, q, h->lst2, r, 1.0, h->yp + 2 * (size_t)q * h->KMp, h->gtmp, h->s);
-    set_bytes_at(h->mask + (size_t)q * h->N, h->lst2, r, 1, h->s);
-    set_ring_inf(h->D, h->dbl, h->p.Kp, h->Q, h->N, q, h->lst2, r, h->s);
-    partition_flags(h->mask + (size_t)q * h->N, nullptr, h->N, h->J[q], nullptr, h->counts, h->s);
+      launch_gather_fwd(a, h->st, h->dbl, q, h->lst2, r, 1.0, h->yp + 2 * (size_t)q * h->KMp, h->gtmp, s);
+    set_bytes_at(h->mask + (size_t)q * N, h->lst2, r, 1, s);
+    set_ring_inf(h->D, h->dbl, h->p.Kp, h->Q, N, q, h->lst2, r, s);
+    partition_flags(h->mask + (size_t)q * N, nullptr, N, h->J[q], nullptr, h->counts, s);
     TRY(read_counts(h));
     h->nq[q] = h->counts_h[0];
     TRY(compact_operator(h, q));
@@ -789,7 +798,7 @@ int kkt_reinstate(sadmm_t h, int* n_back, bool check_only = false) {
     } else if (prefer_lowrank(h, r, h->nq[q])) {
       TRY(lowrank_update(h, q, h->lst2, r, +1));
       h->fac_valid[q] = false;
-      launch_xy(make_args(h), h->st, h->dbl, q, q + 1, h->s);
+      launch_xy(make_args(h), h->st, h->dbl, q, q + 1, s);
       HIPCHK(h, hipGetLastError());
     } else {
       rebuild.push_back(q);
@@ -1100,9 +1109,9 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
   if (hb & HALT_CONV) {
     bool any_frozen = false;
     for (int q = 0; q < h->Q; ++q) any_frozen = any_frozen || h->nq[q] < h->N;
-    // the re-check judges every elimination: SSC's, and the selector the
-    // solve started from (caller mask or CNN)
-    const bool judge = h->p.kkt && (h->p.prune || h->start_restricted) && any_frozen;
+    // the re-check judges solves that start from a selector (caller mask or
+    // CNN): every elimination in them, the selector's and SSC's
+    const bool judge = h->p.kkt && h->start_restricted && any_frozen;
     if (judge && h->kkt_rounds >= KKT_ROUNDS) {
       // round cap reached: certify without reinstating
       int bad = 0;
@@ -1381,7 +1390,7 @@ void sadmm_default_params(sadmm_params* p) {
   p->eps_abs = 0.0; p->eps_rel = 1e-4;
   p->max_iter = 200; p->stop = 1; p->check_every = 8;
   p->prune = 0; p->Kp = 5; p->eps_p = 1e-5; p->prune_mode = 0;
-  p->kkt = 0; p->kkt_tol = 0.0;
+  p->kkt = 0; p->kkt_tol = 1e-2;
   p->balance_every = 0; p->balance_mu = 10.0; p->balance_tau = 2.0;
   p->storage = SADMM_ST_FP32;
   p->reuse_factor = 1;
@@ -2077,6 +2086,7 @@ void sadmm_destroy(sadmm_t h) {
   }
   for (void* p : {(void*)h->A64, (void*)h->dirD, (void*)h->dirX, (void*)h->dirT, (void*)h->dir_desc})
     if (p) hipFree(p);
+  if (h->kg) hipFree(h->kg);
   for (double* p : h->rec)
     if (p) hipFree(p);
   for (unsigned long long* p : h->rmaxc)

@@ -141,9 +141,10 @@ void launch_gather_fwd(const IterArgs& a, int st, bool dbl, int q, const int* id
 // Optimality re-check of eliminated pixels of sensor q (idx, count):
 // g = mu A[:,n]^H e + gamma X[q,n] + beta u[n] with e = A_q x_q - y_q
 // (complex128, KMp); flag[j] = |g| > thr.
-void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
-                      const double* e, double mu, double gamma, double thr, const double* xmax,
-                      uint8_t* flag, hipStream_t s);
+// g_p = mu a_p^H e + gamma x_q[idx_p] + beta u[idx_p] (e = A_q x_q - y_q) for
+// the listed pixels (complex128, by list slot)
+void launch_kkt_grad(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
+                     const double* e, double mu, double gamma, double* g, hipStream_t s);
 
 // |A_q^H y_q| over all pixels for every sensor, into out (Q x N doubles).
 // Correction products over every sensor (one launch per step):

@@ -250,7 +250,6 @@ struct DotExtra {
   const double* vec;    // WY / XY / KKT / MF: complex128 source vector(s)
   int64_t vec_stride;   // per-sensor stride (complex entries)
   double mu, gamma, thr;
-  const double* xmax;   // KKT: max_n |x_q[n]| of the sensor (device scalar)
   uint8_t* flag;        // KKT
   double* out;          // MF (|.|), WY (complex); GRAD / FIX: g (complex128, by pixel)
   int q0;               // WY / XY: first sensor of the launch
@@ -315,41 +314,6 @@ __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* s
   for (int c = 0; c < C; ++c) {
     acc[c].re = wave_sum(acc[c].re);
     acc[c].im = wave_sum(acc[c].im);
-  }
-}
-
-// coldot_multi that also returns the squared norms of the C columns.
-template <int ST, class TA, int C>
-__device__ inline void coldot_multi_nrm(const void* const (&col)[C], const C2<TA>* sv, int KMp, int lane,
-                                        C2<TA> (&acc)[C], TA (&nrm)[C]) {
-  using T = typename Store<ST>::T;
-  constexpr int R = Store<ST>::RPT;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    acc[c] = {(TA)0, (TA)0};
-    nrm[c] = (TA)0;
-  }
-  for (int i0 = lane * R; i0 < KMp; i0 += SADMM_WAVE * R) {
-    C2<TA> v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = sv[sv_slot<ST>(i0 + r)];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      T re[R], im[R];
-      Store<ST>::load(col[c], i0, KMp, re, im);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const C2<TA> e = {(TA)re[r], (TA)im[r]};
-        cfmac(acc[c], e, v[r]);
-        nrm[c] += e.re * e.re + e.im * e.im;
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    acc[c].re = wave_sum(acc[c].re);
-    acc[c].im = wave_sum(acc[c].im);
-    nrm[c] = wave_sum(nrm[c]);
   }
 }
 
@@ -421,25 +385,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     else cols[c] = col_ptr<ST>(sd.Afull, sd.lda, p);
   }
   C2<TA> dots[DC];
-  TA nrms[DC];
-  if constexpr (EPI == EPI_KKT) {
-    // the re-check needs each column's squared norm (coordinate curvature)
-    if constexpr (ST == ST_MF) {
-#pragma unroll
-      for (int c = 0; c < DC; c += 2) {
-        const void* const pair[2] = {cols[c], cols[c + 1]};
-        C2<TA> d2[2];
-        TA n2[2];
-        coldot_multi_nrm<ST, TA, 2>(pair, sv, a.KMp, lane, d2, n2);
-        dots[c] = d2[0];
-        dots[c + 1] = d2[1];
-        nrms[c] = n2[0];
-        nrms[c + 1] = n2[1];
-      }
-    } else {
-      coldot_multi_nrm<ST, TA, DC>(cols, sv, a.KMp, lane, dots, nrms);
-    }
-  } else if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_W1 || EPI == EPI_WY1) {
+  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_W1 || EPI == EPI_WY1) {
     int rbeg = 0, rend = -1;
     if (sd.wtri) {
       if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
@@ -498,10 +444,8 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const C2<T> uv = ldc<T>(a.u, n);
       const double gre = x.mu * d.re + x.gamma * (double)xv.re + a.beta * (double)uv.re;
       const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
-      // the step this pixel's own x-update coordinate would take from its
-      // frozen value: gradient / curvature (mu |a_n|^2 + beta + gamma)
-      const double step = hypot(gre, gim) / (x.mu * (double)nrms[c] + a.beta + x.gamma);
-      x.flag[p] = step > x.thr * x.xmax[0] ? 1 : 0;
+      x.out[2 * p] = gre;
+      x.out[2 * p + 1] = gim;
     } else if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
       a.ws[2 * ((int64_t)q * a.KMp + p)] = d.re;
       a.ws[2 * ((int64_t)q * a.KMp + p) + 1] = d.im;
@@ -873,8 +817,7 @@ void launch_gather_fwd(const IterArgs& a, int st, bool dbl, int q, const int* id
 
 template <int ST>
 static void kkt_impl(const IterArgs& a, int q, const int* idx, int count, const double* e,
-                     double mu, double gamma, double thr, const double* xmax, uint8_t* flag,
-                     hipStream_t s) {
+                     double mu, double gamma, double* g, hipStream_t s) {
   using T = typename Store<ST>::T;
   if (count <= 0) return;
   DotExtra x{};
@@ -884,24 +827,21 @@ static void kkt_impl(const IterArgs& a, int q, const int* idx, int count, const 
   x.vec = e;
   x.mu = mu;
   x.gamma = gamma;
-  x.thr = thr;
-  x.xmax = xmax;
-  x.flag = flag;
+  x.out = g;
   const int cpb = 4 * dot_cols<ST>();
   const size_t smem = (size_t)sv_len<ST>(a.KMp) * sizeof(cd);
   coldot_kernel<ST, EPI_KKT><<<dim3((count + cpb - 1) / cpb, 1), 256, smem, s>>>(a, x);
 }
 
-void launch_kkt_check(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
-                      const double* e, double mu, double gamma, double thr, const double* xmax,
-                      uint8_t* flag, hipStream_t s) {
+void launch_kkt_grad(const IterArgs& a, int st, bool dbl, int q, const int* idx, int count,
+                     const double* e, double mu, double gamma, double* g, hipStream_t s) {
   (void)dbl;
   switch (st) {
-    case ST_FP64: kkt_impl<ST_FP64>(a, q, idx, count, e, mu, gamma, thr, xmax, flag, s); break;
-    case ST_FP32: kkt_impl<ST_FP32>(a, q, idx, count, e, mu, gamma, thr, xmax, flag, s); break;
-    case ST_FP16P: kkt_impl<ST_FP16P>(a, q, idx, count, e, mu, gamma, thr, xmax, flag, s); break;
-    case ST_BF16P: kkt_impl<ST_BF16P>(a, q, idx, count, e, mu, gamma, thr, xmax, flag, s); break;
-    case ST_MF: kkt_impl<ST_MF>(a, q, idx, count, e, mu, gamma, thr, xmax, flag, s); break;
+    case ST_FP64: kkt_impl<ST_FP64>(a, q, idx, count, e, mu, gamma, g, s); break;
+    case ST_FP32: kkt_impl<ST_FP32>(a, q, idx, count, e, mu, gamma, g, s); break;
+    case ST_FP16P: kkt_impl<ST_FP16P>(a, q, idx, count, e, mu, gamma, g, s); break;
+    case ST_BF16P: kkt_impl<ST_BF16P>(a, q, idx, count, e, mu, gamma, g, s); break;
+    case ST_MF: kkt_impl<ST_MF>(a, q, idx, count, e, mu, gamma, g, s); break;
   }
 }
 

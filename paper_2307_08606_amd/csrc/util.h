@@ -46,6 +46,8 @@ void diff_norm2_c128(const double* a, const double* b, int64_t n, double* out, h
 void diff_norm2_c64(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
 void maxabs_c(const void* x, bool dbl, int64_t n, double* out, hipStream_t s);
 void bp_sum(const double* c, int Q, int64_t N, double* out, hipStream_t s);
+// flag[p] = |g_p| > thr (complex128 g)
+void grad_flag(const double* g, int n, double thr, uint8_t* flag, hipStream_t s);
 void stack_real(const void* src, bool c128, int64_t rows, int64_t cols, int64_t ld, double* dst, hipStream_t s);
 // out[0] = |F (a - b)[J]|^2 (F Hermitian nq x nq, leading dimension fld)
 void herm_apply_norm2(const double* F, int fld, int nq, const int* J, const double* a, const double* b,

@@ -370,6 +370,13 @@ __global__ __launch_bounds__(256) void stack_real_kernel(const T* __restrict__ s
   d[2 * rows + 1] = 0.0;
 }
 
+// flag[p] = |g_p| > thr (g complex128)
+__global__ __launch_bounds__(256) void grad_flag_kernel(const double* __restrict__ g, int n, double thr,
+                                                        uint8_t* __restrict__ flag) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < n) flag[p] = hypot(g[2 * p], g[2 * p + 1]) > thr ? 1 : 0;
+}
+
 inline int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
@@ -389,6 +396,10 @@ void stack_real(const void* src, bool c128, int64_t rows, int64_t cols, int64_t 
   const unsigned g = (unsigned)((n + 255) / 256);
   if (c128) stack_real_kernel<double><<<g, 256, 0, s>>>(static_cast<const double*>(src), rows, cols, ld, dst);
   else stack_real_kernel<float><<<g, 256, 0, s>>>(static_cast<const float*>(src), rows, cols, ld, dst);
+}
+
+void grad_flag(const double* g, int n, double thr, uint8_t* flag, hipStream_t s) {
+  if (n > 0) grad_flag_kernel<<<blocks(n), 256, 0, s>>>(g, n, thr, flag);
 }
 
 void bp_sum(const double* c, int Q, int64_t N, double* out, hipStream_t s) {

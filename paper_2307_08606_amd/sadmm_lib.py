@@ -168,7 +168,7 @@ class Solver:
 
     def __init__(self, Q, K, M, N, *, mu=1.0, beta=1.0, gamma=1.0, lam=0.0, eps_abs=0.0,
                  eps_rel=1e-4, max_iter=200, stop=True, check_every=8, prune=False, Kp=5,
-                 eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=0.0, storage="fp32",
+                 eps_p=1e-5, prune_mode="freeze", kkt=False, kkt_tol=1e-2, storage="fp32",
                  reuse_factor=True, gram="int8", direct=True, refine_every=0, nonneg=False,
                  balance_every=0, balance_mu=10.0, balance_tau=2.0, stream=None, share=None):
         p = sadmm_params()

@@ -11,6 +11,13 @@ input, and the label of pixel n is 1 when the converged accelerated solve
 eliminated) has z_n = 0 and has eliminated n from every sensor.  The network (sadmm_cnn_*) is trained with its own forward/backward
 kernels and Adam.  Prints per-epoch loss and held-out precision/recall at the
 elimination threshold.
+
+Each scene also reports the fraction of pixels that could be eliminated at
+x = 0 from every sensor without the optimality re-check reinstating them:
+max_q |x_q[n]| / max_m |x_q[m]| <= 10 eps_rel (the re-check's default
+tolerance; frozen at 0, a pixel's coordinate step is about |x_q[n]|).  With
+--measure-only only that is measured (any workload, c5 included) and printed
+as JSON.
 """
 
 from __future__ import annotations
@@ -30,8 +37,8 @@ from paper_2307_08606_amd import sadmm_lib as lib  # noqa: E402
 from scenegen import CONFIGS, config_geometry, config_scene  # noqa: E402
 
 
-def make_solver(g, cfg, lam, stream, max_iter=60):
-    s = lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", prune=True, kkt=False, reuse_factor=True,
+def make_solver(g, cfg, lam, stream, max_iter=60, storage="fp32"):
+    s = lib.Solver(g.Q, g.K, g.M, g.N, storage=storage, prune=True, kkt=False, reuse_factor=True,
                    max_iter=max_iter, stop=False, check_every=8, Kp=cfg["Kp"], eps_p=cfg["eps_p"],
                    eps_abs=0.0, eps_rel=cfg["eps_rel"], mu=cfg["mu"], beta=cfg["beta"],
                    gamma=cfg["gamma"], lam=lam, stream=stream)
@@ -49,7 +56,16 @@ def scene_sample(s, g, seed, workload):
     z = s.image()
     masks = np.stack([s.active_mask(q).astype(bool) for q in range(g.Q)])
     t = ((np.abs(z) == 0) & (~masks).all(axis=0)).astype(np.float32)
-    return x, t.reshape(g.n_side, g.n_side)
+    return x, t.reshape(g.n_side, g.n_side), zero_eliminable(s, g)
+
+
+def zero_eliminable(s, g, tol=None):
+    """Fraction of pixels whose every sensor value is within the re-check's
+    tolerance of 0 (relative to that sensor's largest), and of (q, n) pairs."""
+    tol = 10.0 * s.params.eps_rel if tol is None else tol
+    ax = np.abs(np.stack([s.sensor_image(q) for q in range(g.Q)]))
+    small = ax <= tol * ax.max(axis=1, keepdims=True)
+    return float(small.all(axis=0).mean()), float(small.mean())
 
 
 def main():
@@ -65,6 +81,8 @@ def main():
     ap.add_argument("--threshold", type=float, default=0.9)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "cnn_c2.npz"))
+    ap.add_argument("--measure-only", action="store_true",
+                    help="only measure the zero-eliminable fractions of --scenes scenes")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -75,13 +93,27 @@ def main():
         ref = json.load(open(os.path.join(os.path.dirname(HERE), "tests", "golden", "c2_seed100.json")))
         lam = ref["lam"]
     g = config_geometry(a.workload)
-    s = make_solver(g, cfg, lam, stream)
+    s = make_solver(g, cfg, lam, stream, storage="mf" if g.N > 128 * 128 else "fp32")
     t0 = time.time()
-    train = [scene_sample(s, g, 10000 + i, a.workload) for i in range(a.scenes)]
-    held = [scene_sample(s, g, 30000 + i, a.workload) for i in range(a.heldout)]
+    if a.measure_only:
+        fr = []
+        for i in range(a.scenes):
+            sc = config_scene(a.workload, 10000 + i)
+            s.solve(sc.y)
+            fr.append(zero_eliminable(s, g))
+        print(json.dumps(dict(workload=a.workload, scenes=a.scenes, lam=lam, iterations=60,
+                              tol=10.0 * s.params.eps_rel,
+                              pixel_fraction=[f[0] for f in fr], pair_fraction=[f[1] for f in fr],
+                              seconds=round(time.time() - t0, 1))), flush=True)
+        return
+    train = [scene_sample(s, g, 10000 + i, a.workload)[:2] for i in range(a.scenes)]
+    held_full = [scene_sample(s, g, 30000 + i, a.workload) for i in range(a.heldout)]
+    held = [h[:2] for h in held_full]
     pos = float(np.mean([t.mean() for _, t in train]))
+    zel = [h[2] for h in held_full]
     print(f"labels: {a.scenes} training scenes, positive fraction {pos:.3f}, "
-          f"{time.time() - t0:.1f} s", flush=True)
+          f"{time.time() - t0:.1f} s; zero-eliminable pixels {np.mean([z[0] for z in zel]):.2e}, "
+          f"(q, n) pairs {np.mean([z[1] for z in zel]):.2e} (held-out scenes)", flush=True)
     net = lib.Cnn(g.Q, a.channels, g.n_side, g.n_side, stream=stream)
     rng = np.random.default_rng(a.seed)
     init = {}

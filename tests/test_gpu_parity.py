@@ -422,3 +422,29 @@ def test_half_precision_storage_c1(gpu_lib, storage, bar):
     ref = oracle.solve(A, sc.y, oracle_params(hp, max_iter=3000, eps_rel=1e-10))
     s, info = gpu_run(gpu_lib, g, A, sc.y, hp, storage, max_iter=100, stop=False)
     assert nmse(s.image(), ref.z) <= bar
+
+
+@pytest.mark.parametrize("frac", [0.5, 1.0, 0.98])
+def test_kkt_judges_random_initial_selector_fp64(gpu_lib, frac):
+    """An initial selector that freezes a random fraction of the pixels at 0 in
+    every sensor: the re-check (|g| > kkt_tol lambda over every elimination
+    of the solve, the selector's and SSC's) reinstates what the oracle
+    reinstates, in the same rounds, and the result is the full problem's
+    optimum."""
+    g, sc, A, hp = problem(seed=1, lam_frac=0.2)
+    rng = np.random.default_rng(0)
+    m = np.repeat(rng.random((1, g.N)) >= frac, g.Q, axis=0)
+    kw = dict(max_iter=2000, eps_rel=1e-4, prune=True, kkt=True, Kp=5, eps_p=1e-5)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", mask0=m.astype(np.uint8), **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, **kw), mask0=m)
+    plain = oracle.solve(A, sc.y, oracle_params(hp, max_iter=2000, eps_rel=1e-4))
+    print(frac, info["iters"], ref.iters, info["reinstated"], ref.reinstated, info["status"], ref.converged,
+          flush=True)
+    assert info["reinstated"] == ref.reinstated
+    assert info["iters"] == ref.iters
+    if ref.converged:
+        assert info["status"] == 0
+        assert rel(s.image(), ref.z) < 1e-8
+        assert nmse(s.image(), plain.z) < 1e-6
+    else:
+        assert info["status"] == 3 and ref.kkt_violations > 0
