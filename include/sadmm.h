@@ -273,6 +273,22 @@ int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap,
 int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_device,
                          double* out);
 
+/* Tile autotuner of the forward product (columns per work-group, from
+ * 256, 512, 1024; not part of the method, only of its speed).  For each
+ * width it runs min(iters, params.max_iter) plain iterations of this
+ * handle's problem on the measurements y twice (as sadmm_solve, with
+ * stopping, elimination, re-check, refinement and balancing off; the factor
+ * is built once), times the second run with device events, keeps the
+ * fastest width for the handle and records it for the key (storage, rows,
+ * power-of-two bucket of N): handles created later in this process with the
+ * same key start from it.  *chunk receives the width; iters = 0 only
+ * reports the handle's current width.  The parameters are unchanged
+ * afterwards and the next solve starts afresh; results of later solves
+ * differ from the untuned width's only by summation order.  SADMM_E_ARG for
+ * iters = 1 or < 0 and for handles that share an operator. */
+int sadmm_autotune(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, int32_t iters,
+                   int32_t* chunk);
+
 /* Back-projection image of Sec. IV (Fig. 1): |sum_q A_q^H y_q| per pixel,
  * the coherent sum over the sensors of each sensor's adjoint applied to its
  * measurements (y: Q x KM complex, sensor-major, in dtype; on_device selects

@@ -15,6 +15,9 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -110,6 +113,7 @@ struct sadmm_s {
   std::vector<cd*> hpdD, hpdX, hpdT;          // per-sensor inverse scratch
   int rmax = 0, rpad_max = 0;
   int chunk = 256, nchunk = 0, nblk = 0;
+  int nchunk_cap = 0;             // chunks the forward buffers hold (chunk 256, the smallest tuned)
   double xref_norm2 = 0.0, nmse_target = 0.0;
   bool have_ref = false;
   sadmm_cnn_t cnn = nullptr;
@@ -238,6 +242,29 @@ void prof_resolve(sadmm_t h) {
   }
   h->marks.clear();
   h->evnext = 0;
+}
+
+// Forward-product tile width (columns per work-group) chosen by
+// sadmm_autotune, per (storage, rows rounded to 32, pixel-count bucket); a
+// handle created later for the same key starts from it.
+constexpr int FWD_CHUNK_MIN = 256;
+constexpr int FWD_CHUNKS[] = {256, 512, 1024};
+static_assert(FWD_CHUNKS[2] <= MAX_CHUNK, "forward tile wider than its LDS coefficient tile");
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tuned;
+int n_bucket(int N) {   // power-of-two bucket of the pixel count
+  int b = 0;
+  while ((1 << (b + 1)) <= N) ++b;
+  return b;
+}
+int tuned_chunk(int st, int KMp, int N) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(st, KMp, n_bucket(N)));
+  return it == g_tuned.end() ? 0 : it->second;
+}
+void set_tuned_chunk(int st, int KMp, int N, int chunk) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[std::make_tuple(st, KMp, n_bucket(N))] = chunk;
 }
 
 IterArgs make_args(sadmm_t h) {
@@ -1446,7 +1473,12 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   // 5.5 at 256), but at least 16 chunks per sensor; 16-bit planes keep 256.
   if (h->st == ST_FP16P || h->st == ST_BF16P) h->chunk = 256;
   else h->chunk = std::min(1024, std::max(256, (h->N / 16) / 256 * 256));
+  {
+    const int tuned = tuned_chunk(h->st, h->KMp, h->N);
+    if (tuned > 0) h->chunk = tuned;
+  }
   h->nchunk = (h->N + h->chunk - 1) / h->chunk;
+  h->nchunk_cap = (h->N + FWD_CHUNK_MIN - 1) / FWD_CHUNK_MIN;
   h->nblk = (h->N + 255) / 256;
   const int Q = h->Q, N = h->N, KMp = h->KMp;
   const size_t cN = h->csz * N;
@@ -1490,8 +1522,8 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   A_(dalloc(h, &h->u, cN));
   A_(dalloc(h, &h->xref, cN));
   A_(dalloc(h, &h->D, (h->dbl ? 8 : 4) * (size_t)p->Kp * Q * N));
-  A_(dalloc(h, &h->tpart, h->csz * (size_t)Q * h->nchunk * KMp));
-  A_(dalloc(h, &h->gtmp, h->csz * (size_t)h->nchunk * KMp));
+  A_(dalloc(h, &h->tpart, h->csz * (size_t)Q * h->nchunk_cap * KMp));
+  A_(dalloc(h, &h->gtmp, h->csz * (size_t)h->nchunk_cap * KMp));
   A_(dalloc(h, &h->t, h->csz * (size_t)Q * KMp));
   A_(dalloc(h, &h->w, h->csz * (size_t)Q * KMp));
   A_(dalloc_t(h, &h->y, 16 * (size_t)Q * KMp));
@@ -1718,6 +1750,49 @@ int sadmm_solve(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, sadm
   std::vector<sadmm_t> hs{h};
   TRY(iterate(hs, /*single=*/true));
   return solve_epilogue(h, info);
+}
+
+int sadmm_autotune(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, int32_t iters, int32_t* chunk) {
+  if (!h || !chunk) return SADMM_E_ARG;
+  if (iters == 0) { *chunk = h->chunk; return SADMM_OK; }
+  if (iters < 2) return fail_msg(h, SADMM_E_ARG, "autotune: iters >= 2 (or 0 to query)");
+  if (h->shared_src || h->n_sharers) return fail_msg(h, SADMM_E_ARG, "autotune: not for shared operators");
+  const sadmm_params saved = h->p;
+  // plain iterations of the handle's problem, factor built once and reused
+  h->p.max_iter = std::min(iters, saved.max_iter);
+  h->p.stop = 0; h->p.prune = 0; h->p.kkt = 0; h->p.refine_every = 0; h->p.balance_every = 0;
+  h->p.reuse_factor = 1;
+  auto drop_graph = [&]() {
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+  };
+  int best = h->chunk, rc = SADMM_OK;
+  double best_ms = 1e300;
+  for (int c : FWD_CHUNKS) {
+    if (c > FWD_CHUNK_MIN && c >= h->N) break;        // one chunk already covers the image
+    h->chunk = c;
+    h->nchunk = (h->N + c - 1) / c;
+    drop_graph();
+    sadmm_info inf{};
+    // untimed pass: captures this width's graph (and builds the factor once)
+    rc = sadmm_solve(h, y, dtype, on_device, &inf);
+    if (rc != SADMM_OK) break;
+    rc = sadmm_solve(h, y, dtype, on_device, &inf);
+    if (rc != SADMM_OK) break;
+    const double ms = h->t_iter / std::max(1, inf.iters);
+    if (ms < best_ms) { best_ms = ms; best = c; }
+  }
+  h->p = saved;
+  h->chunk = best;
+  h->nchunk = (h->N + best - 1) / best;
+  drop_graph();
+  h->solved = false;
+  if (rc != SADMM_OK) return rc;
+  set_tuned_chunk(h->st, h->KMp, h->N, best);
+  *chunk = best;
+  return SADMM_OK;
 }
 
 int sadmm_solve_batch(sadmm_t* hs, int32_t S, const void* const* ys, int32_t dtype, int32_t on_device,

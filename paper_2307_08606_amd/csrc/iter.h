@@ -77,6 +77,8 @@ struct BatchDims {
 };
 
 constexpr int FWD_THREADS = 256;
+// most columns one forward work-group takes (its coefficient tile in LDS)
+constexpr int MAX_CHUNK = 1024;
 // Columns per wavefront of the column-dot kernels: two for stored FP32 / FP64
 // entries (more waves in flight), four for 16-bit and generated entries (one
 // LDS read of the staged vector serves more columns).

@@ -30,8 +30,6 @@
 
 namespace {
 
-constexpr int MAX_CHUNK = 1024;
-
 template <class T> __device__ inline C2<T> ldc(const void* p, int64_t i) {
   return reinterpret_cast<const C2<T>*>(p)[i];
 }

@@ -122,6 +122,7 @@ sadmm_cnn_destroy = _sig("sadmm_cnn_destroy", None, _H)
 sadmm_cnn_last_error = _sig("sadmm_cnn_last_error", C.c_char_p, _H)
 sadmm_set_pruning_cnn = _sig("sadmm_set_pruning_cnn", C.c_int, _H, _H, C.c_double)
 sadmm_last_error = _sig("sadmm_last_error", C.c_char_p, _H)
+sadmm_autotune = _sig("sadmm_autotune", C.c_int, _H, _P, C.c_int32, C.c_int32, C.c_int32, _P)
 sadmm_back_projection = _sig("sadmm_back_projection", C.c_int, _H, _P, C.c_int32, C.c_int32, _P)
 sadmm_stack_real = _sig("sadmm_stack_real", C.c_int, _P, C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P,
                         C.c_void_p)
@@ -313,6 +314,16 @@ class Solver:
         self._check(sadmm_matched_filter(self._h, _ptr(y), _dtype_code(y), _on_device(y),
                                          _ptr(out)))
         return out
+
+    def autotune(self, y, iters=8) -> int:
+        """Time the forward-product tile widths on this problem, keep the
+        fastest (iters = 0: report the current one)."""
+        if isinstance(y, np.ndarray):
+            y = np.ascontiguousarray(y)
+        c = C.c_int32(0)
+        self._check(sadmm_autotune(self._h, _ptr(y), _dtype_code(y), _on_device(y), int(iters),
+                                   C.addressof(c)))
+        return c.value
 
     def back_projection(self, y) -> np.ndarray:
         """|sum_q A_q^H y_q| (N doubles)."""

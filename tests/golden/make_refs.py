@@ -16,6 +16,12 @@ scenegen.configs.c4_frames), batch seed 7, 16 frames:
   c4_batch_seed7.json    per-frame lambda_max and lambda (= 0.2 lambda_max)
 
     python tests/golden/make_refs.py c4
+
+The full batched workload (256 frames, same seed, so its first 16 frames are
+those above), lambda_max by the Woodbury / conjugate-gradient path:
+  c4_batch256_seed7.json
+
+    python tests/golden/make_refs.py c4 256
 """
 
 import json
@@ -71,20 +77,24 @@ def main(seed: int = 100, max_iter: int = 300):
 
 def main_c4(seed: int = 7, n_frames: int = 16, lambda_frac: float = 0.2):
     frames = c4_frames(n_frames, seed)
-    for fr in frames:
+    for i, fr in enumerate(frames):
         sc = c4_scene(fr)
         A = [steering(sc.geom, q) for q in range(sc.geom.Q)]
-        fr["lambda_max"] = oracle.lambda_max(A, sc.y, 1.0, 1.0)
+        # the Woodbury / conjugate-gradient path (exact to its tolerance)
+        fr["lambda_max"] = oracle.lambda_max(A, sc.y, 1.0, 1.0, dense_limit=0 if n_frames > 16 else 4096)
         fr["lam"] = lambda_frac * fr["lambda_max"]
+        if n_frames > 16 and i % 16 == 0:
+            print(f"frame {i}", flush=True)
     info = dict(workload="c4", seed=seed, n_frames=n_frames, lambda_frac=lambda_frac,
                 mu=1.0, beta=1.0, gamma=1.0, frames=frames)
-    with open(os.path.join(HERE, f"c4_batch_seed{seed}.json"), "w") as f:
+    name = f"c4_batch_seed{seed}.json" if n_frames == 16 else f"c4_batch{n_frames}_seed{seed}.json"
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(info, f, indent=1)
     print(json.dumps(info, indent=1))
 
 
 if __name__ == "__main__":
-    if sys.argv[1:] == ["c4"]:
-        main_c4()
+    if sys.argv[1:2] == ["c4"]:
+        main_c4(n_frames=int(sys.argv[2]) if len(sys.argv) > 2 else 16)
     else:
         main()
