@@ -68,9 +68,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
-    ap.add_argument("--only", default="", choices=["", "pruned", "plain", "iter"],
+    ap.add_argument("--only", default="", choices=["", "pruned", "plain", "iter", "c4", "c4batch"],
                     help="'pruned' or 'plain' to time one variant; 'iter' runs only steady "
-                         "iterations (c2 FP32, 40; c5 matrix-free, 10) for counter runs")
+                         "iterations (c2 FP32, 40; c5 matrix-free, 10) for counter runs; "
+                         "'c4' runs only the batched-frames leg and prints its figures; 'c4batch' "
+                         "only its batched solves (one warm-up, one timed), for kernel traces")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -222,21 +224,38 @@ def c5_asadmm_leg(torch, lib, stream, hp, max_iter=60):
     return r
 
 
-def batch_leg(torch, lib, stream, storage, reps=3):
+def batch_leg(torch, lib, stream, reps=2, n_check=8, legs=("sequential", "batched")):
+    """c4: 256 independent frames of uneven sensor count (4, 6, 8) and grid
+    (32^2 .. 96^2 pixels), M = 8, K = 128, operators generated on the device
+    and stored as planar BF16 (FP32 arithmetic, FP64 factor, FP32 correction
+    every 10 iterations), pruned, each run to eps_rel = 1e-4 with a fresh
+    factor.  One tile autotune per pixel-count bucket first; then frames/s
+    solved one by one and as one batch (one launch per kernel for all
+    frames); NMSE of a sample of the batched images against FP64 solves of
+    the same frames run to eps_rel = 1e-7."""
     from scenegen.configs import c4_scene
-    info = json.load(open(os.path.join(ROOT, "tests", "golden", "c4_batch_seed7.json")))
-    solvers, ys = [], []
-    for fr in info["frames"]:
-        sc = c4_scene(fr)
-        g = sc.geom
-        s = lib.Solver(g.Q, g.K, g.M, g.N, storage=storage, prune=True, kkt=False,
-                       reuse_factor=False, max_iter=300, stop=True, check_every=8, Kp=5,
-                       eps_p=1e-5, eps_abs=0.0, eps_rel=1e-4, stream=stream, mu=info["mu"],
-                       beta=info["beta"], gamma=info["gamma"], lam=fr["lam"])
+    info = json.load(open(os.path.join(ROOT, "tests", "golden", "c4_batch256_seed7.json")))
+    frames = info["frames"]
+    scenes = [c4_scene(fr) for fr in frames]
+    base = dict(prune=True, kkt=False, reuse_factor=False, max_iter=300, stop=True, check_every=8,
+                Kp=5, eps_p=1e-5, eps_abs=0.0, eps_rel=1e-4, stream=stream, mu=info["mu"],
+                beta=info["beta"], gamma=info["gamma"])
+
+    def handle(i, storage, **kw):
+        g = scenes[i].geom
+        s = lib.Solver(g.Q, g.K, g.M, g.N, storage=storage, lam=frames[i]["lam"], **{**base, **kw})
         for q in range(g.Q):
             s.set_operator_geometry(q, g.tx[q], g.rx[q], g.pix, g.f0, g.bw)
-        solvers.append(s)
-        ys.append(torch.from_numpy(np.ascontiguousarray(sc.y)).to("cuda"))
+        return s
+
+    ys = [torch.from_numpy(np.ascontiguousarray(sc.y)).to("cuda") for sc in scenes]
+    widths = {}
+    for i, fr in enumerate(frames):                  # one tune per pixel-count bucket
+        if fr["n_side"] not in widths:
+            s = handle(i, "bf16", refine_every=10)
+            widths[fr["n_side"]] = s.autotune(ys[i], 8)
+            s.close()
+    solvers = [handle(i, "bf16", refine_every=10) for i in range(len(frames))]
 
     def one_by_one():
         return [s.solve(y) for s, y in zip(solvers, ys)]
@@ -246,6 +265,8 @@ def batch_leg(torch, lib, stream, storage, reps=3):
 
     out = {}
     for name, fn in (("sequential", one_by_one), ("batched", batched)):
+        if name not in legs:
+            continue
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -253,10 +274,30 @@ def batch_leg(torch, lib, stream, storage, reps=3):
             infos = fn()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
-        out[name] = dict(ms=ms, iters=[i["iters"] for i in infos])
+        out[name] = dict(ms=ms, iters=[i["iters"] for i in infos],
+                         status=[i["status"] for i in infos])
+    # accuracy of the batched BF16 images: frames spread over the sizes
+    order = sorted(range(len(frames)), key=lambda i: (scenes[i].geom.N * scenes[i].geom.Q, i))
+    pick = [order[int(round(j * (len(order) - 1) / max(n_check - 1, 1)))] for j in range(n_check)]
+    nm = []
+    for i in pick[:n_check]:
+        r = handle(i, "fp64", prune=False, eps_rel=1e-7, max_iter=3000, check_every=16)
+        inf = r.solve(ys[i])
+        z64 = r.image()
+        r.close()
+        z = solvers[i].image()
+        nm.append(dict(frame=i, Q=scenes[i].geom.Q, N=scenes[i].geom.N, ref_status=inf["status"],
+                       nmse=float(np.linalg.norm(z - z64) ** 2 / np.linalg.norm(z64) ** 2)))
+    free, total = torch.cuda.mem_get_info()
+    out["device_mem_in_use_GB"] = round((total - free) / 1e9, 1)
     for s in solvers:
         s.close()
-    out["frames"] = len(solvers)
+    out["frames"] = len(frames)
+    out["widths"] = {str(k): v for k, v in sorted(widths.items())}
+    out["nmse_vs_fp64"] = nm
+    out["sum_QN"] = int(sum(sc.geom.Q * sc.geom.N for sc in scenes))
+    it_b = out[legs[-1]]["iters"]
+    out["sum_iters_QN"] = int(sum(it * sc.geom.Q * sc.geom.N for it, sc in zip(it_b, scenes)))
     return out
 
 
@@ -408,6 +449,15 @@ def main():
     if args.only == "iter":
         iter_only(torch, lib, stream, g, hp, y_dev, args.storage)
         return
+    if args.only == "c4":
+        print(json.dumps(batch_leg(torch, lib, stream)), flush=True)
+        return
+    if args.only == "c4batch":
+        r = batch_leg(torch, lib, stream, reps=1, n_check=0, legs=("batched",))
+        print(json.dumps(dict(frames=r["frames"], batched_ms=round(r["batched"]["ms"], 1),
+                              iters=int(sum(r["batched"]["iters"])), sum_iters_QN=r["sum_iters_QN"])),
+              flush=True)
+        return
 
     results = {}
     variants = [("pruned", True), ("plain", False)]
@@ -494,10 +544,10 @@ def main():
         results["c5_mf"] = dict(factor_ms=t5["factor_ms"], iter_ms=t5b["iter_ms"] / 10,
                                 stats=st5, elems_per_iter=el)
 
-    # batched uneven frames (c4): 16 frames of different Q and grid size solved
-    # one by one and as one batch (one launch per kernel for all frames)
+    # batched uneven frames (c4): 256 frames of different Q and grid size
+    # solved one by one and as one batch (one launch per kernel for all frames)
     if not args.only:
-        results["c4"] = batch_leg(torch, lib, stream, args.storage)
+        results["c4"] = batch_leg(torch, lib, stream)
     # frames of one geometry sharing the c2 operator (multi-RHS products)
     if not args.only and args.storage == "fp32":
         results["shared"] = shared_leg(torch, lib, stream, info)
@@ -551,9 +601,19 @@ def main():
         extra["measured_denominators"] = dens
     if "c4" in results:
         r4 = results["c4"]
+        extra["c4_frames"] = r4["frames"]
+        extra["c4_storage"] = "bf16 planes, FP32 arithmetic, FP64 factor, correction every 10"
         for k in ("sequential", "batched"):
             extra[f"c4_{k}_frames_per_s"] = round(r4["frames"] / (r4[k]["ms"] * 1e-3), 1)
-        extra["c4_iters"] = r4["batched"]["iters"]
+            extra[f"c4_{k}_ms"] = round(r4[k]["ms"], 1)
+        it = np.array(r4["batched"]["iters"])
+        extra["c4_iters"] = dict(min=int(it.min()), median=float(np.median(it)), max=int(it.max()),
+                                 total=int(it.sum()))
+        extra["c4_all_converged"] = all(st == 0 for st in r4["batched"]["status"])
+        extra["c4_tile_widths"] = r4["widths"]
+        extra["c4_max_nmse_vs_fp64"] = max(d["nmse"] for d in r4["nmse_vs_fp64"])
+        extra["c4_nmse_vs_fp64"] = r4["nmse_vs_fp64"]
+        extra["c4_device_mem_in_use_GB"] = r4["device_mem_in_use_GB"]
     for name in ("pruned", "plain"):
         if name in results:
             r = results[name]

@@ -126,7 +126,14 @@ typedef struct {
                                  the solve stops only if the x-update moves by at
                                  most eps_pri under the new g (the change of
                                  (mu Ahat^H Ahat + cI)^{-1} g over the active
-                                 pixels), else it iterates on.  0 (default): off */
+                                 pixels), else it iterates on.  With pruning, SSC
+                                 judges only iterates of a settled corrected
+                                 problem: it eliminates nothing until a correction
+                                 has moved the x-update by at most eps_pri (or by
+                                 at most 1e-5 of the iterate norm in eps_pri, the
+                                 FP32 floor of the correction), and its
+                                 K_p-window starts after the last correction that
+                                 moved it by more.  0 (default): off */
   int32_t nonneg;             /* 1: the image is a non-negative magnitude (Sec. II):
                                  z = max(Re(xbar + u) - lambda / beta, 0) instead
                                  of the complex soft threshold.  With a real
@@ -263,7 +270,9 @@ int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count)
  * which = 0 r, 1 s, 2 eps_pri, 3 eps_dual, 4 nmse, 5 max_q N_q / N,
  * 6 change of the x-update when a stale 16-bit correction was retaken at a
  * passed stop test (0 at other iterations; compared with eps_pri),
- * 7 beta in force after the iteration (residual balancing).
+ * 7 beta in force after the iteration (residual balancing),
+ * 8 move of the x-update caused by each 16-bit correction, at the iteration
+ * that took it (0 at other iterations).
  * *count receives the number of iterations recorded. */
 int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap,
                       int32_t* count);

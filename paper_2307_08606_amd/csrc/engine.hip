@@ -21,6 +21,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -94,8 +95,12 @@ struct sadmm_s {
   SensorDesc* sens_mf_d = nullptr;   // sensor table viewing rec as a matrix-free operator
   double *gfix = nullptr, *re1 = nullptr, *re2 = nullptr, *rw = nullptr;
   double *gprev = nullptr, *dg = nullptr;   // previous correction, per-sensor squared changes
+  double* dg_h = nullptr;                   // pinned host copy of dg
   void *g32 = nullptr, *xfix = nullptr, *xprev = nullptr;
   int k_refined = 0;             // iteration of the last correction
+  double shift = 0.0;            // x-update move caused by the last correction
+  bool settled = false;          // that move was within the settling tolerance
+  int k_jump = 0;                // iteration of the last correction that did not settle
   // W not formed after a build (W64 holds U = X^H, hpdX holds X = L^{-1})
   std::vector<uint8_t> wtri;
   double* ws = nullptr;          // Q x KMp complex128: X v of the triangular products
@@ -122,7 +127,7 @@ struct sadmm_s {
 
   // results of the last solve
   sadmm_info info{};
-  std::vector<double> hist_h;   // 8 x max_iter
+  std::vector<double> hist_h;   // 9 x max_iter
   int hist_count = 0;
   double t_total = 0, t_factor = 0, t_iter = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
@@ -146,6 +151,7 @@ struct sadmm_s {
   bool start_restricted = false;   // the solve started with eliminated pixels
   double last_dg = 0.0;            // x-update change of the last correction retake
   std::vector<std::pair<int, double>> retake_pts;   // (iteration, that change) per retake
+  std::vector<std::pair<int, double>> shift_pts;    // (iteration, x-update move) per correction
 
   // optional per-kernel-class event timing (sadmm_set_profiling)
   bool prof = false;
@@ -296,6 +302,16 @@ IterArgs make_args(sadmm_t h) {
   a.ws = h->ws;
   a.gfix = h->p.refine_every > 0 ? h->gfix : nullptr;
   a.xfix = h->p.refine_every > 0 ? h->xfix : nullptr;
+  // With the correction of a 16-bit operator, SSC judges only iterates of
+  // the corrected problem once that problem has settled: the latest
+  // correction moved the x-update by at most the settling tolerance, and the
+  // K_p-window starts after the last correction that moved it by more
+  // (its x jumps).  Pixels frozen while the correction still moves keep
+  // values of a fixed point that is not the final one, and the consensus
+  // then reaches the tolerance only as slowly as the dual absorbs the
+  // difference.
+  a.ssc_from = h->p.refine_every <= 0 ? 0
+               : (h->settled ? h->k_jump + h->p.Kp + 1 : std::numeric_limits<int>::max());
   return a;
 }
 
@@ -886,6 +902,10 @@ int refine_setup(sadmm_t h) {
   TRY(grab((void**)&h->gfix, 16 * QN));
   TRY(grab((void**)&h->gprev, 16 * QN));
   TRY(grab((void**)&h->dg, sizeof(double) * h->Q));
+  if (!h->dg_h && hipHostMalloc((void**)&h->dg_h, sizeof(double) * h->Q) != hipSuccess) {
+    h->dg_h = nullptr;
+    return fail_msg(h, SADMM_E_NOMEM, "refinement buffers: pinned host copy");
+  }
   TRY(grab(&h->g32, h->csz * QN));
   TRY(grab(&h->xfix, h->csz * QN));
   TRY(grab(&h->xprev, h->csz * QN));
@@ -1033,7 +1053,11 @@ int solve_prologue_finish(sadmm_t h) {
   h->beta_pts.assign(1, {1, h->p.beta});
   h->kkt_rounds = 0;
   h->k_refined = 0;
+  h->shift = 0.0;
+  h->settled = false;
+  h->k_jump = 0;
   h->retake_pts.clear();
+  h->shift_pts.clear();
   h->status = 1;
   h->done = false;
   const IterArgs a = make_args(h);
@@ -1051,11 +1075,12 @@ int solve_prologue_finish(sadmm_t h) {
 // xfix = (mu Ahat^H Ahat + cI)^{-1} g = (g - Ahat^H W Ahat g) / c, a direct
 // sensor adds g to its right-hand side.  A x runs over every pixel, frozen
 // ones included (y' holds their contribution through Ahat).
-int refine(sadmm_t h, int k) {
-  for (int q = 0; q < h->Q; ++q)
-    if (!h->direct[q]) TRY(ensure_w(h, q));   // the W v step reads W itself
+int refine_enqueue(sadmm_t h) {
   hipStream_t s = h->s;
   const size_t QK = (size_t)h->Q * h->KMp;
+  const size_t QN = (size_t)h->Q * h->N;
+  HIPCHK(h, hipMemcpyAsync(h->gprev, h->gfix, 16 * QN, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->xprev, h->xfix, h->csz * QN, hipMemcpyDeviceToDevice, s));
   const double mu = h->p.mu, cinv = 1.0 / (h->p.beta + h->p.gamma);
   const IterArgs a = make_args(h);
   IterArgs am = a;
@@ -1075,9 +1100,50 @@ int refine(sadmm_t h, int k) {
   launch_refine_fwd(a, h->st, true, h->g32, 1.0, h->re2, s);
   launch_factor_vec(a, h->re2, h->rw, s);
   launch_refine_fix(a, h->st, max_nq, h->rw, h->gfix, cinv, h->xfix, s);
+  // The move of the x-update under the new correction:
+  // (mu Ahat^H Ahat + cI)^{-1} times the change of g, i.e. the change of xfix
+  // for a Woodbury sensor and F applied to the change of g for a direct one.
+  for (int q = 0; q < h->Q; ++q) {
+    const size_t o = (size_t)q * h->N;
+    if (h->direct[q])
+      herm_apply_norm2(reinterpret_cast<const double*>(h->Fd[q]), h->fld[q], h->nq[q], h->J[q],
+                       h->gfix + 2 * o, h->gprev + 2 * o, h->dg + q, s);
+    else if (h->dbl)
+      diff_norm2_c128(static_cast<const double*>(h->xfix) + 2 * o,
+                      static_cast<const double*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
+    else
+      diff_norm2_c64(static_cast<const float*>(h->xfix) + 2 * o,
+                     static_cast<const float*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
+  }
+  HIPCHK(h, hipMemcpyAsync(h->dg_h, h->dg, sizeof(double) * h->Q, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipStreamSynchronize(s));
+  return SADMM_OK;
+}
+
+// Completes a correction queued by refine_enqueue, once h->s has drained.
+void refine_finish(sadmm_t h, int k) {
+  double d2 = 0.0;
+  for (int q = 0; q < h->Q; ++q) d2 += h->dg_h[q];
+  h->shift = std::sqrt(d2);
+  // settled: the move is within the primal tolerance, or within 1e-5 of the
+  // iterate's norm (the scale in eps_pri), below which it is the FP32
+  // rounding of the correction itself and no longer shrinks
+  double tol = h->ctl_h->eps_pri;
+  if (h->p.eps_rel > 0.0) {
+    const double sqQN = std::sqrt((double)h->Q * h->N);
+    tol = std::max(tol, 1e-5 * (h->ctl_h->eps_pri - sqQN * h->p.eps_abs) / h->p.eps_rel);
+  }
+  h->settled = h->shift <= tol;
+  if (!h->settled) h->k_jump = k;
+  h->shift_pts.push_back({k, h->shift});
   h->k_refined = k;
+  h->args_dirty = true;      // SSC's window start moves with the correction
+}
+
+int refine(sadmm_t h, int k) {
+  TRY(refine_enqueue(h));
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  refine_finish(h, k);
   return SADMM_OK;
 }
 
@@ -1177,28 +1243,8 @@ int handle_halt(sadmm_t h, const Ctl& c, bool* active) {
       // error and the FP32 rounding of A^H(y - A x) sit, by the operator's
       // large singular values.)
       if (c.k >= h->p.max_iter) { h->status = 1; h->done = true; return SADMM_OK; }
-      const size_t QN = (size_t)h->Q * h->N;
-      HIPCHK(h, hipMemcpyAsync(h->gprev, h->gfix, 16 * QN, hipMemcpyDeviceToDevice, s));
-      HIPCHK(h, hipMemcpyAsync(h->xprev, h->xfix, h->csz * QN, hipMemcpyDeviceToDevice, s));
       TRY(refine(h, c.k));
-      for (int q = 0; q < h->Q; ++q) {
-        const size_t o = (size_t)q * h->N;
-        if (h->direct[q])
-          herm_apply_norm2(reinterpret_cast<const double*>(h->Fd[q]), h->fld[q], h->nq[q], h->J[q],
-                           h->gfix + 2 * o, h->gprev + 2 * o, h->dg + q, s);
-        else if (h->dbl)
-          diff_norm2_c128(static_cast<const double*>(h->xfix) + 2 * o,
-                          static_cast<const double*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
-        else
-          diff_norm2_c64(static_cast<const float*>(h->xfix) + 2 * o,
-                         static_cast<const float*>(h->xprev) + 2 * o, h->N, h->dg + q, s);
-      }
-      std::vector<double> dq(h->Q, 0.0);
-      HIPCHK(h, hipMemcpyAsync(dq.data(), h->dg, sizeof(double) * h->Q, hipMemcpyDeviceToHost, s));
-      HIPCHK(h, hipStreamSynchronize(s));
-      double d2 = 0.0;
-      for (int q = 0; q < h->Q; ++q) d2 += dq[q];
-      h->last_dg = std::sqrt(d2);
+      h->last_dg = h->shift;
       h->retake_pts.push_back({c.k, h->last_dg});
       if (!(h->last_dg <= c.eps_pri)) {
         *h->halt_h = 0;
@@ -1241,6 +1287,7 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
   Ctl** ctlp_d = nullptr;
   Ctl* ctl_all_d = nullptr;
   std::vector<Ctl> ctl_all(S);
+  std::vector<IterArgs> av(S);          // host copies of the argument table
   std::vector<void*> tmp;
   auto cleanup = [&]() { for (void* p : tmp) hipFree(p); };
   if (!single) {
@@ -1253,7 +1300,6 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
     tmp.push_back(p); ctlp_d = static_cast<Ctl**>(p);
     if (hipMalloc(&p, sizeof(Ctl) * S) != hipSuccess) { cleanup(); return fail_msg(h0, SADMM_E_NOMEM, "batch tables"); }
     tmp.push_back(p); ctl_all_d = static_cast<Ctl*>(p);
-    std::vector<IterArgs> av(S);
     std::vector<Ctl*> cp(S);
     for (int i = 0; i < S; ++i) { av[i] = make_args(hs[i]); cp[i] = hs[i]->ctl; }
     if (hipMemcpy(args_d, av.data(), sizeof(IterArgs) * S, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1282,11 +1328,13 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
   const int check = h0->p.check_every;
   int rc = SADMM_OK;
   for (;;) {
-    // a single scene reads its status exactly where a correction is due
-    // (a batch corrects at the first status read at or after it)
+    // status read where the earliest correction of a running scene is due
+    // (scenes that halted in between run behind the others and correct at
+    // the first status read at or after theirs)
     int nq_iter = check;
-    if (single && h0->p.refine_every > 0)
-      nq_iter = std::max(1, std::min(check, h0->k_refined + h0->p.refine_every - h0->ctl_h->k));
+    for (const sadmm_t h : hs)
+      if (!h->done && h->p.refine_every > 0)
+        nq_iter = std::min(nq_iter, std::max(1, h->k_refined + h->p.refine_every - h->ctl_h->k));
     for (int i = 0; i < nq_iter; ++i) {
       if (ge) {
         if (hipGraphLaunch(ge, gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "graph launch failed"); break; }
@@ -1334,25 +1382,46 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
           hipStreamSynchronize(gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "status read failed"); break; }
     }
     bool any = false;
+    std::vector<int> due;                 // scenes whose scheduled correction is due
     for (int i = 0; i < S && rc == SADMM_OK; ++i) {
       sadmm_t h = hs[i];
       if (h->done) continue;
       *h->ctl_h = ctl_all[i];
       bool active = false;
       rc = handle_halt(h, ctl_all[i], &active);
-      if (rc == SADMM_OK && h->args_dirty) {
-        const IterArgs an = make_args(h);
-        if (hipMemcpyAsync(args_d + i, &an, sizeof(IterArgs), hipMemcpyHostToDevice, gs) != hipSuccess ||
-            hipStreamSynchronize(gs) != hipSuccess)
-          rc = fail_msg(h, SADMM_E_HIP, "argument upload failed");
-        h->args_dirty = false;
-      }
       if (rc == SADMM_OK && active && h->p.refine_every > 0 &&
           ctl_all[i].k - h->k_refined >= h->p.refine_every)
-        rc = refine(h, ctl_all[i].k);
+        due.push_back(i);
       if (rc != SADMM_OK && h != h0) h0->err = h->err;
       any = any || active;
     }
+    // the due corrections of every scene queued together, one wait
+    for (size_t j = 0; j < due.size() && rc == SADMM_OK; ++j) {
+      rc = refine_enqueue(hs[due[j]]);
+      if (rc != SADMM_OK && hs[due[j]] != h0) h0->err = hs[due[j]]->err;
+    }
+    if (rc == SADMM_OK && !due.empty()) {
+      std::vector<hipStream_t> ss;
+      for (int i : due)
+        if (std::find(ss.begin(), ss.end(), hs[i]->s) == ss.end()) ss.push_back(hs[i]->s);
+      for (hipStream_t st : ss)
+        if (hipStreamSynchronize(st) != hipSuccess) rc = fail_msg(h0, SADMM_E_HIP, "correction failed");
+      for (int i : due)
+        if (rc == SADMM_OK) refine_finish(hs[i], ctl_all[i].k);
+    }
+    // changed iteration arguments, one wait
+    bool uploaded = false;
+    for (int i = 0; i < S && rc == SADMM_OK; ++i) {
+      sadmm_t h = hs[i];
+      if (!h->args_dirty) continue;
+      av[i] = make_args(h);
+      if (hipMemcpyAsync(args_d + i, &av[i], sizeof(IterArgs), hipMemcpyHostToDevice, gs) != hipSuccess)
+        rc = fail_msg(h0, SADMM_E_HIP, "argument upload failed");
+      h->args_dirty = false;
+      uploaded = true;
+    }
+    if (rc == SADMM_OK && uploaded && hipStreamSynchronize(gs) != hipSuccess)
+      rc = fail_msg(h0, SADMM_E_HIP, "argument upload failed");
     if (rc != SADMM_OK || !any) break;
   }
   if (!single) {
@@ -1376,7 +1445,7 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
   HIPCHK(h, hipMemcpy(h->ctl_h, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
   const Ctl c = *h->ctl_h;
   h->hist_count = c.k;
-  h->hist_h.assign(8 * (size_t)h->p.max_iter, 0.0);
+  h->hist_h.assign(9 * (size_t)h->p.max_iter, 0.0);
   HIPCHK(h, hipMemcpy(h->hist_h.data(), h->hist, sizeof(double) * 5 * h->p.max_iter, hipMemcpyDeviceToHost));
   for (int k = 1; k <= c.k; ++k) {
     double f = h->frac_pts[0].second;
@@ -1386,6 +1455,8 @@ int solve_epilogue(sadmm_t h, sadmm_info* info) {
   }
   for (auto& pt : h->retake_pts)
     if (pt.first >= 1 && pt.first <= h->p.max_iter) h->hist_h[6 * (size_t)h->p.max_iter + pt.first - 1] = pt.second;
+  for (auto& pt : h->shift_pts)
+    if (pt.first >= 1 && pt.first <= h->p.max_iter) h->hist_h[8 * (size_t)h->p.max_iter + pt.first - 1] = pt.second;
   for (int k = 1; k <= c.k; ++k) {
     double b = h->beta_pts[0].second;
     for (auto& pt : h->beta_pts)
@@ -1973,7 +2044,7 @@ int sadmm_get_active_indices(sadmm_t h, int32_t q, int32_t* idx, int32_t* count)
 
 int sadmm_get_history(sadmm_t h, int32_t which, double* out, int32_t cap, int32_t* count) {
   if (!h) return SADMM_E_ARG;
-  if (!out || !count || which < 0 || which > 7 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
+  if (!out || !count || which < 0 || which > 8 || cap < 0) return fail_msg(h, SADMM_E_ARG, "get_history: bad argument");
   if (!h->solved) return fail_msg(h, SADMM_E_STATE, "get_history: no solve yet");
   const int n = std::min(cap, h->hist_count);
   std::memcpy(out, h->hist_h.data() + (size_t)which * h->p.max_iter, sizeof(double) * n);
@@ -2170,6 +2241,7 @@ void sadmm_destroy(sadmm_t h) {
                   (void*)h->rw, (void*)h->gprev, (void*)h->dg, h->xprev})
     if (p) hipFree(p);
   if (h->ctl_h) hipHostFree(h->ctl_h);
+  if (h->dg_h) hipHostFree(h->dg_h);
   if (h->counts_h) hipHostFree(h->counts_h);
   if (h->halt_h) hipHostFree(h->halt_h);
   if (h->ev0) hipEventDestroy(h->ev0);

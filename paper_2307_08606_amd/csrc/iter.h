@@ -51,6 +51,8 @@ struct IterArgs {
   double* red;         // pixel-kernel block partials (nblk x 8)
   int nblk;
   int max_iter;
+  int ssc_from;        // first iteration at which SSC may eliminate (its window
+                       // then lies after the latest operator correction)
   Ctl* ctl;
   double* hist;        // 6 x max_iter
   uint8_t* keep;       // Q x N: SSC keep flag per active position
@@ -153,7 +155,8 @@ void launch_kkt_grad(const IterArgs& a, int st, bool dbl, int q, const int* idx,
 //   launch_refine_fwd:  out_q += sign * A_q x_q over the active pixels J_q
 //                       (active) or all N pixels, x from xsrc (Q x N compute
 //                       precision) or X; tpart is the scratch; out Q x KMp c128;
-//   launch_factor_vec:  out_q = W64_q v_q (W Hermitian, FP64);
+//   launch_factor_vec:  out_q = W_q v_q (W Hermitian, FP64; held as W64_q, or
+//                       as the triangular pair X_q^H X_q, using ws as scratch);
 //   launch_refine_grad: g[q, J_q[p]] = scale (A_q^H e_q)_p, or with accumulate
 //                       += it, also writing the sum in compute precision to g32;
 //   launch_refine_fix:  xfix[q, J_q[p]] = cinv (g - A_q^H w_q)_p.

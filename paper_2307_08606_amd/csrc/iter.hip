@@ -232,10 +232,12 @@ __global__ __launch_bounds__(256) void fwd_all_reduce_kernel(IterArgs a, int act
 
 // ------------------------------------------------------------------ column dots
 enum : int { EPI_W = 0, EPI_XUPD = 1, EPI_WY = 2, EPI_XY = 3, EPI_KKT = 4, EPI_MF = 5,
-              EPI_GRAD = 6, EPI_FIX = 7, EPI_WVEC = 8, EPI_W1 = 9, EPI_WY1 = 10 };
-// W products of a sensor with wtri: EPI_W1 / EPI_WY1 form ws = X t / X y' by
-// column dots of U = X^H (column p nonzero in rows 0..p), then EPI_W / EPI_WY
-// take X^H ws by column dots of X (column p nonzero in rows p..KMp-1).
+              EPI_GRAD = 6, EPI_FIX = 7, EPI_WVEC = 8, EPI_W1 = 9, EPI_WY1 = 10,
+              EPI_WVEC1 = 11 };
+// W products of a sensor with wtri: EPI_W1 / EPI_WY1 / EPI_WVEC1 form
+// ws = X t / X y' / X v by column dots of U = X^H (column p nonzero in rows
+// 0..p), then EPI_W / EPI_WY / EPI_WVEC take X^H ws by column dots of X
+// (column p nonzero in rows p..KMp-1).
 // Column dots over a caller's pixel list of one sensor (x.q, x.idx, x.count)
 template <int EPI> constexpr bool listed_cols() { return EPI == EPI_KKT; }
 // Column dots over the active pixels J_q of every sensor (blockIdx.y = sensor)
@@ -332,10 +334,12 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   constexpr int DC = dot_cols<ST>();
   if ((EPI == EPI_W || EPI == EPI_W1 || EPI == EPI_XUPD) && a.ctl->halt) return;
   const SensorDesc sd = a.sens[q];
-  if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC || EPI == EPI_W1) && sd.direct) return;
-  if ((EPI == EPI_W1 || EPI == EPI_WY1) && !sd.wtri) return;
+  if ((EPI == EPI_W || EPI == EPI_FIX || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WVEC1) && sd.direct)
+    return;
+  if ((EPI == EPI_W1 || EPI == EPI_WY1 || EPI == EPI_WVEC1) && !sd.wtri) return;
   int ncols;
-  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1)
+  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1 ||
+                EPI == EPI_WVEC1)
     ncols = a.KMp;
   else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY || active_cols<EPI>()) ncols = sd.nq;
   else if constexpr (listed_cols<EPI>()) ncols = x.count;
@@ -348,7 +352,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   // stage the vector operand
   for (int i = threadIdx.x; i < a.KMp; i += 256) {
     C2<TA> v;
-    if constexpr ((EPI == EPI_W || EPI == EPI_WY) && std::is_same<TA, double>::value) {
+    if constexpr ((EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) && std::is_same<TA, double>::value) {
       if (sd.wtri) {   // second half of X^H (X v)
         v = {(TA)a.ws[2 * ((int64_t)q * a.KMp + i)], (TA)a.ws[2 * ((int64_t)q * a.KMp + i) + 1]};
         sv[sv_slot<ST>(i)] = v;
@@ -375,7 +379,8 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
 #pragma unroll
   for (int c = 0; c < DC; ++c) {
     const int p = min(pw + c, ncols - 1);   // past the end: repeat the last column
-    if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1)
+    if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC || EPI == EPI_W1 || EPI == EPI_WY1 ||
+                  EPI == EPI_WVEC1)
       cols[c] = col_ptr<ST>(sd.W64, a.KMp, p);
     else if constexpr (EPI == EPI_XUPD || EPI == EPI_XY) cols[c] = col_ptr<ST>(sd.A, sd.lda, p);
     else if constexpr (listed_cols<EPI>()) cols[c] = col_ptr<ST>(sd.Afull, sd.lda, x.idx[p]);
@@ -383,10 +388,11 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
     else cols[c] = col_ptr<ST>(sd.Afull, sd.lda, p);
   }
   C2<TA> dots[DC];
-  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_W1 || EPI == EPI_WY1) {
+  if constexpr (EPI == EPI_W || EPI == EPI_WY || EPI == EPI_W1 || EPI == EPI_WY1 || EPI == EPI_WVEC ||
+                EPI == EPI_WVEC1) {
     int rbeg = 0, rend = -1;
     if (sd.wtri) {
-      if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
+      if constexpr (EPI == EPI_W1 || EPI == EPI_WY1 || EPI == EPI_WVEC1) {
         rend = min(a.KMp, (pw + DC + 63) & ~63);   // U: rows <= p
       } else {
 #pragma unroll
@@ -444,7 +450,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       const double gim = x.mu * d.im + x.gamma * (double)xv.im + a.beta * (double)uv.im;
       x.out[2 * p] = gre;
       x.out[2 * p + 1] = gim;
-    } else if constexpr (EPI == EPI_W1 || EPI == EPI_WY1) {
+    } else if constexpr (EPI == EPI_W1 || EPI == EPI_WY1 || EPI == EPI_WVEC1) {
       a.ws[2 * ((int64_t)q * a.KMp + p)] = d.re;
       a.ws[2 * ((int64_t)q * a.KMp + p) + 1] = d.im;
     } else if constexpr (EPI == EPI_WVEC) {
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(256) void ssc_kernel(BatchView bv) {
   if (!a.prune) return;
   if (ctl->halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_PRUNE)) return;
   const int k = ctl->k;
-  if (k < a.Kp || !ctl->gate) return;
+  if (k < a.Kp || k < a.ssc_from || !ctl->gate) return;
   const int q = sl.y;
   const SensorDesc sd = a.sens[q];
   const int p = blockIdx.x * 256 + threadIdx.x;
@@ -869,8 +875,11 @@ void launch_factor_vec(const IterArgs& a, const double* v, double* out, hipStrea
   x.vec_stride = a.KMp;
   x.out = out;
   const int cpb = 4 * dot_cols<ST_FP64>();
-  coldot_kernel<ST_FP64, EPI_WVEC, float><<<dim3((a.KMp + cpb - 1) / cpb, a.Q), 256,
-                                             (size_t)a.KMp * sizeof(cd), s>>>(a, x);
+  const dim3 grid((a.KMp + cpb - 1) / cpb, a.Q);
+  // sensors holding the triangular pair: ws = X v first (into the iteration's
+  // scratch, free between iterations), then X^H ws
+  coldot_kernel<ST_FP64, EPI_WVEC1, float><<<grid, 256, (size_t)a.KMp * sizeof(cd), s>>>(a, x);
+  coldot_kernel<ST_FP64, EPI_WVEC, float><<<grid, 256, (size_t)a.KMp * sizeof(cd), s>>>(a, x);
 }
 
 template <int ST>

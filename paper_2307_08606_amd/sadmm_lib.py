@@ -34,7 +34,7 @@ ST_FP64, ST_FP32, ST_FP16P, ST_BF16P, ST_MATRIX_FREE = 0, 1, 2, 3, 4
 STORAGE = {"fp64": ST_FP64, "fp32": ST_FP32, "fp16": ST_FP16P, "bf16": ST_BF16P,
            "mf": ST_MATRIX_FREE}
 HIST = {"r": 0, "s": 1, "eps_pri": 2, "eps_dual": 3, "nmse": 4, "max_active_frac": 5,
-        "retake_change": 6, "beta": 7}
+        "retake_change": 6, "beta": 7, "correction_move": 8}
 
 
 class sadmm_params(C.Structure):
