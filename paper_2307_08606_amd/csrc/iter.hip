@@ -66,6 +66,37 @@ __device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* col
   if constexpr (ST == ST_MF) {
     // generated entries: few columns in flight keep registers (and waves) for
     // the generation arithmetic
+    const double* rec0 = reinterpret_cast<const double*>(col_ptr<ST>(A, lda, colidx ? colidx[p0] : p0));
+    const int K = (int)rec0[0], M = (int)rec0[1];
+    if ((K & (R - 1)) == 0) {
+      // the thread's 8 rows lie in one receiver: the term coef * a0 of the
+      // anchor entry a0 is rotated row by row (one complex rotation and one
+      // complex add per entry, against a rotation of the entry and a
+      // complex multiply-add)
+      const int m = row / K, k = row - m * K;
+      if (m >= M) return;                     // padding rows: zero entries
+#pragma unroll 2
+      for (int e = 0; e < np; ++e) {
+        const int col = colidx ? colidx[p0 + e] : p0 + e;
+        float ar, ai, rc, rs;
+        Store<ST_MF>::anchor(col_ptr<ST>(A, lda, col), m, k, M, &ar, &ai, &rc, &rs);
+        const C2<T> cf = coef[e];
+        T wr = fmaf(ar, cf.re, -(ai * cf.im));
+        T wi = fmaf(ar, cf.im, ai * cf.re);
+        acc[0].re += wr;
+        acc[0].im += wi;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {   // w <- w (rc - j rs)
+          const T nr = fmaf(wr, rc, wi * rs);
+          const T ni = fmaf(wi, rc, -(wr * rs));
+          wr = nr;
+          wi = ni;
+          acc[r].re += wr;
+          acc[r].im += wi;
+        }
+      }
+      return;
+    }
 #pragma unroll 2
     for (int e = 0; e < np; ++e) step(e);
   } else {
@@ -298,16 +329,62 @@ __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* s
   for (int c = 0; c < C; ++c) acc[c] = {(TA)0, (TA)0};
   // rows [rbeg, rend): rbeg a multiple of the sweep width or 0
   const int re_ = rend < 0 ? KMp : rend;
-  for (int i0 = rbeg + lane * R; i0 < re_; i0 += SADMM_WAVE * R) {
-    C2<TA> v[R];
+  if constexpr (ST == ST_MF) {
+    const double* rec0 = reinterpret_cast<const double*>(col[0]);
+    const int K = (int)rec0[0], M = (int)rec0[1];
+    if ((K & (R - 1)) == 0) {
+      // a lane's 8 rows lie in one receiver: sum_r conj(a0 rho^r) v_r =
+      // conj(a0) * sum_r conj(rho)^r v_r, the sum by Horner's rule (one
+      // complex multiply-add per entry, against a rotation of the entry and
+      // a complex multiply-add)
+      for (int i0 = rbeg + lane * R; i0 < re_; i0 += SADMM_WAVE * R) {
+        const int m = i0 / K;
+        if (m >= M) break;                    // padding rows: zero entries
+        const int k = i0 - m * K;
+        C2<TA> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = sv[sv_slot<ST>(i0 + r)];
+        for (int r = 0; r < R; ++r) v[r] = sv[sv_slot<ST>(i0 + r)];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      T re[R], im[R];
-      Store<ST>::load(col[c], i0, KMp, re, im);
+        for (int c = 0; c < C; ++c) {
+          float ar, ai, rc, rs;
+          Store<ST_MF>::anchor(col[c], m, k, M, &ar, &ai, &rc, &rs);
+          const TA cr = (TA)rc, ci = (TA)rs;  // conj(rho) = rc + j rs
+          TA hr = v[R - 1].re, hi = v[R - 1].im;
 #pragma unroll
-      for (int r = 0; r < R; ++r) cfmac(acc[c], C2<TA>{(TA)re[r], (TA)im[r]}, v[r]);
+          for (int r = R - 2; r >= 0; --r) {
+            const TA nr = fma(cr, hr, fma(-ci, hi, v[r].re));
+            const TA ni = fma(cr, hi, fma(ci, hr, v[r].im));
+            hr = nr;
+            hi = ni;
+          }
+          cfmac(acc[c], C2<TA>{(TA)ar, (TA)ai}, C2<TA>{hr, hi});
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        acc[c].re = wave_sum(acc[c].re);
+        acc[c].im = wave_sum(acc[c].im);
+      }
+      return;
+    }
+  }
+  // general case: generated entries cost registers, so the matrix-free
+  // operator takes its columns two per sweep
+  constexpr int CS = (ST == ST_MF && C > 2) ? 2 : C;
+  static_assert(C % CS == 0, "column groups");
+#pragma unroll
+  for (int c0 = 0; c0 < C; c0 += CS) {
+    for (int i0 = rbeg + lane * R; i0 < re_; i0 += SADMM_WAVE * R) {
+      C2<TA> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = sv[sv_slot<ST>(i0 + r)];
+#pragma unroll
+      for (int c = c0; c < c0 + CS; ++c) {
+        T re[R], im[R];
+        Store<ST>::load(col[c], i0, KMp, re, im);
+#pragma unroll
+        for (int r = 0; r < R; ++r) cfmac(acc[c], C2<TA>{(TA)re[r], (TA)im[r]}, v[r]);
+      }
     }
   }
 #pragma unroll
@@ -402,25 +479,19 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
       }
     }
     coldot_multi<ST, TA, DC>(cols, sv, a.KMp, lane, dots, rbeg, rend);
-  } else if constexpr (ST == ST_MF) {
-    // generated entries cost registers: two columns per sweep
-    static_assert(DC % 2 == 0, "column pairs");
-#pragma unroll
-    for (int c = 0; c < DC; c += 2) {
-      const void* const pair[2] = {cols[c], cols[c + 1]};
-      C2<TA> d2[2];
-      coldot_multi<ST, TA, 2>(pair, sv, a.KMp, lane, d2);
-      dots[c] = d2[0];
-      dots[c + 1] = d2[1];
-    }
   } else {
     coldot_multi<ST, TA, DC>(cols, sv, a.KMp, lane, dots);
   }
-  if (lane != 0) return;
-  for (int c = 0; c < DC; ++c) {
-    const int p = pw + c;
-    if (p >= ncols) break;
-    const C2<TA> d = dots[c];
+  // The butterfly reduction leaves the same sums in every lane: lane c
+  // finishes column pw + c, so a wave's columns complete together.
+  if (lane >= DC) return;
+  const int p = pw + lane;
+  if (p >= ncols) return;
+  C2<TA> d = dots[0];
+#pragma unroll
+  for (int c = 1; c < DC; ++c)
+    if (lane == c) d = dots[c];
+  {
     if constexpr (EPI == EPI_W) {
       stc<T>(a.w, (int64_t)q * a.KMp + p, C2<T>{(T)d.re, (T)d.im});
     } else if constexpr (EPI == EPI_XUPD) {
@@ -520,14 +591,18 @@ __device__ inline void xdir_body(const IterArgs& a, int q) {
       }
     }
   }
-  if (lane != 0) return;
+  // every lane holds the sums: lane c finishes column c of the wave
+  if (lane >= DC) return;
   const int slot = a.ctl->k % a.Kp;
+  {
+    const int p = col0 + wv * DC + lane;
+    if (p >= sd.nq) return;
+    cd ac = acc[0];
 #pragma unroll
-  for (int c = 0; c < DC; ++c) {
-    const int p = col0 + wv * DC + c;
-    if (p >= sd.nq) break;
+    for (int c = 1; c < DC; ++c)
+      if (lane == c) ac = acc[c];
     const int n = sd.J[p];
-    const C2<T> xn = {(T)acc[c].re, (T)acc[c].im};
+    const C2<T> xn = {(T)ac.re, (T)ac.im};
     const int64_t o = (int64_t)q * a.N + n;
     const C2<T> dx = csub(xn, ldc<T>(a.X, o));
     stc<T>(a.X, o, xn);
