@@ -374,6 +374,9 @@ __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* s
   static_assert(C % CS == 0, "column groups");
 #pragma unroll
   for (int c0 = 0; c0 < C; c0 += CS) {
+    // stored entries of at most 8 bytes per lane and column: four row steps
+    // in flight, so that each lane keeps 64-128 bytes of loads outstanding
+#pragma unroll(R <= 2 ? 4 : 1)
     for (int i0 = rbeg + lane * R; i0 < re_; i0 += SADMM_WAVE * R) {
       C2<TA> v[R];
 #pragma unroll
@@ -422,7 +425,12 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   else if constexpr (listed_cols<EPI>()) ncols = x.count;
   else ncols = a.N;
   const int cols_per_block = 4 * DC;
-  const int col0 = blockIdx.x * cols_per_block;
+  // U's column p holds rows 0..p: its triangle pass takes the longest
+  // columns first, so the last work-groups of the grid are the short ones
+  // (X's pass, rows p..KMp-1, is longest first in the plain order)
+  const int bx = (EPI == EPI_W1 || EPI == EPI_WY1 || EPI == EPI_WVEC1)
+                     ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int col0 = bx * cols_per_block;
   if (col0 >= ncols) return;
   extern __shared__ unsigned char smem_raw[];
   C2<TA>* sv = reinterpret_cast<C2<TA>*>(smem_raw);
