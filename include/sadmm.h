@@ -115,8 +115,11 @@ typedef struct {
                                  (mu Ahat^H Ahat + cI)^{-1} of order N_q, 1 keeps the
                                  Woodbury form (Sec. III solves the N_q system) */
   int32_t refine_every;       /* FP16P / BF16P storage only, operator set from the
-                                 geometry: every refine_every iterations (a batch:
-                                 at the first status read at or after that) the
+                                 geometry: at iterations 2, 4, 8, ... (the spacing
+                                 doubling up to refine_every, then every
+                                 refine_every iterations; a scene of a batch that
+                                 halted in between corrects at the first status
+                                 read at or after that) the
                                  correction g = mu (A^H (y - A x) - Ahat^H (y' - Ahat x))
                                  of the stored operator Ahat toward the accurate A
                                  (FP32 entries regenerated as in MATRIX_FREE) enters

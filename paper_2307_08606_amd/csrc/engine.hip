@@ -1075,8 +1075,7 @@ int solve_prologue_finish(sadmm_t h) {
 // xfix = (mu Ahat^H Ahat + cI)^{-1} g = (g - Ahat^H W Ahat g) / c, a direct
 // sensor adds g to its right-hand side.  A x runs over every pixel, frozen
 // ones included (y' holds their contribution through Ahat).
-int refine_enqueue(sadmm_t h) {
-  hipStream_t s = h->s;
+int refine_enqueue(sadmm_t h, hipStream_t s) {
   const size_t QK = (size_t)h->Q * h->KMp;
   const size_t QN = (size_t)h->Q * h->N;
   HIPCHK(h, hipMemcpyAsync(h->gprev, h->gfix, 16 * QN, hipMemcpyDeviceToDevice, s));
@@ -1120,7 +1119,18 @@ int refine_enqueue(sadmm_t h) {
   return SADMM_OK;
 }
 
-// Completes a correction queued by refine_enqueue, once h->s has drained.
+// Iterations from the last scheduled correction to the next: the spacing
+// doubles from 2 (corrections at 2, 4, 8, 16, ...) until it reaches
+// refine_every.  A correction is taken at the current x, so its own error is
+// proportional to the distance of x from the fixed point: early ones, while
+// ADMM still moves x by more than that error, cost no convergence, and the
+// fixed point is corrected as x approaches it instead of in jumps after x
+// has settled on the uncorrected one.
+int refine_gap(sadmm_t h) {
+  return std::min(h->p.refine_every, std::max(2, h->k_refined));
+}
+
+// Completes a correction queued by refine_enqueue, once its stream has drained.
 void refine_finish(sadmm_t h, int k) {
   double d2 = 0.0;
   for (int q = 0; q < h->Q; ++q) d2 += h->dg_h[q];
@@ -1141,7 +1151,7 @@ void refine_finish(sadmm_t h, int k) {
 }
 
 int refine(sadmm_t h, int k) {
-  TRY(refine_enqueue(h));
+  TRY(refine_enqueue(h, h->s));
   HIPCHK(h, hipStreamSynchronize(h->s));
   refine_finish(h, k);
   return SADMM_OK;
@@ -1334,7 +1344,7 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
     int nq_iter = check;
     for (const sadmm_t h : hs)
       if (!h->done && h->p.refine_every > 0)
-        nq_iter = std::min(nq_iter, std::max(1, h->k_refined + h->p.refine_every - h->ctl_h->k));
+        nq_iter = std::min(nq_iter, std::max(1, h->k_refined + refine_gap(h) - h->ctl_h->k));
     for (int i = 0; i < nq_iter; ++i) {
       if (ge) {
         if (hipGraphLaunch(ge, gs) != hipSuccess) { rc = fail_msg(h0, SADMM_E_HIP, "graph launch failed"); break; }
@@ -1390,20 +1400,24 @@ int iterate(std::vector<sadmm_t>& hs, bool single, const SharedBatch* shared = n
       bool active = false;
       rc = handle_halt(h, ctl_all[i], &active);
       if (rc == SADMM_OK && active && h->p.refine_every > 0 &&
-          ctl_all[i].k - h->k_refined >= h->p.refine_every)
+          ctl_all[i].k - h->k_refined >= refine_gap(h))
         due.push_back(i);
       if (rc != SADMM_OK && h != h0) h0->err = h->err;
       any = any || active;
     }
-    // the due corrections of every scene queued together, one wait
+    // The due corrections of every scene queued together, one wait.  A
+    // batch puts each scene's on that scene's own (idle) graph stream: the
+    // kernels of one scene's correction are small, and the scenes' run side
+    // by side instead of one after another.
+    auto fix_stream = [&](sadmm_t h) { return single ? h->s : h->gs; };
     for (size_t j = 0; j < due.size() && rc == SADMM_OK; ++j) {
-      rc = refine_enqueue(hs[due[j]]);
+      rc = refine_enqueue(hs[due[j]], fix_stream(hs[due[j]]));
       if (rc != SADMM_OK && hs[due[j]] != h0) h0->err = hs[due[j]]->err;
     }
     if (rc == SADMM_OK && !due.empty()) {
       std::vector<hipStream_t> ss;
       for (int i : due)
-        if (std::find(ss.begin(), ss.end(), hs[i]->s) == ss.end()) ss.push_back(hs[i]->s);
+        if (std::find(ss.begin(), ss.end(), fix_stream(hs[i])) == ss.end()) ss.push_back(fix_stream(hs[i]));
       for (hipStream_t st : ss)
         if (hipStreamSynchronize(st) != hipSuccess) rc = fail_msg(h0, SADMM_E_HIP, "correction failed");
       for (int i : due)
