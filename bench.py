@@ -339,6 +339,31 @@ def batch_leg(torch, lib, stream, reps=2, n_check=8,
     return out
 
 
+def c1_leg(torch, lib, stream, iters=200, reps=5):
+    """c1 workload (Q=4, M=4, K=64, N=32^2, seed 0, lambda = 0.2 lambda_max
+    from the stored reference): a solve of exactly `iters` iterations (stop
+    test off) with its factor already built, FP32 storage, replayed from the
+    iteration graph; the shape is latency-bound (8 MiB of operator)."""
+    from scenegen import config_scene
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "c1_seed0.json")))
+    sc = config_scene("c1", 0)
+    g = sc.geom
+    s = lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", prune=False, reuse_factor=True, max_iter=iters,
+                   stop=False, check_every=iters, stream=stream, mu=ref["mu"], beta=ref["beta"],
+                   gamma=ref["gamma"], lam=ref["lam"])
+    for q in range(g.Q):
+        s.set_operator_geometry(q, g.tx[q], g.rx[q], g.pix, g.f0, g.bw)
+    y = torch.from_numpy(np.ascontiguousarray(sc.y)).to("cuda")
+    s.solve(y)                                     # factor and graph
+    ms = []
+    for _ in range(reps):
+        s.solve(y)
+        ms.append(s.timing()["iter_ms"])
+    s.close()
+    it_ms = float(np.median(ms)) / iters
+    return dict(iter_us=it_ms * 1e3, iters_per_s=1e3 / it_ms)
+
+
 def shared_leg(torch, lib, stream, info, S=32, iters=31):
     """S frames of the c2 geometry (scene seeds 100..100+S-1) sharing one FP32
     operator: one solve_batch iterates all of them with multi-right-hand-side
@@ -582,6 +607,10 @@ def main():
         results["c5_mf"] = dict(factor_ms=t5["factor_ms"], iter_ms=t5b["iter_ms"] / 10,
                                 stats=st5, elems_per_iter=el)
 
+    # c1 (Q=4, KM=256, N=32^2): latency-bound steady iterations, 200 fixed
+    # iterations replayed from the iteration graph, FP32, lambda = 0.2 lambda_max
+    if not args.only:
+        results["c1"] = c1_leg(torch, lib, stream)
     # batched uneven frames (c4): 256 frames of different Q and grid size
     # solved one by one and as one batch (one launch per kernel for all frames)
     if not args.only:
@@ -637,6 +666,9 @@ def main():
         extra["c5_asadmm_vs_sadmm"] = results["c5_asadmm"]
     if dens:
         extra["measured_denominators"] = dens
+    if "c1" in results:
+        extra["c1_iters_per_s"] = round(results["c1"]["iters_per_s"], 1)
+        extra["c1_iter_us"] = round(results["c1"]["iter_us"], 2)
     if "c4" in results:
         r4 = results["c4"]
         extra["c4_frames"] = r4["frames"]

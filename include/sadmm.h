@@ -286,7 +286,8 @@ int sadmm_matched_filter(sadmm_t h, const void* y, int32_t dtype, int32_t on_dev
                          double* out);
 
 /* Tile autotuner of the forward product (columns per work-group, from
- * 256, 512, 1024; not part of the method, only of its speed).  For each
+ * 64, 128, 256, 512, 1024; images of 4096 pixels or more from 256 up; not
+ * part of the method, only of its speed).  For each
  * width it runs min(iters, params.max_iter) plain iterations of this
  * handle's problem on the measurements y twice (as sadmm_solve, with
  * stopping, elimination, re-check, refinement and balancing off; the factor

@@ -118,7 +118,8 @@ struct sadmm_s {
   std::vector<cd*> hpdD, hpdX, hpdT;          // per-sensor inverse scratch
   int rmax = 0, rpad_max = 0;
   int chunk = 256, nchunk = 0, nblk = 0;
-  int nchunk_cap = 0;             // chunks the forward buffers hold (chunk 256, the smallest tuned)
+  int chunk_min = 256;            // narrowest forward tile this handle may take
+  int nchunk_cap = 0;             // chunks the forward buffers hold (at chunk_min)
   double xref_norm2 = 0.0, nmse_target = 0.0;
   bool have_ref = false;
   sadmm_cnn_t cnn = nullptr;
@@ -253,9 +254,13 @@ void prof_resolve(sadmm_t h) {
 // Forward-product tile width (columns per work-group) chosen by
 // sadmm_autotune, per (storage, rows rounded to 32, pixel-count bucket); a
 // handle created later for the same key starts from it.
-constexpr int FWD_CHUNK_MIN = 256;
-constexpr int FWD_CHUNKS[] = {256, 512, 1024};
-static_assert(FWD_CHUNKS[2] <= MAX_CHUNK, "forward tile wider than its LDS coefficient tile");
+constexpr int FWD_CHUNKS[] = {64, 128, 256, 512, 1024};
+static_assert(FWD_CHUNKS[4] <= MAX_CHUNK, "forward tile wider than its LDS coefficient tile");
+// Narrowest tile: images below 4096 pixels (every pixel-count bucket below
+// 2^12) take tiles from 64 columns, so that their few rows still spread over
+// enough work-groups; larger ones from 256 (their partial-sum buffers stay
+// within Q * N / 256 * KMp entries).
+int fwd_chunk_min(int N) { return N < 4096 ? 64 : 256; }
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, int> g_tuned;
 int n_bucket(int N) {   // power-of-two bucket of the pixel count
@@ -1555,15 +1560,21 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   else { h->ldA = 2 * (int64_t)h->KMp; h->slot = 2; }
   // forward product: columns per work-group.  Long streams of stored FP32 /
   // FP64 or generated entries (1024 columns at N = 128^2: 6.2 TB/s against
-  // 5.5 at 256), but at least 16 chunks per sensor; 16-bit planes keep 256.
-  if (h->st == ST_FP16P || h->st == ST_BF16P) h->chunk = 256;
-  else h->chunk = std::min(1024, std::max(256, (h->N / 16) / 256 * 256));
+  // 5.5 at 256), but at least 16 chunks per sensor; 16-bit planes at most
+  // 256.  At c1 (N = 32^2, 256 rows) 64 columns took the forward from 14 to
+  // 4 us.
+  h->chunk_min = fwd_chunk_min(h->N);
+  {
+    const int cm = h->chunk_min;
+    const int wide = (h->st == ST_FP16P || h->st == ST_BF16P) ? 256 : 1024;
+    h->chunk = std::min(wide, std::max(cm, (h->N / 16) / cm * cm));
+  }
   {
     const int tuned = tuned_chunk(h->st, h->KMp, h->N);
-    if (tuned > 0) h->chunk = tuned;
+    if (tuned >= h->chunk_min) h->chunk = tuned;
   }
   h->nchunk = (h->N + h->chunk - 1) / h->chunk;
-  h->nchunk_cap = (h->N + FWD_CHUNK_MIN - 1) / FWD_CHUNK_MIN;
+  h->nchunk_cap = (h->N + h->chunk_min - 1) / h->chunk_min;
   h->nblk = (h->N + 255) / 256;
   const int Q = h->Q, N = h->N, KMp = h->KMp;
   const size_t cN = h->csz * N;
@@ -1856,7 +1867,8 @@ int sadmm_autotune(sadmm_t h, const void* y, int32_t dtype, int32_t on_device, i
   int best = h->chunk, rc = SADMM_OK;
   double best_ms = 1e300;
   for (int c : FWD_CHUNKS) {
-    if (c > FWD_CHUNK_MIN && c >= h->N) break;        // one chunk already covers the image
+    if (c < h->chunk_min) continue;
+    if (c > h->chunk_min && c >= h->N) break;         // one chunk already covers the image
     h->chunk = c;
     h->nchunk = (h->N + c - 1) / c;
     drop_graph();

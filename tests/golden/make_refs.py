@@ -22,6 +22,11 @@ those above), lambda_max by the Woodbury / conjugate-gradient path:
   c4_batch256_seed7.json
 
     python tests/golden/make_refs.py c4 256
+
+Workload c1 (Q=4, M=4, K=64, 32x32 pixels, 10 targets, 20 dB), scene seed 0:
+  c1_seed0.json          lambda_max and lambda (= 0.2 lambda_max)
+
+    python tests/golden/make_refs.py c1
 """
 
 import json
@@ -93,8 +98,22 @@ def main_c4(seed: int = 7, n_frames: int = 16, lambda_frac: float = 0.2):
     print(json.dumps(info, indent=1))
 
 
+def main_c1(seed: int = 0, lambda_frac: float = 0.2):
+    cfg = CONFIGS["c1"]
+    sc = config_scene("c1", seed)
+    A = [steering(sc.geom, q) for q in range(sc.geom.Q)]
+    lmax = oracle.lambda_max(A, sc.y, cfg["mu"], cfg["gamma"])
+    info = dict(workload="c1", seed=seed, lambda_max=lmax, lambda_frac=lambda_frac,
+                lam=lambda_frac * lmax, mu=cfg["mu"], beta=cfg["beta"], gamma=cfg["gamma"])
+    with open(os.path.join(HERE, f"c1_seed{seed}.json"), "w") as f:
+        json.dump(info, f, indent=1)
+    print(json.dumps(info, indent=1))
+
+
 if __name__ == "__main__":
-    if sys.argv[1:2] == ["c4"]:
+    if sys.argv[1:2] == ["c1"]:
+        main_c1()
+    elif sys.argv[1:2] == ["c4"]:
         main_c4(n_frames=int(sys.argv[2]) if len(sys.argv) > 2 else 16)
     else:
         main()

@@ -125,6 +125,31 @@ def test_pruned_fp64_masks_bit_exact(gpu_lib, seed, lam_frac, eps_rel):
     assert info["max_active_frac"] < 1.0
 
 
+@pytest.mark.parametrize("gamma", [100.0, 10.0])
+def test_paper_hyperparameters_c1(gpu_lib, gamma):
+    """The paper's own parameters (Sec. IV: mu = 3, beta = 100, lambda = 20,
+    eps_abs = 1e-4, eps_rel = 1e-2, K_p = 5, eps_p = 1e-5) on the c1 geometry,
+    with the ridge gamma = beta and a weaker one: the accelerated FP64 solve
+    matches the oracle's trajectory (iterations, prune events, selectors, the
+    sensor images).  lambda = 20 lies above lambda_max there, so the image is
+    0 while the per-sensor iterates are not."""
+    g = make_geometry(4, 4, 64, 32)
+    sc = make_scene(g, 0, 10, 20.0)
+    A = [steering(g, q) for q in range(g.Q)]
+    hp = dict(mu=3.0, beta=100.0, gamma=gamma, lam=20.0)
+    assert oracle.lambda_max(A, sc.y, hp["mu"], gamma) < hp["lam"]
+    kw = dict(max_iter=500, eps_abs=1e-4, eps_rel=1e-2, prune=True, Kp=5, eps_p=1e-5)
+    s, info = gpu_run(gpu_lib, g, A, sc.y, hp, "fp64", **kw)
+    ref = oracle.solve(A, sc.y, oracle_params(hp, **kw))
+    print(f"gamma {gamma}: {ref.iters} iterations, {ref.prune_events} prune events", flush=True)
+    assert ref.converged and info["status"] == 0
+    assert info["iters"] == ref.iters and info["prune_events"] == ref.prune_events
+    for q in range(g.Q):
+        assert np.array_equal(s.active_mask(q).astype(bool), ref.active[q])
+        assert rel(s.sensor_image(q), ref.X[q]) < 1e-8
+    assert np.all(ref.z == 0) and np.all(s.image() == 0)
+
+
 def test_pruned_fp32_image_c1(gpu_lib):
     """FP32 accelerated solve, 60 fixed iterations (SSC eliminates settled
     pixels once the gate opens): image within NMSE 1e-6 of the oracle's."""
