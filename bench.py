@@ -226,8 +226,8 @@ def c5_asadmm_leg(torch, lib, stream, hp, max_iter=60):
 
 def batch_leg(torch, lib, stream, reps=2, n_check=8,
               legs=("fp32_plain_sequential", "fp32_plain_batched", "sequential", "batched",
-                    "ttn_fp32_plain_sequential", "ttn_fp32_plain_batched", "ttn_sequential",
-                    "ttn_batched")):
+                    "shared_batched", "ttn_fp32_plain_sequential", "ttn_fp32_plain_batched",
+                    "ttn_sequential", "ttn_batched", "ttn_shared_batched")):
     """c4: 256 independent frames of uneven sensor count (4, 6, 8) and grid
     (32^2 .. 96^2 pixels), M = 8, K = 128, operators generated on the device,
     a fresh factor per solve.  Two configurations: plain SADMM with the
@@ -236,7 +236,12 @@ def batch_leg(torch, lib, stream, reps=2, n_check=8,
     and FP32 corrections at iterations 2, 4, 8, then every 10).  Each is timed
     solving the frames one by one (*sequential) and as one batch (*batched:
     one launch per kernel for all frames), after one tile autotune per
-    pixel-count bucket and storage, in two stopping modes: every frame run to
+    pixel-count bucket and storage.  The frames of one (Q, N) class share the
+    array geometry, hence the operator: *shared_batched solves each class as
+    one batch of handles borrowing one FP32 operator and its factor (plain
+    SADMM; one factor build per class and call; the products of all frames
+    of a class as multi-right-hand-side products).  Two stopping modes: every
+    frame run to
     eps_rel = 1e-4, and (ttn_*) every frame stopped at the first iteration
     with NMSE <= 1e-3 against the FP64 solve of the same frame (eps_rel =
     1e-7, computed first, outside the timing).  NMSE of a sample of the
@@ -320,11 +325,51 @@ def batch_leg(torch, lib, stream, reps=2, n_check=8,
         out[f"{cname}_device_mem_in_use_GB"] = round((total - free) / 1e9, 1)
         for s in solvers:
             s.close()
+    if any(l.replace("ttn_", "") == "shared_batched" for l in legs):
+        classes = {}
+        for i, fr in enumerate(frames):
+            classes.setdefault((fr["Q"], fr["n_side"]), []).append(i)
+        groups = []
+        for key in sorted(classes):
+            idx = classes[key]
+            for c0 in range(0, len(idx), 64):          # at most 64 scenes per shared batch
+                part = idx[c0:c0 + 64]
+                g = scenes[part[0]].geom
+                src = handle(part[0], storage="fp32", prune=False)
+                kw = {**base, "prune": False}
+                hs = [src] + [lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", lam=frames[i]["lam"],
+                                         share=src, **kw) for i in part[1:]]
+                groups.append((part, hs))
+
+        def run_shared():
+            infos = [None] * len(frames)
+            for part, hs in groups:
+                for i, inf in zip(part, lib.solve_batch(hs, [ys[i] for i in part])):
+                    infos[i] = inf
+            return infos
+
+        for ttn in (False, True):
+            leg = ("ttn_" if ttn else "") + "shared_batched"
+            if leg not in legs:
+                continue
+            for part, hs in groups:
+                for i, h in zip(part, hs):
+                    h.set_reference(xref[i] if ttn else None, 1e-3 if ttn else 0.0)
+            out[leg] = timed(run_shared)
+            if not ttn:
+                for part, hs in groups:
+                    for i, h in zip(part, hs):
+                        if i in pick:
+                            images[("fp32_shared", i)] = h.image()
+        out["shared_classes"] = len(classes)
+        for part, hs in groups:
+            for h in reversed(hs):
+                h.close()
     nm = []
     for i in pick:
         z64 = xref[i].cpu().numpy()
         d = dict(frame=i, Q=scenes[i].geom.Q, N=scenes[i].geom.N, ref_status=ref_status[i])
-        for cname in configs:
+        for cname in list(configs) + ["fp32_shared"]:
             if (cname, i) in images:
                 z = images[(cname, i)]
                 d[f"{cname}_nmse"] = float(np.linalg.norm(z - z64) ** 2 / np.linalg.norm(z64) ** 2)
@@ -334,7 +379,7 @@ def batch_leg(torch, lib, stream, reps=2, n_check=8,
     out["nmse_vs_fp64"] = nm
     out["refs_converged"] = all(v == 0 for v in ref_status.values())
     out["sum_QN"] = int(sum(sc.geom.Q * sc.geom.N for sc in scenes))
-    it_b = out[legs[-1]]["iters"]
+    it_b = out["batched" if "batched" in out else legs[-1]]["iters"]
     out["sum_iters_QN"] = int(sum(it * sc.geom.Q * sc.geom.N for it, sc in zip(it_b, scenes)))
     return out
 
@@ -675,8 +720,9 @@ def main():
         extra["c4_storage"] = {"fp32_plain": "FP32 operator, plain SADMM",
                                "accelerated": "BF16 planes (FP32 arithmetic, FP64 factor, correction "
                                               "every 10 iterations), SSC pruning"}
-        for k in ("fp32_plain_sequential", "fp32_plain_batched", "sequential", "batched",
-                  "ttn_fp32_plain_sequential", "ttn_fp32_plain_batched", "ttn_sequential", "ttn_batched"):
+        for k in ("fp32_plain_sequential", "fp32_plain_batched", "sequential", "batched", "shared_batched",
+                  "ttn_fp32_plain_sequential", "ttn_fp32_plain_batched", "ttn_sequential", "ttn_batched",
+                  "ttn_shared_batched"):
             if k in r4:
                 extra[f"c4_{k}_frames_per_s"] = round(r4["frames"] / (r4[k]["ms"] * 1e-3), 1)
                 extra[f"c4_{k}_ms"] = round(r4[k]["ms"], 1)
@@ -687,12 +733,14 @@ def main():
                 extra[f"c4_{k}_all_stopped_as_asked"] = all(
                     st == (2 if k.startswith("ttn_") else 0) for st in r4[k]["status"])
         for pre in ("", "ttn_"):
-            if pre + "batched" in r4 and pre + "fp32_plain_sequential" in r4:
-                extra[f"c4_{pre}accelerated_batched_vs_plain_fp32_sequential"] = round(
-                    r4[pre + "fp32_plain_sequential"]["ms"] / r4[pre + "batched"]["ms"], 2)
+            for leg in ("batched", "shared_batched"):
+                if pre + leg in r4 and pre + "fp32_plain_sequential" in r4:
+                    name = "accelerated_batched" if leg == "batched" else "shared_batched"
+                    extra[f"c4_{pre}{name}_vs_plain_fp32_sequential"] = round(
+                        r4[pre + "fp32_plain_sequential"]["ms"] / r4[pre + leg]["ms"], 2)
         extra["c4_fp64_references_converged"] = r4["refs_converged"]
         extra["c4_tile_widths"] = r4["widths"]
-        for c in ("fp32_plain", "bf16"):
+        for c in ("fp32_plain", "bf16", "fp32_shared"):
             vals = [d[f"{c}_nmse"] for d in r4["nmse_vs_fp64"] if f"{c}_nmse" in d]
             if vals:
                 extra[f"c4_{c}_max_nmse_vs_fp64"] = max(vals)
