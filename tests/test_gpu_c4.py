@@ -147,3 +147,33 @@ def test_bf16_batch_frames_that_froze_early(gpu_lib):
         assert nmse <= 1e-3
     for h in hs + ref:
         h.close()
+
+
+def test_shared_class_batch_matches_oracle(gpu_lib):
+    """Frames of one (Q, N) class of the 256-frame batch share the array
+    geometry and so the operator: six (Q = 4, 32^2) frames solved as one
+    shared batch (one FP32 operator and factor, multi-right-hand-side
+    products) meet the FP32 bar against the oracle's solve of each frame."""
+    info = json.load(open(os.path.join(HERE, "golden", "c4_batch256_seed7.json")))
+    idx = [i for i, fr in enumerate(info["frames"]) if (fr["Q"], fr["n_side"]) == (4, 32)][:6]
+    frames = [info["frames"][i] for i in idx]
+    scenes = [c4_scene(fr) for fr in frames]
+    g = scenes[0].geom
+    kw = dict(storage="fp32", kkt=False, reuse_factor=False, check_every=8)
+    src = gpu_lib.Solver(g.Q, g.K, g.M, g.N, **kw, **params(info, frames[0], prune=False))
+    for q in range(g.Q):
+        src.set_operator_geometry(q, g.tx[q], g.rx[q], g.pix, g.f0, g.bw)
+    hs = [src] + [gpu_lib.Solver(g.Q, g.K, g.M, g.N, share=src, **kw, **params(info, fr, prune=False))
+                  for fr in frames[1:]]
+    infos = gpu_lib.solve_batch(hs, [sc.y for sc in scenes])
+    A = [steering(g, q) for q in range(g.Q)]
+    for j in (0, 3):
+        ref = oracle.solve(A, scenes[j].y, oracle.Params(**params(info, frames[j], prune=False)))
+        z = hs[j].image()
+        nmse = np.linalg.norm(z - ref.z) ** 2 / np.linalg.norm(ref.z) ** 2
+        print(f"frame {idx[j]}: {infos[j]['iters']} iterations (oracle {ref.iters}), NMSE {nmse:.2e}",
+              flush=True)
+        assert infos[j]["status"] == 0 and abs(infos[j]["iters"] - ref.iters) <= 1
+        assert nmse <= 1e-6
+    for h in reversed(hs):
+        h.close()
