@@ -110,8 +110,7 @@ struct sadmm_s {
   std::vector<unsigned long long*> rmaxc;   // per sensor: row maxima of the full operator
   int2* tiles_d = nullptr;       // Gram tile order (tri_tile_order)
   int ntiles = 0;
-  void* gi8_ws = nullptr;        // its digit-plane workspace
-  size_t gi8_ws_bytes = 0;
+  int dev = 0;                   // device the handle was created on
   cd *Ar = nullptr, *V = nullptr, *Tm = nullptr, *Cm = nullptr, *Dg = nullptr, *Xg = nullptr,
      *Tg = nullptr;
   MmDesc* mm_d = nullptr;     // GEMM descriptors of the factorisations
@@ -399,28 +398,51 @@ int desc_table(sadmm_t h0, T* own, size_t own_cap, size_t need, std::vector<void
   return SADMM_OK;
 }
 
+// Digit-plane workspace of the integer Gram: one per device, shared by every
+// handle on it (a build needs it only while its Gram kernels run).  Builds
+// order themselves by an event: a build's stream waits for the previous
+// user's last Gram kernel before its own touch the buffer, and records the
+// event after them; growing the buffer waits for it to go idle first.
+struct GramWorkspace {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t last = nullptr;      // after the latest user's kernels
+  bool used = false;
+};
+std::mutex g_gws_mu;
+std::map<int, GramWorkspace> g_gws;
+
 // W64 = Ahat Ahat^H + rho I by the integer digit products (gram.h) for the
-// items, in groups whose digit planes fit a bounded workspace owned by h0.
+// items, in groups whose digit planes fit a bounded workspace.
 int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void*>& tmp) {
   constexpr size_t kCap = size_t(4) << 30;
   int max_n = 0;
   for (const FacItem& it : items) max_n = std::max(max_n, it.h->N);
   const size_t per = (gram_i8_workspace(h0->KMp, max_n) + 255) / 256 * 256;
   const size_t group = std::max<size_t>(1, std::min<size_t>(items.size(), kCap / per));
-  if (h0->gi8_ws_bytes < group * per) {   // owned here (not in allocs): it may grow
-    if (h0->gi8_ws) {
-      HIPCHK(h0, hipStreamSynchronize(h0->s));
-      hipFree(h0->gi8_ws);
+  std::lock_guard<std::mutex> lock(g_gws_mu);     // held while this build's kernels are queued
+  GramWorkspace& ws = g_gws[h0->dev];
+  if (!ws.last && hipEventCreateWithFlags(&ws.last, hipEventDisableTiming) != hipSuccess) {
+    ws.last = nullptr;
+    return fail_msg(h0, SADMM_E_HIP, "integer Gram workspace: event creation");
+  }
+  if (ws.bytes < group * per) {
+    if (ws.p) {
+      if (ws.used) HIPCHK(h0, hipEventSynchronize(ws.last));
+      hipFree(ws.p);
     }
-    h0->gi8_ws = nullptr;
-    h0->gi8_ws_bytes = 0;
-    const hipError_t e = hipMalloc(&h0->gi8_ws, group * per);
+    ws.p = nullptr;
+    ws.bytes = 0;
+    ws.used = false;
+    const hipError_t e = hipMalloc(&ws.p, group * per);
     if (e != hipSuccess) {
-      h0->gi8_ws = nullptr;
+      ws.p = nullptr;
       return fail_msg(h0, SADMM_E_NOMEM, "integer Gram workspace (%zu bytes): %s", group * per,
                       hipGetErrorString(e));
     }
-    h0->gi8_ws_bytes = group * per;
+    ws.bytes = group * per;
+  } else if (ws.used) {
+    HIPCHK(h0, hipStreamWaitEvent(h0->s, ws.last, 0));
   }
   GramI8Desc* dd = nullptr;
   TRY(desc_table(h0, h0->gi8_d, (size_t)h0->Q, group, tmp, &dd));
@@ -443,7 +465,7 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
       d.A = ahat_ptr(h, q); d.ldA = h->ldA; d.kmp = h->KMp;
       d.m = h->KMp; d.k = h->nq[q];
       d.C = h->W64[q]; d.ldc = h->KMp; d.diag = factor_rho(h);
-      gram_i8_layout(d, static_cast<char*>(h0->gi8_ws) + i * per);
+      gram_i8_layout(d, static_cast<char*>(ws.p) + i * per);
       if (given) d.rmax = h->rmaxc[q];
       max_k = std::max(max_k, d.k);
       prof_work(h0, SADMM_KC_SLICE, (double)h->nq[q] * h->KMp * (op_bytes(h) + 8.0));
@@ -460,6 +482,8 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
     }
     HIPCHK(h0, hipGetLastError());
   }
+  HIPCHK(h0, hipEventRecord(ws.last, h0->s));
+  ws.used = true;
   return SADMM_OK;
 }
 
@@ -1543,6 +1567,7 @@ static int create_impl(const sadmm_params* p, sadmm_t src, sadmm_t* out) {
   int rc = validate(p);
   if (rc != SADMM_OK) return rc;
   sadmm_t h = new sadmm_s();
+  if (hipGetDevice(&h->dev) != hipSuccess) h->dev = 0;
   h->shared_src = src;
   if (src) src->n_sharers += 1;   // (given back by sadmm_destroy, also on a failed create)
   h->p = *p;
@@ -2250,7 +2275,6 @@ void sadmm_destroy(sadmm_t h) {
   if (h->s) hipStreamSynchronize(h->s);
   else hipDeviceSynchronize();
   for (void* p : h->allocs) hipFree(p);
-  if (h->gi8_ws) hipFree(h->gi8_ws);
   for (int q = 0; q < (int)h->Fd.size(); ++q) {
     if (h->Fd[q]) hipFree(h->Fd[q]);
     if (h->b0d[q]) hipFree(h->b0d[q]);
