@@ -104,10 +104,13 @@ typedef struct {
                                  starting selector; 0: every solve rebuilds it */
   int32_t gram;               /* Gram Ahat Ahat^H of a factor build.  0 (default): for
                                  FP32 / FP16P / BF16P / MATRIX_FREE storage, an exact
-                                 integer product on int8 matrix instructions of the
-                                 operator rounded to 30 bits below each row's largest
-                                 magnitude (FP64 storage always takes path 1);
-                                 1: FP64 matrix instructions on the stored values */
+                                 integer product on the int8 16x16x64 matrix
+                                 instruction of the operator rounded to 30 bits below
+                                 each row's largest magnitude (FP64 storage always
+                                 takes path 1); 1: FP64 matrix instructions on the
+                                 stored values; 2: the same integer product as 0 on
+                                 the int8 32x32x32 instruction (identical results,
+                                 slower at one wave per SIMD; a cross-check) */
   int32_t direct;             /* x-update form of a sensor whose active set N_q falls
                                  below the per-iteration bytes crossover (2.41 KM for
                                  FP64 storage, 1.62 KM for FP32, 1.28 KM for 16-bit,

@@ -383,7 +383,7 @@ struct FacItem {
 };
 
 double factor_rho(sadmm_t h) { return (h->p.beta + h->p.gamma) / h->p.mu; }
-bool integer_gram(sadmm_t h) { return h->p.gram == 0 && h->st != ST_FP64; }
+bool integer_gram(sadmm_t h) { return (h->p.gram == 0 || h->p.gram == 2) && h->st != ST_FP64; }
 
 // Device table of `need` descriptors: h0's own when it is large enough, else a
 // temporary one (freed by the caller through tmp after the stream syncs).
@@ -477,7 +477,7 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
     prof_end(h0, SADMM_KC_SLICE, pe);
     for (int c = 0; c < gram_i8_chunks(max_k); ++c) {
       pe = prof_begin(h0);
-      gram_i8_chunk(dd, (int)n, c, h0->tiles_d, h0->ntiles, h0->s);
+      gram_i8_chunk(dd, (int)n, c, h0->tiles_d, h0->ntiles, h0->p.gram == 2, h0->s);
       prof_end(h0, SADMM_KC_GRAM, pe);
     }
     HIPCHK(h0, hipGetLastError());
@@ -490,7 +490,7 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
 // Row maxima of sensor q's full operator for the integer Gram (FP32, 16-bit
 // and matrix-free storage), once per operator.
 int cache_rowmax(sadmm_t h, int q) {
-  if (h->st == ST_FP64 || h->p.gram != 0 || h->shared_src) return SADMM_OK;
+  if (!integer_gram(h) || h->shared_src) return SADMM_OK;
   const int KMr = round_up(h->KMp, 64);
   if ((int)h->rmaxc.size() < h->Q) h->rmaxc.assign(h->Q, nullptr);
   if (!h->rmaxc[q] && hipMalloc((void**)&h->rmaxc[q], sizeof(unsigned long long) * KMr) != hipSuccess) {
@@ -893,7 +893,7 @@ int validate(const sadmm_params* p) {
   if (p->max_iter < 1 || p->check_every < 1) return SADMM_E_ARG;
   if (p->Kp < 1 || p->Kp > 64 || !(p->eps_p >= 0)) return SADMM_E_ARG;
   if (p->storage < SADMM_ST_FP64 || p->storage > SADMM_ST_MATRIX_FREE) return SADMM_E_ARG;
-  if (p->gram < 0 || p->gram > 1) return SADMM_E_ARG;
+  if (p->gram < 0 || p->gram > 2) return SADMM_E_ARG;
   if (p->direct < 0 || p->direct > 1) return SADMM_E_ARG;
   if (p->refine_every < 0) return SADMM_E_ARG;
   if (p->nonneg < 0 || p->nonneg > 1) return SADMM_E_ARG;

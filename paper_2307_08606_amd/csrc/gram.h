@@ -54,5 +54,6 @@ void gram_i8_prepare(const GramI8Desc* d_desc, int batch, int max_m, int max_k, 
 // Only the row maxima into d.rmax (KMr entries; d.S and d.rs are not used).
 void gram_i8_rowmax(const GramI8Desc* d_desc, int batch, int max_m, int max_k, int st, hipStream_t s);
 int gram_i8_chunks(int max_k);
+// wide: the 32x32x32 instruction (else the 16x16x64 one; identical results).
 void gram_i8_chunk(const GramI8Desc* d_desc, int batch, int chunk, const int2* tiles, int ntiles,
-                   hipStream_t s);
+                   bool wide, hipStream_t s);

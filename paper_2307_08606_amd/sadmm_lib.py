@@ -183,7 +183,7 @@ class Solver:
         p.kkt, p.kkt_tol = int(bool(kkt)), kkt_tol
         p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         p.reuse_factor = int(bool(reuse_factor))
-        p.gram = {"int8": 0, "fp64": 1}[gram]
+        p.gram = {"int8": 0, "fp64": 1, "int8_32": 2}[gram]
         p.direct = 0 if direct else 1
         p.refine_every = int(refine_every)
         p.nonneg = int(bool(nonneg))

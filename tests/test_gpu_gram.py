@@ -114,3 +114,23 @@ def test_integer_gram_three_chunks_matches_fp64_gram(gpu_lib, storage):
         err = _rel(Wi[q], Wd[q])
         print(storage, q, f"{err:.3e}")
         assert err <= 1e-7, (storage, q, err)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 32, 92), (3, 4, 40, 60), (2, 8, 128, 40)])
+def test_wide_and_narrow_instruction_grams_are_identical(gpu_lib, shape):
+    """The integer Gram on the 16x16x64 instruction (default) and on the
+    32x32x32 one sum the same int8 digit products into the same int32 class
+    accumulators, so the factors are equal bit for bit: KM = 96 (half-empty
+    last row tile), N = 8464 (two chunks, the second ragged); KM = 160,
+    N = 3600; KM = 1024 (16 row tiles, 136 tiles per sensor), N = 1600."""
+    Q, M, K, n_side = shape
+    g = make_geometry(Q, M, K, n_side)
+    A = [steering(g, q).astype(np.complex64) for q in range(g.Q)]
+    rng = np.random.default_rng(7)
+    y = (rng.standard_normal((g.Q, g.K * g.M)) + 1j * rng.standard_normal((g.Q, g.K * g.M)))
+    y = y.astype(np.complex64)
+    for storage in ("fp32", "bf16"):
+        Wn = _factors(gpu_lib, g, A, y, storage, "int8")
+        Ww = _factors(gpu_lib, g, A, y, storage, "int8_32")
+        for q in range(g.Q):
+            assert np.array_equal(Ww[q], Wn[q]), (storage, q)
