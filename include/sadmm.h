@@ -110,7 +110,7 @@ typedef struct {
                                  takes path 1); 1: FP64 matrix instructions on the
                                  stored values; 2: the same integer product as 0 on
                                  the int8 32x32x32 instruction (identical results,
-                                 slower at one wave per SIMD; a cross-check) */
+                                 slower; a cross-check) */
   int32_t direct;             /* x-update form of a sensor whose active set N_q falls
                                  below the per-iteration bytes crossover (2.41 KM for
                                  FP64 storage, 1.62 KM for FP32, 1.28 KM for 16-bit,

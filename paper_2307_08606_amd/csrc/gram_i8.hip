@@ -389,92 +389,190 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
 // The same products on the int8 32x32x32 instruction, which sustains about
 // 1.5 times the rate of the 16x16x64 one in register-only loops on this GPU
 // (up to 4.5 against 3.0 POP/s).  Work-group: the same 64 x 64 complex tile
-// and double-buffered stages, four waves of one 32 x 32 block each (all ten
-// class accumulators in the wave), one work-group per CU (128 KB of LDS).
-// At 386 registers a wave runs alone on its SIMD, nothing hides its LDS
-// waits, and the kernel is slower than the 16x16x64 one (6.8 against 5.8 ms
-// per c2 chunk); it is kept as a cross-check of the integer arithmetic
-// (identical results).
+// and double-buffered stages, eight waves: each 32 x 32 block of the tile
+// has two, one accumulating the classes 0..2 (six digit pairs), the other the
+// classes 3..4 (seven pairs), so that a wave holds at most six 16-register
+// accumulators and two waves fit each SIMD.  The classes' FP64 sum meets in
+// LDS, in the order of the 16x16x64 kernel (identical results).  It runs
+// 6.7 ms per c2 chunk against 5.8 for gram_i8_kernel (as did one wave of all
+// ten accumulators per block, at one wave per SIMD), so it is kept only as a
+// cross-check of the integer arithmetic.
 // Lane layout (pinned by an in-bounds probe): lane l carries A row l % 32 and
 // B column l % 32 with k-bytes 16 (l / 32) + [0, 16) of the 32-byte step;
 // result component e of lane l is element (8 (e / 4) + 4 (l / 32) + e % 4,
 // l % 32).
 typedef int v16i __attribute__((ext_vector_type(16)));
-constexpr int G32_WAVES = 4;
+constexpr int G32_WAVES = 8;
 constexpr int G32_THREADS = 64 * G32_WAVES;
 
-struct LDigit32 { v4i r, i, nr; };
-template <int S>
-__device__ inline LDigit32 load_l32(const Panel& sp, int row, int off) {
-  LDigit32 L;
-  L.r = *reinterpret_cast<const v4i*>(&sp[0][S][0][row][off]);
-  L.i = *reinterpret_cast<const v4i*>(&sp[0][S][1][row][off]);
-  L.nr = ~L.r;
-  return L;
-}
-struct RDigits32 { v4i r[4], i[4]; };
-__device__ inline void load_r32(const Panel& sp, int row, int off, RDigits32& R) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    R.r[t] = *reinterpret_cast<const v4i*>(&sp[1][t][0][row][off]);
-    R.i[t] = *reinterpret_cast<const v4i*>(&sp[1][t][1][row][off]);
-  }
-}
 __device__ inline v16i mma32(v4i a, v4i b, v16i c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
-// The products of L digit S with R digits T0 .. T0 + NT - 1 (classes S + t):
-// the first halves of all pairs, then the second halves, so that the two
-// products into one accumulator are 2 NT instructions apart.
-template <int S, int T0, int NT>
-__device__ inline void digit32(const LDigit32& L, const RDigits32& R, v16i (&re)[NCLS], v16i (&im)[NCLS]) {
-#pragma unroll
-  for (int t = T0; t < T0 + NT; ++t) {
-    re[S + t] = mma32(L.r, R.r[t], re[S + t]);
-    im[S + t] = mma32(L.i, R.r[t], im[S + t]);
-  }
-#pragma unroll
-  for (int t = T0; t < T0 + NT; ++t) {
-    re[S + t] = mma32(L.i, R.i[t], re[S + t]);
-    im[S + t] = mma32(L.nr, R.i[t], im[S + t]);
-  }
-}
-// The operands of one 32-byte step (k-step) of the wave's block: L rows
-// lrow and R rows rrow, quarter q of the staged 64-byte rows.
-struct Ops32 { v4i lr[4], li[4], rr[4], ri[4]; };
-__device__ inline void load_ops32(const Panel& sp, int lrow, int rrow, int q, Ops32& o) {
+// Digit pairs (s, t) of the two class groups, class c = s + t.
+template <int G> struct Pairs32;
+template <> struct Pairs32<0> {           // classes 0, 1, 2: digits 0..2
+  static constexpr int NP = 6, NC = 3, C0 = 0, ND = 3;
+  static constexpr int s[NP] = {0, 0, 1, 0, 1, 2};
+  static constexpr int t[NP] = {0, 1, 0, 2, 1, 0};
+};
+template <> struct Pairs32<1> {           // classes 3, 4: digits 0..3
+  static constexpr int NP = 7, NC = 2, C0 = 3, ND = 4;
+  static constexpr int s[NP] = {0, 1, 2, 3, 1, 2, 3};
+  static constexpr int t[NP] = {3, 2, 1, 0, 3, 2, 1};
+};
+
+// One 32-byte step of the wave's block for class group G: operands of
+// digits 0 .. ND-1 read once (L rows lrow, R rows rrow, quarter q), then the
+// first halves of all pairs and the second halves (the two products into one
+// accumulator 2 NP instructions apart).
+template <int G>
+__device__ inline void kstep32(const Panel& sp, int lrow, int rrow, int q, v16i (&re)[Pairs32<G>::NC],
+                               v16i (&im)[Pairs32<G>::NC]) {
+  using P = Pairs32<G>;
   const int loff = 16 * (q ^ swz(lrow)), roff = 16 * (q ^ swz(rrow));
+  v4i lr[P::ND], li[P::ND], rr[P::ND], ri[P::ND];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    o.rr[t] = *reinterpret_cast<const v4i*>(&sp[1][t][0][rrow][roff]);
-    o.ri[t] = *reinterpret_cast<const v4i*>(&sp[1][t][1][rrow][roff]);
-    o.lr[t] = *reinterpret_cast<const v4i*>(&sp[0][t][0][lrow][loff]);
-    o.li[t] = *reinterpret_cast<const v4i*>(&sp[0][t][1][lrow][loff]);
+  for (int d = 0; d < P::ND; ++d) {
+    lr[d] = *reinterpret_cast<const v4i*>(&sp[0][d][0][lrow][loff]);
+    li[d] = *reinterpret_cast<const v4i*>(&sp[0][d][1][lrow][loff]);
+    rr[d] = *reinterpret_cast<const v4i*>(&sp[1][d][0][rrow][roff]);
+    ri[d] = *reinterpret_cast<const v4i*>(&sp[1][d][1][rrow][roff]);
+  }
+#pragma unroll
+  for (int k = 0; k < P::NP; ++k) {
+    const int c = P::s[k] + P::t[k] - P::C0;
+    re[c] = mma32(lr[P::s[k]], rr[P::t[k]], re[c]);
+    im[c] = mma32(li[P::s[k]], rr[P::t[k]], im[c]);
+  }
+#pragma unroll
+  for (int k = 0; k < P::NP; ++k) {
+    const int c = P::s[k] + P::t[k] - P::C0;
+    re[c] = mma32(li[P::s[k]], ri[P::t[k]], re[c]);
+    im[c] = mma32(~lr[P::s[k]], ri[P::t[k]], im[c]);
   }
 }
-template <int S, int NT>
-__device__ inline void mma_digit32(const Ops32& o, v16i (&re)[NCLS], v16i (&im)[NCLS]) {
-  const RDigits32 R = {{o.rr[0], o.rr[1], o.rr[2], o.rr[3]}, {o.ri[0], o.ri[1], o.ri[2], o.ri[3]}};
-  const LDigit32 L = {o.lr[S], o.li[S], ~o.lr[S]};
-  digit32<S, 0, NT>(L, R, re, im);
-}
-__device__ inline void mma_step32(const Ops32& o, v16i (&re)[NCLS], v16i (&im)[NCLS]) {
-  mma_digit32<0, 4>(o, re, im);
-  mma_digit32<1, 4>(o, re, im);
-  mma_digit32<2, 3>(o, re, im);
-  mma_digit32<3, 2>(o, re, im);
-}
-// Both 32-byte steps of a staged 64-column stage, the second step's operands
-// read from LDS before the first step's products are issued (they arrive
-// while those run).
-__device__ inline void stage32(const Panel& sp, int lrow, int rrow, int kh, v16i (&re)[NCLS],
-                               v16i (&im)[NCLS]) {
-  Ops32 a, b;
-  load_ops32(sp, lrow, rrow, kh, a);
-  load_ops32(sp, lrow, rrow, 2 + kh, b);
-  __builtin_amdgcn_sched_barrier(0);     // keep every read ahead of the products
-  mma_step32(a, re, im);
-  mma_step32(b, re, im);
+
+// The stages of the chunk for class group G (every wave of the work-group
+// runs the same barriers), then the group's classes of the block's elements
+// in FP64 (x = largest class first, see the epilogue).  Group 1 leaves its
+// partial sums in `part` (doubles, [re/im][element e][lane]); group 0 adds
+// its classes to them and writes C.
+template <int G>
+__device__ inline void gram32_wave(const GramI8Desc& d, Panel (&sp)[2], int chunk, int ti, int tj, int n0,
+                                   int n1, int blk, double* part) {
+  using P = Pairs32<G>;
+  const int t = threadIdx.x, lane = t & 63;
+  const int ba = blk & 1, bb = blk >> 1;   // L rows 32 ba.., R rows 32 bb..
+  const int lrow = 32 * ba + (lane & 31), rrow = 32 * bb + (lane & 31), kh = lane >> 5;
+  v16i re[P::NC], im[P::NC];
+#pragma unroll
+  for (int c = 0; c < P::NC; ++c)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      re[c][e] = 0;
+      im[c][e] = 0;
+    }
+  // staging as in gram_i8_kernel: thread t moves row (t >> 2) & 63, quarter
+  // t & 3 of the eight planes of side t >> 8 (L, then R)
+  constexpr int PPT = 8;
+  constexpr int64_t plane = 4096;
+  constexpr int kPlaneLds = GT * GROW;
+  const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
+  const int8_t* src = d.S + stage_block(side ? tj : ti, 0, d.ldS) + prow * 64 + 16 * pq;
+  int8_t* dst0 = &sp[0][side][0][0][prow][16 * (pq ^ swz(prow))];
+  int8_t* dst1 = &sp[1][side][0][0][prow][16 * (pq ^ swz(prow))];
+  u4v pa[PPT];
+  if (n0 < n1) {
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS) * kStageBlock + e * plane);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS + 1) * kStageBlock + e * plane);
+  }
+  for (int nb = n0; nb < n1; nb += 2 * GKS) {
+    kstep32<G>(sp[0], lrow, rrow, kh, re, im);                   // stage nb
+    kstep32<G>(sp[0], lrow, rrow, 2 + kh, re, im);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst1 + e * kPlaneLds) = pa[e];
+    __syncthreads();
+    if (nb + 2 * GKS < n1) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 2) * kStageBlock + e * plane);
+    }
+    kstep32<G>(sp[1], lrow, rrow, kh, re, im);                   // stage nb + GKS
+    kstep32<G>(sp[1], lrow, rrow, 2 + kh, re, im);
+    if (nb + 2 * GKS < n1) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    }
+    __syncthreads();
+    if (nb + 3 * GKS < n1) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 3) * kStageBlock + e * plane);
+    }
+  }
+  // ---- epilogue: the classes summed in FP64 from the largest c down (the
+  // order of gram_i8_kernel); group 1 (classes 4, 3) first, through LDS
+  const int* rs = d.rs + (int64_t)chunk * 4 * d.KMr;
+  const int j = tj * GT + 32 * bb + (lane & 31);
+  int r4[4] = {0, 0, 0, 0};
+  double mxj = 0.0;
+  if (j < d.m) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r4[q] = rs[(int64_t)q * d.KMr + j];
+    mxj = __longlong_as_double((long long)d.rmax[j]);
+  }
+  // class c holds the pairs (c - t, t), max(0, c - 3) <= t <= min(3, c)
+  const int cre_all[NCLS] = {r4[0], r4[0] + r4[1], r4[0] + r4[1] + r4[2], r4[0] + r4[1] + r4[2] + r4[3],
+                             r4[1] + r4[2] + r4[3]};
+  double* pr = part + (int64_t)blk * 2 * 16 * 64;       // [re/im][e][lane] of this block
+  __syncthreads();                                      // the panels are free: part aliases them
+  if constexpr (G == 1) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      double vr = 0.0, vi = 0.0;
+#pragma unroll
+      for (int c = NCLS - 1; c >= P::C0; --c) {
+        const double wgt = ldexp(1.0, -8 * c);
+        vr += (double)re[c - P::C0][e] * wgt;
+        vi += ((double)im[c - P::C0][e] + (double)cre_all[c]) * wgt;
+      }
+      pr[e * 64 + lane] = vr;
+      pr[(16 + e) * 64 + lane] = vi;
+    }
+  }
+  __syncthreads();
+  if constexpr (G == 0) {
+    int E = 0;
+    if (mxj > 0.0) (void)frexp(mxj, &E);
+    const double sj = ldexp(1.0, E - 6);
+    const int i0 = ti * GT;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = i0 + 32 * ba + 8 * (e >> 2) + 4 * kh + (e & 3);
+      if (i >= d.m || j >= d.m || j > i) continue;
+      const double mx = __longlong_as_double((long long)d.rmax[i]);
+      int Ei = 0;
+      if (mx > 0.0) (void)frexp(mx, &Ei);
+      const double si = ldexp(1.0, Ei - 6);
+      double vr = pr[e * 64 + lane], vi = pr[(16 + e) * 64 + lane];
+#pragma unroll
+      for (int c = P::NC - 1; c >= 0; --c) {
+        const double wgt = ldexp(1.0, -8 * c);
+        vr += (double)re[c][e] * wgt;
+        vi += ((double)im[c][e] + (double)cre_all[c]) * wgt;
+      }
+      cd v = {vr * (si * sj), vi * (si * sj)};
+      cd* cij = d.C + (int64_t)j * d.ldc + i;
+      if (chunk > 0) { v.re += cij->re; v.im += cij->im; }
+      else if (i == j) v.re += d.diag;
+      if (i == j) v.im = 0.0;
+      *cij = v;
+      if (i != j) d.C[(int64_t)i * d.ldc + j] = cd{v.re, -v.im};
+    }
+  }
 }
 
 __global__ __launch_bounds__(G32_THREADS) void gram_i8_32_kernel(const GramI8Desc* __restrict__ descs, int chunk,
@@ -482,116 +580,16 @@ __global__ __launch_bounds__(G32_THREADS) void gram_i8_32_kernel(const GramI8Des
   const GramI8Desc d = descs[blockIdx.y];
   int ti, tj;
   if (!xcd_tile(tiles, ntiles, &ti, &tj)) return;
-  const int i0 = ti * GT, j0 = tj * GT;
-  if (i0 >= d.m) return;
+  if (ti * GT >= d.m) return;
   const int n0 = chunk * GI8_CHUNK;
   if (chunk > 0 && n0 >= d.ldS) return;   // nothing to add
   const int n1 = min(n0 + GI8_CHUNK, d.ldS);
   __shared__ __align__(16) Panel sp[2];   // double buffer: stage 2 s in sp[0], 2 s + 1 in sp[1]
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int ba = w & 1, bb = w >> 1;     // the wave's block: L rows 32 ba.., R rows 32 bb..
-  const int lrow = 32 * ba + (lane & 31), rrow = 32 * bb + (lane & 31), kh = lane >> 5;
-  v16i re[NCLS], im[NCLS];
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      re[c][e] = 0;
-      im[c][e] = 0;
-    }
-  // staging: thread t moves row t >> 2, quarter t & 3 of the 8 planes of each
-  // side (L then R) of a stage
-  constexpr int PPT = 16;
-  constexpr int64_t plane = 4096;        // between the planes of a stage block
-  constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
-  constexpr int kSideLds = 8 * kPlaneLds;
-  const int prow = t >> 2, pq = t & 3;
-  const int8_t* srcL = d.S + stage_block(ti, 0, d.ldS) + prow * 64 + 16 * pq;
-  const int8_t* srcR = d.S + stage_block(tj, 0, d.ldS) + prow * 64 + 16 * pq;
-  int8_t* dst0 = &sp[0][0][0][0][prow][16 * (pq ^ swz(prow))];
-  int8_t* dst1 = &sp[1][0][0][0][prow][16 * (pq ^ swz(prow))];
-  auto fetch = [&](u4v (&pa)[PPT], int stage) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      pa[e] = *reinterpret_cast<const u4v*>(srcL + stage * kStageBlock + e * plane);
-      pa[8 + e] = *reinterpret_cast<const u4v*>(srcR + stage * kStageBlock + e * plane);
-    }
-  };
-  auto store = [&](const u4v (&pa)[PPT], int8_t* dst) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      *reinterpret_cast<u4v*>(dst + e * kPlaneLds) = pa[e];
-      *reinterpret_cast<u4v*>(dst + kSideLds + e * kPlaneLds) = pa[8 + e];
-    }
-  };
-  // Stage s is staged in sp[s & 1]; its loads are issued one stage ahead (in
-  // flight during the products of the stage before) and stored to LDS after
-  // those products.  One barrier per stage: a buffer is refilled only after
-  // the barrier that follows the products reading it.
-  u4v pa[PPT];
-  if (n0 < n1) {
-    fetch(pa, n0 / GKS);
-    store(pa, dst0);
-    __syncthreads();
-    fetch(pa, n0 / GKS + 1);
-  }
-  for (int nb = n0; nb < n1; nb += 2 * GKS) {
-    stage32(sp[0], lrow, rrow, kh, re, im);                      // stage nb
-    store(pa, dst1);
-    __syncthreads();
-    if (nb + 2 * GKS < n1) fetch(pa, nb / GKS + 2);
-    stage32(sp[1], lrow, rrow, kh, re, im);                      // stage nb + GKS
-    if (nb + 2 * GKS < n1) store(pa, dst0);
-    __syncthreads();
-    if (nb + 3 * GKS < n1) fetch(pa, nb / GKS + 3);
-  }
-  // ---- epilogue: FP64 sum of the classes, lower triangle and its mirror
-  const int* rs = d.rs + (int64_t)chunk * 4 * d.KMr;
-  const int j = j0 + 32 * bb + (lane & 31);
-  int cre[NCLS];   // imaginary correction: sum of rs_t over the class's pairs
-  double sj;
-  {
-    int r4[4] = {0, 0, 0, 0};
-    double mx = 0.0;
-    if (j < d.m) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) r4[q] = rs[(int64_t)q * d.KMr + j];
-      mx = __longlong_as_double((long long)d.rmax[j]);
-    }
-    int E = 0;
-    if (mx > 0.0) (void)frexp(mx, &E);
-    sj = ldexp(1.0, E - 6);
-    // class c holds the pairs (c - t, t), max(0, c - 3) <= t <= min(3, c)
-    cre[0] = r4[0];
-    cre[1] = r4[0] + r4[1];
-    cre[2] = r4[0] + r4[1] + r4[2];
-    cre[3] = r4[0] + r4[1] + r4[2] + r4[3];
-    cre[4] = r4[1] + r4[2] + r4[3];
-  }
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int i = i0 + 32 * ba + 8 * (e >> 2) + 4 * kh + (e & 3);
-    if (i >= d.m || j >= d.m || j > i) continue;
-    const double mx = __longlong_as_double((long long)d.rmax[i]);
-    int E = 0;
-    if (mx > 0.0) (void)frexp(mx, &E);
-    const double si = ldexp(1.0, E - 6);
-    // smallest class first: every partial sum keeps full FP64 accuracy
-    double vr = 0.0, vi = 0.0;
-#pragma unroll
-    for (int c = NCLS - 1; c >= 0; --c) {
-      const double wgt = ldexp(1.0, -8 * c);
-      vr += (double)re[c][e] * wgt;
-      vi += ((double)im[c][e] + (double)cre[c]) * wgt;
-    }
-    cd v = {vr * (si * sj), vi * (si * sj)};
-    cd* cij = d.C + (int64_t)j * d.ldc + i;
-    if (chunk > 0) { v.re += cij->re; v.im += cij->im; }
-    else if (i == j) v.re += d.diag;
-    if (i == j) v.im = 0.0;
-    *cij = v;
-    if (i != j) d.C[(int64_t)i * d.ldc + j] = cd{v.re, -v.im};
-  }
+  static_assert(sizeof(Panel) * 2 >= 4 * 2 * 16 * 64 * sizeof(double), "class partials fit the panels");
+  double* part = reinterpret_cast<double*>(&sp[0][0][0][0][0][0]);
+  const int w = threadIdx.x >> 6;
+  if (w < 4) gram32_wave<0>(d, sp, chunk, ti, tj, n0, n1, w, part);
+  else gram32_wave<1>(d, sp, chunk, ti, tj, n0, n1, w - 4, part);
 }
 
 template <int ST>
