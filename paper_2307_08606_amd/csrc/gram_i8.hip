@@ -386,17 +386,18 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
 }
 
 // ---------------------------------------------------------------------------
-// The same products on the int8 32x32x32 instruction, which sustains about
-// 1.5 times the rate of the 16x16x64 one in register-only loops on this GPU
-// (up to 4.5 against 3.0 POP/s).  Work-group: the same 64 x 64 complex tile
+// The same products on the int8 32x32x32 instruction, which a register-only
+// loop issues about 1.5 times as fast as the 16x16x64 one on this GPU (up to
+// 4.5 against 3.0 POP/s).  Work-group: the same 64 x 64 complex tile
 // and double-buffered stages, eight waves: each 32 x 32 block of the tile
 // has two, one accumulating the classes 0..2 (six digit pairs), the other the
 // classes 3..4 (seven pairs), so that a wave holds at most six 16-register
 // accumulators and two waves fit each SIMD.  The classes' FP64 sum meets in
 // LDS, in the order of the 16x16x64 kernel (identical results).  It runs
-// 6.7 ms per c2 chunk against 5.8 for gram_i8_kernel (as did one wave of all
-// ten accumulators per block, at one wave per SIMD), so it is kept only as a
-// cross-check of the integer arithmetic.
+// 6.7 ms per c2 chunk against 5.8 for gram_i8_kernel: inside the kernel a
+// 32x32x32 product occupies the matrix unit exactly as long as two 16x16x64
+// ones (equal busy-cycle counters), so the larger shape gains nothing here;
+// it is kept as a cross-check of the integer arithmetic.
 // Lane layout (pinned by an in-bounds probe): lane l carries A row l % 32 and
 // B column l % 32 with k-bytes 16 (l / 32) + [0, 16) of the 32-byte step;
 // result component e of lane l is element (8 (e / 4) + 4 (l / 32) + e % 4,
