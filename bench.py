@@ -529,7 +529,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the engine is single-GPU "
-              "(multi-GPU sharding is described in DESIGN.md, not built).", file=sys.stderr)
+              "(sharding over several GPUs is not built).", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calib:

@@ -420,7 +420,7 @@ int gram_integer(sadmm_t h0, const std::vector<FacItem>& items, std::vector<void
   for (const FacItem& it : items) max_n = std::max(max_n, it.h->N);
   const size_t per = (gram_i8_workspace(h0->KMp, max_n) + 255) / 256 * 256;
   const size_t group = std::max<size_t>(1, std::min<size_t>(items.size(), kCap / per));
-  std::lock_guard<std::mutex> lock(g_gws_mu);     // held while this build's kernels are queued
+  std::lock_guard<std::mutex> lock(g_gws_mu);     // held while this factor build's kernels are queued
   GramWorkspace& ws = g_gws[h0->dev];
   if (!ws.last && hipEventCreateWithFlags(&ws.last, hipEventDisableTiming) != hipSuccess) {
     ws.last = nullptr;
