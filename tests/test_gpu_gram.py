@@ -134,3 +134,28 @@ def test_wide_and_narrow_instruction_grams_are_identical(gpu_lib, shape):
         Ww = _factors(gpu_lib, g, A, y, storage, "int8_32")
         for q in range(g.Q):
             assert np.array_equal(Ww[q], Wn[q]), (storage, q)
+
+
+def test_shared_workspace_across_handles_and_streams(gpu_lib, problem):
+    """The digit-plane workspace is one per device: handles on two streams
+    building factors back to back (each build ordered after the previous
+    user's Gram kernels by an event) get the factors of a handle alone."""
+    import torch
+    g, A, y = problem
+    ref = _factors(gpu_lib, g, A, y, "fp32", "int8")
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    hs = []
+    for st in streams:
+        s = gpu_lib.Solver(g.Q, g.K, g.M, g.N, storage="fp32", lam=0.05, max_iter=1, stop=False,
+                           reuse_factor=False, stream=st.cuda_stream)
+        for q in range(g.Q):
+            s.set_operator(q, A[q])
+        hs.append(s)
+    for _ in range(2):
+        for s in hs:
+            s.solve(y)
+    torch.cuda.synchronize()
+    for s in hs:
+        for q in range(g.Q):
+            assert np.array_equal(s.factor(q), ref[q])
+        s.close()
