@@ -165,3 +165,57 @@ def test_cnn_false_prune_is_reinstated(gpu_lib):
     z = s.image()
     assert np.linalg.norm(z - ref.z) <= 1e-8 * np.linalg.norm(ref.z)
     assert np.linalg.norm(z - plain.z) ** 2 <= 1e-6 * np.linalg.norm(plain.z) ** 2
+
+
+def test_trained_selector_against_the_method_without_it(gpu_lib):
+    """What a trained network gains over the same solve without it, stated:
+    a CNN trained on the GPU (its own kernels) on labels from pruned oracle
+    solves of six small scenes selects pixels on a held-out scene; the
+    learned solve (FP32, KKT re-check on) reaches the unpruned optimum
+    (NMSE <= 1e-6), and its iterations, eliminations and reinstatements are
+    printed beside the plain solve's.  Under the ridge reading the optimum's
+    per-sensor values are not 0 off the support, so learned eliminations are
+    undone by the re-check and cost iterations rather than save them."""
+    import time
+    Q, M, K, n = 3, 4, 32, 16
+    g = make_geometry(Q, M, K, n)
+    A = [steering(g, q) for q in range(Q)]
+    c = gpu_lib.Cnn(Q, 8, n, n)
+    c.set_params(ocnn.init_params(Q, 8, seed=3))
+    data = []
+    for seed in range(20, 26):
+        sc = make_scene(g, seed, 5, 20.0)
+        lam = 0.2 * oracle.lambda_max(A, sc.y, 1.0, 1.0)
+        # 150 iterations past the SSC gate: the label is "eliminated from every
+        # sensor and 0 in the image" (the off-support pixels here)
+        r = oracle.solve(A, sc.y, oracle.Params(lam=lam, max_iter=150, eps_rel=1e-4, prune=True, stop=False))
+        x = ocnn.normalize_input(oracle.matched_filter(A, sc.y).reshape(Q, n, n))
+        data.append((x, ocnn.labels_from_solution(r.z, r.active).reshape(n, n)))
+    for _ in range(40):
+        for x, t in data:
+            c.train_step(x, t, 1.0, 3e-3)
+    sc = make_scene(g, 40, 5, 20.0)
+    lam = 0.2 * oracle.lambda_max(A, sc.y, 1.0, 1.0)
+    kw = dict(storage="fp32", lam=lam, max_iter=2000, eps_rel=1e-5, kkt=True)
+    out = {}
+    for name in ("plain", "learned"):
+        s = gpu_lib.Solver(Q, K, M, g.N, **kw)
+        for q in range(Q):
+            s.set_operator(q, A[q])
+        if name == "learned":
+            s.set_pruning_cnn(c, 0.5)
+        s.solve(sc.y)                      # warm-up
+        t0 = time.perf_counter()
+        info = s.solve(sc.y)
+        out[name] = dict(ms=(time.perf_counter() - t0) * 1e3, iters=info["iters"], status=info["status"],
+                         reinstated=info["reinstated"], z=s.image(),
+                         eliminated_at_start=int(sum((~s.active_mask(q).astype(bool)).sum() for q in range(Q)))
+                         if name == "plain" else None)
+        s.close()
+    zp, zl = out["plain"]["z"], out["learned"]["z"]
+    nmse = float(np.linalg.norm(zl - zp) ** 2 / np.linalg.norm(zp) ** 2)
+    print(f"plain: {out['plain']['iters']} iterations, {out['plain']['ms']:.2f} ms; learned: "
+          f"{out['learned']['iters']} iterations, {out['learned']['ms']:.2f} ms, "
+          f"{out['learned']['reinstated']} reinstated; NMSE learned vs plain {nmse:.2e}", flush=True)
+    assert out["plain"]["status"] == 0 and out["learned"]["status"] == 0
+    assert nmse <= 1e-6
