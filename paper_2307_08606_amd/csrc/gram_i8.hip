@@ -27,7 +27,6 @@
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));   // (uint4 arrays stay in scratch)
 
 constexpr int GT = 64;      // tile rows / columns (complex)
 constexpr int GKS = 64;     // columns per stage (k of one instruction)
@@ -178,6 +177,39 @@ __device__ inline int swz(int row) {
   return ((r >> 1) + (r >> 3)) & 3;
 }
 constexpr int NCLS = 5;                      // classes c = s + t = 0..4
+#define LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+// Wait until every global load of the wave (register or LDS destination) has
+// landed; LDS and export counters untouched.
+__device__ inline void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Staging of one stage (16 planes: L/R x digit x re/im, 64 rows x 64 bytes
+// each) by a work-group of 512 threads, straight from the stage blocks into
+// LDS with no register staging.  Thread t moves row (t >> 2) & 63 of the
+// eight planes of side t >> 8 (L, then R).  The instruction writes lane l's
+// 16 bytes at 16 l from the wave's LDS base, i.e. at row prow, quarter slot
+// l & 3 of the wave's 16 rows, so the lane fetches the row's quarter
+// (l & 3) ^ swz(prow): the swizzle is applied on the global side.
+struct StageLoader {
+  static constexpr int64_t kPlane = 4096;        // between the planes of a stage block
+  static constexpr int kPlaneLds = GT * GROW;    // between the (digit, re/im) planes in LDS
+  const int8_t* src;
+  int8_t* lds[2];
+  __device__ StageLoader(const GramI8Desc& d, Panel (&sp)[2], int ti, int tj) {
+    const int t = threadIdx.x, prow = (t >> 2) & 63, side = t >> 8, lrow = 16 * ((t >> 6) & 3);
+    src = d.S + stage_block(side ? tj : ti, 0, d.ldS) + prow * 64 + 16 * ((t & 3) ^ swz(prow));
+    lds[0] = &sp[0][side][0][0][lrow][0];
+    lds[1] = &sp[1][side][0][0][lrow][0];
+  }
+  // stage `stage` (columns 64 stage ..) of both panels into sp[buf]
+  __device__ void issue(int stage, int buf) const {
+    const int8_t* g = src + (int64_t)stage * kStageBlock;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      __builtin_amdgcn_global_load_lds(g + e * kPlane, LDS_PTR(lds[buf] + e * kPlaneLds), 16, 0, 0);
+    __builtin_amdgcn_sched_barrier(0x0008);   // not sunk to the wait; matrix products may pass
+  }
+};
+
 // Eight waves per work-group (two per SIMD, so one wave's LDS reads overlap
 // the other's matrix instructions): wave w owns rows 32 (w & 1) + [0, 32)
 // (two 16-row blocks a) and columns 16 (w >> 1) + [0, 16) (one block).
@@ -257,6 +289,7 @@ __device__ inline void kstep(const Panel& sp, int wr, int wc, int r16, int kq,
     pair_mma<1, 4>(L, R, re, im); }
 }
 
+
 // One chunk of columns [chunk * GI8_CHUNK, +GI8_CHUNK): chunk 0 writes
 // C = G_0 + diag I, later chunks add.
 __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __restrict__ descs, int chunk,
@@ -284,50 +317,27 @@ __global__ __launch_bounds__(GTHREADS) void gram_i8_kernel(const GramI8Desc* __r
         re[c][a][b] = v4i{0, 0, 0, 0};
         im[c][a][b] = v4i{0, 0, 0, 0};
       }
-  // staging: 16 planes (L/R x digit x re/im) x 64 rows x 64 bytes per stage;
-  // thread t moves row (t >> 2) & 63, quarter t & 3 of the eight planes
-  // 8 (t >> 8) + e of the L/R x digit x re/im order (L for t < 256, R above).
-  constexpr int PPT = 16 * 256 / GTHREADS;   // planes per thread
-  constexpr int64_t plane = 4096;   // between the planes of a stage block
-  const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
-  // stage n (columns n .. n + 63) of this thread's row: src + stage_block offset
-  const int8_t* src = d.S + stage_block(side ? tj : ti, 0, d.ldS) + prow * 64 + 16 * pq;
-  int8_t* dst0 = &sp[0][side][0][0][prow][16 * (pq ^ swz(prow))];
-  int8_t* dst1 = &sp[1][side][0][0][prow][16 * (pq ^ swz(prow))];
-  constexpr int kPlaneLds = GT * GROW;   // LDS bytes between (digit, re/im) planes
-  // Stage s is staged in sp[s & 1]; its loads are issued one stage ahead (in
-  // flight during the products of the stage before) and stored to LDS after
-  // those products.  One barrier per stage: a buffer is refilled only after
-  // the barrier that follows the products reading it.
-  u4v pa[PPT];
+  const StageLoader ld(d, sp, ti, tj);
+  // Stage s lands in sp[s & 1]; its loads are issued as the products of
+  // stage s - 1 start and waited for before the barrier that ends them.  One
+  // barrier per stage: a buffer is refilled only after the barrier that
+  // follows the products reading it.
   if (n0 < n1) {
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS) * kStageBlock + e * plane);
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    ld.issue(n0 / GKS, 0);
+    wait_loads();
     __syncthreads();
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS + 1) * kStageBlock + e * plane);
   }
   for (int nb = n0; nb < n1; nb += 2 * GKS) {
+    ld.issue(nb / GKS + 1, 1);                                   // sp[1] is free since the last barrier
     kstep(sp[0], wr, wc, r16, kqs, re, im);                      // stage nb
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst1 + e * kPlaneLds) = pa[e];
+    wait_loads();
     __syncthreads();
-    if (nb + 2 * GKS < n1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 2) * kStageBlock + e * plane);
-    }
+    // the last pair reloads its own second stage (L2-resident, never read):
+    // without a branch the loads can issue among the products that trail the barrier
+    ld.issue(min(nb / GKS + 2, n1 / GKS - 1), 0);
     kstep(sp[1], wr, wc, r16, kqs, re, im);                      // stage nb + GKS
-    if (nb + 2 * GKS < n1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
-    }
+    wait_loads();
     __syncthreads();
-    if (nb + 3 * GKS < n1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 3) * kStageBlock + e * plane);
-    }
   }
   // ---- epilogue: FP64 sum of the classes, lower triangle and its mirror
   const int* rs = d.rs + (int64_t)chunk * 4 * d.KMr;
@@ -473,46 +483,24 @@ __device__ inline void gram32_wave(const GramI8Desc& d, Panel (&sp)[2], int chun
       re[c][e] = 0;
       im[c][e] = 0;
     }
-  // staging as in gram_i8_kernel: thread t moves row (t >> 2) & 63, quarter
-  // t & 3 of the eight planes of side t >> 8 (L, then R)
-  constexpr int PPT = 8;
-  constexpr int64_t plane = 4096;
-  constexpr int kPlaneLds = GT * GROW;
-  const int prow = (t >> 2) & 63, pq = t & 3, side = t >> 8;
-  const int8_t* src = d.S + stage_block(side ? tj : ti, 0, d.ldS) + prow * 64 + 16 * pq;
-  int8_t* dst0 = &sp[0][side][0][0][prow][16 * (pq ^ swz(prow))];
-  int8_t* dst1 = &sp[1][side][0][0][prow][16 * (pq ^ swz(prow))];
-  u4v pa[PPT];
+  // staging and barriers as in gram_i8_kernel
+  const StageLoader ld(d, sp, ti, tj);
   if (n0 < n1) {
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS) * kStageBlock + e * plane);
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
+    ld.issue(n0 / GKS, 0);
+    wait_loads();
     __syncthreads();
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (n0 / GKS + 1) * kStageBlock + e * plane);
   }
   for (int nb = n0; nb < n1; nb += 2 * GKS) {
+    ld.issue(nb / GKS + 1, 1);
     kstep32<G>(sp[0], lrow, rrow, kh, re, im);                   // stage nb
     kstep32<G>(sp[0], lrow, rrow, 2 + kh, re, im);
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst1 + e * kPlaneLds) = pa[e];
+    wait_loads();
     __syncthreads();
-    if (nb + 2 * GKS < n1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 2) * kStageBlock + e * plane);
-    }
+    ld.issue(min(nb / GKS + 2, n1 / GKS - 1), 0);
     kstep32<G>(sp[1], lrow, rrow, kh, re, im);                   // stage nb + GKS
     kstep32<G>(sp[1], lrow, rrow, 2 + kh, re, im);
-    if (nb + 2 * GKS < n1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) *reinterpret_cast<u4v*>(dst0 + e * kPlaneLds) = pa[e];
-    }
+    wait_loads();
     __syncthreads();
-    if (nb + 3 * GKS < n1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) pa[e] = *reinterpret_cast<const u4v*>(src + (nb / GKS + 3) * kStageBlock + e * plane);
-    }
   }
   // ---- epilogue: the classes summed in FP64 from the largest c down (the
   // order of gram_i8_kernel); group 1 (classes 4, 3) first, through LDS
