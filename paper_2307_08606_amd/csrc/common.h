@@ -260,6 +260,8 @@ struct Ctl {
   int gone_total;   // pixels SSC decided to eliminate at the last iteration
   int max_iter;
   int bal;          // residual balancing at the last iteration: +1 beta up, -1 down, 0 none
+  unsigned pix_done;   // pixel-update blocks finished this iteration (the last one resets it)
+  unsigned ssc_done;   // SSC-check blocks finished this iteration (the last one resets it)
   int pad;
   double r, s, eps_pri, eps_dual, nmse;
 };

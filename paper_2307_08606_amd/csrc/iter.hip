@@ -633,6 +633,55 @@ __global__ __launch_bounds__(256) void coldot_batch_kernel(BatchView bv) {
 }
 
 // ------------------------------------------------------------------ pixel update
+// Residuals, stop test, balancing decision and history of one iteration of a
+// scene from the pixel blocks' partial sums, by one work-group of 256.
+__device__ __forceinline__ void finalize_scene(const IterArgs& a, double* sm) {
+  Ctl* ctl = a.ctl;
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < a.nblk; b += 256) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part[j] += a.red[(int64_t)b * 8 + j];
+  }
+  block_sum256<double, 8>(part, sm);
+  if (threadIdx.x != 0) return;
+  const double Q = a.Q;
+  const int k = ctl->k + 1;
+  const double r = sqrt(Q) * sqrt(part[0]);
+  const double s = a.beta * sqrt(part[1]);
+  const double sqQN = sqrt(Q * (double)a.N);
+  const double eps_pri = sqQN * a.eps_abs + a.eps_rel * fmax(sqrt(part[2]), sqrt(part[3]));
+  const double eps_dual = sqQN * a.eps_abs + a.eps_rel * a.beta * sqrt(Q) * sqrt(part[4]);
+  const double nmse = a.xref ? part[5] / a.xref_norm2 : 0.0;
+  int halt = 0;
+  bool finite = true;
+  for (int j = 0; j < 6; ++j) finite = finite && isfinite(part[j]);
+  if (!finite) halt |= HALT_NAN;
+  if (a.stop && r <= eps_pri && s <= eps_dual) halt |= HALT_CONV;
+  if (a.xref && a.nmse_target > 0.0 && nmse <= a.nmse_target) halt |= HALT_NMSE;
+  if (k >= a.max_iter) halt |= HALT_MAXIT;
+  // residual balancing (Boyd et al. 2011, Sec. 3.4.1), decided here and
+  // applied by the host after this iteration's SSC check
+  int bal = 0;
+  if (a.bal_every > 0 && !(halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_MAXIT)) && k % a.bal_every == 0) {
+    if (r > a.bal_mu * s) bal = 1;
+    else if (s > a.bal_mu * r) bal = -1;
+    if (bal) halt |= HALT_BAL;
+  }
+  ctl->bal = bal;
+  double* h = a.hist;
+  const int mi = a.max_iter;
+  h[0 * mi + k - 1] = r;
+  h[1 * mi + k - 1] = s;
+  h[2 * mi + k - 1] = eps_pri;
+  h[3 * mi + k - 1] = eps_dual;
+  h[4 * mi + k - 1] = nmse;
+  ctl->r = r; ctl->s = s; ctl->eps_pri = eps_pri; ctl->eps_dual = eps_dual; ctl->nmse = nmse;
+  ctl->gate = (r <= eps_pri) ? 1 : 0;
+  ctl->nan = finite ? 0 : 1;
+  ctl->k = k;
+  ctl->halt = halt;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
   const IterArgs& a = bv.args[blockIdx.y];
@@ -684,61 +733,23 @@ __global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
     stc<T>(a.u, n, un);
   }
   block_sum256<double, 8>(part, sm);
+  // The scene's last block to finish (counted on the control block) finds
+  // every partial written and ends the iteration; it also clears the count
+  // for the next iteration, so replays need no reset.
+  __shared__ int last;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) a.red[(int64_t)blockIdx.x * 8 + j] = part[j];
+    __threadfence();   // the partials are visible before the count
+    last = atomicAdd(&a.ctl->pix_done, 1u) == (unsigned)a.nblk - 1;
   }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) a.ctl->pix_done = 0;
+  finalize_scene(a, sm);
 }
 
-__global__ __launch_bounds__(256) void finalize_kernel(BatchView bv) {
-  const IterArgs& a = bv.args[blockIdx.x];
-  Ctl* ctl = a.ctl;
-  if (ctl->halt) return;
-  __shared__ double sm[4 * 8];
-  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < a.nblk; b += 256) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) part[j] += a.red[(int64_t)b * 8 + j];
-  }
-  block_sum256<double, 8>(part, sm);
-  if (threadIdx.x != 0) return;
-  const double Q = a.Q;
-  const int k = ctl->k + 1;
-  const double r = sqrt(Q) * sqrt(part[0]);
-  const double s = a.beta * sqrt(part[1]);
-  const double sqQN = sqrt(Q * (double)a.N);
-  const double eps_pri = sqQN * a.eps_abs + a.eps_rel * fmax(sqrt(part[2]), sqrt(part[3]));
-  const double eps_dual = sqQN * a.eps_abs + a.eps_rel * a.beta * sqrt(Q) * sqrt(part[4]);
-  const double nmse = a.xref ? part[5] / a.xref_norm2 : 0.0;
-  int halt = 0;
-  bool finite = true;
-  for (int j = 0; j < 6; ++j) finite = finite && isfinite(part[j]);
-  if (!finite) halt |= HALT_NAN;
-  if (a.stop && r <= eps_pri && s <= eps_dual) halt |= HALT_CONV;
-  if (a.xref && a.nmse_target > 0.0 && nmse <= a.nmse_target) halt |= HALT_NMSE;
-  if (k >= a.max_iter) halt |= HALT_MAXIT;
-  // residual balancing (Boyd et al. 2011, Sec. 3.4.1), decided here and
-  // applied by the host after this iteration's SSC check
-  int bal = 0;
-  if (a.bal_every > 0 && !(halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_MAXIT)) && k % a.bal_every == 0) {
-    if (r > a.bal_mu * s) bal = 1;
-    else if (s > a.bal_mu * r) bal = -1;
-    if (bal) halt |= HALT_BAL;
-  }
-  ctl->bal = bal;
-  double* h = a.hist;
-  const int mi = a.max_iter;
-  h[0 * mi + k - 1] = r;
-  h[1 * mi + k - 1] = s;
-  h[2 * mi + k - 1] = eps_pri;
-  h[3 * mi + k - 1] = eps_dual;
-  h[4 * mi + k - 1] = nmse;
-  ctl->r = r; ctl->s = s; ctl->eps_pri = eps_pri; ctl->eps_dual = eps_dual; ctl->nmse = nmse;
-  ctl->gate = (r <= eps_pri) ? 1 : 0;
-  ctl->nan = finite ? 0 : 1;
-  ctl->k = k;
-  ctl->halt = halt;
-}
 
 // SSC check (Alg. 1, steps 1-2): runs when the gate is open and K_p
 // differences exist.  Runs at the last permitted iteration too (max_iter),
@@ -755,25 +766,28 @@ __global__ __launch_bounds__(256) void ssc_kernel(BatchView bv) {
   const int q = sl.y;
   const SensorDesc sd = a.sens[q];
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= sd.nq) return;
-  const int n = sd.J[p];
-  const T* D = reinterpret_cast<const T*>(a.D);
-  T zs = (T)0;
-  for (int sl = 0; sl < a.Kp; ++sl) zs += D[((int64_t)sl * a.Q + q) * a.N + n];
-  const T zeta = zs / (T)a.Kp;
-  const bool keep = zeta >= (T)a.eps_p;
-  a.keep[(int64_t)q * a.N + p] = keep ? 1 : 0;
-  if (!keep) atomicAdd(&a.gone[q], 1);
-}
-
-// Raises the prune halt bit when the SSC check removed anything.
-__global__ void ssc_flag_kernel(BatchView bv) {
-  const IterArgs& a = bv.args[blockIdx.x];
-  Ctl* ctl = a.ctl;
-  if (threadIdx.x != 0 || !a.prune) return;
-  if (ctl->halt & (HALT_CONV | HALT_NAN | HALT_NMSE | HALT_PRUNE)) return;
+  if (p < sd.nq) {
+    const int n = sd.J[p];
+    const T* D = reinterpret_cast<const T*>(a.D);
+    T zs = (T)0;
+    for (int sl = 0; sl < a.Kp; ++sl) zs += D[((int64_t)sl * a.Q + q) * a.N + n];
+    const T zeta = zs / (T)a.Kp;
+    const bool keep = zeta >= (T)a.eps_p;
+    a.keep[(int64_t)q * a.N + p] = keep ? 1 : 0;
+    if (!keep) atomicAdd(&a.gone[q], 1);
+  }
+  // The scene's last block (of gridDim.x per sensor, Q sensors) raises the
+  // prune halt bit when the check removed anything, and clears the count.
+  __shared__ int last;
+  __threadfence();   // this thread's eliminations are counted before the block is
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&ctl->ssc_done, 1u) == gridDim.x * (unsigned)a.Q - 1;
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  ctl->ssc_done = 0;
   int tot = 0;
-  for (int q = 0; q < a.Q; ++q) tot += a.gone[q];
+  for (int qq = 0; qq < a.Q; ++qq) tot += atomicAdd(&a.gone[qq], 0);
   if (tot > 0) {
     ctl->gone_total = tot;
     ctl->halt |= HALT_PRUNE;
@@ -787,10 +801,8 @@ __global__ void gather_ctl_kernel(Ctl* const* ptrs, Ctl* out, int n) {
 
 template <class T>
 void launch_pixel_stage_t(const BatchView& b, const BatchDims& d, hipStream_t s) {
-  pixel_kernel<T><<<dim3(d.nblk_max, d.nscene), 256, 0, s>>>(b);
-  finalize_kernel<<<d.nscene, 256, 0, s>>>(b);
+  pixel_kernel<T><<<dim3(d.nblk_max, d.nscene), 256, 0, s>>>(b);   // ends with the scene's residuals
   ssc_kernel<T><<<dim3((d.N_max + 255) / 256, d.nslot), 256, 0, s>>>(b);
-  ssc_flag_kernel<<<d.nscene, 64, 0, s>>>(b);
 }
 
 template <int ST>
