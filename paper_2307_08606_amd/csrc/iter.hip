@@ -105,6 +105,22 @@ __device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* col
   }
 }
 
+// use(i, load(i)) for i = 0 .. n-1 in index order, with the loads of G
+// consecutive indices issued before their uses: a short dynamic loop of
+// dependent adds otherwise waits out one memory latency per index.
+template <int G, class L, class U>
+__device__ inline void in_order(int n, L load, U use) {
+  for (int i0 = 0; i0 < n; i0 += G) {
+    decltype(load(0)) v[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (i0 + j < n) v[j] = load(i0 + j);
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (i0 + j < n) use(i0 + j, v[j]);
+  }
+}
+
 template <int ST>
 __global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(BatchView bv) {
   using T = typename Store<ST>::T;
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(BatchView bv) {
   const int nch = (nq + a.chunk - 1) / a.chunk;
   const C2<T>* tp = reinterpret_cast<const C2<T>*>(a.tpart) + (int64_t)q * a.nchunk * a.KMp + i;
   C2<T> s = {(T)0, (T)0};
-  for (int c = 0; c < nch; ++c) s = cadd(s, tp[(int64_t)c * a.KMp]);
+  in_order<8>(nch, [&](int c) { return tp[(int64_t)c * a.KMp]; }, [&](int, C2<T> v) { s = cadd(s, v); });
   stc<T>(a.t, (int64_t)q * a.KMp + i, s);
 }
 
@@ -206,7 +222,7 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(int KMp, int nch, co
   if (i >= KMp) return;
   const C2<T>* tp = reinterpret_cast<const C2<T>*>(tmp) + i;
   C2<T> s = {(T)0, (T)0};
-  for (int c = 0; c < nch; ++c) s = cadd(s, tp[(int64_t)c * KMp]);
+  in_order<8>(nch, [&](int c) { return tp[(int64_t)c * KMp]; }, [&](int, C2<T> v) { s = cadd(s, v); });
   out[2 * i] += sign * (double)s.re;
   out[2 * i + 1] += sign * (double)s.im;
 }
@@ -255,7 +271,7 @@ __global__ __launch_bounds__(256) void fwd_all_reduce_kernel(IterArgs a, int act
   const int nch = (count + a.chunk - 1) / a.chunk;
   const C2<T>* tp = reinterpret_cast<const C2<T>*>(a.tpart) + (int64_t)q * a.nchunk * a.KMp + i;
   C2<T> sm = {(T)0, (T)0};
-  for (int c = 0; c < nch; ++c) sm = cadd(sm, tp[(int64_t)c * a.KMp]);
+  in_order<8>(nch, [&](int c) { return tp[(int64_t)c * a.KMp]; }, [&](int, C2<T> v) { sm = cadd(sm, v); });
   double* o = out + 2 * ((int64_t)q * a.KMp + i);
   o[0] += sign * (double)sm.re;
   o[1] += sign * (double)sm.im;
@@ -435,6 +451,7 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
   extern __shared__ unsigned char smem_raw[];
   C2<TA>* sv = reinterpret_cast<C2<TA>*>(smem_raw);
   // stage the vector operand
+#pragma unroll 4
   for (int i = threadIdx.x; i < a.KMp; i += 256) {
     C2<TA> v;
     if constexpr ((EPI == EPI_W || EPI == EPI_WY || EPI == EPI_WVEC) && std::is_same<TA, double>::value) {
@@ -587,6 +604,7 @@ __device__ inline void xdir_body(const IterArgs& a, int q) {
   for (int s0 = 0; s0 < sd.fld; s0 += XDIR_SEG) {
     const int len = min(XDIR_SEG, sd.fld - s0);
     __syncthreads();   // the previous segment is consumed
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += 256) sv[i] = sd.rdir[s0 + i];
     __syncthreads();
 #pragma unroll
@@ -691,7 +709,8 @@ __global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n < a.N) {
     C2<T> sum = {(T)0, (T)0};
-    for (int q = 0; q < a.Q; ++q) sum = cadd(sum, ldc<T>(a.X, (int64_t)q * a.N + n));
+    in_order<8>(a.Q, [&](int q) { return ldc<T>(a.X, (int64_t)q * a.N + n); },
+                [&](int, C2<T> v) { sum = cadd(sum, v); });
     const T Qt = (T)a.Q;
     const C2<T> xb = {sum.re / Qt, sum.im / Qt};
     const C2<T> zo = ldc<T>(a.z, n), xbo = ldc<T>(a.xbar, n), uo = ldc<T>(a.u, n);
@@ -711,14 +730,16 @@ __global__ __launch_bounds__(256) void pixel_kernel(BatchView bv) {
     // its norm for the primal tolerance
     const C2<T> zx = csub(zn, xb);
     double s2 = 0.0, nx2 = 0.0, nz2 = 0.0;
-    for (int q = 0; q < a.Q; ++q) {
+    struct DX { C2<T> dx, x; };
+    in_order<8>(a.Q, [&](int q) {
       const int64_t o = (int64_t)q * a.N + n;
-      const C2<T> d = cadd(ldc<T>(a.dX, o), dz);
-      const C2<T> xq = ldc<T>(a.X, o);
+      return DX{ldc<T>(a.dX, o), ldc<T>(a.X, o)};
+    }, [&](int, DX v) {
+      const C2<T> d = cadd(v.dx, dz);
       s2 += (double)cabs2(d);
-      nx2 += (double)cabs2(xq);
-      nz2 += (double)cabs2(cadd(xq, zx));
-    }
+      nx2 += (double)cabs2(v.x);
+      nz2 += (double)cabs2(cadd(v.x, zx));
+    });
     part[0] = (double)cabs2(csub(xb, zn));
     part[1] = s2;
     part[2] = nx2;
@@ -770,7 +791,7 @@ __global__ __launch_bounds__(256) void ssc_kernel(BatchView bv) {
     const int n = sd.J[p];
     const T* D = reinterpret_cast<const T*>(a.D);
     T zs = (T)0;
-    for (int sl = 0; sl < a.Kp; ++sl) zs += D[((int64_t)sl * a.Q + q) * a.N + n];
+    in_order<8>(a.Kp, [&](int sl) { return D[((int64_t)sl * a.Q + q) * a.N + n]; }, [&](int, T v) { zs += v; });
     const T zeta = zs / (T)a.Kp;
     const bool keep = zeta >= (T)a.eps_p;
     a.keep[(int64_t)q * a.N + p] = keep ? 1 : 0;
