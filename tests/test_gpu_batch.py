@@ -66,3 +66,26 @@ def test_batch_matches_oracle_with_early_stops(gpu_lib):
                                                   prune=c["prune"]))
         assert info["status"] == 0 and info["iters"] == ref.iters
         assert np.linalg.norm(s.image() - ref.z) <= 1e-8 * np.linalg.norm(ref.z)
+
+
+def test_repeated_batch_solves_are_identical(gpu_lib):
+    """The same batch solved twice on the same handles, and then each scene
+    alone again: every iteration's end-of-iteration work (residuals, stop
+    test, prune flag) runs in the last work-group of its kernel, picked by a
+    completion count that each iteration leaves at zero; a count left over
+    from a solve would shift the next solve's residuals or prune decisions."""
+    probs = [scene(c["Q"], c["M"], c["K"], c["n_side"], c["seed"], c["n_targets"]) for c in SCENES]
+    batch = [solver(gpu_lib, g, A, lam, "fp32", prune=c["prune"], max_iter=c["max_iter"],
+                    stop=True, eps_rel=1e-4) for (g, sc, A, lam), c in zip(probs, SCENES)]
+    ys = [sc.y for (g, sc, A, lam) in probs]
+    first = gpu_lib.solve_batch(batch, ys)
+    z1 = [s.image() for s in batch]
+    second = gpu_lib.solve_batch(batch, ys)
+    for i, s in enumerate(batch):
+        assert second[i]["iters"] == first[i]["iters"], i
+        assert second[i]["prune_events"] == first[i]["prune_events"], i
+        assert np.array_equal(s.image(), z1[i]), i
+    for i, s in enumerate(batch):
+        info = s.solve(ys[i])
+        assert info["iters"] == first[i]["iters"], i
+        assert np.array_equal(s.image(), z1[i]), i
