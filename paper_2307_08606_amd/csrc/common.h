@@ -51,9 +51,15 @@ template <> struct Store<ST_FP64> {
   using T = double;
   static constexpr int RPT = 1;
   static constexpr int BYTES = 16;   // per complex entry
+  // NT: a non-temporal load, for passes over more data than the caches hold
+  template <bool NT = false>
   __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
     (void)KM;
-    const double2 v = reinterpret_cast<const double2*>(col)[i];
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* p = reinterpret_cast<const d2*>(col) + i;
+    d2 v;
+    if constexpr (NT) v = __builtin_nontemporal_load(p);
+    else v = *p;
     re[0] = v.x; im[0] = v.y;
   }
   __device__ static inline cd get(const void* col, int i, int KM) {
@@ -61,19 +67,37 @@ template <> struct Store<ST_FP64> {
     const double2 v = reinterpret_cast<const double2*>(col)[i];
     return {v.x, v.y};
   }
+  // get() for a pass that reads each entry once (non-temporal load)
+  __device__ static inline cd get_stream(const void* col, int i, int KM) {
+    (void)KM;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(col) + i);
+    return {v.x, v.y};
+  }
 };
 template <> struct Store<ST_FP32> {
   using T = float;
   static constexpr int RPT = 2;
   static constexpr int BYTES = 8;
+  template <bool NT = false>
   __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
     (void)KM;
-    const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(col) + i);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4* p = reinterpret_cast<const f4*>(reinterpret_cast<const float2*>(col) + i);
+    f4 v;
+    if constexpr (NT) v = __builtin_nontemporal_load(p);
+    else v = *p;
     re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w;
   }
   __device__ static inline cd get(const void* col, int i, int KM) {
     (void)KM;
     const float2 v = reinterpret_cast<const float2*>(col)[i];
+    return {(double)v.x, (double)v.y};
+  }
+  __device__ static inline cd get_stream(const void* col, int i, int KM) {
+    (void)KM;
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(col) + i);
     return {(double)v.x, (double)v.y};
   }
 };
@@ -86,10 +110,20 @@ template <int STP> struct StoreP16 {
   using T = float;
   static constexpr int RPT = 8;
   static constexpr int BYTES = 4;
+  template <bool NT = false>
   __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
     const uint16_t* c = reinterpret_cast<const uint16_t*>(col);
-    const uint4 vr = *reinterpret_cast<const uint4*>(c + i);
-    const uint4 vi = *reinterpret_cast<const uint4*>(c + KM + i);
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4* pr = reinterpret_cast<const u4*>(c + i);
+    const u4* pi = reinterpret_cast<const u4*>(c + KM + i);
+    u4 vr, vi;
+    if constexpr (NT) {
+      vr = __builtin_nontemporal_load(pr);
+      vi = __builtin_nontemporal_load(pi);
+    } else {
+      vr = *pr;
+      vi = *pi;
+    }
     const uint32_t r4[4] = {vr.x, vr.y, vr.z, vr.w};
     const uint32_t i4[4] = {vi.x, vi.y, vi.z, vi.w};
 #pragma unroll
@@ -103,6 +137,11 @@ template <int STP> struct StoreP16 {
   __device__ static inline cd get(const void* col, int i, int KM) {
     const uint16_t* c = reinterpret_cast<const uint16_t*>(col);
     return {(double)p16_to_f<STP>(c[i]), (double)p16_to_f<STP>(c[KM + i])};
+  }
+  __device__ static inline cd get_stream(const void* col, int i, int KM) {
+    const uint16_t* c = reinterpret_cast<const uint16_t*>(col);
+    return {(double)p16_to_f<STP>(__builtin_nontemporal_load(c + i)),
+            (double)p16_to_f<STP>(__builtin_nontemporal_load(c + KM + i))};
   }
 };
 template <> struct Store<ST_FP16P> : StoreP16<ST_FP16P> {};
@@ -138,6 +177,7 @@ template <> struct Store<ST_MF> {
   static constexpr int RPT = 8;
   static constexpr int BYTES = 0;   // nothing stored per entry
   // rows i .. i+7, i a multiple of 8
+  template <bool NT = false>   // (nothing is loaded per entry)
   __device__ static inline void load(const void* col, int i, int KM, T* re, T* im) {
     (void)KM;
     const double* rec = reinterpret_cast<const double*>(col);
@@ -216,6 +256,7 @@ template <> struct Store<ST_MF> {
       if (i - g == r) { vr = re[r]; vi = im[r]; }
     return {(double)vr, (double)vi};
   }
+  __device__ static inline cd get_stream(const void* col, int i, int KM) { return get(col, i, KM); }
 };
 
 // Address of column `n` for a storage with leading dimension ld (in slots).

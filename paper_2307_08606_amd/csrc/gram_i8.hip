@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void rowmax_kernel(const GramI8Desc* __restric
   const int n0 = blockIdx.y * per, n1 = min(d.k, n0 + per);
   double mx = 0.0;
   for (int n = n0; n < n1; ++n) {
-    const cd v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, n), i, d.kmp);
+    const cd v = Store<ST>::get_stream(col_ptr<ST>(d.A, d.ldA, n), i, d.kmp);
     mx = fmax(mx, fmax(fabs(v.re), fabs(v.im)));
   }
   if (n1 > n0) atomicMax(&d.rmax[i], (unsigned long long)__double_as_longlong(mx));
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
         const int gn = cb + PER * cg + 4 * wd + e;
         float vv[2] = {0.f, 0.f};
         if (gi < d.m && gn < d.k) {
-          const cd v = Store<ST>::get(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
+          const cd v = Store<ST>::get_stream(col_ptr<ST>(d.A, d.ldA, gn), gi, d.kmp);
           vv[0] = (float)v.re;
           vv[1] = (float)v.im;
         }
@@ -151,8 +151,10 @@ __global__ __launch_bounds__(256) void slice_kernel(const GramI8Desc* __restrict
       const int col = cb + 64 * sg + 16 * c4;
       if (col >= d.ldS) continue;
       const uint32_t* w = &sd[q][r][(64 * sg + 16 * c4) / 4];
-      *reinterpret_cast<uint4*>(d.S + stage_block(blockIdx.y, col / 64, d.ldS) + (int64_t)q * 4096 + r * 64 +
-                                16 * c4) = make_uint4(w[0], w[1], w[2], w[3]);
+      typedef unsigned u4 __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(u4{w[0], w[1], w[2], w[3]},
+                                  reinterpret_cast<u4*>(d.S + stage_block(blockIdx.y, col / 64, d.ldS) +
+                                                        (int64_t)q * 4096 + r * 64 + 16 * c4));
     }
   }
   // per-row digit sums of the block's columns (all in one chunk)

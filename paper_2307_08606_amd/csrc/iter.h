@@ -63,6 +63,10 @@ struct IterArgs {
   const double* gfix;  // complex128
   const void* xfix;    // compute precision
   double* ws;          // Q x KMp complex128: X v of the triangular W products
+  // 1: the passes over the operator (stream_op) or over the W factors
+  // (stream_w) read more than the caches keep between iterations, so their
+  // loads are non-temporal
+  int stream_op, stream_w;
 };
 
 // A batch of independent problems ("scenes") iterated by one launch per

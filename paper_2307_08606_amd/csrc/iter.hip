@@ -49,7 +49,7 @@ __device__ inline C2<T> shared_v(const IterArgs& a, int q, int n) {
 }
 
 // ------------------------------------------------------------------ forward
-template <int ST>
+template <int ST, bool NT = false>
 __device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* colidx, int p0, int np,
                                       const C2<typename Store<ST>::T>* coef, int row, int KMp,
                                       C2<typename Store<ST>::T>* acc) {
@@ -58,7 +58,7 @@ __device__ inline void fwd_accumulate(const void* A, int64_t lda, const int* col
   auto step = [&](int e) {
     const int col = colidx ? colidx[p0 + e] : p0 + e;
     T re[R], im[R];
-    Store<ST>::load(col_ptr<ST>(A, lda, col), row, KMp, re, im);
+    Store<ST>::template load<NT>(col_ptr<ST>(A, lda, col), row, KMp, re, im);
     const C2<T> cf = coef[e];
 #pragma unroll
     for (int r = 0; r < R; ++r) cfma(acc[r], C2<T>{re[r], im[r]}, cf);
@@ -145,7 +145,8 @@ __global__ __launch_bounds__(FWD_THREADS) void fwd_iter_kernel(BatchView bv) {
   C2<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = {(T)0, (T)0};
-  fwd_accumulate<ST>(sd.A, sd.lda, nullptr, p0, np, coef, row, a.KMp, acc);
+  if (a.stream_op) fwd_accumulate<ST, true>(sd.A, sd.lda, nullptr, p0, np, coef, row, a.KMp, acc);
+  else fwd_accumulate<ST, false>(sd.A, sd.lda, nullptr, p0, np, coef, row, a.KMp, acc);
   C2<T>* out = reinterpret_cast<C2<T>*>(a.tpart) + ((int64_t)q * a.nchunk + ch) * a.KMp + row;
 #pragma unroll
   for (int r = 0; r < R; ++r) out[r] = acc[r];
@@ -209,7 +210,8 @@ __global__ __launch_bounds__(FWD_THREADS) void fwd_gather_kernel(IterArgs a, int
   C2<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = {(T)0, (T)0};
-  fwd_accumulate<ST>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
+  if (a.stream_op) fwd_accumulate<ST, true>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
+  else fwd_accumulate<ST, false>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
   C2<T>* out = reinterpret_cast<C2<T>*>(tmp) + (int64_t)ch * a.KMp + row;
 #pragma unroll
   for (int r = 0; r < R; ++r) out[r] = acc[r];
@@ -254,7 +256,8 @@ __global__ __launch_bounds__(FWD_THREADS) void fwd_all_kernel(IterArgs a, int ac
   C2<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = {(T)0, (T)0};
-  fwd_accumulate<ST>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
+  if (a.stream_op) fwd_accumulate<ST, true>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
+  else fwd_accumulate<ST, false>(sd.Afull, sd.lda, idx, p0, np, coef, row, a.KMp, acc);
   C2<T>* out = reinterpret_cast<C2<T>*>(a.tpart) + ((int64_t)q * a.nchunk + ch) * a.KMp + row;
 #pragma unroll
   for (int r = 0; r < R; ++r) out[r] = acc[r];
@@ -336,7 +339,7 @@ template <int ST> __device__ inline int sv_slot(int i) {
 // Dots of C operator columns with the LDS vector sv in one sweep over the
 // rows: every LDS read of the vector serves all C columns, and the C column
 // loads of a row step are in flight together.
-template <int ST, class TA, int C>
+template <int ST, class TA, int C, bool NT = false>
 __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* sv, int KMp, int lane,
                                     C2<TA> (&acc)[C], int rbeg = 0, int rend = -1) {
   using T = typename Store<ST>::T;
@@ -400,7 +403,7 @@ __device__ inline void coldot_multi(const void* const (&col)[C], const C2<TA>* s
 #pragma unroll
       for (int c = c0; c < c0 + CS; ++c) {
         T re[R], im[R];
-        Store<ST>::load(col[c], i0, KMp, re, im);
+        Store<ST>::template load<NT>(col[c], i0, KMp, re, im);
 #pragma unroll
         for (int r = 0; r < R; ++r) cfmac(acc[c], C2<TA>{(TA)re[r], (TA)im[r]}, v[r]);
       }
@@ -503,9 +506,11 @@ __device__ inline void coldot_body(const IterArgs& a, const DotExtra& x, int q) 
         rbeg = pw & ~63;
       }
     }
-    coldot_multi<ST, TA, DC>(cols, sv, a.KMp, lane, dots, rbeg, rend);
+    if (a.stream_w) coldot_multi<ST, TA, DC, true>(cols, sv, a.KMp, lane, dots, rbeg, rend);
+    else coldot_multi<ST, TA, DC, false>(cols, sv, a.KMp, lane, dots, rbeg, rend);
   } else {
-    coldot_multi<ST, TA, DC>(cols, sv, a.KMp, lane, dots);
+    if (a.stream_op) coldot_multi<ST, TA, DC, true>(cols, sv, a.KMp, lane, dots);
+    else coldot_multi<ST, TA, DC, false>(cols, sv, a.KMp, lane, dots);
   }
   // The butterfly reduction leaves the same sums in every lane: lane c
   // finishes column pw + c, so a wave's columns complete together.
